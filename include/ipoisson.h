@@ -1,0 +1,154 @@
+/*
+ * ipoisson.h -- C ABI of the MI355X infinite-domain Poisson solver.
+ *
+ * The solver evaluates phi(x) = integral over R^d of G(|x - s|) rho(s) ds at
+ * every node of a uniform rectangular grid (d = 1, 2, 3), i.e. the solution
+ * of Delta phi = rho in free space restricted to the box, following
+ * C. R. Anderson, "High order accurate solution of Poisson's equation in
+ * infinite domains for smooth functions" (arXiv 2108.11871):
+ *
+ *   phi = phi_star + phi_H                                   (Section 2)
+ *   phi_star : sine-transform solve with zero boundary values (Section 3)
+ *   g        : boundary values of phi, trapezoidal sum of G against rho
+ *              evaluated through slice-wise FFT convolutions  (Section 4)
+ *   phi_H    : 4th- or 6th-order discrete harmonic function with boundary
+ *              values g (compact operator, deferred correction,
+ *              cubic extrapolation)                            (Section 5)
+ *   d = 1    : phi_H is the linear function through the two end values.
+ *
+ * Grid and layout
+ *   n[i] nodes along axis i (n[i] = M_i + 1 panels), spacing h[i]; node
+ *   (i0, ..., i_{d-1}) lies at a + (i0 h0, ..., i_{d-1} h_{d-1}); the result
+ *   does not depend on the origin a.  Arrays are row-major with axis d-1
+ *   contiguous: node (i0, i1, i2) is element (i0 * n1 + i1) * n2 + i2.
+ *   All array arguments are DEVICE pointers (hipMalloc'd memory or the data
+ *   of a GPU tensor) of n0 * ... * n_{d-1} doubles.
+ *
+ * Input contract
+ *   rho values on boundary nodes are ignored.  The method assumes the
+ *   support of rho keeps a positive distance from the boundary (Section 2);
+ *   this is not checked, and accuracy degrades when it is violated.
+ *   On output, phi holds g on every boundary node (faces, edges, corners)
+ *   and phi_star + phi_H on every interior node.
+ *
+ * Errors
+ *   Every call returns an ips_status.  Nothing aborts, exits or throws
+ *   across the ABI.  On error the content of output arrays is unspecified.
+ *   ips_last_error_detail() returns a message for the calling thread.
+ *
+ * Ownership and threading
+ *   The caller owns rho and phi; the library never frees them and keeps no
+ *   reference to them after the work enqueued by a call has completed.
+ *   A plan owns its device workspace and tables.  One plan must not execute
+ *   concurrently on two streams; different plans may.
+ */
+#ifndef IPOISSON_H
+#define IPOISSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ips_plan_s *ips_plan;
+typedef struct ips_batch_s *ips_batch;
+
+typedef enum {
+    IPS_OK = 0,
+    IPS_E_INVALID_ARG = -1, /* bad dimension, size, spacing, order, pointer */
+    IPS_E_UNSUPPORTED = -2, /* valid request outside what this build handles */
+    IPS_E_NO_MEMORY = -3,   /* device or host allocation failed */
+    IPS_E_DEVICE = -4,      /* a HIP runtime call failed */
+    IPS_E_WORKSPACE = -5    /* caller-supplied workspace too small */
+} ips_status;
+
+/* Arithmetic used by the transforms.  The boundary-potential accumulation
+ * and the deferred-correction differences stay FP64 in every mode. */
+typedef enum {
+    IPS_FP64 = 0,       /* everything in FP64 */
+    IPS_MIXED_FP32 = 1  /* sine-transform passes of phi in FP32 */
+} ips_precision;
+
+/*
+ * ips_solve -- one blocking solve on the null stream of the current device.
+ *   d      : 1, 2 or 3
+ *   n      : d node counts, n[i] >= 3; for order 6 and d >= 2, n[i] >= 8
+ *            (the extrapolation reaches five nodes in from the boundary)
+ *   h      : d mesh widths, finite and > 0
+ *   rho    : device array, n0*...*n_{d-1} doubles (boundary values ignored)
+ *   order  : 4 or 6 (accuracy order of the harmonic part, Section 5);
+ *            ignored for d = 1
+ *   phi    : device array of the same size, must not overlap rho
+ * Plans are cached per (device, d, n, h, order) behind a mutex.
+ */
+int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int order,
+              double *phi);
+
+/*
+ * ips_plan_create -- build a reusable plan on the current device: FFT
+ * descriptors, eigenvalue and sine tables, the Fourier transforms of the
+ * Green's-function kernels used by the boundary convolutions (Section 4),
+ * and all device workspace.  Arguments as ips_solve, plus:
+ *   precision : an ips_precision value
+ *   flags     : must be 0
+ * On success *out receives the plan; release it with ips_plan_destroy.
+ */
+int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int order,
+                    int precision, unsigned flags);
+
+/* Bytes of device memory held by the plan (workspace plus tables). */
+int ips_plan_workspace_size(ips_plan p, size_t *bytes);
+
+/*
+ * ips_execute -- enqueue one solve on `stream` (a hipStream_t, NULL = null
+ * stream).  Returns once the work is enqueued; it allocates nothing and
+ * performs no host synchronisation, so it may be captured in a hipGraph.
+ * rho and phi as in ips_solve; they must stay valid until the stream has
+ * executed the work.
+ */
+int ips_execute(ips_plan p, const double *rho, double *phi, void *stream);
+
+/*
+ * ips_execute_adjoint -- enqueue rho_bar = A^T phi_bar, where A is the
+ * linear map rho -> phi that ips_execute applies (same plan).  rho_bar has
+ * the grid's size; its boundary entries are set to 0 (phi ignores rho there).
+ * Used for gradients: if J depends on phi, dJ/drho = A^T dJ/dphi.
+ */
+int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void *stream);
+
+/* Release a plan and its device memory (waits for nothing: the caller must
+ * make sure no enqueued work still uses it). NULL is accepted. */
+int ips_plan_destroy(ips_plan p);
+
+/*
+ * ips_batch_create -- plans for `count` independent problems of possibly
+ * different sizes and spacings, executed together.
+ *   d[b], n[b][0..d[b]-1], h[b][0..d[b]-1] describe problem b
+ *   order, precision, flags as ips_plan_create
+ */
+int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)[3],
+                     const double (*h)[3], int order, int precision, unsigned flags);
+
+/*
+ * ips_batch_execute -- enqueue all problems of the batch on `stream`.
+ *   rho[b], phi[b] : device arrays of problem b (host array of pointers)
+ * Problems are independent; the call allocates nothing.
+ */
+int ips_batch_execute(ips_batch b, const double *const *rho, double *const *phi, void *stream);
+
+int ips_batch_destroy(ips_batch b);
+
+/* Static description of a status code. */
+const char *ips_status_string(int status);
+
+/* Copy the calling thread's last error message into buf (NUL-terminated,
+ * truncated to len). Returns IPS_OK, or IPS_E_INVALID_ARG if buf is NULL. */
+int ips_last_error_detail(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IPOISSON_H */

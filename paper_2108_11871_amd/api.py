@@ -1,0 +1,163 @@
+"""Python binding of the HIP solver: torch tensors in, torch tensors out.
+
+Only argument marshalling happens here: tensors provide device memory and the
+current HIP stream, every arithmetic step runs in libipoisson.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import IPS_FP64, IPS_MIXED_FP32, check, f64_array, i64_array, library_path, lib
+
+PRECISIONS = {"fp64": IPS_FP64, "mixed_fp32": IPS_MIXED_FP32}
+
+__all__ = ["solve", "Plan", "Batch", "SolveFn", "PRECISIONS", "library_path"]
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_grid(t: torch.Tensor):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError("rho must be float64")
+    if not t.is_cuda:
+        raise ValueError("rho must live on a GPU device")
+    if not t.is_contiguous():
+        raise ValueError("rho must be contiguous (row-major, last axis fastest)")
+    if t.dim() not in (1, 2, 3):
+        raise ValueError("rho must have 1, 2 or 3 dimensions")
+
+
+class Plan:
+    """A reusable solve of one grid geometry (ips_plan_create / ips_execute)."""
+
+    def __init__(self, shape: Sequence[int], h, order: int = 6, precision: str = "fp64",
+                 device=None):
+        self.shape = tuple(int(v) for v in shape)
+        d = len(self.shape)
+        hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
+        if len(hh) != d:
+            raise ValueError("h needs one entry per axis")
+        self.h = tuple(float(v) for v in hh)
+        self.order = int(order)
+        self.precision = precision
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().ips_plan_create(ctypes.byref(handle), d, i64_array(self.shape),
+                                        f64_array(self.h), self.order, PRECISIONS[precision], 0))
+        self._h = handle
+
+    @property
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        check(lib().ips_plan_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def __call__(self, rho: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _check_grid(rho)
+        if tuple(rho.shape) != self.shape:
+            raise ValueError("rho shape %s does not match the plan %s" % (tuple(rho.shape), self.shape))
+        if out is None:
+            out = torch.empty_like(rho)
+        with torch.cuda.device(rho.device):
+            check(lib().ips_execute(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(_stream_handle(rho.device))))
+        return out
+
+    def adjoint(self, phi_bar: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _check_grid(phi_bar)
+        if out is None:
+            out = torch.empty_like(phi_bar)
+        with torch.cuda.device(phi_bar.device):
+            check(lib().ips_execute_adjoint(self._h, ctypes.c_void_p(phi_bar.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(_stream_handle(phi_bar.device))))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ips_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(rho: torch.Tensor, h, order: int = 6) -> torch.Tensor:
+    """phi = G * rho on the grid of rho (FP64, blocking call of ips_solve on the null stream)."""
+    _check_grid(rho)
+    d = rho.dim()
+    hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
+    out = torch.empty_like(rho)
+    torch.cuda.current_stream(rho.device).synchronize()
+    with torch.cuda.device(rho.device):
+        check(lib().ips_solve(d, i64_array(rho.shape), f64_array(hh),
+                              ctypes.c_void_p(rho.data_ptr()), int(order),
+                              ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+class Batch:
+    """Many independent problems of uneven size (ips_batch_create / ips_batch_execute)."""
+
+    def __init__(self, shapes, hs, order: int = 6, precision: str = "fp64"):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        count = len(self.shapes)
+        dims = (ctypes.c_int * count)(*[len(s) for s in self.shapes])
+        nn = (ctypes.c_int64 * (3 * count))()
+        hh = (ctypes.c_double * (3 * count))()
+        for b, (s, h) in enumerate(zip(self.shapes, hs)):
+            for a in range(len(s)):
+                nn[3 * b + a] = s[a]
+                hh[3 * b + a] = float(h[a])
+        handle = ctypes.c_void_p()
+        check(lib().ips_batch_create(ctypes.byref(handle), count, dims, nn, hh, int(order),
+                                     PRECISIONS[precision], 0))
+        self._h = handle
+        self.count = count
+
+    def __call__(self, rhos, outs=None):
+        if outs is None:
+            outs = [torch.empty_like(r) for r in rhos]
+        rp = (ctypes.c_void_p * self.count)(*[r.data_ptr() for r in rhos])
+        pp = (ctypes.c_void_p * self.count)(*[o.data_ptr() for o in outs])
+        dev = rhos[0].device
+        with torch.cuda.device(dev):
+            check(lib().ips_batch_execute(self._h, rp, pp, ctypes.c_void_p(_stream_handle(dev))))
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ips_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SolveFn(torch.autograd.Function):
+    """phi = A rho with dJ/drho = A^T dJ/dphi (A^T runs in the HIP adjoint)."""
+
+    @staticmethod
+    def forward(ctx, rho, plan: Plan):
+        ctx.plan = plan
+        return plan(rho.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        return ctx.plan.adjoint(grad_phi.contiguous()), None

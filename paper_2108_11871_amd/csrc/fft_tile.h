@@ -1,0 +1,396 @@
+// LDS-resident tile FFT engine for gfx950 (wave64).
+//
+// A tile holds W real pencils ("columns") of one transform axis.  Columns
+// 2s and 2s+1 form complex sequence s (real part / imaginary part), so one
+// complex FFT of length N = 2M transforms two real pencils at once.  The tile
+// lives in LDS as a real array buf[row * rs + col] (rows 0..N-1, rs = W + 1:
+// the odd padding keeps row-wise and column-wise accesses nearly free of
+// bank conflicts); complex element (n, s) is (buf[n*rs + 2s], buf[n*rs + 2s+1]).
+//
+// Transform kinds built on the length-N complex FFT (M = N/2):
+//   forward, zero padded : f_1..f_{M-1} at positions 1..M-1, zeros elsewhere;
+//                          C[k] = sum_j f_j cos(pi k j/M), k = 0..M
+//                          S[k] = sum_j f_j sin(pi k j/M), k = 1..M-1
+//                          "slot" layout: row k = C[k], row M+k = S[k]
+//                          (S alone is the raw DST-I)
+//   forward, even        : f_0..f_M mirrored to length N; the spectrum is real,
+//                          F[k] = f_0 + (-1)^k f_M + 2 sum_{j=1}^{M-1} f_j cos(pi k j/M)
+//   inverse, hermitian   : from slots C, S: y_j = sum_{k=0}^{N-1} F_k e^{+i pi k j/M}
+//                          with F_k = C_k - i S_k and F_{N-k} = conj(F_k), i.e.
+//                          y_j = C_0 + (-1)^j C_M + 2 sum_{k=1}^{M-1}(C_k cos + S_k sin)
+//
+// The FFT itself is a Stockham autosort transform with radix-2/3/4/5/7/8
+// butterflies held in registers and a direct (output-by-output) stage for
+// any other prime factor.  Twiddles come from a table w[t] = exp(-2 pi i t/N)
+// computed on the host in extended precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ips {
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+
+// multiply by -i (forward) or +i (inverse)
+template <typename T>
+__device__ __forceinline__ cx<T> rot90(cx<T> a, bool inv)
+{
+    return inv ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+constexpr int kMaxStages = 16;
+
+struct FftDesc {
+    int N;   // transform length (even)
+    int M;   // N / 2
+    int nst; // number of Stockham stages
+    int rad[kMaxStages];
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> lds_c(const T *buf, int rs, int n, int s)
+{
+    const T *p = buf + n * rs + 2 * s;
+    return {p[0], p[1]};
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_cs(T *buf, int rs, int n, int s, cx<T> v)
+{
+    T *p = buf + n * rs + 2 * s;
+    p[0] = v.x;
+    p[1] = v.y;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> twid(const cx<T> *tw, int t, bool inv)
+{
+    cx<T> w = tw[t];
+    if (inv) w.y = -w.y;
+    return w;
+}
+
+// In-register DFT of length R (forward: exp(-2 pi i/R); inverse: conjugate).
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool inv)
+{
+    if constexpr (R == 2) {
+        cx<T> t = a[1];
+        a[1] = csub(a[0], t);
+        a[0] = cadd(a[0], t);
+    } else if constexpr (R == 4) {
+        cx<T> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+        cx<T> s13 = cadd(a[1], a[3]), d13 = rot90(csub(a[1], a[3]), inv);
+        a[0] = cadd(s02, s13);
+        a[2] = csub(s02, s13);
+        a[1] = cadd(d02, d13);
+        a[3] = csub(d02, d13);
+    } else if constexpr (R == 8) {
+        cx<T> e[4] = {a[0], a[2], a[4], a[6]};
+        cx<T> o[4] = {a[1], a[3], a[5], a[7]};
+        dft_small<T, 4>(e, tw, N, inv);
+        dft_small<T, 4>(o, tw, N, inv);
+        const T r = (T)0.70710678118654752440084436210484903928;
+        // o[k] *= w8^k
+        cx<T> o1 = inv ? cx<T>{r * (o[1].x - o[1].y), r * (o[1].x + o[1].y)}
+                       : cx<T>{r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)};
+        cx<T> o2 = rot90(o[2], inv);
+        cx<T> o3 = inv ? cx<T>{-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y)}
+                       : cx<T>{r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)};
+        a[0] = cadd(e[0], o[0]);
+        a[4] = csub(e[0], o[0]);
+        a[1] = cadd(e[1], o1);
+        a[5] = csub(e[1], o1);
+        a[2] = cadd(e[2], o2);
+        a[6] = csub(e[2], o2);
+        a[3] = cadd(e[3], o3);
+        a[7] = csub(e[3], o3);
+    } else {
+        // R = 3, 5, 7: direct sum with table roots of unity w_R^m = w_N^(m N/R)
+        cx<T> out[R];
+        const int step = N / R;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            cx<T> acc = a[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(a[r], twid(tw, ((r * q) % R) * step, inv)));
+            out[q] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[q] = out[q];
+    }
+}
+
+// One Stockham stage of radix R (R <= 8) over nseq sequences of length N.
+// MAXE bounds the complex elements a thread holds (nseq * N <= MAXE * NT).
+template <typename T, int R, int MAXE, int NT>
+__device__ __forceinline__ void stage_bfly(T *buf, int rs, int nseq, int N, int Ns,
+                                           const cx<T> *tw, bool inv)
+{
+    constexpr int BPT = (MAXE + R - 1) / R;
+    const int NR = N / R;
+    const int nbf = nseq * NR;
+    const int tstep = N / (Ns * R);
+    cx<T> v[BPT][R];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        if (b < nbf) {
+            const int s = b % nseq, j = b / nseq;
+            const int jm = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = lds_c(buf, rs, j + r * NR, s);
+            if (jm != 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid(tw, jm * r * tstep, inv));
+            }
+            dft_small<T, R>(v[i], tw, N, inv);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        if (b < nbf) {
+            const int s = b % nseq, j = b / nseq;
+            const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_cs(buf, rs, base + r * Ns, s, v[i][r]);
+        }
+    }
+    __syncthreads();
+}
+
+// Stockham stage of arbitrary radix R computed output by output.
+template <typename T, int MAXE, int NT>
+__device__ __forceinline__ void stage_direct(T *buf, int rs, int nseq, int N, int Ns, int R,
+                                             const cx<T> *tw, bool inv)
+{
+    const int NR = N / R;
+    const int tot = nseq * N;
+    const int tstep = N / (Ns * R);
+    cx<T> out[MAXE];
+#pragma unroll
+    for (int i = 0; i < MAXE; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < tot) {
+            const int s = e % nseq, o = e / nseq;
+            const int jm = o % Ns, t = o / Ns, q = t % R, jh = t / R;
+            const int j = jh * Ns + jm;
+            const int E = jm * tstep + q * NR; // exponent per input index r, in units of w_N
+            cx<T> acc = lds_c(buf, rs, j, s);
+            int ex = 0;
+            for (int r = 1; r < R; ++r) {
+                ex += E;
+                if (ex >= N) ex -= N;
+                acc = cadd(acc, cmul(lds_c(buf, rs, j + r * NR, s), twid(tw, ex, inv)));
+            }
+            out[i] = acc;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXE; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < tot) lds_cs(buf, rs, e / nseq, e % nseq, out[i]);
+    }
+    __syncthreads();
+}
+
+// Full length-N complex FFT of nseq sequences held in LDS (in place).
+template <typename T, int MAXE, int NT>
+__device__ void fft_tile(T *buf, int rs, int nseq, const FftDesc &fd, const cx<T> *tw, bool inv)
+{
+    int Ns = 1;
+    for (int st = 0; st < fd.nst; ++st) {
+        const int R = fd.rad[st];
+        switch (R) {
+        case 2: stage_bfly<T, 2, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
+        case 3: stage_bfly<T, 3, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
+        case 4: stage_bfly<T, 4, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
+        case 5: stage_bfly<T, 5, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
+        case 7: stage_bfly<T, 7, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
+        case 8: stage_bfly<T, 8, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
+        default: stage_direct<T, MAXE, NT>(buf, rs, nseq, fd.N, Ns, R, tw, inv); break;
+        }
+        Ns *= R;
+    }
+}
+
+// After a forward zero-padded FFT: write C and S in slot layout (in place).
+template <typename T, int MAXE, int NT>
+__device__ void post_cs(T *buf, int rs, int nseq, int M)
+{
+    constexpr int PPT = MAXE / 2 + 1;
+    const int N = 2 * M;
+    const int tot = nseq * (M + 1);
+    T ca[PPT], cb[PPT], sa[PPT], sb[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < tot) {
+            const int s = e % nseq, k = e / nseq;
+            const cx<T> z1 = lds_c(buf, rs, k, s);
+            const cx<T> z2 = lds_c(buf, rs, k == 0 ? 0 : N - k, s);
+            ca[i] = (T)0.5 * (z1.x + z2.x);
+            cb[i] = (T)0.5 * (z1.y + z2.y);
+            sa[i] = (T)0.5 * (z2.y - z1.y);
+            sb[i] = (T)0.5 * (z1.x - z2.x);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < tot) {
+            const int s = e % nseq, k = e / nseq;
+            buf[k * rs + 2 * s] = ca[i];
+            buf[k * rs + 2 * s + 1] = cb[i];
+            if (k >= 1 && k < M) {
+                buf[(M + k) * rs + 2 * s] = sa[i];
+                buf[(M + k) * rs + 2 * s + 1] = sb[i];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Before an inverse FFT: slots (C, S) -> hermitian-packed complex sequences.
+template <typename T, int MAXE, int NT>
+__device__ void pre_herm(T *buf, int rs, int nseq, int M, bool c_zero)
+{
+    constexpr int PPT = MAXE / 2 + 1;
+    const int N = 2 * M;
+    const int tot = nseq * (M + 1);
+    cx<T> z1[PPT], z2[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < tot) {
+            const int s = e % nseq, k = e / nseq;
+            T ca = 0, cb = 0, sa = 0, sb = 0;
+            if (!c_zero) {
+                ca = buf[k * rs + 2 * s];
+                cb = buf[k * rs + 2 * s + 1];
+            }
+            if (k >= 1 && k < M) {
+                sa = buf[(M + k) * rs + 2 * s];
+                sb = buf[(M + k) * rs + 2 * s + 1];
+            }
+            z1[i] = {ca + sb, cb - sa};
+            z2[i] = {ca - sb, cb + sa};
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < tot) {
+            const int s = e % nseq, k = e / nseq;
+            lds_cs(buf, rs, k, s, z1[i]);
+            if (k >= 1 && k < M) lds_cs(buf, rs, N - k, s, z2[i]);
+        }
+    }
+    __syncthreads();
+}
+
+// Even extension: rows 1..M-1 copied to rows N-1..M+1.
+template <typename T, int NT>
+__device__ void pre_even(T *buf, int rs, int W, int M)
+{
+    const int N = 2 * M;
+    const int tot = (M - 1) * W;
+    for (int e = threadIdx.x; e < tot; e += NT) {
+        const int c = e % W, j = 1 + e / W;
+        buf[(N - j) * rs + c] = buf[j * rs + c];
+    }
+    __syncthreads();
+}
+
+template <typename T, int NT>
+__device__ void zero_rows(T *buf, int rs, int W, int r0, int r1)
+{
+    const int tot = (r1 - r0) * W;
+    for (int e = threadIdx.x; e < tot; e += NT) buf[(r0 + e / W) * rs + e % W] = (T)0;
+}
+
+template <typename T, int NT>
+__device__ void load_twiddles(cx<T> *dst, const cx<double> *src, int N)
+{
+    for (int t = threadIdx.x; t < N; t += NT) {
+        cx<double> w = src[t];
+        dst[t] = {(T)w.x, (T)w.y};
+    }
+}
+
+// Global -> LDS: rows [0, nrows) x cols [0, W) of the tile land at LDS rows
+// row0.. ; columns >= ncols are zero.  Element (r, c) is src[r*rsd + c*csd].
+template <typename T, typename TI, int NT>
+__device__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, int ncols,
+                          int64_t rsd, int64_t csd, int W)
+{
+    const int tot = nrows * W;
+    if (rsd == 1 && csd != 1) {
+        for (int e = threadIdx.x; e < tot; e += NT) {
+            const int r = e % nrows, c = e / nrows;
+            T v = (T)0;
+            if (c < ncols) v = (T)src[r + c * csd];
+            buf[(row0 + r) * rs + c] = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < tot; e += NT) {
+            const int c = e % W, r = e / W;
+            T v = (T)0;
+            if (c < ncols) v = (T)src[r * rsd + c * csd];
+            buf[(row0 + r) * rs + c] = v;
+        }
+    }
+}
+
+// LDS -> global: LDS rows row0..row0+nrows-1, cols [0, ncols) go to
+// dst[r*rsd + c*csd] scaled by `scale`.
+template <typename T, typename TO, int NT>
+__device__ void tile_store(const T *buf, int rs, int row0, TO *dst, int nrows, int ncols,
+                           int64_t rsd, int64_t csd, T scale)
+{
+    if (rsd == 1 && csd != 1) {
+        const int tot = nrows * ncols;
+        for (int e = threadIdx.x; e < tot; e += NT) {
+            const int r = e % nrows, c = e / nrows;
+            dst[r + c * csd] = (TO)(scale * buf[(row0 + r) * rs + c]);
+        }
+    } else {
+        const int tot = nrows * ncols;
+        for (int e = threadIdx.x; e < tot; e += NT) {
+            const int c = e % ncols, r = e / ncols;
+            dst[r * rsd + c * csd] = (TO)(scale * buf[(row0 + r) * rs + c]);
+        }
+    }
+}
+
+// Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD works on
+// one contiguous range of logical tiles (neighbouring tiles share its L2).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks)
+{
+    constexpr int kXcd = 8;
+    if (nblocks < kXcd || nblocks % kXcd != 0) return bid;
+    return (bid % kXcd) * (nblocks / kXcd) + bid / kXcd;
+}
+
+} // namespace ips

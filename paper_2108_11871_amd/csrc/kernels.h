@@ -1,0 +1,157 @@
+// Kernel argument blocks and launchers of the HIP solver (internal header).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_tile.h"
+
+namespace ips {
+
+enum InMode { IN_ZPAD = 0, IN_EVEN = 1, IN_HERM = 2, IN_SPECS = 3 };
+
+// Generic pencil pass: one transform along the tile rows, tile columns are a
+// block of W consecutive columns, grid.y runs over a batch index.
+struct PassArgs {
+    const void *in;
+    void *out;
+    int64_t irs, ics, ibs; // input strides (elements) of row, column, batch
+    int64_t ors, ocs, obs; // output strides
+    int nrows_in;          // rows read (M-1 for IN_ZPAD/IN_SPECS, M+1 for IN_EVEN, N for IN_HERM)
+    int ncols;             // columns in total
+    int nbatch;
+    int in_mode;
+    int out_r0, out_nrows; // LDS rows [out_r0, out_r0 + out_nrows) are stored as rows 0..
+    double scale;
+    int W; // columns per block (even)
+    FftDesc fd;
+    const cx<double> *tw; // N twiddles exp(-2 pi i t / N)
+};
+
+// Boundary convolution, contraction over the batch axis (3D faces normal to
+// the batch axis).  Input: slot-transformed data along the contiguous axis.
+struct BcArgs {
+    const double *in;
+    int64_t irs, ibs;  // row (pencil axis) and batch strides, column stride 1
+    int nrows_in;      // M_p - 1
+    int ncols;         // 2 M_c slots
+    int Mc;            // M of the contiguous axis
+    int nbatch;        // interior length of the contracted axis
+    int chunk;         // batch entries per block
+    const double *K;   // kernel spectra K[d][k_p][k_c], d = distance index
+    int64_t Kd, Kp;    // strides of d and k_p (k_c stride 1)
+    double *part;      // partial face spectra [nchunk][2][2 M_p][ncols]
+    double *Bout;      // optional: S_p S_c part -> Bout[batch*Bbs + (k_p-1)*Brs + (k_c-1)]
+    int64_t Bbs, Brs;
+    int W;
+    FftDesc fd;
+    const cx<double> *tw;
+};
+
+// Boundary convolution, contraction over the tile columns (faces normal to
+// the column axis).  grid.x = chunks of columns, grid.y = batch entries.
+struct CcArgs {
+    const double *in;
+    int64_t irs, ics, ibs;
+    int nrows_in;      // M_p - 1
+    int ncols;         // interior length of the contracted axis
+    int nbatch;        // slots of the remaining in-face axis (1 if none)
+    int Mo;            // M of that axis (slot -> wavenumber), 0 if none
+    int cols_per_chunk;
+    const double *K;   // K[d][k_o][k_p], k_p contiguous
+    int64_t Kd, Ko;
+    double *part;      // [nchunk][2][nbatch][2 M_p]
+    double *Bout;      // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + batch*Bbs]
+    int64_t Bcs, Brs, Bbs;
+    int W;
+    FftDesc fd;
+    const cx<double> *tw;
+};
+
+// Per-axis tables of a plan (device pointers, index k-1 for k = 1..M-1).
+struct AxisTabs {
+    const double *lam;  // -(4/h^2) sin^2(pi k / 2M)       eigenvalue of D2
+    const double *q;    // (pi k / L)^2                    continuous eigenvalue
+    const double *s;    // s[(j-1)*(M-1) + k-1] = sin(pi k j / M), j = 1..5
+};
+
+struct Geo {
+    int d;
+    int M[3];
+    double h[3];
+    double c2[3][3]; // (h_i^2 + h_j^2)/12
+    double c4[3][3]; // h_i^4/240 + h_i^2 h_j^2/144  (coefficient of D2_i D2_i D2_j)
+    double pref;     // prod 2/M_i
+};
+
+// Shell spectra: g~ layers (2 per axis) and the deferred-correction layers
+// (4 per axis, layers 1, 2, M-2, M-1).  Index [layer][k_b-1][k_c-1] over the
+// two other axes in increasing order (3D) or [layer][k_b-1] (2D).
+struct ShellSpec {
+    const double *G[3];
+    const double *D[3];
+};
+
+struct FinalArgs {
+    void *buf;  // B: raw DST of rho along the last d-1 axes; overwritten in place
+    int64_t irs, ics, ibs;
+    int nrows_in; // M_0 - 1
+    int ncols, nbatch;
+    int W;
+    int order;
+    int mixed;   // buf holds float instead of double
+    Geo geo;
+    AxisTabs tab[3];
+    ShellSpec sh;
+    FftDesc fd;
+    const cx<double> *tw;
+};
+
+struct H2Args {
+    int axis; // contraction axis (problem axis index)
+    Geo geo;
+    AxisTabs tab[3];
+    ShellSpec sh;
+    double *T; // [10][I_b][I_c] (3D) or [10][I_b] (2D)
+};
+
+struct DcorrArgs {
+    Geo geo;
+    int64_t n[3];
+    const double *phi;     // grid with boundary values already written
+    const double *RS[3];   // R_spec on the depth-5 shell layers [10][..][..]
+    double *D[3];          // outputs [4][..][..]
+};
+
+struct GtArgs {
+    Geo geo;
+    int64_t n[3];
+    const double *phi;
+    double *G[3]; // [2][..][..]
+};
+
+struct BwriteArgs {
+    Geo geo;
+    int64_t n[3];
+    const double *F[3];   // face values after the inverse transforms
+    int64_t fs[3][3];     // strides (face, row, col) of F[a]
+    double scale[3];
+    double *phi;
+};
+
+hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
+hipError_t launch_bc(const BcArgs &a, int nchunk, hipStream_t st);
+hipError_t launch_cc(const CcArgs &a, int nchunk, hipStream_t st);
+hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st);
+hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st);
+hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);
+hipError_t launch_h2(const H2Args &a, hipStream_t st);
+hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st);
+hipError_t launch_final(const FinalArgs &a, hipStream_t st);
+hipError_t launch_ksample(double *out, int d, int axis, const int *M, const double *h,
+                          hipStream_t st);
+hipError_t launch_1d(const double *rho, double *phi, int M, double h, const FftDesc &fd,
+                     const cx<double> *tw, const AxisTabs &tab, double *scratch, hipStream_t st);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
+
+} // namespace ips

@@ -1,0 +1,907 @@
+// HIP kernels of the infinite-domain Poisson solver (gfx950).
+//
+// Stage map (paper sections):
+//   k_pass    pencil transforms: DST-I / zero-padded cos+sin / even (DCT-I) /
+//             hermitian synthesis along one axis (Sections 3, 4, 5)
+//   k_bc,k_cc boundary values as sums over slices of 2D (3D problems) or 1D
+//             (2D problems) discrete convolutions, accumulated in Fourier
+//             space with the kernel spectra (Section 4, eqs. Trap2D,
+//             Trap2Dconvolution, convolution)
+//   k_gtilde  transfer of the boundary values of the compact operator to the
+//             right-hand side next to the boundary (eq. harmonic4thOrderNH2D)
+//   k_h2      sixth-order right-hand side on the nodes near the boundary,
+//             from its sine coefficients (eqs. 6thOrderRelation2D/3D)
+//   k_dcorr   boundary terms of that right-hand side and its cubic
+//             extrapolation next to the boundary (Section 5)
+//   k_final   spectral combination phi_star + phi_H and first inverse pass
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace ips {
+
+constexpr int NT = 256;
+
+// Allow more than 64 KiB of dynamic LDS where a tile needs it (gfx950 has 160 KiB).
+static void set_lds(const void *fn, size_t bytes)
+{
+    if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T>
+static size_t tile_lds(int N, int W)
+{
+    return (size_t)N * sizeof(cx<T>) + (size_t)N * (W + 1) * sizeof(T);
+}
+
+// ---------------------------------------------------------------------------
+// Generic pencil pass
+// ---------------------------------------------------------------------------
+template <typename T, typename TI, typename TO, int MAXE>
+__global__ __launch_bounds__(NT) void k_pass(PassArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
+    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
+    const int ncb = (a.ncols + W - 1) / W;
+    const int lb = xcd_remap(blockIdx.x, ncb * a.nbatch);
+    const int cb = lb % ncb, bt = lb / ncb;
+    const int c0 = cb * W;
+    const int nc = min(W, a.ncols - c0);
+    const TI *in = static_cast<const TI *>(a.in) + bt * a.ibs + c0 * a.ics;
+    TO *out = static_cast<TO *>(a.out) + bt * a.obs + c0 * a.ocs;
+    load_twiddles<T, NT>(tw, a.tw, N);
+    bool inv = false;
+    if (a.in_mode == IN_ZPAD) {
+        zero_rows<T, NT>(buf, rs, W, 0, 1);
+        zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
+        tile_load<T, TI, NT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, W);
+        __syncthreads();
+    } else if (a.in_mode == IN_EVEN) {
+        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, W);
+        __syncthreads();
+        pre_even<T, NT>(buf, rs, W, M);
+    } else if (a.in_mode == IN_HERM) {
+        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, W);
+        __syncthreads();
+        pre_herm<T, MAXE, NT>(buf, rs, W / 2, M, false);
+        inv = true;
+    } else {
+        tile_load<T, TI, NT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, W);
+        __syncthreads();
+        pre_herm<T, MAXE, NT>(buf, rs, W / 2, M, true);
+        inv = true;
+    }
+    fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, inv);
+    if (a.in_mode == IN_ZPAD) post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
+    tile_store<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale);
+}
+
+template <typename T, typename TI, typename TO>
+static hipError_t launch_pass_t(const PassArgs &a, hipStream_t st)
+{
+    const int ncb = (a.ncols + a.W - 1) / a.W;
+    const int64_t nblk = (int64_t)ncb * a.nbatch;
+    const size_t lds = tile_lds<T>(a.fd.N, a.W);
+    const int work = (a.W / 2) * a.fd.N;
+    if (nblk <= 0) return hipSuccess;
+    if (work <= 4 * NT) {
+        set_lds((const void *)&k_pass<T, TI, TO, 4>, lds);
+        hipLaunchKernelGGL((k_pass<T, TI, TO, 4>), dim3((unsigned)nblk), dim3(NT), lds, st, a);
+    } else if (work <= 8 * NT) {
+        set_lds((const void *)&k_pass<T, TI, TO, 8>, lds);
+        hipLaunchKernelGGL((k_pass<T, TI, TO, 8>), dim3((unsigned)nblk), dim3(NT), lds, st, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st)
+{
+    if (!in_f32 && !out_f32) return launch_pass_t<double, double, double>(a, st);
+    if (in_f32 && out_f32) return launch_pass_t<float, float, float>(a, st);
+    if (!in_f32 && out_f32) return launch_pass_t<float, double, float>(a, st);
+    return launch_pass_t<float, float, double>(a, st);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary convolution, contraction over the batch axis (3D)
+// ---------------------------------------------------------------------------
+template <int MAXE>
+__global__ __launch_bounds__(NT) void k_bc(BcArgs a, int nchunk)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
+    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
+    const int ncb = (a.ncols + W - 1) / W;
+    const int lb = xcd_remap(blockIdx.x, ncb * nchunk);
+    const int cb = lb % ncb, ch = lb / ncb;
+    const int c0 = cb * W;
+    const int nc = min(W, a.ncols - c0);
+    const int b0 = ch * a.chunk, b1 = min(a.nbatch, b0 + a.chunk);
+    constexpr int APT = 2 * MAXE;
+    double acc0[APT], acc1[APT];
+#pragma unroll
+    for (int i = 0; i < APT; ++i) acc0[i] = acc1[i] = 0.0;
+    load_twiddles<double, NT>(tw, a.tw, N);
+    for (int b = b0; b < b1; ++b) {
+        zero_rows<double, NT>(buf, rs, W, 0, 1);
+        zero_rows<double, NT>(buf, rs, W, 1 + a.nrows_in, N);
+        tile_load<double, double, NT>(buf, rs, 1, a.in + b * a.ibs + c0, a.nrows_in, nc, a.irs, 1, W);
+        __syncthreads();
+        fft_tile<double, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
+        post_cs<double, MAXE, NT>(buf, rs, W / 2, M);
+        const double *K0 = a.K + (int64_t)b * a.Kd;
+        const double *K1 = a.K + (int64_t)(a.nbatch - 1 - b) * a.Kd;
+#pragma unroll
+        for (int i = 0; i < APT; ++i) {
+            const int pos = threadIdx.x + i * NT;
+            const int row = pos / W, c = pos % W;
+            if (row < N && c < nc) {
+                const double v = buf[row * rs + c];
+                const int kp = row <= M ? row : row - M;
+                const int sc = c0 + c;
+                const int kc = sc <= a.Mc ? sc : sc - a.Mc;
+                const int64_t ko = (int64_t)kp * a.Kp + kc;
+                acc0[i] += K0[ko] * v;
+                acc1[i] += K1[ko] * v;
+                if (a.Bout && row > M && sc > a.Mc)
+                    a.Bout[b * a.Bbs + (int64_t)(row - M - 1) * a.Brs + (sc - a.Mc - 1)] = v;
+            }
+        }
+        __syncthreads();
+    }
+    double *p0 = a.part + (int64_t)(2 * ch) * N * a.ncols;
+    double *p1 = p0 + (int64_t)N * a.ncols;
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+        const int pos = threadIdx.x + i * NT;
+        const int row = pos / W, c = pos % W;
+        if (row < N && c < nc) {
+            p0[(int64_t)row * a.ncols + c0 + c] = acc0[i];
+            p1[(int64_t)row * a.ncols + c0 + c] = acc1[i];
+        }
+    }
+}
+
+hipError_t launch_bc(const BcArgs &a, int nchunk, hipStream_t st)
+{
+    const int ncb = (a.ncols + a.W - 1) / a.W;
+    const size_t lds = tile_lds<double>(a.fd.N, a.W);
+    const int work = (a.W / 2) * a.fd.N;
+    if (work > 8 * NT) return hipErrorInvalidValue;
+    set_lds((const void *)&k_bc<8>, lds);
+    hipLaunchKernelGGL((k_bc<8>), dim3(ncb * nchunk), dim3(NT), lds, st, a, nchunk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Boundary convolution, contraction over the tile columns (3D and 2D)
+// ---------------------------------------------------------------------------
+template <int MAXE>
+__global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
+    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
+    const int lb = xcd_remap(blockIdx.x, nchunk * a.nbatch);
+    const int ch = lb % nchunk, bt = lb / nchunk;
+    const int kb = a.Mo > 0 ? (bt <= a.Mo ? bt : bt - a.Mo) : 0;
+    constexpr int RPT = 8; // N <= 2048
+    double acc0[RPT], acc1[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc0[i] = acc1[i] = 0.0;
+    load_twiddles<double, NT>(tw, a.tw, N);
+    const int cbeg = ch * a.cols_per_chunk;
+    const int cend = min(a.ncols, cbeg + a.cols_per_chunk);
+    for (int c0 = cbeg; c0 < cend; c0 += W) {
+        const int nc = min(W, cend - c0);
+        zero_rows<double, NT>(buf, rs, W, 0, 1);
+        zero_rows<double, NT>(buf, rs, W, 1 + a.nrows_in, N);
+        tile_load<double, double, NT>(buf, rs, 1, a.in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc,
+                                      a.irs, a.ics, W);
+        __syncthreads();
+        fft_tile<double, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
+        post_cs<double, MAXE, NT>(buf, rs, W / 2, M);
+        if (a.Bout) {
+            const int tot = (M - 1) * nc;
+            for (int e = threadIdx.x; e < tot; e += NT) {
+                const int r = e % (M - 1), c = e / (M - 1);
+                a.Bout[(int64_t)(c0 + c) * a.Bcs + (int64_t)r * a.Brs + (int64_t)bt * a.Bbs] =
+                    buf[(M + 1 + r) * rs + c];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int row = threadIdx.x + i * NT;
+            if (row < N) {
+                const int kp = row <= M ? row : row - M;
+                const double *Kr = a.K + (int64_t)kb * a.Ko + kp;
+                for (int c = 0; c < nc; ++c) {
+                    const double v = buf[row * rs + c];
+                    const int dd = c0 + c;
+                    acc0[i] += Kr[(int64_t)dd * a.Kd] * v;
+                    acc1[i] += Kr[(int64_t)(a.ncols - 1 - dd) * a.Kd] * v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double *p0 = a.part + ((int64_t)(2 * ch) * a.nbatch + bt) * N;
+    double *p1 = p0 + (int64_t)a.nbatch * N;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int row = threadIdx.x + i * NT;
+        if (row < N) {
+            p0[row] = acc0[i];
+            p1[row] = acc1[i];
+        }
+    }
+}
+
+hipError_t launch_cc(const CcArgs &a, int nchunk, hipStream_t st)
+{
+    const size_t lds = tile_lds<double>(a.fd.N, a.W);
+    const int work = (a.W / 2) * a.fd.N;
+    if (work > 8 * NT || a.fd.N > 8 * NT) return hipErrorInvalidValue;
+    set_lds((const void *)&k_cc<8>, lds);
+    hipLaunchKernelGGL((k_cc<8>), dim3(nchunk * a.nbatch), dim3(NT), lds, st, a, nchunk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small element-wise kernels
+// ---------------------------------------------------------------------------
+__global__ void k_reduce(const double *part, double *out, int64_t len, int nchunk)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += part[c * len + i];
+        out[i] = s;
+    }
+}
+
+hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st)
+{
+    const int nb = (int)std::min<int64_t>((len + NT - 1) / NT, 4096);
+    hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(NT), 0, st, part, out, len, nchunk);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(double *p, int64_t n, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st)
+{
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + NT - 1) / NT, 8192));
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NT), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// Node index helpers ---------------------------------------------------------
+__device__ __forceinline__ int64_t node_off(const int64_t *n, int d, const int *i)
+{
+    int64_t o = 0;
+    for (int a = 0; a < d; ++a) o = o * n[a] + i[a];
+    return o;
+}
+
+__device__ __forceinline__ bool on_boundary(const Geo &g, const int *i)
+{
+    for (int a = 0; a < g.d; ++a)
+        if (i[a] == 0 || i[a] == g.M[a]) return true;
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Boundary values -> phi (faces, then edges and corners by lowest axis)
+// ---------------------------------------------------------------------------
+__global__ void k_bwrite(BwriteArgs a)
+{
+    const Geo &g = a.geo;
+    const int d = g.d;
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int fam = 0; fam < d; ++fam) {
+        // ranges of the in-face axes: lower axes exclude their end nodes
+        int lo[2] = {0, 0}, len[2] = {1, 1}, ax[2] = {0, 0}, na = 0;
+        for (int b = 0; b < d; ++b) {
+            if (b == fam) continue;
+            ax[na] = b;
+            lo[na] = b < fam ? 1 : 0;
+            len[na] = b < fam ? g.M[b] - 1 : g.M[b] + 1;
+            ++na;
+        }
+        const int64_t cnt = 2 * (int64_t)len[0] * len[1];
+        if (e < cnt) {
+            const int f = (int)(e / ((int64_t)len[0] * len[1]));
+            const int64_t r = e % ((int64_t)len[0] * len[1]);
+            int j[2];
+            j[0] = lo[0] + (int)(na == 2 ? r / len[1] : r);
+            j[1] = na == 2 ? lo[1] + (int)(r % len[1]) : 0;
+            int idx[3];
+            idx[fam] = f ? g.M[fam] : 0;
+            for (int q = 0; q < na; ++q) idx[ax[q]] = j[q];
+            const double v =
+                a.F[fam][f * a.fs[fam][0] + j[0] * a.fs[fam][1] + (na == 2 ? j[1] * a.fs[fam][2] : 0)];
+            a.phi[node_off(a.n, d, idx)] = a.scale[fam] * v;
+            return;
+        }
+        e -= cnt;
+    }
+}
+
+hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st)
+{
+    int64_t tot = 0;
+    const Geo &g = a.geo;
+    for (int fam = 0; fam < g.d; ++fam) {
+        int64_t c = 2;
+        for (int b = 0; b < g.d; ++b)
+            if (b != fam) c *= b < fam ? g.M[b] - 1 : g.M[b] + 1;
+        tot += c;
+    }
+    hipLaunchKernelGGL(k_bwrite, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// g~ = -(L_h B) on the interior nodes next to the boundary, split into one
+// layer pair per axis (a node belongs to the lowest axis whose index is 1 or
+// M-1 there; other layers hold 0 at that node).
+// ---------------------------------------------------------------------------
+__global__ void k_gtilde(GtArgs a)
+{
+    const Geo &g = a.geo;
+    const int d = g.d;
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int fam = 0; fam < d; ++fam) {
+        int len[2] = {1, 1}, ax[2] = {0, 0}, na = 0;
+        for (int b = 0; b < d; ++b)
+            if (b != fam) {
+                ax[na] = b;
+                len[na] = g.M[b] - 1;
+                ++na;
+            }
+        const int64_t per = (int64_t)len[0] * len[1];
+        if (e < 2 * per) {
+            const int f = (int)(e / per);
+            const int64_t r = e % per;
+            int i[3];
+            i[fam] = f ? g.M[fam] - 1 : 1;
+            i[ax[0]] = 1 + (int)(na == 2 ? r / len[1] : r);
+            if (na == 2) i[ax[1]] = 1 + (int)(r % len[1]);
+            // with M = 2 both layers are the same nodes: keep only the first
+            bool owned = !(f == 1 && g.M[fam] == 2);
+            for (int b = 0; b < fam; ++b)
+                if (i[b] == 1 || i[b] == g.M[b] - 1) owned = false;
+            double s = 0.0;
+            if (owned) {
+                // face neighbours
+                for (int p = 0; p < d; ++p) {
+                    double w = 1.0 / (g.h[p] * g.h[p]);
+                    for (int q = 0; q < d; ++q)
+                        if (q != p) w -= 2.0 * g.c2[p][q] / (g.h[p] * g.h[p] * g.h[q] * g.h[q]);
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        int j[3] = {i[0], i[1], i[2]};
+                        j[p] += sg;
+                        if (on_boundary(g, j)) s += w * a.phi[node_off(a.n, d, j)];
+                    }
+                }
+                // edge neighbours
+                for (int p = 0; p < d; ++p)
+                    for (int q = p + 1; q < d; ++q) {
+                        const double w = g.c2[p][q] / (g.h[p] * g.h[p] * g.h[q] * g.h[q]);
+                        for (int sp = -1; sp <= 1; sp += 2)
+                            for (int sq = -1; sq <= 1; sq += 2) {
+                                int j[3] = {i[0], i[1], i[2]};
+                                j[p] += sp;
+                                j[q] += sq;
+                                if (on_boundary(g, j)) s += w * a.phi[node_off(a.n, d, j)];
+                            }
+                    }
+                s = -s;
+            }
+            a.G[fam][e] = s;
+            return;
+        }
+        e -= 2 * per;
+    }
+}
+
+hipError_t launch_gtilde(const GtArgs &a, hipStream_t st)
+{
+    const Geo &g = a.geo;
+    int64_t tot = 0;
+    for (int fam = 0; fam < g.d; ++fam) {
+        int64_t c = 2;
+        for (int b = 0; b < g.d; ++b)
+            if (b != fam) c *= g.M[b] - 1;
+        tot += c;
+    }
+    hipLaunchKernelGGL(k_gtilde, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Spectral pieces shared by k_h2 and k_final
+// ---------------------------------------------------------------------------
+struct Spec {
+    double lam[3];
+    double Lambda; // eigenvalue of L_0
+    double mR;     // symbol of the sixth-order right-hand side operator
+};
+
+__device__ __forceinline__ void spec_eval(const Geo &g, const AxisTabs *tab, const int *k, Spec &s)
+{
+    const int d = g.d;
+    for (int a = 0; a < d; ++a) s.lam[a] = tab[a].lam[k[a] - 1];
+    double L = 0.0, R = 0.0;
+    for (int a = 0; a < d; ++a) L += s.lam[a];
+    for (int i = 0; i < d; ++i)
+        for (int j = i + 1; j < d; ++j) {
+            const double p = s.lam[i] * s.lam[j];
+            L += g.c2[i][j] * p;
+            R += p * (g.c4[i][j] * s.lam[i] + g.c4[j][i] * s.lam[j]);
+        }
+    s.Lambda = L;
+    s.mR = R;
+}
+
+// index of the two (or one) other axes of `a` in a shell layer array
+__device__ __forceinline__ int64_t shell_idx(const Geo &g, int a, const int *k)
+{
+    int64_t o = 0;
+    for (int b = 0; b < g.d; ++b)
+        if (b != a) o = o * (g.M[b] - 1) + (k[b] - 1);
+    return o;
+}
+
+__device__ __forceinline__ int64_t shell_size(const Geo &g, int a)
+{
+    int64_t s = 1;
+    for (int b = 0; b < g.d; ++b)
+        if (b != a) s *= g.M[b] - 1;
+    return s;
+}
+
+// raw DST of g~ at wavenumber k
+__device__ __forceinline__ double gt_hat(const Geo &g, const AxisTabs *tab, const ShellSpec &sh,
+                                         const int *k)
+{
+    double v = 0.0;
+    for (int a = 0; a < g.d; ++a) {
+        const int64_t o = shell_idx(g, a, k);
+        const int64_t ss = shell_size(g, a);
+        const double sg = (k[a] & 1) ? 1.0 : -1.0;
+        v += tab[a].s[k[a] - 1] * (sh.G[a][o] + sg * sh.G[a][ss + o]);
+    }
+    return v;
+}
+
+// raw DST of the deferred-correction shell field D at wavenumber k
+__device__ __forceinline__ double d_hat(const Geo &g, const AxisTabs *tab, const ShellSpec &sh,
+                                        const int *k)
+{
+    double v = 0.0;
+    for (int a = 0; a < g.d; ++a) {
+        const int64_t o = shell_idx(g, a, k);
+        const int64_t ss = shell_size(g, a);
+        const double sg = (k[a] & 1) ? 1.0 : -1.0;
+        const int m1 = g.M[a] - 1;
+        const double *D = sh.D[a];
+        v += tab[a].s[k[a] - 1] * (D[o] + sg * D[3 * ss + o]) +
+             tab[a].s[m1 + k[a] - 1] * (D[ss + o] + sg * D[2 * ss + o]);
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Sixth-order right-hand side of the harmonic part on the depth-5 layers of
+// axis `axis`: T[j][k_other] = sum_{k_axis} sin(pi k_axis j / M) c_R(k),
+// with c_R = prod(2/M) * m_R(k) * gt_hat(k) / Lambda(k) the sine coefficients
+// of the stencil applied to the interior part of u1.  Layers j = 1..5 and
+// M-5..M-1 (parity split: sin(pi k (M-j)/M) = (-1)^(k+1) sin(pi k j / M)).
+// ---------------------------------------------------------------------------
+__global__ void k_h2(H2Args a)
+{
+    const Geo &g = a.geo;
+    const int d = g.d, ax = a.axis;
+    const int64_t tot = shell_size(g, ax);
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    int k[3] = {1, 1, 1};
+    {
+        int64_t r = e;
+        for (int b = d - 1; b >= 0; --b) {
+            if (b == ax) continue;
+            k[b] = 1 + (int)(r % (g.M[b] - 1));
+            r /= (g.M[b] - 1);
+        }
+    }
+    const int Ma = g.M[ax];
+    const double *sj = a.tab[ax].s;
+    double ev[5] = {0, 0, 0, 0, 0}, od[5] = {0, 0, 0, 0, 0};
+    for (int ka = 1; ka < Ma; ++ka) {
+        k[ax] = ka;
+        Spec s;
+        spec_eval(g, a.tab, k, s);
+        const double c = g.pref * s.mR * gt_hat(g, a.tab, a.sh, k) / s.Lambda;
+        if (ka & 1) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) od[j] += sj[j * (Ma - 1) + ka - 1] * c;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ev[j] += sj[j * (Ma - 1) + ka - 1] * c;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        a.T[j * tot + e] = od[j] + ev[j];
+        a.T[(5 + j) * tot + e] = od[j] - ev[j];
+    }
+}
+
+hipError_t launch_h2(const H2Args &a, hipStream_t st)
+{
+    int64_t tot = 1;
+    for (int b = 0; b < a.geo.d; ++b)
+        if (b != a.axis) tot *= a.geo.M[b] - 1;
+    hipLaunchKernelGGL(k_h2, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// D = R - R_spec on the nodes with an index in {1, 2, M-2, M-1}:
+//   R_core = R_spec + (boundary terms of the D2^2 D2 stencils, which reach
+//            the faces from core nodes with an index 2 or M-2)
+//   R      = tensor-product cubic extrapolation of R_core to indices 1, M-1
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int layer5(int i, int M)
+{
+    if (i >= 1 && i <= 5) return i - 1;
+    if (i >= M - 5 && i <= M - 1) return 5 + (M - 1 - i);
+    return -1;
+}
+
+__device__ double rs_lookup(const DcorrArgs &a, const int *p)
+{
+    const Geo &g = a.geo;
+    for (int ax = 0; ax < g.d; ++ax) {
+        const int jj = layer5(p[ax], g.M[ax]);
+        if (jj >= 0) {
+            const int64_t ss = shell_size(g, ax);
+            return a.RS[ax][jj * ss + shell_idx(g, ax, p)];
+        }
+    }
+    return 0.0; // not reached for the nodes this kernel visits
+}
+
+__device__ double rcore(const DcorrArgs &a, const int *p)
+{
+    const Geo &g = a.geo;
+    const int d = g.d;
+    double v = rs_lookup(a, p);
+    for (int ax = 0; ax < d; ++ax) {
+        int face;
+        if (p[ax] == 2)
+            face = 0;
+        else if (p[ax] == g.M[ax] - 2)
+            face = g.M[ax];
+        else
+            continue;
+        const double h2 = g.h[ax] * g.h[ax];
+        double t = 0.0;
+        for (int b = 0; b < d; ++b) {
+            if (b == ax) continue;
+            int q[3] = {p[0], p[1], p[2]};
+            q[ax] = face;
+            const double f0 = a.phi[node_off(a.n, d, q)];
+            q[b] = p[b] - 1;
+            const double fm = a.phi[node_off(a.n, d, q)];
+            q[b] = p[b] + 1;
+            const double fp = a.phi[node_off(a.n, d, q)];
+            t += g.c4[ax][b] * (fm - 2.0 * f0 + fp) / (g.h[b] * g.h[b]);
+        }
+        v += t / (h2 * h2);
+    }
+    return v;
+}
+
+__global__ void k_dcorr(DcorrArgs a)
+{
+    const Geo &g = a.geo;
+    const int d = g.d;
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int fam = 0; fam < d; ++fam) {
+        const int64_t per = shell_size(g, fam);
+        if (e < 4 * per) {
+            const int jj = (int)(e / per);
+            int64_t r = e % per;
+            int i[3] = {0, 0, 0};
+            const int L[4] = {1, 2, g.M[fam] - 2, g.M[fam] - 1};
+            i[fam] = L[jj];
+            for (int b = d - 1; b >= 0; --b) {
+                if (b == fam) continue;
+                i[b] = 1 + (int)(r % (g.M[b] - 1));
+                r /= (g.M[b] - 1);
+            }
+            bool owned = true;
+            for (int b = 0; b < fam; ++b) {
+                const int m = g.M[b];
+                if (i[b] == 1 || i[b] == 2 || i[b] == m - 2 || i[b] == m - 1) owned = false;
+            }
+            double out = 0.0;
+            if (owned) {
+                // per-axis extrapolation stencils
+                int pos[3][4];
+                double wt[3][4];
+                int cnt[3] = {1, 1, 1};
+                for (int b = 0; b < 3; ++b) {
+                    pos[b][0] = b < d ? i[b] : 0;
+                    wt[b][0] = 1.0;
+                }
+                for (int b = 0; b < d; ++b) {
+                    const int m = g.M[b];
+                    if (i[b] == 1 || i[b] == m - 1) {
+                        const int sgn = i[b] == 1 ? 1 : -1;
+                        const double w4[4] = {4.0, -6.0, 4.0, -1.0};
+                        for (int t = 0; t < 4; ++t) {
+                            pos[b][t] = i[b] + sgn * (t + 1);
+                            wt[b][t] = w4[t];
+                        }
+                        cnt[b] = 4;
+                    }
+                }
+                double R = 0.0;
+                for (int t0 = 0; t0 < cnt[0]; ++t0)
+                    for (int t1 = 0; t1 < cnt[1]; ++t1)
+                        for (int t2 = 0; t2 < cnt[2]; ++t2) {
+                            const int p[3] = {pos[0][t0], pos[1][t1], pos[2][t2]};
+                            R += wt[0][t0] * wt[1][t1] * wt[2][t2] * rcore(a, p);
+                        }
+                out = R - rs_lookup(a, i);
+            }
+            a.D[fam][e] = out;
+            return;
+        }
+        e -= 4 * per;
+    }
+}
+
+hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st)
+{
+    int64_t tot = 0;
+    for (int fam = 0; fam < a.geo.d; ++fam) {
+        int64_t c = 4;
+        for (int b = 0; b < a.geo.d; ++b)
+            if (b != fam) c *= a.geo.M[b] - 1;
+        tot += c;
+    }
+    hipLaunchKernelGGL(k_dcorr, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Final pass along axis 0: raw DST of B along axis 0 -> beta (raw DST of rho),
+// spectral combination
+//   c(k) = prod(2/M) [ -beta / (pi^2 sum k^2/L^2)
+//                      + (gt_hat (1 + m_R/Lambda) + D_hat) / Lambda ]   (order 6)
+//   c(k) = prod(2/M) [ -beta / (pi^2 sum k^2/L^2) + gt_hat / Lambda ]     (order 4)
+// then the inverse sine transform along axis 0, written back in place.
+// ---------------------------------------------------------------------------
+template <typename T, int MAXE>
+__global__ __launch_bounds__(NT) void k_final(FinalArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
+    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
+    const int ncb = (a.ncols + W - 1) / W;
+    const int lb = xcd_remap(blockIdx.x, ncb * a.nbatch);
+    const int cb = lb % ncb, bt = lb / ncb;
+    const int c0 = cb * W;
+    const int nc = min(W, a.ncols - c0);
+    T *g = static_cast<T *>(a.buf) + bt * a.ibs + c0 * a.ics;
+    load_twiddles<T, NT>(tw, a.tw, N);
+    zero_rows<T, NT>(buf, rs, W, 0, 1);
+    zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
+    tile_load<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, W);
+    __syncthreads();
+    fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
+    post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
+    const Geo &geo = a.geo;
+    const int tot = (M - 1) * W;
+    for (int e = threadIdx.x; e < tot; e += NT) {
+        const int c = e % W, kx = 1 + e / W;
+        double cval = 0.0;
+        if (c < nc) {
+            int k[3];
+            k[0] = kx;
+            if (geo.d == 3) {
+                k[1] = 1 + bt;
+                k[2] = 1 + c0 + c;
+            } else {
+                k[1] = 1 + c0 + c;
+                k[2] = 1;
+            }
+            const double beta = (double)buf[(M + kx) * rs + c];
+            double q = 0.0;
+            for (int ax = 0; ax < geo.d; ++ax) q += a.tab[ax].q[k[ax] - 1];
+            Spec s;
+            spec_eval(geo, a.tab, k, s);
+            const double gh = gt_hat(geo, a.tab, a.sh, k);
+            double harm;
+            if (a.order == 6)
+                harm = (gh * (1.0 + s.mR / s.Lambda) + d_hat(geo, a.tab, a.sh, k)) / s.Lambda;
+            else
+                harm = gh / s.Lambda;
+            cval = geo.pref * (harm - beta / q);
+        }
+        buf[(M + kx) * rs + c] = (T)cval;
+    }
+    __syncthreads();
+    pre_herm<T, MAXE, NT>(buf, rs, W / 2, M, true);
+    fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, true);
+    tile_store<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5);
+}
+
+hipError_t launch_final(const FinalArgs &a, hipStream_t st)
+{
+    const int ncb = (a.ncols + a.W - 1) / a.W;
+    const int nblk = ncb * a.nbatch;
+    const int work = (a.W / 2) * a.fd.N;
+    if (work > 8 * NT) return hipErrorInvalidValue;
+    if (a.mixed) {
+        const size_t lds = tile_lds<float>(a.fd.N, a.W);
+        if (work <= 4 * NT) {
+            set_lds((const void *)&k_final<float, 4>, lds);
+            hipLaunchKernelGGL((k_final<float, 4>), dim3(nblk), dim3(NT), lds, st, a);
+        } else {
+            set_lds((const void *)&k_final<float, 8>, lds);
+            hipLaunchKernelGGL((k_final<float, 8>), dim3(nblk), dim3(NT), lds, st, a);
+        }
+    } else {
+        const size_t lds = tile_lds<double>(a.fd.N, a.W);
+        if (work <= 4 * NT) {
+            set_lds((const void *)&k_final<double, 4>, lds);
+            hipLaunchKernelGGL((k_final<double, 4>), dim3(nblk), dim3(NT), lds, st, a);
+        } else {
+            set_lds((const void *)&k_final<double, 8>, lds);
+            hipLaunchKernelGGL((k_final<double, 8>), dim3(nblk), dim3(NT), lds, st, a);
+        }
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Kernel samples for the boundary convolutions: for faces normal to axis a,
+// K[dd][ib][ic] = G(sqrt(((dd+1) h_a)^2 + (ib h_b)^2 + (ic h_c)^2)),
+// dd = 0..M_a-2, ib = 0..M_b, ic = 0..M_c  (2D: K[dd][ib]).
+// ---------------------------------------------------------------------------
+__global__ void k_ksample(double *out, int d, int a, int b, int c, int Ma, int Mb, int Mc,
+                          double ha, double hb, double hc)
+{
+    const int64_t nb = Mb + 1, ncn = d == 3 ? Mc + 1 : 1;
+    const int64_t tot = (int64_t)(Ma - 1) * nb * ncn;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int ic = (int)(e % ncn);
+        const int ib = (int)((e / ncn) % nb);
+        const int dd = (int)(e / (ncn * nb));
+        const double x = (dd + 1) * ha, y = ib * hb, z = ic * hc;
+        const double r = sqrt(x * x + y * y + (d == 3 ? z * z : 0.0));
+        double G;
+        if (d == 3)
+            G = -1.0 / (4.0 * M_PI * r);
+        else
+            G = log(r) / (2.0 * M_PI);
+        out[e] = G;
+    }
+}
+
+hipError_t launch_ksample(double *out, int d, int axis, const int *M, const double *h,
+                          hipStream_t st)
+{
+    // axes in the order the contraction kernels index their tables
+    int a = axis, b, c = 0;
+    if (d == 2) {
+        b = 1 - axis;
+    } else if (axis == 0) {
+        b = 1;
+        c = 2;
+    } else if (axis == 1) {
+        b = 0;
+        c = 2;
+    } else {
+        b = 1;
+        c = 0;
+    }
+    const int64_t tot = (int64_t)(M[a] - 1) * (M[b] + 1) * (d == 3 ? M[c] + 1 : 1);
+    const int nb = (int)std::min<int64_t>((tot + NT - 1) / NT, 65536);
+    hipLaunchKernelGGL(k_ksample, dim3(nb), dim3(NT), 0, st, out, d, a, b, c, M[a], M[b],
+                       d == 3 ? M[c] : 0, h[a], h[b], d == 3 ? h[c] : 0.0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 1D: phi* by one sine-transform pencil, end values by direct sums of
+// G(r) = r/2, phi_H linear between them.
+// ---------------------------------------------------------------------------
+template <int MAXE>
+__global__ __launch_bounds__(NT) void k_1d(const double *rho, double *phi, int M, double h,
+                                           FftDesc fd, const cx<double> *twg, AxisTabs tab)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = fd.N, W = 2, rs = 3;
+    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
+    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
+    __shared__ double red[2][NT];
+    load_twiddles<double, NT>(tw, twg, N);
+    // end values
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = 1 + threadIdx.x; j < M; j += NT) {
+        s0 += (0.5 * j * h) * rho[j];
+        s1 += (0.5 * (M - j) * h) * rho[j];
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    zero_rows<double, NT>(buf, rs, W, 0, 1);
+    zero_rows<double, NT>(buf, rs, W, M, N);
+    tile_load<double, double, NT>(buf, rs, 1, rho + 1, M - 1, 1, 1, 1, W);
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    const double g0 = h * red[0][0], g1 = h * red[1][0];
+    fft_tile<double, MAXE, NT>(buf, rs, 1, fd, tw, false);
+    post_cs<double, MAXE, NT>(buf, rs, 1, M);
+    for (int k = 1 + threadIdx.x; k < M; k += NT)
+        buf[(M + k) * rs] = -(2.0 / M) * buf[(M + k) * rs] / tab.q[k - 1];
+    __syncthreads();
+    pre_herm<double, MAXE, NT>(buf, rs, 1, M, true);
+    fft_tile<double, MAXE, NT>(buf, rs, 1, fd, tw, true);
+    for (int j = threadIdx.x; j <= M; j += NT) {
+        double v;
+        if (j == 0)
+            v = g0;
+        else if (j == M)
+            v = g1;
+        else
+            v = 0.5 * buf[j * rs] + g0 + (g1 - g0) * ((double)j / M);
+        phi[j] = v;
+    }
+}
+
+hipError_t launch_1d(const double *rho, double *phi, int M, double h, const FftDesc &fd,
+                     const cx<double> *tw, const AxisTabs &tab, double * /*scratch*/,
+                     hipStream_t st)
+{
+    const size_t lds = tile_lds<double>(fd.N, 2);
+    if (fd.N <= 4 * NT) {
+        set_lds((const void *)&k_1d<4>, lds);
+        hipLaunchKernelGGL((k_1d<4>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
+    } else if (fd.N <= 8 * NT) {
+        set_lds((const void *)&k_1d<8>, lds);
+        hipLaunchKernelGGL((k_1d<8>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+} // namespace ips

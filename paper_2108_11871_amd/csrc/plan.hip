@@ -1,0 +1,948 @@
+// Host side of the solver: plans, workspace, the launch sequence of one
+// solve, and the C ABI declared in include/ipoisson.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "ipoisson.h"
+#include "kernels.h"
+
+using namespace ips;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define IPS_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(IPS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+constexpr int kMaxN = 2048; // longest transform (2M) held in one LDS tile
+
+// FFT length N = 2M as a list of Stockham radices (8, 4, 2, 3, 5, 7, other primes)
+bool factor_fft(int N, FftDesc &fd)
+{
+    fd.N = N;
+    fd.M = N / 2;
+    fd.nst = 0;
+    int r = N;
+    auto push = [&](int R) {
+        if (fd.nst >= kMaxStages) return false;
+        fd.rad[fd.nst++] = R;
+        return true;
+    };
+    while (r % 8 == 0) {
+        if (!push(8)) return false;
+        r /= 8;
+    }
+    while (r % 4 == 0) {
+        if (!push(4)) return false;
+        r /= 4;
+    }
+    while (r % 2 == 0) {
+        if (!push(2)) return false;
+        r /= 2;
+    }
+    for (int p = 3; r > 1; p += 2) {
+        while (r % p == 0) {
+            if (!push(p)) return false;
+            r /= p;
+        }
+    }
+    return true;
+}
+
+struct DevBuf {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    int alloc(void **p, size_t n)
+    {
+        *p = nullptr;
+        if (n == 0) n = 8;
+        if (getenv("IPS_TEST_FAIL_ALLOC")) return fail(IPS_E_NO_MEMORY, "allocation failure forced by IPS_TEST_FAIL_ALLOC");
+        hipError_t e = hipMalloc(p, n);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            (void)hipGetLastError();
+            return fail(IPS_E_NO_MEMORY, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
+        ptrs.push_back(*p);
+        bytes += n;
+        return IPS_OK;
+    }
+    void release()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+int tile_width(int N, int maxwork, int ncols)
+{
+    int nseq = std::max(1, maxwork / N);
+    int W = 2 * nseq;
+    int need = ncols + (ncols & 1);
+    if (need < 2) need = 2;
+    return std::min(W, need);
+}
+
+} // namespace
+
+struct ips_plan_s {
+    int d = 0;
+    int64_t n[3] = {1, 1, 1};
+    double h[3] = {1, 1, 1};
+    int order = 6, precision = 0;
+    int device = 0;
+    Geo geo{};
+    int M[3] = {0, 0, 0}, I[3] = {0, 0, 0}, N[3] = {0, 0, 0};
+    FftDesc fd[3]{};
+    cx<double> *tw[3] = {nullptr, nullptr, nullptr};
+    AxisTabs tab[3]{};
+    double *K[3] = {nullptr, nullptr, nullptr};
+    double *A = nullptr;
+    void *B = nullptr;
+    double *part[3] = {nullptr, nullptr, nullptr};
+    int nch[3] = {1, 1, 1};
+    int chunk[3] = {1, 1, 1};
+    double *F[3] = {nullptr, nullptr, nullptr};
+    double *G[3] = {nullptr, nullptr, nullptr};
+    double *T[3] = {nullptr, nullptr, nullptr};
+    double *D[3] = {nullptr, nullptr, nullptr};
+    DevBuf mem;
+};
+
+namespace {
+
+int validate(int d, const int64_t *n, const double *h, int order, int precision, unsigned flags)
+{
+    if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
+    if (!n || !h) return fail(IPS_E_INVALID_ARG, "n and h must not be NULL");
+    if (flags != 0) return fail(IPS_E_INVALID_ARG, "flags must be 0");
+    if (precision != IPS_FP64 && precision != IPS_MIXED_FP32)
+        return fail(IPS_E_INVALID_ARG, "unknown precision");
+    if (d >= 2 && order != 4 && order != 6) return fail(IPS_E_INVALID_ARG, "order must be 4 or 6");
+    for (int a = 0; a < d; ++a) {
+        if (n[a] < 3) return fail(IPS_E_INVALID_ARG, "every n[i] must be >= 3");
+        if (!(h[a] > 0.0) || !std::isfinite(h[a]))
+            return fail(IPS_E_INVALID_ARG, "every h[i] must be finite and > 0");
+        if (d >= 2 && order == 6 && n[a] < 8)
+            return fail(IPS_E_INVALID_ARG, "order 6 needs n[i] >= 8 (extrapolation stencil)");
+        if (2 * (n[a] - 1) > kMaxN)
+            return fail(IPS_E_UNSUPPORTED, "n[i] - 1 must not exceed " + std::to_string(kMaxN / 2));
+    }
+    if (d == 1 && precision != IPS_FP64)
+        return fail(IPS_E_UNSUPPORTED, "d = 1 runs in FP64 only");
+    return IPS_OK;
+}
+
+// Host tables of one axis, computed in long double and rounded once.
+std::vector<double> axis_tables(int M, double h)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const int m1 = M - 1;
+    std::vector<double> t((size_t)m1 * 7);
+    const long double L = (long double)M * h;
+    for (int k = 1; k < M; ++k) {
+        const long double s = sinl(pi * k / (2.0L * M));
+        t[k - 1] = (double)(-(4.0L / ((long double)h * h)) * s * s);
+        const long double q = pi * k / L;
+        t[m1 + k - 1] = (double)(q * q);
+        for (int j = 1; j <= 5; ++j) {
+            const long long r = ((long long)k * j) % (2LL * M);
+            t[(size_t)(1 + j) * m1 + k - 1] = (double)sinl(pi * (long double)r / M);
+        }
+    }
+    return t;
+}
+
+std::vector<cx<double>> twiddles(int N)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<cx<double>> w(N);
+    for (int t = 0; t < N; ++t) {
+        const long double a = 2.0L * pi * t / N;
+        w[t] = {(double)cosl(a), (double)(-sinl(a))};
+    }
+    return w;
+}
+
+int run_pass(PassArgs a, const FftDesc &fd, const cx<double> *tw, bool in_f32, bool out_f32,
+             hipStream_t st)
+{
+    a.fd = fd;
+    a.tw = tw;
+    if (a.W == 0) a.W = tile_width(fd.N, 2048, a.ncols);
+    IPS_HIP(launch_pass(a, in_f32, out_f32, st));
+    return IPS_OK;
+}
+
+// Forward raw DST (IN_ZPAD -> S rows) or inverse (IN_SPECS -> real rows) of
+// the last two (or one) axes of a stack of shell layers [nl][I_b][I_c].
+int shell_dst(ips_plan p, double *buf, int nl, int fam, bool inverse, hipStream_t st)
+{
+    int ax[2], na = 0;
+    for (int b = 0; b < p->d; ++b)
+        if (b != fam) ax[na++] = b;
+    const int last = ax[na - 1];
+    const int64_t plane = na == 2 ? (int64_t)p->I[ax[0]] * p->I[ax[1]] : p->I[ax[0]];
+    auto one = [&](int axis, int64_t rstride, int64_t cstride, int ncols, int nbatch,
+                   int64_t bstride) -> int {
+        PassArgs a{};
+        a.in = buf;
+        a.out = buf;
+        a.irs = a.ors = rstride;
+        a.ics = a.ocs = cstride;
+        a.ibs = a.obs = bstride;
+        a.nrows_in = p->I[axis];
+        a.ncols = ncols;
+        a.nbatch = nbatch;
+        a.in_mode = inverse ? IN_SPECS : IN_ZPAD;
+        a.out_r0 = inverse ? 1 : p->M[axis] + 1;
+        a.out_nrows = p->I[axis];
+        a.scale = inverse ? 0.5 : 1.0;
+        return run_pass(a, p->fd[axis], p->tw[axis], false, false, st);
+    };
+    int rc;
+    if (na == 2) {
+        // along the contiguous axis: rows stride 1, columns = lower axis
+        rc = one(last, 1, p->I[last], p->I[ax[0]], nl, plane);
+        if (rc) return rc;
+        rc = one(ax[0], p->I[last], 1, p->I[last], nl, plane);
+    } else {
+        rc = one(last, 1, plane, nl, 1, 0);
+    }
+    return rc;
+}
+
+int plan_build(ips_plan p, hipStream_t st)
+{
+    const int d = p->d;
+    Geo &g = p->geo;
+    g.d = d;
+    g.pref = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        g.M[a] = a < d ? p->M[a] : 1;
+        g.h[a] = a < d ? p->h[a] : 1.0;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            g.c2[i][j] = (g.h[i] * g.h[i] + g.h[j] * g.h[j]) / 12.0;
+            g.c4[i][j] = g.h[i] * g.h[i] * g.h[i] * g.h[i] / 240.0 +
+                         g.h[i] * g.h[i] * g.h[j] * g.h[j] / 144.0;
+        }
+    for (int a = 0; a < d; ++a) g.pref *= 2.0 / p->M[a];
+
+    for (int a = 0; a < d; ++a) {
+        if (!factor_fft(p->N[a], p->fd[a])) return fail(IPS_E_UNSUPPORTED, "FFT length not factorable");
+        std::vector<cx<double>> w = twiddles(p->N[a]);
+        int rc = p->mem.alloc((void **)&p->tw[a], w.size() * sizeof(cx<double>));
+        if (rc) return rc;
+        IPS_HIP(hipMemcpy(p->tw[a], w.data(), w.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
+        std::vector<double> t = axis_tables(p->M[a], p->h[a]);
+        double *dt = nullptr;
+        rc = p->mem.alloc((void **)&dt, t.size() * sizeof(double));
+        if (rc) return rc;
+        IPS_HIP(hipMemcpy(dt, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+        const int m1 = p->M[a] - 1;
+        p->tab[a].lam = dt;
+        p->tab[a].q = dt + m1;
+        p->tab[a].s = dt + 2 * m1;
+    }
+    if (d == 1) return IPS_OK;
+
+    const int *I = p->I, *M = p->M, *N = p->N;
+    // workspace
+    size_t vol = 1;
+    for (int a = 0; a < d; ++a) vol *= (size_t)I[a];
+    const size_t wsz = p->precision == IPS_MIXED_FP32 ? sizeof(float) : sizeof(double);
+    int rc = p->mem.alloc(&p->B, vol * wsz);
+    if (rc) return rc;
+    if (d == 3) {
+        const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
+        rc = p->mem.alloc((void **)&p->A, std::max(a1, a2) * sizeof(double));
+        if (rc) return rc;
+    }
+    for (int fam = 0; fam < d; ++fam) {
+        size_t fsz = 2;
+        for (int b = 0; b < d; ++b)
+            if (b != fam) fsz *= (size_t)N[b];
+        size_t ss = 1;
+        for (int b = 0; b < d; ++b)
+            if (b != fam) ss *= (size_t)I[b];
+        // chunking of the contraction
+        int nch;
+        if (d == 3 && fam < 2) {
+            const int ncols = N[2];
+            const int W = tile_width(N[fam == 0 ? 1 : 0], 2048, ncols);
+            const int ncb = (ncols + W - 1) / W;
+            nch = std::max(1, std::min(I[fam], (2048 + ncb - 1) / ncb));
+            const int chunk = (I[fam] + nch - 1) / nch;
+            p->chunk[fam] = chunk;
+            nch = (I[fam] + chunk - 1) / chunk;
+        } else {
+            const int pen = d == 3 ? 0 : 1 - fam;
+            const int nbatch = d == 3 ? N[1] : 1;
+            const int W = tile_width(N[pen], 2048, I[fam]);
+            const int ncb = (I[fam] + W - 1) / W;
+            nch = std::max(1, std::min(ncb, (2048 + nbatch - 1) / nbatch));
+            const int per = (ncb + nch - 1) / nch;
+            p->chunk[fam] = per * W;
+            nch = (I[fam] + per * W - 1) / (per * W);
+        }
+        p->nch[fam] = nch;
+        if ((rc = p->mem.alloc((void **)&p->part[fam], fsz * nch * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&p->F[fam], fsz * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&p->G[fam], 2 * ss * sizeof(double)))) return rc;
+        if (p->order == 6) {
+            if ((rc = p->mem.alloc((void **)&p->T[fam], 10 * ss * sizeof(double)))) return rc;
+            if ((rc = p->mem.alloc((void **)&p->D[fam], 4 * ss * sizeof(double)))) return rc;
+        }
+        // kernel spectra: samples then even transforms along the in-face axes
+        size_t ksz = (size_t)I[fam];
+        for (int b = 0; b < d; ++b)
+            if (b != fam) ksz *= (size_t)(M[b] + 1);
+        if ((rc = p->mem.alloc((void **)&p->K[fam], ksz * sizeof(double)))) return rc;
+        IPS_HIP(launch_ksample(p->K[fam], d, fam, M, p->h, st));
+        if (d == 2) {
+            const int b = 1 - fam;
+            PassArgs a{};
+            a.in = a.out = p->K[fam];
+            a.irs = a.ors = 1;
+            a.ics = a.ocs = M[b] + 1;
+            a.nrows_in = M[b] + 1;
+            a.ncols = I[fam];
+            a.nbatch = 1;
+            a.in_mode = IN_EVEN;
+            a.out_r0 = 0;
+            a.out_nrows = M[b] + 1;
+            a.scale = 1.0;
+            if ((rc = run_pass(a, p->fd[b], p->tw[b], false, false, st))) return rc;
+        } else {
+            int b, c;
+            if (fam == 0) {
+                b = 1;
+                c = 2;
+            } else if (fam == 1) {
+                b = 0;
+                c = 2;
+            } else {
+                b = 1;
+                c = 0;
+            }
+            const int64_t plane = (int64_t)(M[b] + 1) * (M[c] + 1);
+            PassArgs a{};
+            a.in = a.out = p->K[fam];
+            a.irs = a.ors = 1;
+            a.ics = a.ocs = M[c] + 1;
+            a.ibs = a.obs = plane;
+            a.nrows_in = M[c] + 1;
+            a.ncols = M[b] + 1;
+            a.nbatch = I[fam];
+            a.in_mode = IN_EVEN;
+            a.out_r0 = 0;
+            a.out_nrows = M[c] + 1;
+            a.scale = 1.0;
+            if ((rc = run_pass(a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            PassArgs b2{};
+            b2.in = b2.out = p->K[fam];
+            b2.irs = b2.ors = M[c] + 1;
+            b2.ics = b2.ocs = 1;
+            b2.ibs = b2.obs = plane;
+            b2.nrows_in = M[b] + 1;
+            b2.ncols = M[c] + 1;
+            b2.nbatch = I[fam];
+            b2.in_mode = IN_EVEN;
+            b2.out_r0 = 0;
+            b2.out_nrows = M[b] + 1;
+            b2.scale = 1.0;
+            if ((rc = run_pass(b2, p->fd[b], p->tw[b], false, false, st))) return rc;
+        }
+    }
+    return IPS_OK;
+}
+
+int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
+{
+    const int d = p->d;
+    const int *I = p->I, *M = p->M, *N = p->N;
+    const int64_t *n = p->n;
+    const bool mixed = p->precision == IPS_MIXED_FP32;
+    int rc;
+    if (d == 1) {
+        IPS_HIP(launch_1d(rho, phi, M[0], p->h[0], p->fd[0], p->tw[0], p->tab[0], nullptr, st));
+        return IPS_OK;
+    }
+    if (d == 3) {
+        const int64_t s1 = n[2], s0 = n[1] * n[2];
+        const double *rin = rho + s0 + s1 + 1;
+        // (1) zero-padded cos/sin transform of rho along z -> A[x][y][slot]
+        {
+            PassArgs a{};
+            a.in = rin;
+            a.out = p->A;
+            a.irs = 1;
+            a.ics = s1;
+            a.ibs = s0;
+            a.ors = 1;
+            a.ocs = N[2];
+            a.obs = (int64_t)I[1] * N[2];
+            a.nrows_in = I[2];
+            a.ncols = I[1];
+            a.nbatch = I[0];
+            a.in_mode = IN_ZPAD;
+            a.out_r0 = 0;
+            a.out_nrows = N[2];
+            a.scale = 1.0;
+            if ((rc = run_pass(a, p->fd[2], p->tw[2], false, false, st))) return rc;
+        }
+        // (2) transform along y, contraction over x: faces x = 0, M0; S_y S_z part -> B
+        {
+            BcArgs a{};
+            a.in = p->A;
+            a.irs = N[2];
+            a.ibs = (int64_t)I[1] * N[2];
+            a.nrows_in = I[1];
+            a.ncols = N[2];
+            a.Mc = M[2];
+            a.nbatch = I[0];
+            a.chunk = p->chunk[0];
+            a.K = p->K[0];
+            a.Kd = (int64_t)(M[1] + 1) * (M[2] + 1);
+            a.Kp = M[2] + 1;
+            a.part = p->part[0];
+            a.Bout = mixed ? nullptr : static_cast<double *>(p->B);
+            a.Bbs = (int64_t)I[1] * I[2];
+            a.Brs = I[2];
+            a.W = tile_width(N[1], 2048, a.ncols);
+            a.fd = p->fd[1];
+            a.tw = p->tw[1];
+            if (mixed) return fail(IPS_E_UNSUPPORTED, "mixed precision not built yet");
+            IPS_HIP(launch_bc(a, p->nch[0], st));
+        }
+        // (3) transform along x, contraction over y: faces y = 0, M1
+        {
+            BcArgs a{};
+            a.in = p->A;
+            a.irs = (int64_t)I[1] * N[2];
+            a.ibs = N[2];
+            a.nrows_in = I[0];
+            a.ncols = N[2];
+            a.Mc = M[2];
+            a.nbatch = I[1];
+            a.chunk = p->chunk[1];
+            a.K = p->K[1];
+            a.Kd = (int64_t)(M[0] + 1) * (M[2] + 1);
+            a.Kp = M[2] + 1;
+            a.part = p->part[1];
+            a.Bout = nullptr;
+            a.W = tile_width(N[0], 2048, a.ncols);
+            a.fd = p->fd[0];
+            a.tw = p->tw[0];
+            IPS_HIP(launch_bc(a, p->nch[1], st));
+        }
+        // (4) zero-padded transform of rho along y -> C[x][slot_y][z] (reuses A)
+        {
+            PassArgs a{};
+            a.in = rin;
+            a.out = p->A;
+            a.irs = s1;
+            a.ics = 1;
+            a.ibs = s0;
+            a.ors = I[2];
+            a.ocs = 1;
+            a.obs = (int64_t)N[1] * I[2];
+            a.nrows_in = I[1];
+            a.ncols = I[2];
+            a.nbatch = I[0];
+            a.in_mode = IN_ZPAD;
+            a.out_r0 = 0;
+            a.out_nrows = N[1];
+            a.scale = 1.0;
+            if ((rc = run_pass(a, p->fd[1], p->tw[1], false, false, st))) return rc;
+        }
+        // (5) transform along x, contraction over z: faces z = 0, M2
+        {
+            CcArgs a{};
+            a.in = p->A;
+            a.irs = (int64_t)N[1] * I[2];
+            a.ics = 1;
+            a.ibs = I[2];
+            a.nrows_in = I[0];
+            a.ncols = I[2];
+            a.nbatch = N[1];
+            a.Mo = M[1];
+            a.cols_per_chunk = p->chunk[2];
+            a.K = p->K[2];
+            a.Kd = (int64_t)(M[1] + 1) * (M[0] + 1);
+            a.Ko = M[0] + 1;
+            a.part = p->part[2];
+            a.Bout = nullptr;
+            a.W = tile_width(N[0], 2048, a.ncols);
+            a.fd = p->fd[0];
+            a.tw = p->tw[0];
+            IPS_HIP(launch_cc(a, p->nch[2], st));
+        }
+        // (6) sum the chunk partials
+        for (int fam = 0; fam < 3; ++fam) {
+            int64_t len = 2;
+            for (int b = 0; b < 3; ++b)
+                if (b != fam) len *= N[b];
+            IPS_HIP(launch_reduce(p->part[fam], p->F[fam], len, p->nch[fam], st));
+        }
+        // (7) inverse transforms of the face spectra (in place)
+        for (int fam = 0; fam < 3; ++fam) {
+            // storage [face][row axis r][col axis c] with c contiguous
+            int r, c;
+            if (fam == 0) {
+                r = 1;
+                c = 2;
+            } else if (fam == 1) {
+                r = 0;
+                c = 2;
+            } else {
+                r = 1;
+                c = 0;
+            }
+            const int64_t fstride = (int64_t)N[r] * N[c];
+            PassArgs a{};
+            a.in = a.out = p->F[fam];
+            a.irs = a.ors = 1;
+            a.ics = a.ocs = N[c];
+            a.ibs = a.obs = fstride;
+            a.nrows_in = N[c];
+            a.ncols = N[r];
+            a.nbatch = 2;
+            a.in_mode = IN_HERM;
+            a.out_r0 = 0;
+            a.out_nrows = M[c] + 1;
+            a.scale = 1.0 / N[c];
+            if ((rc = run_pass(a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            PassArgs b{};
+            b.in = b.out = p->F[fam];
+            b.irs = b.ors = N[c];
+            b.ics = b.ocs = 1;
+            b.ibs = b.obs = fstride;
+            b.nrows_in = N[r];
+            b.ncols = M[c] + 1;
+            b.nbatch = 2;
+            b.in_mode = IN_HERM;
+            b.out_r0 = 0;
+            b.out_nrows = M[r] + 1;
+            b.scale = 1.0 / N[r];
+            if ((rc = run_pass(b, p->fd[r], p->tw[r], false, false, st))) return rc;
+        }
+        // (8) boundary values into phi
+        {
+            BwriteArgs a{};
+            a.geo = p->geo;
+            for (int q = 0; q < 3; ++q) a.n[q] = n[q];
+            for (int fam = 0; fam < 3; ++fam) {
+                a.F[fam] = p->F[fam];
+                a.scale[fam] = p->h[0] * p->h[1] * p->h[2];
+            }
+            a.fs[0][0] = (int64_t)N[1] * N[2];
+            a.fs[0][1] = N[2];
+            a.fs[0][2] = 1;
+            a.fs[1][0] = (int64_t)N[0] * N[2];
+            a.fs[1][1] = N[2];
+            a.fs[1][2] = 1;
+            a.fs[2][0] = (int64_t)N[1] * N[0];
+            a.fs[2][1] = 1;
+            a.fs[2][2] = N[0];
+            a.phi = phi;
+            IPS_HIP(launch_bwrite(a, st));
+        }
+    } else {
+        // d == 2
+        const int64_t s0 = n[1];
+        const double *rin = rho + s0 + 1;
+        for (int fam = 0; fam < 2; ++fam) {
+            const int pen = 1 - fam;
+            CcArgs a{};
+            a.in = rin;
+            a.irs = fam == 0 ? 1 : s0;
+            a.ics = fam == 0 ? s0 : 1;
+            a.ibs = 0;
+            a.nrows_in = I[pen];
+            a.ncols = I[fam];
+            a.nbatch = 1;
+            a.Mo = 0;
+            a.cols_per_chunk = p->chunk[fam];
+            a.K = p->K[fam];
+            a.Kd = M[pen] + 1;
+            a.Ko = 0;
+            a.part = p->part[fam];
+            if (fam == 0 && !mixed) {
+                a.Bout = static_cast<double *>(p->B);
+                a.Bcs = I[1];
+                a.Brs = 1;
+                a.Bbs = 0;
+            }
+            if (mixed) return fail(IPS_E_UNSUPPORTED, "mixed precision not built yet");
+            a.W = tile_width(N[pen], 2048, a.ncols);
+            a.fd = p->fd[pen];
+            a.tw = p->tw[pen];
+            IPS_HIP(launch_cc(a, p->nch[fam], st));
+        }
+        for (int fam = 0; fam < 2; ++fam) {
+            const int pen = 1 - fam;
+            IPS_HIP(launch_reduce(p->part[fam], p->F[fam], 2 * (int64_t)N[pen], p->nch[fam], st));
+            PassArgs a{};
+            a.in = a.out = p->F[fam];
+            a.irs = a.ors = 1;
+            a.ics = a.ocs = N[pen];
+            a.ibs = a.obs = 0;
+            a.nrows_in = N[pen];
+            a.ncols = 2;
+            a.nbatch = 1;
+            a.in_mode = IN_HERM;
+            a.out_r0 = 0;
+            a.out_nrows = M[pen] + 1;
+            a.scale = 1.0 / N[pen];
+            if ((rc = run_pass(a, p->fd[pen], p->tw[pen], false, false, st))) return rc;
+        }
+        BwriteArgs a{};
+        a.geo = p->geo;
+        for (int q = 0; q < 3; ++q) a.n[q] = q < 2 ? n[q] : 1;
+        for (int fam = 0; fam < 2; ++fam) {
+            a.F[fam] = p->F[fam];
+            a.fs[fam][0] = N[1 - fam];
+            a.fs[fam][1] = 1;
+            a.fs[fam][2] = 0;
+            a.scale[fam] = p->h[0] * p->h[1];
+        }
+        a.phi = phi;
+        IPS_HIP(launch_bwrite(a, st));
+    }
+
+    // ---- harmonic part: shell spectra ------------------------------------------------
+    {
+        GtArgs a{};
+        a.geo = p->geo;
+        for (int q = 0; q < 3; ++q) a.n[q] = q < d ? n[q] : 1;
+        a.phi = phi;
+        for (int fam = 0; fam < d; ++fam) a.G[fam] = p->G[fam];
+        IPS_HIP(launch_gtilde(a, st));
+        for (int fam = 0; fam < d; ++fam)
+            if ((rc = shell_dst(p, p->G[fam], 2, fam, false, st))) return rc;
+    }
+    ShellSpec sh{};
+    for (int fam = 0; fam < d; ++fam) {
+        sh.G[fam] = p->G[fam];
+        sh.D[fam] = p->D[fam];
+    }
+    if (p->order == 6) {
+        for (int fam = 0; fam < d; ++fam) {
+            H2Args a{};
+            a.axis = fam;
+            a.geo = p->geo;
+            for (int q = 0; q < d; ++q) a.tab[q] = p->tab[q];
+            a.sh = sh;
+            a.T = p->T[fam];
+            IPS_HIP(launch_h2(a, st));
+        }
+        for (int fam = 0; fam < d; ++fam)
+            if ((rc = shell_dst(p, p->T[fam], 10, fam, true, st))) return rc;
+        DcorrArgs a{};
+        a.geo = p->geo;
+        for (int q = 0; q < 3; ++q) a.n[q] = q < d ? n[q] : 1;
+        a.phi = phi;
+        for (int fam = 0; fam < d; ++fam) {
+            a.RS[fam] = p->T[fam];
+            a.D[fam] = p->D[fam];
+        }
+        IPS_HIP(launch_dcorr(a, st));
+        for (int fam = 0; fam < d; ++fam)
+            if ((rc = shell_dst(p, p->D[fam], 4, fam, false, st))) return rc;
+    }
+    // ---- combination and inverse transforms ------------------------------------------
+    {
+        FinalArgs a{};
+        a.buf = p->B;
+        if (d == 3) {
+            a.irs = (int64_t)I[1] * I[2];
+            a.ics = 1;
+            a.ibs = I[2];
+            a.ncols = I[2];
+            a.nbatch = I[1];
+        } else {
+            a.irs = I[1];
+            a.ics = 1;
+            a.ibs = 0;
+            a.ncols = I[1];
+            a.nbatch = 1;
+        }
+        a.nrows_in = I[0];
+        a.W = tile_width(N[0], 2048, a.ncols);
+        a.order = p->order;
+        a.mixed = mixed;
+        a.geo = p->geo;
+        for (int q = 0; q < d; ++q) a.tab[q] = p->tab[q];
+        a.sh = sh;
+        a.fd = p->fd[0];
+        a.tw = p->tw[0];
+        IPS_HIP(launch_final(a, st));
+    }
+    if (d == 3) {
+        PassArgs a{};
+        a.in = a.out = p->B;
+        a.irs = a.ors = I[2];
+        a.ics = a.ocs = 1;
+        a.ibs = a.obs = (int64_t)I[1] * I[2];
+        a.nrows_in = I[1];
+        a.ncols = I[2];
+        a.nbatch = I[0];
+        a.in_mode = IN_SPECS;
+        a.out_r0 = 1;
+        a.out_nrows = I[1];
+        a.scale = 0.5;
+        if ((rc = run_pass(a, p->fd[1], p->tw[1], mixed, mixed, st))) return rc;
+        PassArgs b{};
+        b.in = p->B;
+        b.out = phi + n[1] * n[2] + n[2] + 1;
+        b.irs = 1;
+        b.ics = I[2];
+        b.ibs = (int64_t)I[1] * I[2];
+        b.ors = 1;
+        b.ocs = n[2];
+        b.obs = n[1] * n[2];
+        b.nrows_in = I[2];
+        b.ncols = I[1];
+        b.nbatch = I[0];
+        b.in_mode = IN_SPECS;
+        b.out_r0 = 1;
+        b.out_nrows = I[2];
+        b.scale = 0.5;
+        if ((rc = run_pass(b, p->fd[2], p->tw[2], mixed, false, st))) return rc;
+    } else {
+        PassArgs b{};
+        b.in = p->B;
+        b.out = phi + n[1] + 1;
+        b.irs = 1;
+        b.ics = I[1];
+        b.ibs = 0;
+        b.ors = 1;
+        b.ocs = n[1];
+        b.obs = 0;
+        b.nrows_in = I[1];
+        b.ncols = I[0];
+        b.nbatch = 1;
+        b.in_mode = IN_SPECS;
+        b.out_r0 = 1;
+        b.out_nrows = I[1];
+        b.scale = 0.5;
+        if ((rc = run_pass(b, p->fd[1], p->tw[1], mixed, false, st))) return rc;
+    }
+    return IPS_OK;
+}
+
+void plan_free(ips_plan p)
+{
+    if (!p) return;
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+    p->mem.release();
+    if (cur != p->device) (void)hipSetDevice(cur);
+    delete p;
+}
+
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int, int64_t, int64_t, int64_t, double, double, double, int>, ips_plan> g_cache;
+
+} // namespace
+
+extern "C" {
+
+const char *ips_status_string(int status)
+{
+    switch (status) {
+    case IPS_OK: return "ok";
+    case IPS_E_INVALID_ARG: return "invalid argument";
+    case IPS_E_UNSUPPORTED: return "unsupported request";
+    case IPS_E_NO_MEMORY: return "out of memory";
+    case IPS_E_DEVICE: return "HIP runtime error";
+    case IPS_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+int ips_last_error_detail(char *buf, size_t len)
+{
+    if (!buf) return IPS_E_INVALID_ARG;
+    if (len == 0) return IPS_OK;
+    std::snprintf(buf, len, "%s", g_err.c_str());
+    return IPS_OK;
+}
+
+int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int order,
+                    int precision, unsigned flags)
+{
+    if (!out) return fail(IPS_E_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    int rc = validate(d, n, h, order, precision, flags);
+    if (rc) return rc;
+    ips_plan p = new (std::nothrow) ips_plan_s();
+    if (!p) return fail(IPS_E_NO_MEMORY, "host allocation failed");
+    p->d = d;
+    p->order = d == 1 ? 4 : order;
+    p->precision = precision;
+    for (int a = 0; a < d; ++a) {
+        p->n[a] = n[a];
+        p->h[a] = h[a];
+        p->M[a] = (int)(n[a] - 1);
+        p->I[a] = p->M[a] - 1;
+        p->N[a] = 2 * p->M[a];
+    }
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(IPS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    rc = plan_build(p, nullptr);
+    if (rc == IPS_OK) {
+        e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("plan build: ") + hipGetErrorString(e));
+    }
+    if (rc) {
+        plan_free(p);
+        return rc;
+    }
+    *out = p;
+    return IPS_OK;
+}
+
+int ips_plan_workspace_size(ips_plan p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    *bytes = p->mem.bytes;
+    return IPS_OK;
+}
+
+int ips_execute(ips_plan p, const double *rho, double *phi, void *stream)
+{
+    if (!p) return fail(IPS_E_INVALID_ARG, "plan must not be NULL");
+    if (!rho || !phi) return fail(IPS_E_INVALID_ARG, "rho and phi must not be NULL");
+    size_t cnt = 1;
+    for (int a = 0; a < p->d; ++a) cnt *= (size_t)p->n[a];
+    const char *r0 = reinterpret_cast<const char *>(rho), *p0 = reinterpret_cast<const char *>(phi);
+    if (r0 < p0 + cnt * sizeof(double) && p0 < r0 + cnt * sizeof(double))
+        return fail(IPS_E_INVALID_ARG, "rho and phi must not overlap");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
+    return execute(p, rho, phi, static_cast<hipStream_t>(stream));
+}
+
+int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void *stream)
+{
+    (void)stream;
+    if (!p || !phi_bar || !rho_bar) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    return fail(IPS_E_UNSUPPORTED, "adjoint not available in this build");
+}
+
+int ips_plan_destroy(ips_plan p)
+{
+    if (!p) return IPS_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (auto it = g_cache.begin(); it != g_cache.end(); ++it)
+            if (it->second == p) {
+                g_cache.erase(it);
+                break;
+            }
+    }
+    plan_free(p);
+    return IPS_OK;
+}
+
+int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int order, double *phi)
+{
+    int rc = validate(d, n, h, order, IPS_FP64, 0);
+    if (rc) return rc;
+    if (!rho || !phi) return fail(IPS_E_INVALID_ARG, "rho and phi must not be NULL");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(IPS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    auto key = std::make_tuple(dev, d, n[0], d > 1 ? n[1] : 0, d > 2 ? n[2] : 0, h[0],
+                               d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0, d == 1 ? 4 : order);
+    ips_plan p = nullptr;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        p = it->second;
+    } else {
+        rc = ips_plan_create(&p, d, n, h, order, IPS_FP64, 0);
+        if (rc) return rc;
+        g_cache[key] = p;
+    }
+    rc = ips_execute(p, rho, phi, nullptr);
+    if (rc) return rc;
+    e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return fail(IPS_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    return IPS_OK;
+}
+
+struct ips_batch_s {
+    std::vector<ips_plan> plans;
+};
+
+int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)[3],
+                     const double (*h)[3], int order, int precision, unsigned flags)
+{
+    if (!out) return fail(IPS_E_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (count <= 0 || !d || !n || !h) return fail(IPS_E_INVALID_ARG, "bad batch description");
+    ips_batch b = new (std::nothrow) ips_batch_s();
+    if (!b) return fail(IPS_E_NO_MEMORY, "host allocation failed");
+    for (int i = 0; i < count; ++i) {
+        ips_plan p = nullptr;
+        int rc = ips_plan_create(&p, d[i], n[i], h[i], order, precision, flags);
+        if (rc) {
+            for (ips_plan q : b->plans) plan_free(q);
+            delete b;
+            return rc;
+        }
+        b->plans.push_back(p);
+    }
+    *out = b;
+    return IPS_OK;
+}
+
+int ips_batch_execute(ips_batch b, const double *const *rho, double *const *phi, void *stream)
+{
+    if (!b || !rho || !phi) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        int rc = ips_execute(b->plans[i], rho[i], phi[i], stream);
+        if (rc) return rc;
+    }
+    return IPS_OK;
+}
+
+int ips_batch_destroy(ips_batch b)
+{
+    if (!b) return IPS_OK;
+    for (ips_plan p : b->plans) plan_free(p);
+    delete b;
+    return IPS_OK;
+}
+
+} // extern "C"
