@@ -64,11 +64,16 @@ typedef enum {
     IPS_E_WORKSPACE = -5    /* caller-supplied workspace too small */
 } ips_status;
 
-/* Arithmetic used by the transforms.  The boundary-potential accumulation
- * and the deferred-correction differences stay FP64 in every mode. */
+/* Arithmetic used by the transforms.  Input and output stay FP64; the kernel
+ * spectra, the accumulation of the boundary sums over slices, the inverse
+ * transforms of the face sums, and every step of the harmonic correction
+ * (g~, deferred-correction differences, extrapolation, spectral combination)
+ * stay FP64 in every mode. */
 typedef enum {
-    IPS_FP64 = 0,       /* everything in FP64 */
-    IPS_MIXED_FP32 = 1  /* sine-transform passes of phi in FP32 */
+    IPS_FP64 = 0,              /* everything in FP64 */
+    IPS_MIXED_FP32 = 1,        /* sine-transform passes of phi_star + phi_H in FP32 */
+    IPS_MIXED_FP32_SLICES = 2  /* as 1, and the slice transforms of rho that feed the
+                                  boundary sums in FP32 (accumulated in FP64) */
 } ips_precision;
 
 /*
@@ -92,7 +97,7 @@ int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int o
  * Green's-function kernels used by the boundary convolutions (Section 4),
  * and all device workspace.  Arguments as ips_solve, plus:
  *   precision : an ips_precision value
- *   flags     : must be 0
+ *   flags     : 0 or IPS_FLAG_STAGE_TIMING
  * On success *out receives the plan; release it with ips_plan_destroy.
  */
 int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int order,
@@ -117,6 +122,34 @@ int ips_execute(ips_plan p, const double *rho, double *phi, void *stream);
  * Used for gradients: if J depends on phi, dJ/drho = A^T dJ/dphi.
  */
 int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void *stream);
+
+/*
+ * Stage timing (diagnostics).  A plan created with IPS_FLAG_STAGE_TIMING
+ * records a pair of HIP events around every stage of ips_execute on the
+ * execution stream.  ips_plan_stage_time waits for the recorded events,
+ * adds their elapsed times to the stage totals and returns the totals since
+ * the last reset: *ms_total (milliseconds) and *calls (executions).
+ */
+#define IPS_FLAG_STAGE_TIMING 1u
+
+typedef enum {
+    IPS_STAGE_RHO_Z = 0,  /* cos/sin transform of rho along axis 2 (3D) */
+    IPS_STAGE_CONV_X = 1, /* transform + convolution sum for the axis-0 faces */
+    IPS_STAGE_CONV_Y = 2, /* same for the axis-1 faces (3D) */
+    IPS_STAGE_RHO_Y = 3,  /* cos/sin transform of rho along axis 1 (3D) */
+    IPS_STAGE_CONV_Z = 4, /* same for the axis-2 faces (3D); axis-1 faces (2D) */
+    IPS_STAGE_FACES = 5,  /* chunk sums, inverse face transforms, boundary write */
+    IPS_STAGE_SHELL_GT = 6, /* g~ and its sine transforms */
+    IPS_STAGE_SHELL_R6 = 7, /* sixth-order right-hand side on the shell */
+    IPS_STAGE_FINAL = 8,  /* spectral combination + inverse along axis 0 (1D: whole solve) */
+    IPS_STAGE_INV_Y = 9,  /* inverse sine transform along axis 1 (3D) */
+    IPS_STAGE_INV_Z = 10, /* inverse sine transform along the last axis into phi */
+    IPS_STAGE_COUNT = 11
+} ips_stage;
+
+const char *ips_stage_name(int stage);
+int ips_plan_stage_time(ips_plan p, int stage, double *ms_total, int64_t *calls);
+int ips_plan_reset_stage_times(ips_plan p);
 
 /* Release a plan and its device memory (waits for nothing: the caller must
  * make sure no enqueued work still uses it). NULL is accepted. */

@@ -23,6 +23,10 @@ STATUS = {
 }
 IPS_FP64 = 0
 IPS_MIXED_FP32 = 1
+IPS_MIXED_FP32_SLICES = 2
+IPS_FLAG_STAGE_TIMING = 1
+STAGES = ["rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces", "shell_gt", "shell_r6",
+          "final", "inv_y", "inv_z"]
 
 # Every exported symbol with (restype, argtypes).
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -45,6 +49,9 @@ SIGNATURES = {
     ),
     "ips_batch_execute": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
     "ips_batch_destroy": (ctypes.c_int, [_vp]),
+    "ips_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "ips_plan_stage_time": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _i64p]),
+    "ips_plan_reset_stage_times": (ctypes.c_int, [_vp]),
     "ips_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ips_last_error_detail": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
 }

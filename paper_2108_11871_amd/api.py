@@ -11,9 +11,11 @@ from typing import Sequence
 import torch
 
 from . import _lib
-from ._lib import IPS_FP64, IPS_MIXED_FP32, check, f64_array, i64_array, library_path, lib
+from ._lib import (IPS_FLAG_STAGE_TIMING, IPS_FP64, IPS_MIXED_FP32, IPS_MIXED_FP32_SLICES, STAGES,
+                   check, f64_array, i64_array, library_path, lib)
 
-PRECISIONS = {"fp64": IPS_FP64, "mixed_fp32": IPS_MIXED_FP32}
+PRECISIONS = {"fp64": IPS_FP64, "mixed_fp32": IPS_MIXED_FP32,
+              "mixed_fp32_slices": IPS_MIXED_FP32_SLICES}
 
 __all__ = ["solve", "Plan", "Batch", "SolveFn", "PRECISIONS", "library_path"]
 
@@ -39,7 +41,7 @@ class Plan:
     """A reusable solve of one grid geometry (ips_plan_create / ips_execute)."""
 
     def __init__(self, shape: Sequence[int], h, order: int = 6, precision: str = "fp64",
-                 device=None):
+                 device=None, timing: bool = False):
         self.shape = tuple(int(v) for v in shape)
         d = len(self.shape)
         hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
@@ -52,7 +54,8 @@ class Plan:
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(lib().ips_plan_create(ctypes.byref(handle), d, i64_array(self.shape),
-                                        f64_array(self.h), self.order, PRECISIONS[precision], 0))
+                                        f64_array(self.h), self.order, PRECISIONS[precision],
+                                        IPS_FLAG_STAGE_TIMING if timing else 0))
         self._h = handle
 
     @property
@@ -82,6 +85,19 @@ class Plan:
                                             ctypes.c_void_p(out.data_ptr()),
                                             ctypes.c_void_p(_stream_handle(phi_bar.device))))
         return out
+
+    def stage_times(self) -> dict:
+        """{stage name: (total ms, executions)} since the last reset (timing plans only)."""
+        out = {}
+        for i, name in enumerate(STAGES):
+            ms = ctypes.c_double()
+            calls = ctypes.c_int64()
+            check(lib().ips_plan_stage_time(self._h, i, ctypes.byref(ms), ctypes.byref(calls)))
+            out[name] = (ms.value, calls.value)
+        return out
+
+    def reset_stage_times(self):
+        check(lib().ips_plan_reset_stage_times(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

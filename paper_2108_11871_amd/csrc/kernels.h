@@ -31,7 +31,7 @@ struct PassArgs {
 // Boundary convolution, contraction over the batch axis (3D faces normal to
 // the batch axis).  Input: slot-transformed data along the contiguous axis.
 struct BcArgs {
-    const double *in;
+    const void *in;    // T (the transform type)
     int64_t irs, ibs;  // row (pencil axis) and batch strides, column stride 1
     int nrows_in;      // M_p - 1
     int ncols;         // 2 M_c slots
@@ -41,8 +41,9 @@ struct BcArgs {
     const double *K;   // kernel spectra K[d][k_p][k_c], d = distance index
     int64_t Kd, Kp;    // strides of d and k_p (k_c stride 1)
     double *part;      // partial face spectra [nchunk][2][2 M_p][ncols]
-    double *Bout;      // optional: S_p S_c part -> Bout[batch*Bbs + (k_p-1)*Brs + (k_c-1)]
+    void *Bout;        // optional: S_p S_c part -> Bout[batch*Bbs + (k_p-1)*Brs + (k_c-1)]
     int64_t Bbs, Brs;
+    int Bf32;          // Bout holds float (else the transform type)
     int W;
     FftDesc fd;
     const cx<double> *tw;
@@ -51,7 +52,7 @@ struct BcArgs {
 // Boundary convolution, contraction over the tile columns (faces normal to
 // the column axis).  grid.x = chunks of columns, grid.y = batch entries.
 struct CcArgs {
-    const double *in;
+    const void *in;    // TI (double rho or T slot data)
     int64_t irs, ics, ibs;
     int nrows_in;      // M_p - 1
     int ncols;         // interior length of the contracted axis
@@ -61,8 +62,9 @@ struct CcArgs {
     const double *K;   // K[d][k_o][k_p], k_p contiguous
     int64_t Kd, Ko;
     double *part;      // [nchunk][2][nbatch][2 M_p]
-    double *Bout;      // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + batch*Bbs]
+    void *Bout;        // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + batch*Bbs]
     int64_t Bcs, Brs, Bbs;
+    int Bf32;          // Bout holds float (else the transform type)
     int W;
     FftDesc fd;
     const cx<double> *tw;
@@ -140,8 +142,10 @@ struct BwriteArgs {
 };
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
-hipError_t launch_bc(const BcArgs &a, int nchunk, hipStream_t st);
-hipError_t launch_cc(const CcArgs &a, int nchunk, hipStream_t st);
+// f32: transforms in FP32 (input and B in FP32); accumulation is FP64 always.
+hipError_t launch_bc(const BcArgs &a, int nchunk, bool f32, hipStream_t st);
+// in_f32: input data in FP32 (else FP64); f32: transform type
+hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st);
 hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st);
 hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st);
 hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);

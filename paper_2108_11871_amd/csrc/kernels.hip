@@ -111,31 +111,33 @@ hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t
 // ---------------------------------------------------------------------------
 // Boundary convolution, contraction over the batch axis (3D)
 // ---------------------------------------------------------------------------
-template <int MAXE>
+template <typename T, int MAXE, bool WB>
 __global__ __launch_bounds__(NT) void k_bc(BcArgs a, int nchunk)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
-    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
-    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
+    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
     const int ncb = (a.ncols + W - 1) / W;
     const int lb = xcd_remap(blockIdx.x, ncb * nchunk);
     const int cb = lb % ncb, ch = lb / ncb;
     const int c0 = cb * W;
     const int nc = min(W, a.ncols - c0);
     const int b0 = ch * a.chunk, b1 = min(a.nbatch, b0 + a.chunk);
+    const T *in = static_cast<const T *>(a.in);
+    T *Bout = static_cast<T *>(a.Bout);
     constexpr int APT = 2 * MAXE;
     double acc0[APT], acc1[APT];
 #pragma unroll
     for (int i = 0; i < APT; ++i) acc0[i] = acc1[i] = 0.0;
-    load_twiddles<double, NT>(tw, a.tw, N);
+    load_twiddles<T, NT>(tw, a.tw, N);
     for (int b = b0; b < b1; ++b) {
-        zero_rows<double, NT>(buf, rs, W, 0, 1);
-        zero_rows<double, NT>(buf, rs, W, 1 + a.nrows_in, N);
-        tile_load<double, double, NT>(buf, rs, 1, a.in + b * a.ibs + c0, a.nrows_in, nc, a.irs, 1, W);
+        zero_rows<T, NT>(buf, rs, W, 0, 1);
+        zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
+        tile_load<T, T, NT>(buf, rs, 1, in + b * a.ibs + c0, a.nrows_in, nc, a.irs, 1, W);
         __syncthreads();
-        fft_tile<double, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
-        post_cs<double, MAXE, NT>(buf, rs, W / 2, M);
+        fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
+        post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
         const double *K0 = a.K + (int64_t)b * a.Kd;
         const double *K1 = a.K + (int64_t)(a.nbatch - 1 - b) * a.Kd;
 #pragma unroll
@@ -143,15 +145,20 @@ __global__ __launch_bounds__(NT) void k_bc(BcArgs a, int nchunk)
             const int pos = threadIdx.x + i * NT;
             const int row = pos / W, c = pos % W;
             if (row < N && c < nc) {
-                const double v = buf[row * rs + c];
+                const T v = buf[row * rs + c];
                 const int kp = row <= M ? row : row - M;
                 const int sc = c0 + c;
                 const int kc = sc <= a.Mc ? sc : sc - a.Mc;
                 const int64_t ko = (int64_t)kp * a.Kp + kc;
-                acc0[i] += K0[ko] * v;
-                acc1[i] += K1[ko] * v;
-                if (a.Bout && row > M && sc > a.Mc)
-                    a.Bout[b * a.Bbs + (int64_t)(row - M - 1) * a.Brs + (sc - a.Mc - 1)] = v;
+                acc0[i] += K0[ko] * (double)v;
+                acc1[i] += K1[ko] * (double)v;
+                if (WB && row > M && sc > a.Mc) {
+                    const int64_t bi = b * a.Bbs + (int64_t)(row - M - 1) * a.Brs + (sc - a.Mc - 1);
+                    if (a.Bf32)
+                        static_cast<float *>(a.Bout)[bi] = (float)v;
+                    else
+                        Bout[bi] = v;
+                }
             }
         }
         __syncthreads();
@@ -169,52 +176,66 @@ __global__ __launch_bounds__(NT) void k_bc(BcArgs a, int nchunk)
     }
 }
 
-hipError_t launch_bc(const BcArgs &a, int nchunk, hipStream_t st)
+template <typename T, bool WB>
+static hipError_t launch_bc_t(const BcArgs &a, int nchunk, hipStream_t st)
 {
     const int ncb = (a.ncols + a.W - 1) / a.W;
-    const size_t lds = tile_lds<double>(a.fd.N, a.W);
+    const size_t lds = tile_lds<T>(a.fd.N, a.W);
+    set_lds((const void *)&k_bc<T, 8, WB>, lds);
+    hipLaunchKernelGGL((k_bc<T, 8, WB>), dim3(ncb * nchunk), dim3(NT), lds, st, a, nchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_bc(const BcArgs &a, int nchunk, bool f32, hipStream_t st)
+{
     const int work = (a.W / 2) * a.fd.N;
     if (work > 8 * NT) return hipErrorInvalidValue;
-    set_lds((const void *)&k_bc<8>, lds);
-    hipLaunchKernelGGL((k_bc<8>), dim3(ncb * nchunk), dim3(NT), lds, st, a, nchunk);
-    return hipGetLastError();
+    const bool wb = a.Bout != nullptr;
+    if (f32) return wb ? launch_bc_t<float, true>(a, nchunk, st) : launch_bc_t<float, false>(a, nchunk, st);
+    return wb ? launch_bc_t<double, true>(a, nchunk, st) : launch_bc_t<double, false>(a, nchunk, st);
 }
 
 // ---------------------------------------------------------------------------
 // Boundary convolution, contraction over the tile columns (3D and 2D)
 // ---------------------------------------------------------------------------
-template <int MAXE>
+template <typename T, typename TI, int MAXE, bool WB>
 __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
-    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
-    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
+    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
     const int lb = xcd_remap(blockIdx.x, nchunk * a.nbatch);
     const int ch = lb % nchunk, bt = lb / nchunk;
     const int kb = a.Mo > 0 ? (bt <= a.Mo ? bt : bt - a.Mo) : 0;
+    const TI *in = static_cast<const TI *>(a.in);
+    T *Bout = static_cast<T *>(a.Bout);
     constexpr int RPT = 8; // N <= 2048
     double acc0[RPT], acc1[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc0[i] = acc1[i] = 0.0;
-    load_twiddles<double, NT>(tw, a.tw, N);
+    load_twiddles<T, NT>(tw, a.tw, N);
     const int cbeg = ch * a.cols_per_chunk;
     const int cend = min(a.ncols, cbeg + a.cols_per_chunk);
     for (int c0 = cbeg; c0 < cend; c0 += W) {
         const int nc = min(W, cend - c0);
-        zero_rows<double, NT>(buf, rs, W, 0, 1);
-        zero_rows<double, NT>(buf, rs, W, 1 + a.nrows_in, N);
-        tile_load<double, double, NT>(buf, rs, 1, a.in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc,
-                                      a.irs, a.ics, W);
+        zero_rows<T, NT>(buf, rs, W, 0, 1);
+        zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
+        tile_load<T, TI, NT>(buf, rs, 1, in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc, a.irs,
+                             a.ics, W);
         __syncthreads();
-        fft_tile<double, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
-        post_cs<double, MAXE, NT>(buf, rs, W / 2, M);
-        if (a.Bout) {
+        fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
+        post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
+        if (WB) {
             const int tot = (M - 1) * nc;
             for (int e = threadIdx.x; e < tot; e += NT) {
                 const int r = e % (M - 1), c = e / (M - 1);
-                a.Bout[(int64_t)(c0 + c) * a.Bcs + (int64_t)r * a.Brs + (int64_t)bt * a.Bbs] =
-                    buf[(M + 1 + r) * rs + c];
+                const int64_t bi = (int64_t)(c0 + c) * a.Bcs + (int64_t)r * a.Brs + (int64_t)bt * a.Bbs;
+                const T v = buf[(M + 1 + r) * rs + c];
+                if (a.Bf32)
+                    static_cast<float *>(a.Bout)[bi] = (float)v;
+                else
+                    Bout[bi] = v;
             }
         }
 #pragma unroll
@@ -224,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
                 const int kp = row <= M ? row : row - M;
                 const double *Kr = a.K + (int64_t)kb * a.Ko + kp;
                 for (int c = 0; c < nc; ++c) {
-                    const double v = buf[row * rs + c];
+                    const double v = (double)buf[row * rs + c];
                     const int dd = c0 + c;
                     acc0[i] += Kr[(int64_t)dd * a.Kd] * v;
                     acc1[i] += Kr[(int64_t)(a.ncols - 1 - dd) * a.Kd] * v;
@@ -245,14 +266,29 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
     }
 }
 
-hipError_t launch_cc(const CcArgs &a, int nchunk, hipStream_t st)
+template <typename T, typename TI, bool WB>
+static hipError_t launch_cc_t(const CcArgs &a, int nchunk, hipStream_t st)
 {
-    const size_t lds = tile_lds<double>(a.fd.N, a.W);
+    const size_t lds = tile_lds<T>(a.fd.N, a.W);
+    set_lds((const void *)&k_cc<T, TI, 8, WB>, lds);
+    hipLaunchKernelGGL((k_cc<T, TI, 8, WB>), dim3(nchunk * a.nbatch), dim3(NT), lds, st, a, nchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st)
+{
     const int work = (a.W / 2) * a.fd.N;
     if (work > 8 * NT || a.fd.N > 8 * NT) return hipErrorInvalidValue;
-    set_lds((const void *)&k_cc<8>, lds);
-    hipLaunchKernelGGL((k_cc<8>), dim3(nchunk * a.nbatch), dim3(NT), lds, st, a, nchunk);
-    return hipGetLastError();
+    const bool wb = a.Bout != nullptr;
+    if (!f32) {
+        if (in_f32) return hipErrorInvalidValue;
+        return wb ? launch_cc_t<double, double, true>(a, nchunk, st)
+                  : launch_cc_t<double, double, false>(a, nchunk, st);
+    }
+    if (in_f32) return wb ? launch_cc_t<float, float, true>(a, nchunk, st)
+                          : launch_cc_t<float, float, false>(a, nchunk, st);
+    return wb ? launch_cc_t<float, double, true>(a, nchunk, st)
+              : launch_cc_t<float, double, false>(a, nchunk, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -118,8 +118,8 @@ struct ips_plan_s {
     cx<double> *tw[3] = {nullptr, nullptr, nullptr};
     AxisTabs tab[3]{};
     double *K[3] = {nullptr, nullptr, nullptr};
-    double *A = nullptr;
-    void *B = nullptr;
+    void *A = nullptr; // slot transforms of rho along one axis (3D)
+    void *B = nullptr; // raw DST of rho along the last d-1 axes, then phi in sine space
     double *part[3] = {nullptr, nullptr, nullptr};
     int nch[3] = {1, 1, 1};
     int chunk[3] = {1, 1, 1};
@@ -128,6 +128,13 @@ struct ips_plan_s {
     double *T[3] = {nullptr, nullptr, nullptr};
     double *D[3] = {nullptr, nullptr, nullptr};
     DevBuf mem;
+    // stage timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev_rec;
+    double stage_ms[IPS_STAGE_COUNT] = {};
+    int64_t stage_calls[IPS_STAGE_COUNT] = {};
 };
 
 namespace {
@@ -136,8 +143,8 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
 {
     if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
     if (!n || !h) return fail(IPS_E_INVALID_ARG, "n and h must not be NULL");
-    if (flags != 0) return fail(IPS_E_INVALID_ARG, "flags must be 0");
-    if (precision != IPS_FP64 && precision != IPS_MIXED_FP32)
+    if (flags & ~IPS_FLAG_STAGE_TIMING) return fail(IPS_E_INVALID_ARG, "unknown flag bits");
+    if (precision != IPS_FP64 && precision != IPS_MIXED_FP32 && precision != IPS_MIXED_FP32_SLICES)
         return fail(IPS_E_INVALID_ARG, "unknown precision");
     if (d >= 2 && order != 4 && order != 6) return fail(IPS_E_INVALID_ARG, "order must be 4 or 6");
     for (int a = 0; a < d; ++a) {
@@ -273,12 +280,13 @@ int plan_build(ips_plan p, hipStream_t st)
     // workspace
     size_t vol = 1;
     for (int a = 0; a < d; ++a) vol *= (size_t)I[a];
-    const size_t wsz = p->precision == IPS_MIXED_FP32 ? sizeof(float) : sizeof(double);
+    const size_t wsz = p->precision != IPS_FP64 ? sizeof(float) : sizeof(double);
+    const size_t asz = p->precision == IPS_MIXED_FP32_SLICES ? sizeof(float) : sizeof(double);
     int rc = p->mem.alloc(&p->B, vol * wsz);
     if (rc) return rc;
     if (d == 3) {
         const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
-        rc = p->mem.alloc((void **)&p->A, std::max(a1, a2) * sizeof(double));
+        rc = p->mem.alloc(&p->A, std::max(a1, a2) * asz);
         if (rc) return rc;
     }
     for (int fam = 0; fam < d; ++fam) {
@@ -380,22 +388,62 @@ int plan_build(ips_plan p, hipStream_t st)
     return IPS_OK;
 }
 
+struct StageScope {
+    ips_plan p;
+    int stage;
+    hipStream_t st;
+    hipError_t err = hipSuccess;
+    hipEvent_t e1 = nullptr;
+    static hipError_t get(ips_plan p, hipEvent_t *e)
+    {
+        if (p->ev_used < p->ev_pool.size()) {
+            *e = p->ev_pool[p->ev_used++];
+            return hipSuccess;
+        }
+        hipError_t r = hipEventCreate(e);
+        if (r != hipSuccess) return r;
+        p->ev_pool.push_back(*e);
+        ++p->ev_used;
+        return hipSuccess;
+    }
+    StageScope(ips_plan p_, int s_, hipStream_t st_) : p(p_), stage(s_), st(st_)
+    {
+        if (!p->timing) return;
+        hipEvent_t e0;
+        if ((err = get(p, &e0)) != hipSuccess) return;
+        if ((err = get(p, &e1)) != hipSuccess) return;
+        err = hipEventRecord(e0, st);
+        p->ev_rec.emplace_back(stage, e0, e1);
+    }
+    ~StageScope()
+    {
+        if (p->timing && e1) (void)hipEventRecord(e1, st);
+    }
+};
+
+#define IPS_CAT2(a, b) a##b
+#define IPS_CAT(a, b) IPS_CAT2(a, b)
+#define STAGE(id) StageScope IPS_CAT(stage_scope_, __LINE__)(p, (id), st)
+
 int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
 {
     const int d = p->d;
     const int *I = p->I, *M = p->M, *N = p->N;
     const int64_t *n = p->n;
-    const bool mixed = p->precision == IPS_MIXED_FP32;
+    const bool f32 = p->precision != IPS_FP64;                  // sine passes of phi
+    const bool f32s = p->precision == IPS_MIXED_FP32_SLICES;    // slice transforms of rho
     int rc;
     if (d == 1) {
+        STAGE(IPS_STAGE_FINAL);
         IPS_HIP(launch_1d(rho, phi, M[0], p->h[0], p->fd[0], p->tw[0], p->tab[0], nullptr, st));
         return IPS_OK;
     }
     if (d == 3) {
         const int64_t s1 = n[2], s0 = n[1] * n[2];
         const double *rin = rho + s0 + s1 + 1;
-        // (1) zero-padded cos/sin transform of rho along z -> A[x][y][slot]
         {
+            // (1) zero-padded cos/sin transform of rho along z -> A[x][y][slot]
+            STAGE(IPS_STAGE_RHO_Z);
             PassArgs a{};
             a.in = rin;
             a.out = p->A;
@@ -412,10 +460,11 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = N[2];
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[2], p->tw[2], false, false, st))) return rc;
+            if ((rc = run_pass(a, p->fd[2], p->tw[2], false, f32s, st))) return rc;
         }
-        // (2) transform along y, contraction over x: faces x = 0, M0; S_y S_z part -> B
         {
+            // (2) transform along y, sum over x-slices: faces x = 0, M0; S_y S_z part -> B
+            STAGE(IPS_STAGE_CONV_X);
             BcArgs a{};
             a.in = p->A;
             a.irs = N[2];
@@ -429,17 +478,18 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Kd = (int64_t)(M[1] + 1) * (M[2] + 1);
             a.Kp = M[2] + 1;
             a.part = p->part[0];
-            a.Bout = mixed ? nullptr : static_cast<double *>(p->B);
+            a.Bout = p->B;
+            a.Bf32 = f32;
             a.Bbs = (int64_t)I[1] * I[2];
             a.Brs = I[2];
             a.W = tile_width(N[1], 2048, a.ncols);
             a.fd = p->fd[1];
             a.tw = p->tw[1];
-            if (mixed) return fail(IPS_E_UNSUPPORTED, "mixed precision not built yet");
-            IPS_HIP(launch_bc(a, p->nch[0], st));
+            IPS_HIP(launch_bc(a, p->nch[0], f32s, st));
         }
-        // (3) transform along x, contraction over y: faces y = 0, M1
         {
+            // (3) transform along x, sum over y-slices: faces y = 0, M1
+            STAGE(IPS_STAGE_CONV_Y);
             BcArgs a{};
             a.in = p->A;
             a.irs = (int64_t)I[1] * N[2];
@@ -457,10 +507,11 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.W = tile_width(N[0], 2048, a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
-            IPS_HIP(launch_bc(a, p->nch[1], st));
+            IPS_HIP(launch_bc(a, p->nch[1], f32s, st));
         }
-        // (4) zero-padded transform of rho along y -> C[x][slot_y][z] (reuses A)
         {
+            // (4) zero-padded transform of rho along y -> C[x][slot_y][z] (reuses A)
+            STAGE(IPS_STAGE_RHO_Y);
             PassArgs a{};
             a.in = rin;
             a.out = p->A;
@@ -477,10 +528,11 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = N[1];
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[1], p->tw[1], false, false, st))) return rc;
+            if ((rc = run_pass(a, p->fd[1], p->tw[1], false, f32s, st))) return rc;
         }
-        // (5) transform along x, contraction over z: faces z = 0, M2
         {
+            // (5) transform along x, sum over z-slices: faces z = 0, M2
+            STAGE(IPS_STAGE_CONV_Z);
             CcArgs a{};
             a.in = p->A;
             a.irs = (int64_t)N[1] * I[2];
@@ -499,8 +551,9 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.W = tile_width(N[0], 2048, a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
-            IPS_HIP(launch_cc(a, p->nch[2], st));
+            IPS_HIP(launch_cc(a, p->nch[2], f32s, f32s, st));
         }
+        STAGE(IPS_STAGE_FACES);
         // (6) sum the chunk partials
         for (int fam = 0; fam < 3; ++fam) {
             int64_t len = 2;
@@ -551,31 +604,30 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             if ((rc = run_pass(b, p->fd[r], p->tw[r], false, false, st))) return rc;
         }
         // (8) boundary values into phi
-        {
-            BwriteArgs a{};
-            a.geo = p->geo;
-            for (int q = 0; q < 3; ++q) a.n[q] = n[q];
-            for (int fam = 0; fam < 3; ++fam) {
-                a.F[fam] = p->F[fam];
-                a.scale[fam] = p->h[0] * p->h[1] * p->h[2];
-            }
-            a.fs[0][0] = (int64_t)N[1] * N[2];
-            a.fs[0][1] = N[2];
-            a.fs[0][2] = 1;
-            a.fs[1][0] = (int64_t)N[0] * N[2];
-            a.fs[1][1] = N[2];
-            a.fs[1][2] = 1;
-            a.fs[2][0] = (int64_t)N[1] * N[0];
-            a.fs[2][1] = 1;
-            a.fs[2][2] = N[0];
-            a.phi = phi;
-            IPS_HIP(launch_bwrite(a, st));
+        BwriteArgs a{};
+        a.geo = p->geo;
+        for (int q = 0; q < 3; ++q) a.n[q] = n[q];
+        for (int fam = 0; fam < 3; ++fam) {
+            a.F[fam] = p->F[fam];
+            a.scale[fam] = p->h[0] * p->h[1] * p->h[2];
         }
+        a.fs[0][0] = (int64_t)N[1] * N[2];
+        a.fs[0][1] = N[2];
+        a.fs[0][2] = 1;
+        a.fs[1][0] = (int64_t)N[0] * N[2];
+        a.fs[1][1] = N[2];
+        a.fs[1][2] = 1;
+        a.fs[2][0] = (int64_t)N[1] * N[0];
+        a.fs[2][1] = 1;
+        a.fs[2][2] = N[0];
+        a.phi = phi;
+        IPS_HIP(launch_bwrite(a, st));
     } else {
-        // d == 2
+        // d == 2: faces are lines
         const int64_t s0 = n[1];
         const double *rin = rho + s0 + 1;
         for (int fam = 0; fam < 2; ++fam) {
+            STAGE(fam == 0 ? IPS_STAGE_CONV_X : IPS_STAGE_CONV_Z);
             const int pen = 1 - fam;
             CcArgs a{};
             a.in = rin;
@@ -591,18 +643,19 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Kd = M[pen] + 1;
             a.Ko = 0;
             a.part = p->part[fam];
-            if (fam == 0 && !mixed) {
-                a.Bout = static_cast<double *>(p->B);
+            if (fam == 0) {
+                a.Bout = p->B;
+                a.Bf32 = f32;
                 a.Bcs = I[1];
                 a.Brs = 1;
                 a.Bbs = 0;
             }
-            if (mixed) return fail(IPS_E_UNSUPPORTED, "mixed precision not built yet");
             a.W = tile_width(N[pen], 2048, a.ncols);
             a.fd = p->fd[pen];
             a.tw = p->tw[pen];
-            IPS_HIP(launch_cc(a, p->nch[fam], st));
+            IPS_HIP(launch_cc(a, p->nch[fam], f32s, false, st));
         }
+        STAGE(IPS_STAGE_FACES);
         for (int fam = 0; fam < 2; ++fam) {
             const int pen = 1 - fam;
             IPS_HIP(launch_reduce(p->part[fam], p->F[fam], 2 * (int64_t)N[pen], p->nch[fam], st));
@@ -636,6 +689,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
 
     // ---- harmonic part: shell spectra ------------------------------------------------
     {
+        STAGE(IPS_STAGE_SHELL_GT);
         GtArgs a{};
         a.geo = p->geo;
         for (int q = 0; q < 3; ++q) a.n[q] = q < d ? n[q] : 1;
@@ -651,6 +705,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         sh.D[fam] = p->D[fam];
     }
     if (p->order == 6) {
+        STAGE(IPS_STAGE_SHELL_R6);
         for (int fam = 0; fam < d; ++fam) {
             H2Args a{};
             a.axis = fam;
@@ -676,6 +731,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     }
     // ---- combination and inverse transforms ------------------------------------------
     {
+        STAGE(IPS_STAGE_FINAL);
         FinalArgs a{};
         a.buf = p->B;
         if (d == 3) {
@@ -694,7 +750,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         a.nrows_in = I[0];
         a.W = tile_width(N[0], 2048, a.ncols);
         a.order = p->order;
-        a.mixed = mixed;
+        a.mixed = f32;
         a.geo = p->geo;
         for (int q = 0; q < d; ++q) a.tab[q] = p->tab[q];
         a.sh = sh;
@@ -703,19 +759,23 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         IPS_HIP(launch_final(a, st));
     }
     if (d == 3) {
-        PassArgs a{};
-        a.in = a.out = p->B;
-        a.irs = a.ors = I[2];
-        a.ics = a.ocs = 1;
-        a.ibs = a.obs = (int64_t)I[1] * I[2];
-        a.nrows_in = I[1];
-        a.ncols = I[2];
-        a.nbatch = I[0];
-        a.in_mode = IN_SPECS;
-        a.out_r0 = 1;
-        a.out_nrows = I[1];
-        a.scale = 0.5;
-        if ((rc = run_pass(a, p->fd[1], p->tw[1], mixed, mixed, st))) return rc;
+        {
+            STAGE(IPS_STAGE_INV_Y);
+            PassArgs a{};
+            a.in = a.out = p->B;
+            a.irs = a.ors = I[2];
+            a.ics = a.ocs = 1;
+            a.ibs = a.obs = (int64_t)I[1] * I[2];
+            a.nrows_in = I[1];
+            a.ncols = I[2];
+            a.nbatch = I[0];
+            a.in_mode = IN_SPECS;
+            a.out_r0 = 1;
+            a.out_nrows = I[1];
+            a.scale = 0.5;
+            if ((rc = run_pass(a, p->fd[1], p->tw[1], f32, f32, st))) return rc;
+        }
+        STAGE(IPS_STAGE_INV_Z);
         PassArgs b{};
         b.in = p->B;
         b.out = phi + n[1] * n[2] + n[2] + 1;
@@ -732,8 +792,9 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         b.out_r0 = 1;
         b.out_nrows = I[2];
         b.scale = 0.5;
-        if ((rc = run_pass(b, p->fd[2], p->tw[2], mixed, false, st))) return rc;
+        if ((rc = run_pass(b, p->fd[2], p->tw[2], f32, false, st))) return rc;
     } else {
+        STAGE(IPS_STAGE_INV_Z);
         PassArgs b{};
         b.in = p->B;
         b.out = phi + n[1] + 1;
@@ -750,8 +811,23 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         b.out_r0 = 1;
         b.out_nrows = I[1];
         b.scale = 0.5;
-        if ((rc = run_pass(b, p->fd[1], p->tw[1], mixed, false, st))) return rc;
+        if ((rc = run_pass(b, p->fd[1], p->tw[1], f32, false, st))) return rc;
     }
+    return IPS_OK;
+}
+
+int flush_timing(ips_plan p)
+{
+    for (auto &r : p->ev_rec) {
+        hipEvent_t e0 = std::get<1>(r), e1 = std::get<2>(r);
+        IPS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        IPS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        p->stage_ms[std::get<0>(r)] += ms;
+        p->stage_calls[std::get<0>(r)] += 1;
+    }
+    p->ev_rec.clear();
+    p->ev_used = 0;
     return IPS_OK;
 }
 
@@ -760,6 +836,7 @@ void plan_free(ips_plan p)
     if (!p) return;
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     p->mem.release();
     if (cur != p->device) (void)hipSetDevice(cur);
     delete p;
@@ -805,6 +882,7 @@ int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int
     p->d = d;
     p->order = d == 1 ? 4 : order;
     p->precision = precision;
+    p->timing = (flags & IPS_FLAG_STAGE_TIMING) != 0;
     for (int a = 0; a < d; ++a) {
         p->n[a] = n[a];
         p->h[a] = h[a];
@@ -857,6 +935,38 @@ int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void
     (void)stream;
     if (!p || !phi_bar || !rho_bar) return fail(IPS_E_INVALID_ARG, "NULL argument");
     return fail(IPS_E_UNSUPPORTED, "adjoint not available in this build");
+}
+
+const char *ips_stage_name(int stage)
+{
+    static const char *names[IPS_STAGE_COUNT] = {
+        "rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces",
+        "shell_gt", "shell_r6", "final", "inv_y", "inv_z"};
+    if (stage < 0 || stage >= IPS_STAGE_COUNT) return "unknown";
+    return names[stage];
+}
+
+int ips_plan_stage_time(ips_plan p, int stage, double *ms_total, int64_t *calls)
+{
+    if (!p || !ms_total || !calls) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    if (stage < 0 || stage >= IPS_STAGE_COUNT) return fail(IPS_E_INVALID_ARG, "bad stage");
+    int rc = flush_timing(p);
+    if (rc) return rc;
+    *ms_total = p->stage_ms[stage];
+    *calls = p->stage_calls[stage];
+    return IPS_OK;
+}
+
+int ips_plan_reset_stage_times(ips_plan p)
+{
+    if (!p) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    int rc = flush_timing(p);
+    if (rc) return rc;
+    for (int i = 0; i < IPS_STAGE_COUNT; ++i) {
+        p->stage_ms[i] = 0.0;
+        p->stage_calls[i] = 0;
+    }
+    return IPS_OK;
 }
 
 int ips_plan_destroy(ips_plan p)

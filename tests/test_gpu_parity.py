@@ -110,3 +110,52 @@ def test_ips_solve_entry_point():
     ref = P.solve(rho, h, 6)
     got = api.solve(to_dev(rho), h, order=6).cpu().numpy()
     assert rel_err(got, ref) < TOL
+
+
+MIXED_TOL = 1e-6
+
+
+@pytest.mark.parametrize("mode", ["mixed_fp32", "mixed_fp32_slices"])
+@pytest.mark.parametrize("shape", [(33, 41), (129, 129), (33, 37, 29), (65, 65, 65)])
+def test_mixed_precision_within_1e6(mode, shape):
+    from gpu_util import banner, rel_err
+
+    rho, h, _ = I.workload_bumps(shape, seed=2)
+    banner("mixed %s shape=%s" % (mode, shape))
+    ref = P.solve(rho, h, 6)
+    got = _gpu_solve(rho, h, 6, precision=mode)
+    err = rel_err(got, ref)
+    print("  rel err %.3e" % err, flush=True)
+    assert err < MIXED_TOL
+
+
+def test_mixed_129_order6():
+    from gpu_util import rel_err
+
+    rho, h, _ = I.workload_bumps_3d(129, seed=1)
+    ref = P.solve(rho, h, 6, boundary="fft")
+    for mode in ("mixed_fp32", "mixed_fp32_slices"):
+        err = rel_err(_gpu_solve(rho, h, 6, precision=mode), ref)
+        print("  %s rel err %.3e" % (mode, err), flush=True)
+        assert err < MIXED_TOL
+
+
+def test_stage_timing_plan_matches_plain_plan():
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import to_dev
+
+    rho, h, _ = I.workload_bumps_3d(33, seed=4)
+    r = to_dev(rho)
+    a = api.Plan(rho.shape, h, order=6)
+    b = api.Plan(rho.shape, h, order=6, timing=True)
+    x = a(r)
+    y = b(r)
+    b(r)
+    st = b.stage_times()
+    assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    assert st["conv_x"][1] == 2 and st["final"][0] > 0
+    b.reset_stage_times()
+    assert b.stage_times()["conv_x"][1] == 0
+    a.close()
+    b.close()
