@@ -83,9 +83,13 @@ def nchunks(n: int) -> dict:
     I, N = M - 1, 2 * M
 
     def tw(NN, ncols):
-        W = 2 * max(1, 2048 // NN)
-        need = ncols + (ncols & 1)
-        return min(W, max(need, 2))
+        nseq = 1
+        while 2 * nseq * NN <= 2048:
+            nseq *= 2
+        need = 2
+        while need < ncols:
+            need *= 2
+        return min(2 * nseq, need)
 
     out = {}
     for key in ("x", "y"):

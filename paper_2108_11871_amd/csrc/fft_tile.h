@@ -61,7 +61,18 @@ struct FftDesc {
     int M;   // N / 2
     int nst; // number of Stockham stages
     int rad[kMaxStages];
+    int ns[kMaxStages];          // product of the radices before the stage
+    unsigned nsmag[kMaxStages];  // ceil(2^32 / ns) for ns not a power of two, else 0
+    int nslg[kMaxStages];        // log2(ns) when ns is a power of two
 };
+
+// j mod ns for j < 2^16 (exact with the precomputed reciprocal)
+__device__ __forceinline__ int fmod_ns(int j, int ns, unsigned mag, int lg)
+{
+    if (mag == 0) return j & (ns - 1);
+    const int q = (int)__umulhi((unsigned)j, mag);
+    return j - q * ns;
+}
 
 template <typename T>
 __device__ __forceinline__ cx<T> lds_c(const T *buf, int rs, int n, int s)
@@ -137,28 +148,34 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool
     }
 }
 
-// One Stockham stage of radix R (R <= 8) over nseq sequences of length N.
-// MAXE bounds the complex elements a thread holds (nseq * N <= MAXE * NT).
+// One Stockham stage of radix R (R <= 8) over nseq = 2^lgs sequences of
+// length N.  MAXE bounds the complex elements a thread holds
+// (nseq * N <= MAXE * NT).
 template <typename T, int R, int MAXE, int NT>
-__device__ __forceinline__ void stage_bfly(T *buf, int rs, int nseq, int N, int Ns,
+__device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDesc &fd, int st,
                                            const cx<T> *tw, bool inv)
 {
     constexpr int BPT = (MAXE + R - 1) / R;
+    const int N = fd.N, Ns = fd.ns[st];
     const int NR = N / R;
-    const int nbf = nseq * NR;
+    const int nbf = (NR << lgs);
     const int tstep = N / (Ns * R);
+    const int smask = (1 << lgs) - 1;
     cx<T> v[BPT][R];
+    int base[BPT];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
         const int b = threadIdx.x + i * NT;
         if (b < nbf) {
-            const int s = b % nseq, j = b / nseq;
-            const int jm = j % Ns;
+            const int s = b & smask, j = b >> lgs;
+            const int jm = fmod_ns(j, Ns, fd.nsmag[st], fd.nslg[st]);
+            base[i] = (j - jm) * R + jm;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = lds_c(buf, rs, j + r * NR, s);
             if (jm != 0) {
+                const int e = jm * tstep;
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid(tw, jm * r * tstep, inv));
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid(tw, e * r, inv));
             }
             dft_small<T, R>(v[i], tw, N, inv);
         }
@@ -168,10 +185,9 @@ __device__ __forceinline__ void stage_bfly(T *buf, int rs, int nseq, int N, int 
     for (int i = 0; i < BPT; ++i) {
         const int b = threadIdx.x + i * NT;
         if (b < nbf) {
-            const int s = b % nseq, j = b / nseq;
-            const int base = (j / Ns) * Ns * R + (j % Ns);
+            const int s = b & smask;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds_cs(buf, rs, base + r * Ns, s, v[i][r]);
+            for (int r = 0; r < R; ++r) lds_cs(buf, rs, base[i] + r * Ns, s, v[i][r]);
         }
     }
     __syncthreads();
@@ -179,19 +195,22 @@ __device__ __forceinline__ void stage_bfly(T *buf, int rs, int nseq, int N, int 
 
 // Stockham stage of arbitrary radix R computed output by output.
 template <typename T, int MAXE, int NT>
-__device__ __forceinline__ void stage_direct(T *buf, int rs, int nseq, int N, int Ns, int R,
+__device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftDesc &fd, int st,
                                              const cx<T> *tw, bool inv)
 {
+    const int N = fd.N, Ns = fd.ns[st], R = fd.rad[st];
     const int NR = N / R;
-    const int tot = nseq * N;
+    const int tot = N << lgs;
     const int tstep = N / (Ns * R);
+    const int smask = (1 << lgs) - 1;
     cx<T> out[MAXE];
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
         const int e = threadIdx.x + i * NT;
         if (e < tot) {
-            const int s = e % nseq, o = e / nseq;
-            const int jm = o % Ns, t = o / Ns, q = t % R, jh = t / R;
+            const int s = e & smask, o = e >> lgs;
+            const int jm = fmod_ns(o, Ns, fd.nsmag[st], fd.nslg[st]);
+            const int t = (o - jm) / Ns, q = t % R, jh = t / R;
             const int j = jh * Ns + jm;
             const int E = jm * tstep + q * NR; // exponent per input index r, in units of w_N
             cx<T> acc = lds_c(buf, rs, j, s);
@@ -208,44 +227,54 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int nseq, int N, in
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
         const int e = threadIdx.x + i * NT;
-        if (e < tot) lds_cs(buf, rs, e / nseq, e % nseq, out[i]);
+        if (e < tot) lds_cs(buf, rs, e >> lgs, e & smask, out[i]);
     }
     __syncthreads();
 }
 
-// Full length-N complex FFT of nseq sequences held in LDS (in place).
-template <typename T, int MAXE, int NT>
-__device__ void fft_tile(T *buf, int rs, int nseq, const FftDesc &fd, const cx<T> *tw, bool inv)
+// Full length-N complex FFT of 2^lgs sequences held in LDS (in place).
+// P2: N is a power of two (only radix-2/4/8 stages are compiled in).
+template <typename T, int MAXE, int NT, bool P2 = false>
+__device__ void fft_tile(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, bool inv)
 {
-    int Ns = 1;
-    for (int st = 0; st < fd.nst; ++st) {
-        const int R = fd.rad[st];
-        switch (R) {
-        case 2: stage_bfly<T, 2, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
-        case 3: stage_bfly<T, 3, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
-        case 4: stage_bfly<T, 4, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
-        case 5: stage_bfly<T, 5, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
-        case 7: stage_bfly<T, 7, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
-        case 8: stage_bfly<T, 8, MAXE, NT>(buf, rs, nseq, fd.N, Ns, tw, inv); break;
-        default: stage_direct<T, MAXE, NT>(buf, rs, nseq, fd.N, Ns, R, tw, inv); break;
+    if constexpr (P2) {
+        for (int st = 0; st < fd.nst; ++st) {
+            const int R = fd.rad[st];
+            if (R == 8)
+                stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv);
+            else if (R == 4)
+                stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv);
+            else
+                stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv);
         }
-        Ns *= R;
+        return;
+    }
+    for (int st = 0; st < fd.nst; ++st) {
+        switch (fd.rad[st]) {
+        case 2: stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
+        case 3: stage_bfly<T, 3, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
+        case 4: stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
+        case 5: stage_bfly<T, 5, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
+        case 8: stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
+        default: stage_direct<T, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
+        }
     }
 }
 
 // After a forward zero-padded FFT: write C and S in slot layout (in place).
 template <typename T, int MAXE, int NT>
-__device__ void post_cs(T *buf, int rs, int nseq, int M)
+__device__ void post_cs(T *buf, int rs, int lgs, int M)
 {
     constexpr int PPT = MAXE / 2 + 1;
     const int N = 2 * M;
-    const int tot = nseq * (M + 1);
+    const int tot = (M + 1) << lgs;
+    const int smask = (1 << lgs) - 1;
     T ca[PPT], cb[PPT], sa[PPT], sb[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int e = threadIdx.x + i * NT;
         if (e < tot) {
-            const int s = e % nseq, k = e / nseq;
+            const int s = e & smask, k = e >> lgs;
             const cx<T> z1 = lds_c(buf, rs, k, s);
             const cx<T> z2 = lds_c(buf, rs, k == 0 ? 0 : N - k, s);
             ca[i] = (T)0.5 * (z1.x + z2.x);
@@ -259,7 +288,7 @@ __device__ void post_cs(T *buf, int rs, int nseq, int M)
     for (int i = 0; i < PPT; ++i) {
         const int e = threadIdx.x + i * NT;
         if (e < tot) {
-            const int s = e % nseq, k = e / nseq;
+            const int s = e & smask, k = e >> lgs;
             buf[k * rs + 2 * s] = ca[i];
             buf[k * rs + 2 * s + 1] = cb[i];
             if (k >= 1 && k < M) {
@@ -273,17 +302,18 @@ __device__ void post_cs(T *buf, int rs, int nseq, int M)
 
 // Before an inverse FFT: slots (C, S) -> hermitian-packed complex sequences.
 template <typename T, int MAXE, int NT>
-__device__ void pre_herm(T *buf, int rs, int nseq, int M, bool c_zero)
+__device__ void pre_herm(T *buf, int rs, int lgs, int M, bool c_zero)
 {
     constexpr int PPT = MAXE / 2 + 1;
     const int N = 2 * M;
-    const int tot = nseq * (M + 1);
+    const int tot = (M + 1) << lgs;
+    const int smask = (1 << lgs) - 1;
     cx<T> z1[PPT], z2[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const int e = threadIdx.x + i * NT;
         if (e < tot) {
-            const int s = e % nseq, k = e / nseq;
+            const int s = e & smask, k = e >> lgs;
             T ca = 0, cb = 0, sa = 0, sb = 0;
             if (!c_zero) {
                 ca = buf[k * rs + 2 * s];
@@ -302,7 +332,7 @@ __device__ void pre_herm(T *buf, int rs, int nseq, int M, bool c_zero)
     for (int i = 0; i < PPT; ++i) {
         const int e = threadIdx.x + i * NT;
         if (e < tot) {
-            const int s = e % nseq, k = e / nseq;
+            const int s = e & smask, k = e >> lgs;
             lds_cs(buf, rs, k, s, z1[i]);
             if (k >= 1 && k < M) lds_cs(buf, rs, N - k, s, z2[i]);
         }
@@ -312,22 +342,23 @@ __device__ void pre_herm(T *buf, int rs, int nseq, int M, bool c_zero)
 
 // Even extension: rows 1..M-1 copied to rows N-1..M+1.
 template <typename T, int NT>
-__device__ void pre_even(T *buf, int rs, int W, int M)
+__device__ void pre_even(T *buf, int rs, int lgW, int M)
 {
     const int N = 2 * M;
-    const int tot = (M - 1) * W;
+    const int tot = (M - 1) << lgW;
     for (int e = threadIdx.x; e < tot; e += NT) {
-        const int c = e % W, j = 1 + e / W;
+        const int c = e & ((1 << lgW) - 1), j = 1 + (e >> lgW);
         buf[(N - j) * rs + c] = buf[j * rs + c];
     }
     __syncthreads();
 }
 
 template <typename T, int NT>
-__device__ void zero_rows(T *buf, int rs, int W, int r0, int r1)
+__device__ void zero_rows(T *buf, int rs, int lgW, int r0, int r1)
 {
-    const int tot = (r1 - r0) * W;
-    for (int e = threadIdx.x; e < tot; e += NT) buf[(r0 + e / W) * rs + e % W] = (T)0;
+    const int tot = (r1 - r0) << lgW;
+    const int cm = (1 << lgW) - 1;
+    for (int e = threadIdx.x; e < tot; e += NT) buf[(r0 + (e >> lgW)) * rs + (e & cm)] = (T)0;
 }
 
 template <typename T, int NT>
@@ -339,23 +370,29 @@ __device__ void load_twiddles(cx<T> *dst, const cx<double> *src, int N)
     }
 }
 
-// Global -> LDS: rows [0, nrows) x cols [0, W) of the tile land at LDS rows
-// row0.. ; columns >= ncols are zero.  Element (r, c) is src[r*rsd + c*csd].
+// Global -> LDS: rows [0, nrows) x cols [0, W = 2^lgW) of the tile land at
+// LDS rows row0.. ; columns >= ncols are zero.  Element (r, c) is
+// src[r*rsd + c*csd].  Rows-contiguous sources are read one column per wave.
 template <typename T, typename TI, int NT>
 __device__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, int ncols,
-                          int64_t rsd, int64_t csd, int W)
+                          int64_t rsd, int64_t csd, int lgW)
 {
-    const int tot = nrows * W;
+    const int W = 1 << lgW;
     if (rsd == 1 && csd != 1) {
-        for (int e = threadIdx.x; e < tot; e += NT) {
-            const int r = e % nrows, c = e / nrows;
-            T v = (T)0;
-            if (c < ncols) v = (T)src[r + c * csd];
-            buf[(row0 + r) * rs + c] = v;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int c = wave; c < W; c += NT / 64) {
+            if (c < ncols) {
+                const TI *col = src + c * csd;
+                for (int r = lane; r < nrows; r += 64) buf[(row0 + r) * rs + c] = (T)col[r];
+            } else {
+                for (int r = lane; r < nrows; r += 64) buf[(row0 + r) * rs + c] = (T)0;
+            }
         }
     } else {
+        const int cm = W - 1;
+        const int tot = nrows << lgW;
         for (int e = threadIdx.x; e < tot; e += NT) {
-            const int c = e % W, r = e / W;
+            const int c = e & cm, r = e >> lgW;
             T v = (T)0;
             if (c < ncols) v = (T)src[r * rsd + c * csd];
             buf[(row0 + r) * rs + c] = v;
@@ -367,19 +404,20 @@ __device__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, in
 // dst[r*rsd + c*csd] scaled by `scale`.
 template <typename T, typename TO, int NT>
 __device__ void tile_store(const T *buf, int rs, int row0, TO *dst, int nrows, int ncols,
-                           int64_t rsd, int64_t csd, T scale)
+                           int64_t rsd, int64_t csd, T scale, int lgW)
 {
     if (rsd == 1 && csd != 1) {
-        const int tot = nrows * ncols;
-        for (int e = threadIdx.x; e < tot; e += NT) {
-            const int r = e % nrows, c = e / nrows;
-            dst[r + c * csd] = (TO)(scale * buf[(row0 + r) * rs + c]);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int c = wave; c < ncols; c += NT / 64) {
+            TO *col = dst + c * csd;
+            for (int r = lane; r < nrows; r += 64) col[r] = (TO)(scale * buf[(row0 + r) * rs + c]);
         }
     } else {
-        const int tot = nrows * ncols;
+        const int cm = (1 << lgW) - 1;
+        const int tot = nrows << lgW;
         for (int e = threadIdx.x; e < tot; e += NT) {
-            const int c = e % ncols, r = e / ncols;
-            dst[r * rsd + c * csd] = (TO)(scale * buf[(row0 + r) * rs + c]);
+            const int c = e & cm, r = e >> lgW;
+            if (c < ncols) dst[r * rsd + c * csd] = (TO)(scale * buf[(row0 + r) * rs + c]);
         }
     }
 }

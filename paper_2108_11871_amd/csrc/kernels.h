@@ -109,12 +109,14 @@ struct FinalArgs {
     const cx<double> *tw;
 };
 
+// Sixth-order right-hand side on the depth-5 shell (see k_h2v / k_h2c).
 struct H2Args {
-    int axis; // contraction axis (problem axis index)
+    int axis;  // contraction axis of k_h2c (a problem axis other than the last)
     Geo geo;
     AxisTabs tab[3];
     ShellSpec sh;
-    double *T; // [10][I_b][I_c] (3D) or [10][I_b] (2D)
+    double *V; // sine coefficients of the right-hand side on all interior modes
+    double *T; // [10][I_b][I_c] (3D) or [10][I_b] (2D) for the contracted axis
 };
 
 struct DcorrArgs {
@@ -149,7 +151,8 @@ hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStre
 hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st);
 hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st);
 hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);
-hipError_t launch_h2(const H2Args &a, hipStream_t st);
+hipError_t launch_h2v(const H2Args &a, hipStream_t st);
+hipError_t launch_h2c(const H2Args &a, hipStream_t st);
 hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);
 hipError_t launch_ksample(double *out, int d, int axis, const int *M, const double *h,

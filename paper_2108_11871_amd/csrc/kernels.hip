@@ -39,11 +39,12 @@ static size_t tile_lds(int N, int W)
 // ---------------------------------------------------------------------------
 // Generic pencil pass
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, typename TO, int MAXE>
+template <typename T, typename TI, typename TO, int MAXE, bool P2>
 __global__ __launch_bounds__(NT) void k_pass(PassArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    const int lgW = 31 - __clz(W), lgs = lgW - 1;
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
     T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
     const int ncb = (a.ncols + W - 1) / W;
@@ -56,28 +57,37 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a)
     load_twiddles<T, NT>(tw, a.tw, N);
     bool inv = false;
     if (a.in_mode == IN_ZPAD) {
-        zero_rows<T, NT>(buf, rs, W, 0, 1);
-        zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
-        tile_load<T, TI, NT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, W);
+        zero_rows<T, NT>(buf, rs, lgW, 0, 1);
+        zero_rows<T, NT>(buf, rs, lgW, 1 + a.nrows_in, N);
+        tile_load<T, TI, NT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
     } else if (a.in_mode == IN_EVEN) {
-        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, W);
+        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
-        pre_even<T, NT>(buf, rs, W, M);
+        pre_even<T, NT>(buf, rs, lgW, M);
     } else if (a.in_mode == IN_HERM) {
-        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, W);
+        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
-        pre_herm<T, MAXE, NT>(buf, rs, W / 2, M, false);
+        pre_herm<T, MAXE, NT>(buf, rs, lgs, M, false);
         inv = true;
     } else {
-        tile_load<T, TI, NT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, W);
+        tile_load<T, TI, NT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
-        pre_herm<T, MAXE, NT>(buf, rs, W / 2, M, true);
+        pre_herm<T, MAXE, NT>(buf, rs, lgs, M, true);
         inv = true;
     }
-    fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, inv);
-    if (a.in_mode == IN_ZPAD) post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
-    tile_store<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale);
+    fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, inv);
+    if (a.in_mode == IN_ZPAD) post_cs<T, MAXE, NT>(buf, rs, lgs, M);
+    tile_store<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+}
+
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <typename T, typename TI, typename TO, int MAXE, bool P2>
+static void launch_pass_k(const PassArgs &a, int64_t nblk, size_t lds, hipStream_t st)
+{
+    set_lds((const void *)&k_pass<T, TI, TO, MAXE, P2>, lds);
+    hipLaunchKernelGGL((k_pass<T, TI, TO, MAXE, P2>), dim3((unsigned)nblk), dim3(NT), lds, st, a);
 }
 
 template <typename T, typename TI, typename TO>
@@ -87,13 +97,18 @@ static hipError_t launch_pass_t(const PassArgs &a, hipStream_t st)
     const int64_t nblk = (int64_t)ncb * a.nbatch;
     const size_t lds = tile_lds<T>(a.fd.N, a.W);
     const int work = (a.W / 2) * a.fd.N;
+    const bool p2 = is_pow2(a.fd.N);
     if (nblk <= 0) return hipSuccess;
     if (work <= 4 * NT) {
-        set_lds((const void *)&k_pass<T, TI, TO, 4>, lds);
-        hipLaunchKernelGGL((k_pass<T, TI, TO, 4>), dim3((unsigned)nblk), dim3(NT), lds, st, a);
+        if (p2)
+            launch_pass_k<T, TI, TO, 4, true>(a, nblk, lds, st);
+        else
+            launch_pass_k<T, TI, TO, 4, false>(a, nblk, lds, st);
     } else if (work <= 8 * NT) {
-        set_lds((const void *)&k_pass<T, TI, TO, 8>, lds);
-        hipLaunchKernelGGL((k_pass<T, TI, TO, 8>), dim3((unsigned)nblk), dim3(NT), lds, st, a);
+        if (p2)
+            launch_pass_k<T, TI, TO, 8, true>(a, nblk, lds, st);
+        else
+            launch_pass_k<T, TI, TO, 8, false>(a, nblk, lds, st);
     } else {
         return hipErrorInvalidValue;
     }
@@ -111,11 +126,12 @@ hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t
 // ---------------------------------------------------------------------------
 // Boundary convolution, contraction over the batch axis (3D)
 // ---------------------------------------------------------------------------
-template <typename T, int MAXE, bool WB>
-__global__ __launch_bounds__(NT) void k_bc(BcArgs a, int nchunk)
+template <typename T, int MAXE, bool WB, bool P2, int NTB>
+__global__ __launch_bounds__(NTB) void k_bc(BcArgs a, int nchunk)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    const int lgW = 31 - __clz(W), lgs = lgW - 1;
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
     T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
     const int ncb = (a.ncols + W - 1) / W;
@@ -130,20 +146,20 @@ __global__ __launch_bounds__(NT) void k_bc(BcArgs a, int nchunk)
     double acc0[APT], acc1[APT];
 #pragma unroll
     for (int i = 0; i < APT; ++i) acc0[i] = acc1[i] = 0.0;
-    load_twiddles<T, NT>(tw, a.tw, N);
+    load_twiddles<T, NTB>(tw, a.tw, N);
     for (int b = b0; b < b1; ++b) {
-        zero_rows<T, NT>(buf, rs, W, 0, 1);
-        zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
-        tile_load<T, T, NT>(buf, rs, 1, in + b * a.ibs + c0, a.nrows_in, nc, a.irs, 1, W);
+        zero_rows<T, NTB>(buf, rs, lgW, 0, 1);
+        zero_rows<T, NTB>(buf, rs, lgW, 1 + a.nrows_in, N);
+        tile_load<T, T, NTB>(buf, rs, 1, in + b * a.ibs + c0, a.nrows_in, nc, a.irs, 1, lgW);
         __syncthreads();
-        fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
-        post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
+        fft_tile<T, MAXE, NTB, P2>(buf, rs, lgs, a.fd, tw, false);
+        post_cs<T, MAXE, NTB>(buf, rs, lgs, M);
         const double *K0 = a.K + (int64_t)b * a.Kd;
         const double *K1 = a.K + (int64_t)(a.nbatch - 1 - b) * a.Kd;
 #pragma unroll
         for (int i = 0; i < APT; ++i) {
-            const int pos = threadIdx.x + i * NT;
-            const int row = pos / W, c = pos % W;
+            const int pos = threadIdx.x + i * NTB;
+            const int row = pos >> lgW, c = pos & (W - 1);
             if (row < N && c < nc) {
                 const T v = buf[row * rs + c];
                 const int kp = row <= M ? row : row - M;
@@ -167,8 +183,8 @@ __global__ __launch_bounds__(NT) void k_bc(BcArgs a, int nchunk)
     double *p1 = p0 + (int64_t)N * a.ncols;
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
-        const int pos = threadIdx.x + i * NT;
-        const int row = pos / W, c = pos % W;
+        const int pos = threadIdx.x + i * NTB;
+        const int row = pos >> lgW, c = pos & (W - 1);
         if (row < N && c < nc) {
             p0[(int64_t)row * a.ncols + c0 + c] = acc0[i];
             p1[(int64_t)row * a.ncols + c0 + c] = acc1[i];
@@ -181,8 +197,14 @@ static hipError_t launch_bc_t(const BcArgs &a, int nchunk, hipStream_t st)
 {
     const int ncb = (a.ncols + a.W - 1) / a.W;
     const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    set_lds((const void *)&k_bc<T, 8, WB>, lds);
-    hipLaunchKernelGGL((k_bc<T, 8, WB>), dim3(ncb * nchunk), dim3(NT), lds, st, a, nchunk);
+    constexpr int NTB = 2 * NT; // half the accumulators per thread
+    if (is_pow2(a.fd.N)) {
+        set_lds((const void *)&k_bc<T, 4, WB, true, NTB>, lds);
+        hipLaunchKernelGGL((k_bc<T, 4, WB, true, NTB>), dim3(ncb * nchunk), dim3(NTB), lds, st, a, nchunk);
+    } else {
+        set_lds((const void *)&k_bc<T, 4, WB, false, NTB>, lds);
+        hipLaunchKernelGGL((k_bc<T, 4, WB, false, NTB>), dim3(ncb * nchunk), dim3(NTB), lds, st, a, nchunk);
+    }
     return hipGetLastError();
 }
 
@@ -198,20 +220,33 @@ hipError_t launch_bc(const BcArgs &a, int nchunk, bool f32, hipStream_t st)
 // ---------------------------------------------------------------------------
 // Boundary convolution, contraction over the tile columns (3D and 2D)
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, int MAXE, bool WB>
+template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT>
 __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    const int lgW = 31 - __clz(W), lgs = lgW - 1;
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
     T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
+    // Logical order: for each wavenumber k_b of the other axis, its cos slot
+    // and its sin slot are neighbours, so the blocks reading the same kernel
+    // spectra K[.][k_b][.] run together on one XCD (shared L2).
     const int lb = xcd_remap(blockIdx.x, nchunk * a.nbatch);
-    const int ch = lb % nchunk, bt = lb / nchunk;
+    const int ch = lb % nchunk, q = lb / nchunk;
+    int bt = q;
+    if (a.Mo > 0) {
+        // q = 0 -> slot 0; q = 2kb-1 -> slot kb; q = 2kb -> slot Mo+kb (kb < Mo); q = 2Mo-1 -> slot Mo
+        if (q == 0)
+            bt = 0;
+        else if (q == 2 * a.Mo - 1)
+            bt = a.Mo;
+        else
+            bt = (q & 1) ? (q + 1) / 2 : a.Mo + q / 2;
+    }
     const int kb = a.Mo > 0 ? (bt <= a.Mo ? bt : bt - a.Mo) : 0;
     const TI *in = static_cast<const TI *>(a.in);
     T *Bout = static_cast<T *>(a.Bout);
-    constexpr int RPT = 8; // N <= 2048
-    double acc0[RPT], acc1[RPT];
+    double acc0[RPT], acc1[RPT]; // rows per thread: RPT * NT >= N
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc0[i] = acc1[i] = 0.0;
     load_twiddles<T, NT>(tw, a.tw, N);
@@ -219,13 +254,13 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
     const int cend = min(a.ncols, cbeg + a.cols_per_chunk);
     for (int c0 = cbeg; c0 < cend; c0 += W) {
         const int nc = min(W, cend - c0);
-        zero_rows<T, NT>(buf, rs, W, 0, 1);
-        zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
+        zero_rows<T, NT>(buf, rs, lgW, 0, 1);
+        zero_rows<T, NT>(buf, rs, lgW, 1 + a.nrows_in, N);
         tile_load<T, TI, NT>(buf, rs, 1, in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc, a.irs,
-                             a.ics, W);
+                             a.ics, lgW);
         __syncthreads();
-        fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
-        post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
+        fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, false);
+        post_cs<T, MAXE, NT>(buf, rs, lgs, M);
         if (WB) {
             const int tot = (M - 1) * nc;
             for (int e = threadIdx.x; e < tot; e += NT) {
@@ -270,8 +305,24 @@ template <typename T, typename TI, bool WB>
 static hipError_t launch_cc_t(const CcArgs &a, int nchunk, hipStream_t st)
 {
     const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    set_lds((const void *)&k_cc<T, TI, 8, WB>, lds);
-    hipLaunchKernelGGL((k_cc<T, TI, 8, WB>), dim3(nchunk * a.nbatch), dim3(NT), lds, st, a, nchunk);
+    const dim3 grid(nchunk * a.nbatch);
+    if (a.fd.N <= 2 * NT) {
+        if (is_pow2(a.fd.N)) {
+            set_lds((const void *)&k_cc<T, TI, 8, WB, true, 2>, lds);
+            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, true, 2>), grid, dim3(NT), lds, st, a, nchunk);
+        } else {
+            set_lds((const void *)&k_cc<T, TI, 8, WB, false, 2>, lds);
+            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, false, 2>), grid, dim3(NT), lds, st, a, nchunk);
+        }
+    } else {
+        if (is_pow2(a.fd.N)) {
+            set_lds((const void *)&k_cc<T, TI, 8, WB, true, 8>, lds);
+            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, true, 8>), grid, dim3(NT), lds, st, a, nchunk);
+        } else {
+            set_lds((const void *)&k_cc<T, TI, 8, WB, false, 8>, lds);
+            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, false, 8>), grid, dim3(NT), lds, st, a, nchunk);
+        }
+    }
     return hipGetLastError();
 }
 
@@ -543,57 +594,138 @@ __device__ __forceinline__ double d_hat(const Geo &g, const AxisTabs *tab, const
 }
 
 // ---------------------------------------------------------------------------
-// Sixth-order right-hand side of the harmonic part on the depth-5 layers of
-// axis `axis`: T[j][k_other] = sum_{k_axis} sin(pi k_axis j / M) c_R(k),
-// with c_R = prod(2/M) * m_R(k) * gt_hat(k) / Lambda(k) the sine coefficients
-// of the stencil applied to the interior part of u1.  Layers j = 1..5 and
-// M-5..M-1 (parity split: sin(pi k (M-j)/M) = (-1)^(k+1) sin(pi k j / M)).
+// Sixth-order right-hand side of the harmonic part, interior contribution.
+// The stencils applied to the interior part of u1 act on its sine
+// coefficients as the symbol m_R(k); so the coefficients of that part of the
+// right-hand side are
+//     V(k) = prod(2/M) * m_R(k) * gt_hat(k) / Lambda(k).
+// Its values on the layers j = 1..5 and M-5..M-1 of every axis a are
+//     T_a[j][k_other] = sum_{k_a} sin(pi k_a j / M_a) V(k)
+// (followed by an inverse sine transform over the other axes).  Parity:
+// sin(pi k (M-j)/M) = (-1)^(k+1) sin(pi k j / M).
+// k_h2v writes V and contracts the last axis (one wave per row of V);
+// k_h2c contracts one of the other axes, streaming V.
 // ---------------------------------------------------------------------------
-__global__ void k_h2(H2Args a)
+__global__ __launch_bounds__(NT) void k_h2v(H2Args a)
 {
     const Geo &g = a.geo;
-    const int d = g.d, ax = a.axis;
-    const int64_t tot = shell_size(g, ax);
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= tot) return;
+    const int d = g.d;
+    const int L = d - 1; // last axis
+    const int IL = g.M[L] - 1;
+    int64_t rows = 1;
+    for (int b = 0; b < L; ++b) rows *= g.M[b] - 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    if (row >= rows) return;
     int k[3] = {1, 1, 1};
     {
-        int64_t r = e;
-        for (int b = d - 1; b >= 0; --b) {
-            if (b == ax) continue;
+        int64_t r = row;
+        for (int b = L - 1; b >= 0; --b) {
             k[b] = 1 + (int)(r % (g.M[b] - 1));
             r /= (g.M[b] - 1);
         }
     }
-    const int Ma = g.M[ax];
-    const double *sj = a.tab[ax].s;
+    const double *sj = a.tab[L].s;
     double ev[5] = {0, 0, 0, 0, 0}, od[5] = {0, 0, 0, 0, 0};
-    for (int ka = 1; ka < Ma; ++ka) {
-        k[ax] = ka;
-        Spec s;
-        spec_eval(g, a.tab, k, s);
-        const double c = g.pref * s.mR * gt_hat(g, a.tab, a.sh, k) / s.Lambda;
-        if (ka & 1) {
+    double *Vrow = a.V + row * IL;
+    for (int kL = 1 + lane; kL <= IL; kL += 64) {
+        k[L] = kL;
+        Spec sp;
+        spec_eval(g, a.tab, k, sp);
+        const double v = g.pref * sp.mR * gt_hat(g, a.tab, a.sh, k) / sp.Lambda;
+        Vrow[kL - 1] = v;
+        if (kL & 1) {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) od[j] += sj[j * (Ma - 1) + ka - 1] * c;
+            for (int j = 0; j < 5; ++j) od[j] += sj[j * IL + kL - 1] * v;
         } else {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) ev[j] += sj[j * (Ma - 1) + ka - 1] * c;
+            for (int j = 0; j < 5; ++j) ev[j] += sj[j * IL + kL - 1] * v;
         }
     }
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-        a.T[j * tot + e] = od[j] + ev[j];
-        a.T[(5 + j) * tot + e] = od[j] - ev[j];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            od[j] += __shfl_xor(od[j], m);
+            ev[j] += __shfl_xor(ev[j], m);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            a.T[j * rows + row] = od[j] + ev[j];
+            a.T[(5 + j) * rows + row] = od[j] - ev[j];
+        }
     }
 }
 
-hipError_t launch_h2(const H2Args &a, hipStream_t st)
+hipError_t launch_h2v(const H2Args &a, hipStream_t st)
 {
-    int64_t tot = 1;
+    int64_t rows = 1;
+    for (int b = 0; b < a.geo.d - 1; ++b) rows *= a.geo.M[b] - 1;
+    const int64_t nb = (rows + NT / 64 - 1) / (NT / 64);
+    hipLaunchKernelGGL(k_h2v, dim3((unsigned)nb), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(NT) void k_h2c(H2Args a)
+{
+    constexpr int PB = 64;   // positions per block
+    constexpr int NG = NT / PB; // groups over k_a (k_a = 1 + g + NG t: fixed parity per group)
+    __shared__ double stab[5 * 1024];
+    __shared__ double red[NG][5][PB];
+    const Geo &g = a.geo;
+    const int d = g.d, ax = a.axis;
+    const int Ia = g.M[ax] - 1;
+    // positions: other axes flattened (later axis fastest); V stride of axis ax
+    int64_t P = 1, stride = 1;
+    for (int b = 0; b < d; ++b)
+        if (b != ax) P *= g.M[b] - 1;
+    for (int b = ax + 1; b < d; ++b) stride *= g.M[b] - 1;
+    for (int t = threadIdx.x; t < 5 * Ia; t += NT) stab[t] = a.tab[ax].s[t];
+    const int pl = threadIdx.x % PB, grp = threadIdx.x / PB;
+    const int64_t p = (int64_t)blockIdx.x * PB + pl;
+    __syncthreads();
+    double acc[5] = {0, 0, 0, 0, 0};
+    if (p < P) {
+        // base offset of position p in V: split p into (outer, inner) around axis ax
+        const int64_t outer = p / stride, inner = p % stride;
+        const double *v = a.V + outer * stride * Ia + inner;
+        for (int ka = 1 + grp; ka <= Ia; ka += NG) {
+            const double x = v[(int64_t)(ka - 1) * stride];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) acc[j] += stab[j * Ia + ka - 1] * x;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) red[grp][j][pl] = acc[j];
+    __syncthreads();
+    if (grp == 0 && p < P) {
+        // k_a = 1 + grp + NG t is odd for even grp (NG even)
+        double od[5], ev[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            od[j] = 0.0;
+            ev[j] = 0.0;
+            for (int q = 0; q < NG; ++q) {
+                if (q % 2 == 0)
+                    od[j] += red[q][j][pl];
+                else
+                    ev[j] += red[q][j][pl];
+            }
+            a.T[j * P + p] = od[j] + ev[j];
+            a.T[(5 + j) * P + p] = od[j] - ev[j];
+        }
+    }
+}
+
+hipError_t launch_h2c(const H2Args &a, hipStream_t st)
+{
+    int64_t P = 1;
     for (int b = 0; b < a.geo.d; ++b)
-        if (b != a.axis) tot *= a.geo.M[b] - 1;
-    hipLaunchKernelGGL(k_h2, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
+        if (b != a.axis) P *= a.geo.M[b] - 1;
+    if (a.geo.M[a.axis] - 1 > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_h2c, dim3((unsigned)((P + 63) / 64)), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -736,11 +868,12 @@ hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st)
 //   c(k) = prod(2/M) [ -beta / (pi^2 sum k^2/L^2) + gt_hat / Lambda ]     (order 4)
 // then the inverse sine transform along axis 0, written back in place.
 // ---------------------------------------------------------------------------
-template <typename T, int MAXE>
+template <typename T, int MAXE, bool P2>
 __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    const int lgW = 31 - __clz(W), lgs = lgW - 1;
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
     T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
     const int ncb = (a.ncols + W - 1) / W;
@@ -750,16 +883,16 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
     const int nc = min(W, a.ncols - c0);
     T *g = static_cast<T *>(a.buf) + bt * a.ibs + c0 * a.ics;
     load_twiddles<T, NT>(tw, a.tw, N);
-    zero_rows<T, NT>(buf, rs, W, 0, 1);
-    zero_rows<T, NT>(buf, rs, W, 1 + a.nrows_in, N);
-    tile_load<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, W);
+    zero_rows<T, NT>(buf, rs, lgW, 0, 1);
+    zero_rows<T, NT>(buf, rs, lgW, 1 + a.nrows_in, N);
+    tile_load<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, lgW);
     __syncthreads();
-    fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, false);
-    post_cs<T, MAXE, NT>(buf, rs, W / 2, M);
+    fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, false);
+    post_cs<T, MAXE, NT>(buf, rs, lgs, M);
     const Geo &geo = a.geo;
-    const int tot = (M - 1) * W;
+    const int tot = (M - 1) << lgW;
     for (int e = threadIdx.x; e < tot; e += NT) {
-        const int c = e % W, kx = 1 + e / W;
+        const int c = e & (W - 1), kx = 1 + (e >> lgW);
         double cval = 0.0;
         if (c < nc) {
             int k[3];
@@ -787,9 +920,34 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
         buf[(M + kx) * rs + c] = (T)cval;
     }
     __syncthreads();
-    pre_herm<T, MAXE, NT>(buf, rs, W / 2, M, true);
-    fft_tile<T, MAXE, NT>(buf, rs, W / 2, a.fd, tw, true);
-    tile_store<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5);
+    pre_herm<T, MAXE, NT>(buf, rs, lgs, M, true);
+    fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, true);
+    tile_store<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW);
+}
+
+template <typename T, int MAXE, bool P2>
+static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
+{
+    const size_t lds = tile_lds<T>(a.fd.N, a.W);
+    set_lds((const void *)&k_final<T, MAXE, P2>, lds);
+    hipLaunchKernelGGL((k_final<T, MAXE, P2>), dim3(nblk), dim3(NT), lds, st, a);
+}
+
+template <typename T>
+static void launch_final_t(const FinalArgs &a, int nblk, bool small, hipStream_t st)
+{
+    const bool p2 = is_pow2(a.fd.N);
+    if (small) {
+        if (p2)
+            launch_final_k<T, 4, true>(a, nblk, st);
+        else
+            launch_final_k<T, 4, false>(a, nblk, st);
+    } else {
+        if (p2)
+            launch_final_k<T, 8, true>(a, nblk, st);
+        else
+            launch_final_k<T, 8, false>(a, nblk, st);
+    }
 }
 
 hipError_t launch_final(const FinalArgs &a, hipStream_t st)
@@ -798,25 +956,10 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st)
     const int nblk = ncb * a.nbatch;
     const int work = (a.W / 2) * a.fd.N;
     if (work > 8 * NT) return hipErrorInvalidValue;
-    if (a.mixed) {
-        const size_t lds = tile_lds<float>(a.fd.N, a.W);
-        if (work <= 4 * NT) {
-            set_lds((const void *)&k_final<float, 4>, lds);
-            hipLaunchKernelGGL((k_final<float, 4>), dim3(nblk), dim3(NT), lds, st, a);
-        } else {
-            set_lds((const void *)&k_final<float, 8>, lds);
-            hipLaunchKernelGGL((k_final<float, 8>), dim3(nblk), dim3(NT), lds, st, a);
-        }
-    } else {
-        const size_t lds = tile_lds<double>(a.fd.N, a.W);
-        if (work <= 4 * NT) {
-            set_lds((const void *)&k_final<double, 4>, lds);
-            hipLaunchKernelGGL((k_final<double, 4>), dim3(nblk), dim3(NT), lds, st, a);
-        } else {
-            set_lds((const void *)&k_final<double, 8>, lds);
-            hipLaunchKernelGGL((k_final<double, 8>), dim3(nblk), dim3(NT), lds, st, a);
-        }
-    }
+    if (a.mixed)
+        launch_final_t<float>(a, nblk, work <= 4 * NT, st);
+    else
+        launch_final_t<double>(a, nblk, work <= 4 * NT, st);
     return hipGetLastError();
 }
 
@@ -879,7 +1022,7 @@ __global__ __launch_bounds__(NT) void k_1d(const double *rho, double *phi, int M
                                            FftDesc fd, const cx<double> *twg, AxisTabs tab)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = fd.N, W = 2, rs = 3;
+    const int N = fd.N, rs = 3, lgW = 1;
     cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
     double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
     __shared__ double red[2][NT];
@@ -892,9 +1035,9 @@ __global__ __launch_bounds__(NT) void k_1d(const double *rho, double *phi, int M
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;
-    zero_rows<double, NT>(buf, rs, W, 0, 1);
-    zero_rows<double, NT>(buf, rs, W, M, N);
-    tile_load<double, double, NT>(buf, rs, 1, rho + 1, M - 1, 1, 1, 1, W);
+    zero_rows<double, NT>(buf, rs, lgW, 0, 1);
+    zero_rows<double, NT>(buf, rs, lgW, M, N);
+    tile_load<double, double, NT>(buf, rs, 1, rho + 1, M - 1, 1, 1, 1, lgW);
     __syncthreads();
     for (int w = NT / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
@@ -904,13 +1047,13 @@ __global__ __launch_bounds__(NT) void k_1d(const double *rho, double *phi, int M
         __syncthreads();
     }
     const double g0 = h * red[0][0], g1 = h * red[1][0];
-    fft_tile<double, MAXE, NT>(buf, rs, 1, fd, tw, false);
-    post_cs<double, MAXE, NT>(buf, rs, 1, M);
+    fft_tile<double, MAXE, NT>(buf, rs, 0, fd, tw, false);
+    post_cs<double, MAXE, NT>(buf, rs, 0, M);
     for (int k = 1 + threadIdx.x; k < M; k += NT)
         buf[(M + k) * rs] = -(2.0 / M) * buf[(M + k) * rs] / tab.q[k - 1];
     __syncthreads();
-    pre_herm<double, MAXE, NT>(buf, rs, 1, M, true);
-    fft_tile<double, MAXE, NT>(buf, rs, 1, fd, tw, true);
+    pre_herm<double, MAXE, NT>(buf, rs, 0, M, true);
+    fft_tile<double, MAXE, NT>(buf, rs, 0, fd, tw, true);
     for (int j = threadIdx.x; j <= M; j += NT) {
         double v;
         if (j == 0)

@@ -66,6 +66,16 @@ bool factor_fft(int N, FftDesc &fd)
             r /= p;
         }
     }
+    int ns = 1;
+    for (int st = 0; st < fd.nst; ++st) {
+        fd.ns[st] = ns;
+        const bool pow2 = (ns & (ns - 1)) == 0;
+        fd.nsmag[st] = pow2 ? 0u : (unsigned)((((uint64_t)1 << 32) + ns - 1) / ns);
+        int lg = 0;
+        while ((1 << lg) < ns) ++lg;
+        fd.nslg[st] = lg;
+        ns *= fd.rad[st];
+    }
     return true;
 }
 
@@ -95,12 +105,15 @@ struct DevBuf {
     }
 };
 
+// Columns per tile: a power of two, 2 * nseq with nseq * N <= maxwork,
+// no wider than the columns present (rounded up to a power of two).
 int tile_width(int N, int maxwork, int ncols)
 {
-    int nseq = std::max(1, maxwork / N);
+    int nseq = 1;
+    while (2 * nseq * N <= maxwork) nseq *= 2;
     int W = 2 * nseq;
-    int need = ncols + (ncols & 1);
-    if (need < 2) need = 2;
+    int need = 2;
+    while (need < ncols) need *= 2;
     return std::min(W, need);
 }
 
@@ -127,6 +140,7 @@ struct ips_plan_s {
     double *G[3] = {nullptr, nullptr, nullptr};
     double *T[3] = {nullptr, nullptr, nullptr};
     double *D[3] = {nullptr, nullptr, nullptr};
+    double *V = nullptr; // 2D: sine coefficients of the sixth-order right-hand side
     DevBuf mem;
     // stage timing
     bool timing = false;
@@ -285,8 +299,12 @@ int plan_build(ips_plan p, hipStream_t st)
     int rc = p->mem.alloc(&p->B, vol * wsz);
     if (rc) return rc;
     if (d == 3) {
+        // A also holds the FP64 coefficients V of the sixth-order step (vol doubles)
         const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
-        rc = p->mem.alloc(&p->A, std::max(a1, a2) * asz);
+        rc = p->mem.alloc(&p->A, std::max(std::max(a1, a2) * asz, vol * sizeof(double)));
+        if (rc) return rc;
+    } else if (p->order == 6) {
+        rc = p->mem.alloc((void **)&p->V, vol * sizeof(double));
         if (rc) return rc;
     }
     for (int fam = 0; fam < d; ++fam) {
@@ -706,14 +724,19 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     }
     if (p->order == 6) {
         STAGE(IPS_STAGE_SHELL_R6);
-        for (int fam = 0; fam < d; ++fam) {
+        {
             H2Args a{};
-            a.axis = fam;
             a.geo = p->geo;
             for (int q = 0; q < d; ++q) a.tab[q] = p->tab[q];
             a.sh = sh;
-            a.T = p->T[fam];
-            IPS_HIP(launch_h2(a, st));
+            a.V = d == 3 ? static_cast<double *>(p->A) : p->V;
+            a.T = p->T[d - 1];
+            IPS_HIP(launch_h2v(a, st));
+            for (int fam = 0; fam < d - 1; ++fam) {
+                a.axis = fam;
+                a.T = p->T[fam];
+                IPS_HIP(launch_h2c(a, st));
+            }
         }
         for (int fam = 0; fam < d; ++fam)
             if ((rc = shell_dst(p, p->T[fam], 10, fam, true, st))) return rc;
