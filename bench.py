@@ -36,8 +36,8 @@ MODES = ["fp64", "mixed_fp32", "mixed_fp32_slices"]
 # kernel (function) that implements each timed stage, as rocprofv3 names it
 STAGE_KERNEL = {
     "rho_z": "k_pass",
-    "conv_x": "k_bc (B output)",
-    "conv_y": "k_bc",
+    "conv_x": "k_cc (B output)",
+    "conv_y": "k_cc",
     "rho_y": "k_pass",
     "conv_z": "k_cc",
     "final": "k_final",
@@ -78,7 +78,7 @@ def stage_bytes(n: int, mode: str, nch: dict) -> dict:
 
 
 def nchunks(n: int) -> dict:
-    """Chunk counts of the contraction kernels (mirrors the plan's choice)."""
+    """Chunk counts of the column-contraction kernels (mirrors the plan's choice)."""
     M = n - 1
     I, N = M - 1, 2 * M
 
@@ -92,17 +92,12 @@ def nchunks(n: int) -> dict:
         return min(2 * nseq, need)
 
     out = {}
-    for key in ("x", "y"):
-        W = tw(N, N)
-        ncb = (N + W - 1) // W
-        nch = max(1, min(I, (2048 + ncb - 1) // ncb))
-        chunk = (I + nch - 1) // nch
-        out[key] = (I + chunk - 1) // chunk
-    W = tw(N, I)
-    ncb = (I + W - 1) // W
-    nch = max(1, min(ncb, (2048 + N - 1) // N))
-    per = (ncb + nch - 1) // nch
-    out["z"] = (I + per * W - 1) // (per * W)
+    for key in ("x", "y", "z"):
+        W = tw(N, I)
+        ncb = (I + W - 1) // W
+        nch = max(1, min(ncb, (2048 + N - 1) // N))
+        per = (ncb + nch - 1) // nch
+        out[key] = (I + per * W - 1) // (per * W)
     return out
 
 

@@ -28,27 +28,6 @@ struct PassArgs {
     const cx<double> *tw; // N twiddles exp(-2 pi i t / N)
 };
 
-// Boundary convolution, contraction over the batch axis (3D faces normal to
-// the batch axis).  Input: slot-transformed data along the contiguous axis.
-struct BcArgs {
-    const void *in;    // T (the transform type)
-    int64_t irs, ibs;  // row (pencil axis) and batch strides, column stride 1
-    int nrows_in;      // M_p - 1
-    int ncols;         // 2 M_c slots
-    int Mc;            // M of the contiguous axis
-    int nbatch;        // interior length of the contracted axis
-    int chunk;         // batch entries per block
-    const double *K;   // kernel spectra K[d][k_p][k_c], d = distance index
-    int64_t Kd, Kp;    // strides of d and k_p (k_c stride 1)
-    double *part;      // partial face spectra [nchunk][2][2 M_p][ncols]
-    void *Bout;        // optional: S_p S_c part -> Bout[batch*Bbs + (k_p-1)*Brs + (k_c-1)]
-    int64_t Bbs, Brs;
-    int Bf32;          // Bout holds float (else the transform type)
-    int W;
-    FftDesc fd;
-    const cx<double> *tw;
-};
-
 // Boundary convolution, contraction over the tile columns (faces normal to
 // the column axis).  grid.x = chunks of columns, grid.y = batch entries.
 struct CcArgs {
@@ -62,7 +41,8 @@ struct CcArgs {
     const double *K;   // K[d][k_o][k_p], k_p contiguous
     int64_t Kd, Ko;
     double *part;      // [nchunk][2][nbatch][2 M_p]
-    void *Bout;        // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + batch*Bbs]
+    void *Bout;        // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + (k_o-1)*Bbs],
+                       // written for the sine slots k_o of the batch axis (all batches if Mo == 0)
     int64_t Bcs, Brs, Bbs;
     int Bf32;          // Bout holds float (else the transform type)
     int W;
@@ -92,11 +72,26 @@ struct Geo {
 struct ShellSpec {
     const double *G[3];
     const double *D[3];
+    // Parity-packed form used by the spectral kernels, [par][t][k_other] with
+    // par = k_a & 1 and sg = +1 (odd k_a) or -1 (even k_a):
+    //   t = 0: G_lo + sg G_hi          (multiplies sin(pi k_a / M_a))
+    //   t = 1: D_1 + sg D_{M-1}        (multiplies sin(pi k_a / M_a))
+    //   t = 2: D_2 + sg D_{M-2}        (multiplies sin(2 pi k_a / M_a))
+    const double *P[3];
+};
+
+struct PackArgs {
+    Geo geo;
+    const double *G[3];
+    const double *D[3];
+    double *P[3];
+    int withD; // also pack the deferred-correction layers
 };
 
 struct FinalArgs {
     void *buf;  // B: raw DST of rho along the last d-1 axes; overwritten in place
     int64_t irs, ics, ibs;
+    int cax, bax; // problem axes of the tile columns and of the batch (-1: none)
     int nrows_in; // M_0 - 1
     int ncols, nbatch;
     int W;
@@ -144,18 +139,19 @@ struct BwriteArgs {
 };
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
-// f32: transforms in FP32 (input and B in FP32); accumulation is FP64 always.
-hipError_t launch_bc(const BcArgs &a, int nchunk, bool f32, hipStream_t st);
 // in_f32: input data in FP32 (else FP64); f32: transform type
 hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st);
 hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st);
 hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st);
 hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);
+hipError_t launch_pack(const PackArgs &a, hipStream_t st);
 hipError_t launch_h2v(const H2Args &a, hipStream_t st);
 hipError_t launch_h2c(const H2Args &a, hipStream_t st);
 hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);
-hipError_t launch_ksample(double *out, int d, int axis, const int *M, const double *h,
+// K[dd][ib][ic] (3D) or K[dd][ib] (2D) for faces normal to axis a; (b, c) are
+// the in-face axes in storage order (c contiguous).
+hipError_t launch_ksample(double *out, int d, int a, int b, int c, const int *M, const double *h,
                           hipStream_t st);
 hipError_t launch_1d(const double *rho, double *phi, int M, double h, const FftDesc &fd,
                      const cx<double> *tw, const AxisTabs &tab, double *scratch, hipStream_t st);

@@ -3,7 +3,7 @@
 // Stage map (paper sections):
 //   k_pass    pencil transforms: DST-I / zero-padded cos+sin / even (DCT-I) /
 //             hermitian synthesis along one axis (Sections 3, 4, 5)
-//   k_bc,k_cc boundary values as sums over slices of 2D (3D problems) or 1D
+//   k_cc      boundary values as sums over slices of 2D (3D problems) or 1D
 //             (2D problems) discrete convolutions, accumulated in Fourier
 //             space with the kernel spectra (Section 4, eqs. Trap2D,
 //             Trap2Dconvolution, convolution)
@@ -124,100 +124,6 @@ hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// Boundary convolution, contraction over the batch axis (3D)
-// ---------------------------------------------------------------------------
-template <typename T, int MAXE, bool WB, bool P2, int NTB>
-__global__ __launch_bounds__(NTB) void k_bc(BcArgs a, int nchunk)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
-    const int lgW = 31 - __clz(W), lgs = lgW - 1;
-    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
-    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
-    const int ncb = (a.ncols + W - 1) / W;
-    const int lb = xcd_remap(blockIdx.x, ncb * nchunk);
-    const int cb = lb % ncb, ch = lb / ncb;
-    const int c0 = cb * W;
-    const int nc = min(W, a.ncols - c0);
-    const int b0 = ch * a.chunk, b1 = min(a.nbatch, b0 + a.chunk);
-    const T *in = static_cast<const T *>(a.in);
-    T *Bout = static_cast<T *>(a.Bout);
-    constexpr int APT = 2 * MAXE;
-    double acc0[APT], acc1[APT];
-#pragma unroll
-    for (int i = 0; i < APT; ++i) acc0[i] = acc1[i] = 0.0;
-    load_twiddles<T, NTB>(tw, a.tw, N);
-    for (int b = b0; b < b1; ++b) {
-        zero_rows<T, NTB>(buf, rs, lgW, 0, 1);
-        zero_rows<T, NTB>(buf, rs, lgW, 1 + a.nrows_in, N);
-        tile_load<T, T, NTB>(buf, rs, 1, in + b * a.ibs + c0, a.nrows_in, nc, a.irs, 1, lgW);
-        __syncthreads();
-        fft_tile<T, MAXE, NTB, P2>(buf, rs, lgs, a.fd, tw, false);
-        post_cs<T, MAXE, NTB>(buf, rs, lgs, M);
-        const double *K0 = a.K + (int64_t)b * a.Kd;
-        const double *K1 = a.K + (int64_t)(a.nbatch - 1 - b) * a.Kd;
-#pragma unroll
-        for (int i = 0; i < APT; ++i) {
-            const int pos = threadIdx.x + i * NTB;
-            const int row = pos >> lgW, c = pos & (W - 1);
-            if (row < N && c < nc) {
-                const T v = buf[row * rs + c];
-                const int kp = row <= M ? row : row - M;
-                const int sc = c0 + c;
-                const int kc = sc <= a.Mc ? sc : sc - a.Mc;
-                const int64_t ko = (int64_t)kp * a.Kp + kc;
-                acc0[i] += K0[ko] * (double)v;
-                acc1[i] += K1[ko] * (double)v;
-                if (WB && row > M && sc > a.Mc) {
-                    const int64_t bi = b * a.Bbs + (int64_t)(row - M - 1) * a.Brs + (sc - a.Mc - 1);
-                    if (a.Bf32)
-                        static_cast<float *>(a.Bout)[bi] = (float)v;
-                    else
-                        Bout[bi] = v;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    double *p0 = a.part + (int64_t)(2 * ch) * N * a.ncols;
-    double *p1 = p0 + (int64_t)N * a.ncols;
-#pragma unroll
-    for (int i = 0; i < APT; ++i) {
-        const int pos = threadIdx.x + i * NTB;
-        const int row = pos >> lgW, c = pos & (W - 1);
-        if (row < N && c < nc) {
-            p0[(int64_t)row * a.ncols + c0 + c] = acc0[i];
-            p1[(int64_t)row * a.ncols + c0 + c] = acc1[i];
-        }
-    }
-}
-
-template <typename T, bool WB>
-static hipError_t launch_bc_t(const BcArgs &a, int nchunk, hipStream_t st)
-{
-    const int ncb = (a.ncols + a.W - 1) / a.W;
-    const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    constexpr int NTB = 2 * NT; // half the accumulators per thread
-    if (is_pow2(a.fd.N)) {
-        set_lds((const void *)&k_bc<T, 4, WB, true, NTB>, lds);
-        hipLaunchKernelGGL((k_bc<T, 4, WB, true, NTB>), dim3(ncb * nchunk), dim3(NTB), lds, st, a, nchunk);
-    } else {
-        set_lds((const void *)&k_bc<T, 4, WB, false, NTB>, lds);
-        hipLaunchKernelGGL((k_bc<T, 4, WB, false, NTB>), dim3(ncb * nchunk), dim3(NTB), lds, st, a, nchunk);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_bc(const BcArgs &a, int nchunk, bool f32, hipStream_t st)
-{
-    const int work = (a.W / 2) * a.fd.N;
-    if (work > 8 * NT) return hipErrorInvalidValue;
-    const bool wb = a.Bout != nullptr;
-    if (f32) return wb ? launch_bc_t<float, true>(a, nchunk, st) : launch_bc_t<float, false>(a, nchunk, st);
-    return wb ? launch_bc_t<double, true>(a, nchunk, st) : launch_bc_t<double, false>(a, nchunk, st);
-}
-
-// ---------------------------------------------------------------------------
 // Boundary convolution, contraction over the tile columns (3D and 2D)
 // ---------------------------------------------------------------------------
 template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT>
@@ -261,16 +167,18 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
         __syncthreads();
         fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, false);
         post_cs<T, MAXE, NT>(buf, rs, lgs, M);
-        if (WB) {
-            const int tot = (M - 1) * nc;
-            for (int e = threadIdx.x; e < tot; e += NT) {
-                const int r = e % (M - 1), c = e / (M - 1);
-                const int64_t bi = (int64_t)(c0 + c) * a.Bcs + (int64_t)r * a.Brs + (int64_t)bt * a.Bbs;
-                const T v = buf[(M + 1 + r) * rs + c];
-                if (a.Bf32)
-                    static_cast<float *>(a.Bout)[bi] = (float)v;
-                else
-                    Bout[bi] = v;
+        if (WB && (a.Mo == 0 || bt > a.Mo)) {
+            const int64_t bb = a.Mo == 0 ? 0 : (int64_t)(bt - a.Mo - 1) * a.Bbs;
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            for (int c = wave; c < nc; c += NT / 64) {
+                const int64_t cb = (int64_t)(c0 + c) * a.Bcs + bb;
+                for (int r = lane; r < M - 1; r += 64) {
+                    const T v = buf[(M + 1 + r) * rs + c];
+                    if (a.Bf32)
+                        static_cast<float *>(a.Bout)[cb + (int64_t)r * a.Brs] = (float)v;
+                    else
+                        Bout[cb + (int64_t)r * a.Brs] = v;
+                }
             }
         }
 #pragma unroll
@@ -554,7 +462,7 @@ __device__ __forceinline__ int64_t shell_idx(const Geo &g, int a, const int *k)
     return o;
 }
 
-__device__ __forceinline__ int64_t shell_size(const Geo &g, int a)
+__host__ __device__ __forceinline__ int64_t shell_size(const Geo &g, int a)
 {
     int64_t s = 1;
     for (int b = 0; b < g.d; ++b)
@@ -594,6 +502,57 @@ __device__ __forceinline__ double d_hat(const Geo &g, const AxisTabs *tab, const
 }
 
 // ---------------------------------------------------------------------------
+// Parity packing of the shell spectra (see ShellSpec::P)
+// ---------------------------------------------------------------------------
+__global__ void k_pack(PackArgs a)
+{
+    const Geo &g = a.geo;
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int fam = 0; fam < g.d; ++fam) {
+        const int64_t ss = shell_size(g, fam);
+        if (e < ss) {
+            const double *G = a.G[fam];
+            double *P = a.P[fam];
+            const double g0 = G[e], g1 = G[ss + e];
+            P[e] = g0 - g1;              // par 0 (even k), t 0
+            P[3 * ss + e] = g0 + g1;     // par 1 (odd k), t 0
+            if (a.withD) {
+                const double *D = a.D[fam];
+                const double d1 = D[e], d2 = D[ss + e], d3 = D[2 * ss + e], d4 = D[3 * ss + e];
+                P[ss + e] = d1 - d4;
+                P[2 * ss + e] = d2 - d3;
+                P[4 * ss + e] = d1 + d4;
+                P[5 * ss + e] = d2 + d3;
+            }
+            return;
+        }
+        e -= ss;
+    }
+}
+
+hipError_t launch_pack(const PackArgs &a, hipStream_t st)
+{
+    int64_t tot = 0;
+    for (int fam = 0; fam < a.geo.d; ++fam) tot += shell_size(a.geo, fam);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+// Lambda(k) and m_R(k) from the eigenvalues lam of D2 along each axis.
+__device__ __forceinline__ void lam_symbols(const Geo &g, const double *lam, double &L, double &R)
+{
+    L = 0.0;
+    R = 0.0;
+    for (int a = 0; a < g.d; ++a) L += lam[a];
+    for (int i = 0; i < g.d; ++i)
+        for (int j = i + 1; j < g.d; ++j) {
+            const double p = lam[i] * lam[j];
+            L += g.c2[i][j] * p;
+            R += p * (g.c4[i][j] * lam[i] + g.c4[j][i] * lam[j]);
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Sixth-order right-hand side of the harmonic part, interior contribution.
 // The stencils applied to the interior part of u1 act on its sine
 // coefficients as the symbol m_R(k); so the coefficients of that part of the
@@ -625,14 +584,39 @@ __global__ __launch_bounds__(NT) void k_h2v(H2Args a)
             r /= (g.M[b] - 1);
         }
     }
+    // row invariants: eigenvalues and shell factors of the first d-1 axes,
+    // and the last family's packed g~ values (its other index is the row)
+    double lam[3], s1[3];
+    for (int b = 0; b < L; ++b) {
+        lam[b] = a.tab[b].lam[k[b] - 1];
+        s1[b] = a.tab[b].s[k[b] - 1];
+    }
+    const int64_t ssL = shell_size(g, L);
+    const double gL_even = a.sh.P[L][row], gL_odd = a.sh.P[L][3 * ssL + row];
+    // per-element families b < L: other index includes the last axis
+    const double *Pb[2];
+    int64_t obase[2], ostride[2];
+    for (int b = 0; b < L; ++b) {
+        const int64_t ss = shell_size(g, b);
+        Pb[b] = a.sh.P[b] + ((k[b] & 1) ? 3 * ss : 0);
+        // other index of family b: axes != b in increasing order, last axis fastest
+        int64_t o = 0;
+        for (int c = 0; c < L; ++c)
+            if (c != b) o = o * (g.M[c] - 1) + (k[c] - 1);
+        obase[b] = o * IL;
+        ostride[b] = 1;
+    }
     const double *sj = a.tab[L].s;
+    const double *lamL = a.tab[L].lam;
     double ev[5] = {0, 0, 0, 0, 0}, od[5] = {0, 0, 0, 0, 0};
     double *Vrow = a.V + row * IL;
     for (int kL = 1 + lane; kL <= IL; kL += 64) {
-        k[L] = kL;
-        Spec sp;
-        spec_eval(g, a.tab, k, sp);
-        const double v = g.pref * sp.mR * gt_hat(g, a.tab, a.sh, k) / sp.Lambda;
+        lam[L] = lamL[kL - 1];
+        double Lm, Rm;
+        lam_symbols(g, lam, Lm, Rm);
+        double gt = sj[kL - 1] * ((kL & 1) ? gL_odd : gL_even);
+        for (int b = 0; b < L; ++b) gt += s1[b] * Pb[b][obase[b] + (kL - 1) * ostride[b]];
+        const double v = g.pref * Rm * gt / Lm;
         Vrow[kL - 1] = v;
         if (kL & 1) {
 #pragma unroll
@@ -890,31 +874,48 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
     fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, false);
     post_cs<T, MAXE, NT>(buf, rs, lgs, M);
     const Geo &geo = a.geo;
+    const int d = geo.d;
     const int tot = (M - 1) << lgW;
+    const bool six = a.order == 6;
+    int64_t ss[3] = {1, 1, 1};
+    int Ii[3] = {1, 1, 1};
+    for (int f = 0; f < d; ++f) {
+        ss[f] = shell_size(geo, f);
+        Ii[f] = geo.M[f] - 1;
+    }
     for (int e = threadIdx.x; e < tot; e += NT) {
         const int c = e & (W - 1), kx = 1 + (e >> lgW);
         double cval = 0.0;
         if (c < nc) {
-            int k[3];
-            k[0] = kx;
-            if (geo.d == 3) {
-                k[1] = 1 + bt;
-                k[2] = 1 + c0 + c;
-            } else {
-                k[1] = 1 + c0 + c;
-                k[2] = 1;
-            }
+            int k[3] = {kx, 1, 1};
+            k[a.cax] = 1 + c0 + c;
+            if (a.bax >= 0) k[a.bax] = 1 + bt;
             const double beta = (double)buf[(M + kx) * rs + c];
-            double q = 0.0;
-            for (int ax = 0; ax < geo.d; ++ax) q += a.tab[ax].q[k[ax] - 1];
-            Spec s;
-            spec_eval(geo, a.tab, k, s);
-            const double gh = gt_hat(geo, a.tab, a.sh, k);
-            double harm;
-            if (a.order == 6)
-                harm = (gh * (1.0 + s.mR / s.Lambda) + d_hat(geo, a.tab, a.sh, k)) / s.Lambda;
-            else
-                harm = gh / s.Lambda;
+            // shell index of each family: the other axes, later axis fastest
+            int64_t o[3];
+            if (d == 3) {
+                o[0] = (int64_t)(k[1] - 1) * Ii[2] + (k[2] - 1);
+                o[1] = (int64_t)(k[0] - 1) * Ii[2] + (k[2] - 1);
+                o[2] = (int64_t)(k[0] - 1) * Ii[1] + (k[1] - 1);
+            } else {
+                o[0] = k[1] - 1;
+                o[1] = k[0] - 1;
+                o[2] = 0;
+            }
+            double lam[3], q = 0.0, gt = 0.0, dh = 0.0;
+            for (int f = 0; f < d; ++f) {
+                const int kf = k[f] - 1;
+                lam[f] = a.tab[f].lam[kf];
+                q += a.tab[f].q[kf];
+                const double s1 = a.tab[f].s[kf];
+                const double *P = a.sh.P[f] + ((k[f] & 1) ? 3 * ss[f] : 0) + o[f];
+                gt += s1 * P[0];
+                if (six) dh += s1 * P[ss[f]] + a.tab[f].s[Ii[f] + kf] * P[2 * ss[f]];
+            }
+            double Lm, Rm;
+            lam_symbols(geo, lam, Lm, Rm);
+            const double iL = 1.0 / Lm;
+            const double harm = six ? (gt * (1.0 + Rm * iL) + dh) * iL : gt * iL;
             cval = geo.pref * (harm - beta / q);
         }
         buf[(M + kx) * rs + c] = (T)cval;
@@ -989,23 +990,9 @@ __global__ void k_ksample(double *out, int d, int a, int b, int c, int Ma, int M
     }
 }
 
-hipError_t launch_ksample(double *out, int d, int axis, const int *M, const double *h,
+hipError_t launch_ksample(double *out, int d, int a, int b, int c, const int *M, const double *h,
                           hipStream_t st)
 {
-    // axes in the order the contraction kernels index their tables
-    int a = axis, b, c = 0;
-    if (d == 2) {
-        b = 1 - axis;
-    } else if (axis == 0) {
-        b = 1;
-        c = 2;
-    } else if (axis == 1) {
-        b = 0;
-        c = 2;
-    } else {
-        b = 1;
-        c = 0;
-    }
     const int64_t tot = (int64_t)(M[a] - 1) * (M[b] + 1) * (d == 3 ? M[c] + 1 : 1);
     const int nb = (int)std::min<int64_t>((tot + NT - 1) / NT, 65536);
     hipLaunchKernelGGL(k_ksample, dim3(nb), dim3(NT), 0, st, out, d, a, b, c, M[a], M[b],

@@ -117,6 +117,28 @@ int tile_width(int N, int maxwork, int ncols)
     return std::min(W, need);
 }
 
+// In-face axes (b, c) of the kernel-spectrum table of face family `fam`, in
+// storage order K[dd][k_b][k_c] (c contiguous).  The column-contraction
+// kernels read K[dd][k_o][k_p] with k_p the transform (pencil) axis.
+void kaxes(int d, int fam, int &b, int &c)
+{
+    if (d == 2) {
+        b = 1 - fam;
+        c = 0;
+        return;
+    }
+    if (fam == 0) {
+        b = 2;
+        c = 1; // pencil y, batch slots of z
+    } else if (fam == 1) {
+        b = 2;
+        c = 0; // pencil x, batch slots of z
+    } else {
+        b = 1;
+        c = 0; // pencil x, batch slots of y
+    }
+}
+
 } // namespace
 
 struct ips_plan_s {
@@ -140,6 +162,7 @@ struct ips_plan_s {
     double *G[3] = {nullptr, nullptr, nullptr};
     double *T[3] = {nullptr, nullptr, nullptr};
     double *D[3] = {nullptr, nullptr, nullptr};
+    double *P[3] = {nullptr, nullptr, nullptr}; // parity-packed shell spectra
     double *V = nullptr; // 2D: sine coefficients of the sixth-order right-hand side
     DevBuf mem;
     // stage timing
@@ -314,19 +337,17 @@ int plan_build(ips_plan p, hipStream_t st)
         size_t ss = 1;
         for (int b = 0; b < d; ++b)
             if (b != fam) ss *= (size_t)I[b];
-        // chunking of the contraction
+        // chunking of the contraction over the face-normal axis (column-contraction kernel)
         int nch;
-        if (d == 3 && fam < 2) {
-            const int ncols = N[2];
-            const int W = tile_width(N[fam == 0 ? 1 : 0], 2048, ncols);
-            const int ncb = (ncols + W - 1) / W;
-            nch = std::max(1, std::min(I[fam], (2048 + ncb - 1) / ncb));
-            const int chunk = (I[fam] + nch - 1) / nch;
-            p->chunk[fam] = chunk;
-            nch = (I[fam] + chunk - 1) / chunk;
-        } else {
-            const int pen = d == 3 ? 0 : 1 - fam;
-            const int nbatch = d == 3 ? N[1] : 1;
+        {
+            int pen, nbatch;
+            if (d == 3) {
+                pen = fam == 0 ? 1 : 0;
+                nbatch = fam == 2 ? N[1] : N[2];
+            } else {
+                pen = 1 - fam;
+                nbatch = 1;
+            }
             const int W = tile_width(N[pen], 2048, I[fam]);
             const int ncb = (I[fam] + W - 1) / W;
             nch = std::max(1, std::min(ncb, (2048 + nbatch - 1) / nbatch));
@@ -338,6 +359,7 @@ int plan_build(ips_plan p, hipStream_t st)
         if ((rc = p->mem.alloc((void **)&p->part[fam], fsz * nch * sizeof(double)))) return rc;
         if ((rc = p->mem.alloc((void **)&p->F[fam], fsz * sizeof(double)))) return rc;
         if ((rc = p->mem.alloc((void **)&p->G[fam], 2 * ss * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&p->P[fam], 6 * ss * sizeof(double)))) return rc;
         if (p->order == 6) {
             if ((rc = p->mem.alloc((void **)&p->T[fam], 10 * ss * sizeof(double)))) return rc;
             if ((rc = p->mem.alloc((void **)&p->D[fam], 4 * ss * sizeof(double)))) return rc;
@@ -347,60 +369,50 @@ int plan_build(ips_plan p, hipStream_t st)
         for (int b = 0; b < d; ++b)
             if (b != fam) ksz *= (size_t)(M[b] + 1);
         if ((rc = p->mem.alloc((void **)&p->K[fam], ksz * sizeof(double)))) return rc;
-        IPS_HIP(launch_ksample(p->K[fam], d, fam, M, p->h, st));
+        int kb, kc;
+        kaxes(d, fam, kb, kc);
+        IPS_HIP(launch_ksample(p->K[fam], d, fam, kb, kc, M, p->h, st));
         if (d == 2) {
-            const int b = 1 - fam;
             PassArgs a{};
             a.in = a.out = p->K[fam];
             a.irs = a.ors = 1;
-            a.ics = a.ocs = M[b] + 1;
-            a.nrows_in = M[b] + 1;
+            a.ics = a.ocs = M[kb] + 1;
+            a.nrows_in = M[kb] + 1;
             a.ncols = I[fam];
             a.nbatch = 1;
             a.in_mode = IN_EVEN;
             a.out_r0 = 0;
-            a.out_nrows = M[b] + 1;
+            a.out_nrows = M[kb] + 1;
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[b], p->tw[b], false, false, st))) return rc;
+            if ((rc = run_pass(a, p->fd[kb], p->tw[kb], false, false, st))) return rc;
         } else {
-            int b, c;
-            if (fam == 0) {
-                b = 1;
-                c = 2;
-            } else if (fam == 1) {
-                b = 0;
-                c = 2;
-            } else {
-                b = 1;
-                c = 0;
-            }
-            const int64_t plane = (int64_t)(M[b] + 1) * (M[c] + 1);
+            const int64_t plane = (int64_t)(M[kb] + 1) * (M[kc] + 1);
             PassArgs a{};
             a.in = a.out = p->K[fam];
             a.irs = a.ors = 1;
-            a.ics = a.ocs = M[c] + 1;
+            a.ics = a.ocs = M[kc] + 1;
             a.ibs = a.obs = plane;
-            a.nrows_in = M[c] + 1;
-            a.ncols = M[b] + 1;
+            a.nrows_in = M[kc] + 1;
+            a.ncols = M[kb] + 1;
             a.nbatch = I[fam];
             a.in_mode = IN_EVEN;
             a.out_r0 = 0;
-            a.out_nrows = M[c] + 1;
+            a.out_nrows = M[kc] + 1;
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            if ((rc = run_pass(a, p->fd[kc], p->tw[kc], false, false, st))) return rc;
             PassArgs b2{};
             b2.in = b2.out = p->K[fam];
-            b2.irs = b2.ors = M[c] + 1;
+            b2.irs = b2.ors = M[kc] + 1;
             b2.ics = b2.ocs = 1;
             b2.ibs = b2.obs = plane;
-            b2.nrows_in = M[b] + 1;
-            b2.ncols = M[c] + 1;
+            b2.nrows_in = M[kb] + 1;
+            b2.ncols = M[kc] + 1;
             b2.nbatch = I[fam];
             b2.in_mode = IN_EVEN;
             b2.out_r0 = 0;
-            b2.out_nrows = M[b] + 1;
+            b2.out_nrows = M[kb] + 1;
             b2.scale = 1.0;
-            if ((rc = run_pass(b2, p->fd[b], p->tw[b], false, false, st))) return rc;
+            if ((rc = run_pass(b2, p->fd[kb], p->tw[kb], false, false, st))) return rc;
         }
     }
     return IPS_OK;
@@ -459,8 +471,9 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     if (d == 3) {
         const int64_t s1 = n[2], s0 = n[1] * n[2];
         const double *rin = rho + s0 + s1 + 1;
+        const int64_t vxy = (int64_t)I[0] * I[1];
         {
-            // (1) zero-padded cos/sin transform of rho along z -> A[x][y][slot]
+            // (1) zero-padded cos/sin transform of rho along z -> A[slot_z][x][y]
             STAGE(IPS_STAGE_RHO_Z);
             PassArgs a{};
             a.in = rin;
@@ -468,9 +481,9 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.irs = 1;
             a.ics = s1;
             a.ibs = s0;
-            a.ors = 1;
-            a.ocs = N[2];
-            a.obs = (int64_t)I[1] * N[2];
+            a.ors = vxy;
+            a.ocs = 1;
+            a.obs = I[1];
             a.nrows_in = I[2];
             a.ncols = I[1];
             a.nbatch = I[0];
@@ -481,51 +494,55 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             if ((rc = run_pass(a, p->fd[2], p->tw[2], false, f32s, st))) return rc;
         }
         {
-            // (2) transform along y, sum over x-slices: faces x = 0, M0; S_y S_z part -> B
+            // (2) transform along y, sum over x-slices: faces x = 0, M0;
+            //     the S_y S_z part is B[kz][x][ky]
             STAGE(IPS_STAGE_CONV_X);
-            BcArgs a{};
+            CcArgs a{};
             a.in = p->A;
-            a.irs = N[2];
-            a.ibs = (int64_t)I[1] * N[2];
+            a.irs = 1;
+            a.ics = I[1];
+            a.ibs = vxy;
             a.nrows_in = I[1];
-            a.ncols = N[2];
-            a.Mc = M[2];
-            a.nbatch = I[0];
-            a.chunk = p->chunk[0];
+            a.ncols = I[0];
+            a.nbatch = N[2];
+            a.Mo = M[2];
+            a.cols_per_chunk = p->chunk[0];
             a.K = p->K[0];
-            a.Kd = (int64_t)(M[1] + 1) * (M[2] + 1);
-            a.Kp = M[2] + 1;
+            a.Kd = (int64_t)(M[2] + 1) * (M[1] + 1);
+            a.Ko = M[1] + 1;
             a.part = p->part[0];
             a.Bout = p->B;
             a.Bf32 = f32;
-            a.Bbs = (int64_t)I[1] * I[2];
-            a.Brs = I[2];
+            a.Bcs = I[1];
+            a.Brs = 1;
+            a.Bbs = vxy;
             a.W = tile_width(N[1], 2048, a.ncols);
             a.fd = p->fd[1];
             a.tw = p->tw[1];
-            IPS_HIP(launch_bc(a, p->nch[0], f32s, st));
+            IPS_HIP(launch_cc(a, p->nch[0], f32s, f32s, st));
         }
         {
             // (3) transform along x, sum over y-slices: faces y = 0, M1
             STAGE(IPS_STAGE_CONV_Y);
-            BcArgs a{};
+            CcArgs a{};
             a.in = p->A;
-            a.irs = (int64_t)I[1] * N[2];
-            a.ibs = N[2];
+            a.irs = I[1];
+            a.ics = 1;
+            a.ibs = vxy;
             a.nrows_in = I[0];
-            a.ncols = N[2];
-            a.Mc = M[2];
-            a.nbatch = I[1];
-            a.chunk = p->chunk[1];
+            a.ncols = I[1];
+            a.nbatch = N[2];
+            a.Mo = M[2];
+            a.cols_per_chunk = p->chunk[1];
             a.K = p->K[1];
-            a.Kd = (int64_t)(M[0] + 1) * (M[2] + 1);
-            a.Kp = M[2] + 1;
+            a.Kd = (int64_t)(M[2] + 1) * (M[0] + 1);
+            a.Ko = M[0] + 1;
             a.part = p->part[1];
             a.Bout = nullptr;
             a.W = tile_width(N[0], 2048, a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
-            IPS_HIP(launch_bc(a, p->nch[1], f32s, st));
+            IPS_HIP(launch_cc(a, p->nch[1], f32s, f32s, st));
         }
         {
             // (4) zero-padded transform of rho along y -> C[x][slot_y][z] (reuses A)
@@ -572,27 +589,18 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             IPS_HIP(launch_cc(a, p->nch[2], f32s, f32s, st));
         }
         STAGE(IPS_STAGE_FACES);
-        // (6) sum the chunk partials
+        // (6) sum the chunk partials: face spectra F[fam][face][slot_r][slot_c]
         for (int fam = 0; fam < 3; ++fam) {
             int64_t len = 2;
             for (int b = 0; b < 3; ++b)
                 if (b != fam) len *= N[b];
             IPS_HIP(launch_reduce(p->part[fam], p->F[fam], len, p->nch[fam], st));
         }
-        // (7) inverse transforms of the face spectra (in place)
+        // (7) inverse transforms of the face spectra (in place);
+        //     storage [face][row axis r][col axis c], c contiguous
+        const int fr[3] = {2, 2, 1}, fc[3] = {1, 0, 0};
         for (int fam = 0; fam < 3; ++fam) {
-            // storage [face][row axis r][col axis c] with c contiguous
-            int r, c;
-            if (fam == 0) {
-                r = 1;
-                c = 2;
-            } else if (fam == 1) {
-                r = 0;
-                c = 2;
-            } else {
-                r = 1;
-                c = 0;
-            }
+            const int r = fr[fam], c = fc[fam];
             const int64_t fstride = (int64_t)N[r] * N[c];
             PassArgs a{};
             a.in = a.out = p->F[fam];
@@ -621,23 +629,21 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             b.scale = 1.0 / N[r];
             if ((rc = run_pass(b, p->fd[r], p->tw[r], false, false, st))) return rc;
         }
-        // (8) boundary values into phi
+        // (8) boundary values into phi; F[fam][face][j_r][j_c] -> strides of the in-face
+        //     axes in increasing order
         BwriteArgs a{};
         a.geo = p->geo;
         for (int q = 0; q < 3; ++q) a.n[q] = n[q];
         for (int fam = 0; fam < 3; ++fam) {
             a.F[fam] = p->F[fam];
             a.scale[fam] = p->h[0] * p->h[1] * p->h[2];
+            const int r = fr[fam], c = fc[fam];
+            a.fs[fam][0] = (int64_t)N[r] * N[c];
+            // lower in-face axis first
+            const int lo = std::min(r, c);
+            a.fs[fam][1] = lo == c ? 1 : N[c];
+            a.fs[fam][2] = lo == c ? N[c] : 1;
         }
-        a.fs[0][0] = (int64_t)N[1] * N[2];
-        a.fs[0][1] = N[2];
-        a.fs[0][2] = 1;
-        a.fs[1][0] = (int64_t)N[0] * N[2];
-        a.fs[1][1] = N[2];
-        a.fs[1][2] = 1;
-        a.fs[2][0] = (int64_t)N[1] * N[0];
-        a.fs[2][1] = 1;
-        a.fs[2][2] = N[0];
         a.phi = phi;
         IPS_HIP(launch_bwrite(a, st));
     } else {
@@ -718,10 +724,18 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             if ((rc = shell_dst(p, p->G[fam], 2, fam, false, st))) return rc;
     }
     ShellSpec sh{};
+    PackArgs pk{};
+    pk.geo = p->geo;
     for (int fam = 0; fam < d; ++fam) {
         sh.G[fam] = p->G[fam];
         sh.D[fam] = p->D[fam];
+        sh.P[fam] = p->P[fam];
+        pk.G[fam] = p->G[fam];
+        pk.D[fam] = p->D[fam];
+        pk.P[fam] = p->P[fam];
     }
+    pk.withD = 0;
+    IPS_HIP(launch_pack(pk, st));
     if (p->order == 6) {
         STAGE(IPS_STAGE_SHELL_R6);
         {
@@ -751,6 +765,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         IPS_HIP(launch_dcorr(a, st));
         for (int fam = 0; fam < d; ++fam)
             if ((rc = shell_dst(p, p->D[fam], 4, fam, false, st))) return rc;
+        pk.withD = 1;
+        IPS_HIP(launch_pack(pk, st));
     }
     // ---- combination and inverse transforms ------------------------------------------
     {
@@ -758,17 +774,22 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         FinalArgs a{};
         a.buf = p->B;
         if (d == 3) {
-            a.irs = (int64_t)I[1] * I[2];
+            // B[kz][x][ky]: rows x, columns ky, batch kz
+            a.irs = I[1];
             a.ics = 1;
-            a.ibs = I[2];
-            a.ncols = I[2];
-            a.nbatch = I[1];
+            a.ibs = (int64_t)I[0] * I[1];
+            a.ncols = I[1];
+            a.nbatch = I[2];
+            a.cax = 1;
+            a.bax = 2;
         } else {
             a.irs = I[1];
             a.ics = 1;
             a.ibs = 0;
             a.ncols = I[1];
             a.nbatch = 1;
+            a.cax = 1;
+            a.bax = -1;
         }
         a.nrows_in = I[0];
         a.W = tile_width(N[0], 2048, a.ncols);
@@ -784,14 +805,15 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     if (d == 3) {
         {
             STAGE(IPS_STAGE_INV_Y);
+            // B[kz][x][ky] -> B[kz][x][y]
             PassArgs a{};
             a.in = a.out = p->B;
-            a.irs = a.ors = I[2];
-            a.ics = a.ocs = 1;
-            a.ibs = a.obs = (int64_t)I[1] * I[2];
+            a.irs = a.ors = 1;
+            a.ics = a.ocs = I[1];
+            a.ibs = a.obs = (int64_t)I[0] * I[1];
             a.nrows_in = I[1];
-            a.ncols = I[2];
-            a.nbatch = I[0];
+            a.ncols = I[0];
+            a.nbatch = I[2];
             a.in_mode = IN_SPECS;
             a.out_r0 = 1;
             a.out_nrows = I[1];
@@ -799,12 +821,13 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             if ((rc = run_pass(a, p->fd[1], p->tw[1], f32, f32, st))) return rc;
         }
         STAGE(IPS_STAGE_INV_Z);
+        // B[kz][x][y] -> phi[x][y][z]
         PassArgs b{};
         b.in = p->B;
         b.out = phi + n[1] * n[2] + n[2] + 1;
-        b.irs = 1;
-        b.ics = I[2];
-        b.ibs = (int64_t)I[1] * I[2];
+        b.irs = (int64_t)I[0] * I[1];
+        b.ics = 1;
+        b.ibs = I[1];
         b.ors = 1;
         b.ocs = n[2];
         b.obs = n[1] * n[2];
