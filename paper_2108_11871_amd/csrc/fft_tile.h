@@ -400,6 +400,40 @@ __device__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, in
     }
 }
 
+// As tile_load (columns contiguous or generic), but every element is the sum
+// of nsum copies spaced sstride apart (summing partial results on the fly).
+template <typename T, typename TI, int NT>
+__device__ void tile_load_sum(T *buf, int rs, int row0, const TI *src, int nrows, int ncols,
+                              int64_t rsd, int64_t csd, int lgW, int nsum, int64_t sstride)
+{
+    const int W = 1 << lgW;
+    if (rsd == 1 && csd != 1) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int c = wave; c < W; c += NT / 64) {
+            for (int r = lane; r < nrows; r += 64) {
+                T v = (T)0;
+                if (c < ncols) {
+                    const TI *q = src + c * csd + r;
+                    for (int k = 0; k < nsum; ++k) v += (T)q[k * sstride];
+                }
+                buf[(row0 + r) * rs + c] = v;
+            }
+        }
+        return;
+    }
+    const int cm = W - 1;
+    const int tot = nrows << lgW;
+    for (int e = threadIdx.x; e < tot; e += NT) {
+        const int c = e & cm, r = e >> lgW;
+        T v = (T)0;
+        if (c < ncols) {
+            const TI *q = src + r * rsd + c * csd;
+            for (int k = 0; k < nsum; ++k) v += (T)q[k * sstride];
+        }
+        buf[(row0 + r) * rs + c] = v;
+    }
+}
+
 // LDS -> global: LDS rows row0..row0+nrows-1, cols [0, ncols) go to
 // dst[r*rsd + c*csd] scaled by `scale`.
 template <typename T, typename TO, int NT>

@@ -26,6 +26,8 @@ struct PassArgs {
     int W; // columns per block (even)
     FftDesc fd;
     const cx<double> *tw; // N twiddles exp(-2 pi i t / N)
+    int nsum;             // IN_HERM: input element = sum of nsum copies (0/1: plain load)
+    int64_t sstride;      // spacing of those copies
 };
 
 // Boundary convolution, contraction over the tile columns (faces normal to
@@ -40,7 +42,7 @@ struct CcArgs {
     int cols_per_chunk;
     const double *K;   // K[d][k_o][k_p], k_p contiguous
     int64_t Kd, Ko;
-    double *part;      // [nchunk][2][nbatch][2 M_p]
+    double *part;      // [2][nchunk][nbatch][2 M_p]
     void *Bout;        // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + (k_o-1)*Bbs],
                        // written for the sine slots k_o of the batch axis (all batches if Mo == 0)
     int64_t Bcs, Brs, Bbs;

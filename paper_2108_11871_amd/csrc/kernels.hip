@@ -66,7 +66,11 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a)
         __syncthreads();
         pre_even<T, NT>(buf, rs, lgW, M);
     } else if (a.in_mode == IN_HERM) {
-        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        if (a.nsum > 1)
+            tile_load_sum<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW, a.nsum,
+                                     a.sstride);
+        else
+            tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
         pre_herm<T, MAXE, NT>(buf, rs, lgs, M, false);
         inv = true;
@@ -197,8 +201,9 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
         }
         __syncthreads();
     }
-    double *p0 = a.part + ((int64_t)(2 * ch) * a.nbatch + bt) * N;
-    double *p1 = p0 + (int64_t)a.nbatch * N;
+    // partials [face][chunk][batch][slot]
+    double *p0 = a.part + ((int64_t)ch * a.nbatch + bt) * N;
+    double *p1 = p0 + (int64_t)nchunk * a.nbatch * N;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int row = threadIdx.x + i * NT;
@@ -795,33 +800,28 @@ __global__ void k_dcorr(DcorrArgs a)
             }
             double out = 0.0;
             if (owned) {
-                // per-axis extrapolation stencils
-                int pos[3][4];
-                double wt[3][4];
-                int cnt[3] = {1, 1, 1};
+                // per-axis cubic extrapolation: index 1 <- 4,-6,4,-1 times 2..5
+                // (and mirrored at M-1); other indices map to themselves
+                int cnt[3], sg[3];
                 for (int b = 0; b < 3; ++b) {
-                    pos[b][0] = b < d ? i[b] : 0;
-                    wt[b][0] = 1.0;
-                }
-                for (int b = 0; b < d; ++b) {
-                    const int m = g.M[b];
-                    if (i[b] == 1 || i[b] == m - 1) {
-                        const int sgn = i[b] == 1 ? 1 : -1;
-                        const double w4[4] = {4.0, -6.0, 4.0, -1.0};
-                        for (int t = 0; t < 4; ++t) {
-                            pos[b][t] = i[b] + sgn * (t + 1);
-                            wt[b][t] = w4[t];
-                        }
-                        cnt[b] = 4;
-                    }
+                    const bool ex = b < d && (i[b] == 1 || i[b] == g.M[b] - 1);
+                    cnt[b] = ex ? 4 : 1;
+                    sg[b] = ex ? (i[b] == 1 ? 1 : -1) : 0;
                 }
                 double R = 0.0;
-                for (int t0 = 0; t0 < cnt[0]; ++t0)
-                    for (int t1 = 0; t1 < cnt[1]; ++t1)
+                for (int t0 = 0; t0 < cnt[0]; ++t0) {
+                    const double w0 = cnt[0] == 1 ? 1.0 : (t0 == 1 ? -6.0 : (t0 == 3 ? -1.0 : 4.0));
+                    for (int t1 = 0; t1 < cnt[1]; ++t1) {
+                        const double w1 = cnt[1] == 1 ? 1.0 : (t1 == 1 ? -6.0 : (t1 == 3 ? -1.0 : 4.0));
                         for (int t2 = 0; t2 < cnt[2]; ++t2) {
-                            const int p[3] = {pos[0][t0], pos[1][t1], pos[2][t2]};
-                            R += wt[0][t0] * wt[1][t1] * wt[2][t2] * rcore(a, p);
+                            const double w2 =
+                                cnt[2] == 1 ? 1.0 : (t2 == 1 ? -6.0 : (t2 == 3 ? -1.0 : 4.0));
+                            const int p[3] = {i[0] + sg[0] * (t0 + 1), i[1] + sg[1] * (t1 + 1),
+                                              d == 3 ? i[2] + sg[2] * (t2 + 1) : 0};
+                            R += w0 * w1 * w2 * rcore(a, p);
                         }
+                    }
+                }
                 out = R - rs_lookup(a, i);
             }
             a.D[fam][e] = out;
@@ -873,44 +873,76 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
     __syncthreads();
     fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, false);
     post_cs<T, MAXE, NT>(buf, rs, lgs, M);
+    // Row (axis 0) and column (axis 1) invariants staged in LDS:
+    //   [lam, q, s1, s2, packed shell values of the family whose other index
+    //    is fixed along the row/column, for both parities of the crossing axis]
     const Geo &geo = a.geo;
     const int d = geo.d;
     const int tot = (M - 1) << lgW;
     const bool six = a.order == 6;
-    int64_t ss[3] = {1, 1, 1};
-    int Ii[3] = {1, 1, 1};
-    for (int f = 0; f < d; ++f) {
-        ss[f] = shell_size(geo, f);
-        Ii[f] = geo.M[f] - 1;
+    const int nt = six ? 3 : 1;
+    constexpr int SV = 10;
+    double *rv = reinterpret_cast<double *>(buf + (size_t)N * rs);
+    rv = reinterpret_cast<double *>(((uintptr_t)rv + 7) & ~(uintptr_t)7);
+    double *cv = rv + (size_t)(M - 1) * SV;
+    const int I0 = geo.M[0] - 1, I1 = geo.M[1] - 1, I2 = d == 3 ? geo.M[2] - 1 : 1;
+    const int kB = bt + 1;
+    const int64_t ss0 = shell_size(geo, 0), ss1 = shell_size(geo, 1);
+    for (int i = threadIdx.x; i < I0; i += NT) {
+        double *r = rv + i * SV;
+        r[0] = a.tab[0].lam[i];
+        r[1] = a.tab[0].q[i];
+        r[2] = a.tab[0].s[i];
+        r[3] = a.tab[0].s[I0 + i];
+        // family 1: other index (k0, k2) in 3D, (k0) in 2D
+        const int64_t o = d == 3 ? (int64_t)i * I2 + (kB - 1) : i;
+        for (int par = 0; par < 2; ++par)
+            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = a.sh.P[1][(par * 3 + t) * ss1 + o];
     }
+    for (int i = threadIdx.x; i < nc; i += NT) {
+        double *r = cv + i * SV;
+        const int j = c0 + i; // k1 - 1
+        r[0] = a.tab[1].lam[j];
+        r[1] = a.tab[1].q[j];
+        r[2] = a.tab[1].s[j];
+        r[3] = a.tab[1].s[I1 + j];
+        // family 0: other index (k1, k2) in 3D, (k1) in 2D
+        const int64_t o = d == 3 ? (int64_t)j * I2 + (kB - 1) : j;
+        for (int par = 0; par < 2; ++par)
+            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = a.sh.P[0][(par * 3 + t) * ss0 + o];
+    }
+    // batch (axis 2) constants and the per-element family 2
+    double lamB = 0.0, qB = 0.0, s1B = 0.0, s2B = 0.0;
+    const double *Pz = nullptr;
+    int64_t ss2 = 0;
+    if (d == 3) {
+        lamB = a.tab[2].lam[kB - 1];
+        qB = a.tab[2].q[kB - 1];
+        s1B = a.tab[2].s[kB - 1];
+        s2B = a.tab[2].s[I2 + kB - 1];
+        ss2 = shell_size(geo, 2);
+        Pz = a.sh.P[2] + ((kB & 1) ? 3 * ss2 : 0);
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < tot; e += NT) {
         const int c = e & (W - 1), kx = 1 + (e >> lgW);
         double cval = 0.0;
         if (c < nc) {
-            int k[3] = {kx, 1, 1};
-            k[a.cax] = 1 + c0 + c;
-            if (a.bax >= 0) k[a.bax] = 1 + bt;
+            const int ky = 1 + c0 + c;
+            const double *r = rv + (kx - 1) * SV;
+            const double *q1 = cv + c * SV;
             const double beta = (double)buf[(M + kx) * rs + c];
-            // shell index of each family: the other axes, later axis fastest
-            int64_t o[3];
+            const double *Pr = r + 4 + ((ky & 1) ? 3 : 0);  // family 1 at (kx, kz)
+            const double *Pc = q1 + 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz)
+            double lam[3] = {r[0], q1[0], lamB};
+            double q = r[1] + q1[1] + qB;
+            double gt = r[2] * Pc[0] + q1[2] * Pr[0];
+            double dh = 0.0;
+            if (six) dh = r[2] * Pc[1] + r[3] * Pc[2] + q1[2] * Pr[1] + q1[3] * Pr[2];
             if (d == 3) {
-                o[0] = (int64_t)(k[1] - 1) * Ii[2] + (k[2] - 1);
-                o[1] = (int64_t)(k[0] - 1) * Ii[2] + (k[2] - 1);
-                o[2] = (int64_t)(k[0] - 1) * Ii[1] + (k[1] - 1);
-            } else {
-                o[0] = k[1] - 1;
-                o[1] = k[0] - 1;
-                o[2] = 0;
-            }
-            double lam[3], q = 0.0, gt = 0.0, dh = 0.0;
-            for (int f = 0; f < d; ++f) {
-                const int kf = k[f] - 1;
-                lam[f] = a.tab[f].lam[kf];
-                q += a.tab[f].q[kf];
-                const double s1 = a.tab[f].s[kf];
-                const double *P = a.sh.P[f] + ((k[f] & 1) ? 3 * ss[f] : 0) + o[f];
-                gt += s1 * P[0];
-                if (six) dh += s1 * P[ss[f]] + a.tab[f].s[Ii[f] + kf] * P[2 * ss[f]];
+                const double *Pe = Pz + (int64_t)(kx - 1) * I1 + (ky - 1);
+                gt += s1B * Pe[0];
+                if (six) dh += s1B * Pe[ss2] + s2B * Pe[2 * ss2];
             }
             double Lm, Rm;
             lam_symbols(geo, lam, Lm, Rm);
@@ -929,7 +961,8 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
 template <typename T, int MAXE, bool P2>
 static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
 {
-    const size_t lds = tile_lds<T>(a.fd.N, a.W);
+    // tile + staged row (M0-1 rows) and column (W) invariants, 10 doubles each
+    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)(a.fd.M - 1 + a.W) * 10 * sizeof(double);
     set_lds((const void *)&k_final<T, MAXE, P2>, lds);
     hipLaunchKernelGGL((k_final<T, MAXE, P2>), dim3(nblk), dim3(NT), lds, st, a);
 }

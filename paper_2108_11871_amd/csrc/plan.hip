@@ -163,6 +163,7 @@ struct ips_plan_s {
     double *T[3] = {nullptr, nullptr, nullptr};
     double *D[3] = {nullptr, nullptr, nullptr};
     double *P[3] = {nullptr, nullptr, nullptr}; // parity-packed shell spectra
+    bool cube = false; // all families share sizes and chunking (batched launches)
     double *V = nullptr; // 2D: sine coefficients of the sixth-order right-hand side
     DevBuf mem;
     // stage timing
@@ -195,6 +196,14 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
     }
     if (d == 1 && precision != IPS_FP64)
         return fail(IPS_E_UNSUPPORTED, "d = 1 runs in FP64 only");
+    if (d >= 2) {
+        // LDS of the final pass along axis 0: tile + twiddles + staged row/column tables
+        const int N0 = 2 * (int)(n[0] - 1);
+        const int W = tile_width(N0, 2048, (int)(n[1] - 2));
+        const size_t lds = (size_t)N0 * 16 + (size_t)N0 * (W + 1) * 8 + 8 + (size_t)(n[0] - 2 + W) * 80;
+        if (lds > 160 * 1024)
+            return fail(IPS_E_UNSUPPORTED, "n[0] too large for the final pass of this build");
+    }
     return IPS_OK;
 }
 
@@ -277,6 +286,18 @@ int shell_dst(ips_plan p, double *buf, int nl, int fam, bool inverse, hipStream_
     return rc;
 }
 
+// Shell layer transforms of all families: one launch per direction when the
+// families are uniform (contiguous buffers of identical shape).
+int shell_dst_all(ips_plan p, double *const *arr, int nl, bool inverse, hipStream_t st)
+{
+    if (p->cube) return shell_dst(p, arr[0], nl * p->d, 0, inverse, st);
+    for (int fam = 0; fam < p->d; ++fam) {
+        int rc = shell_dst(p, arr[fam], nl, fam, inverse, st);
+        if (rc) return rc;
+    }
+    return IPS_OK;
+}
+
 int plan_build(ips_plan p, hipStream_t st)
 {
     const int d = p->d;
@@ -330,40 +351,66 @@ int plan_build(ips_plan p, hipStream_t st)
         rc = p->mem.alloc((void **)&p->V, vol * sizeof(double));
         if (rc) return rc;
     }
+    // per-family sizes, then one contiguous buffer per kind (families back to back)
+    size_t fsz[3] = {0, 0, 0}, ssz[3] = {0, 0, 0};
     for (int fam = 0; fam < d; ++fam) {
-        size_t fsz = 2;
+        fsz[fam] = 2;
+        ssz[fam] = 1;
         for (int b = 0; b < d; ++b)
-            if (b != fam) fsz *= (size_t)N[b];
-        size_t ss = 1;
-        for (int b = 0; b < d; ++b)
-            if (b != fam) ss *= (size_t)I[b];
-        // chunking of the contraction over the face-normal axis (column-contraction kernel)
-        int nch;
-        {
-            int pen, nbatch;
-            if (d == 3) {
-                pen = fam == 0 ? 1 : 0;
-                nbatch = fam == 2 ? N[1] : N[2];
-            } else {
-                pen = 1 - fam;
-                nbatch = 1;
+            if (b != fam) {
+                fsz[fam] *= (size_t)N[b];
+                ssz[fam] *= (size_t)I[b];
             }
-            const int W = tile_width(N[pen], 2048, I[fam]);
-            const int ncb = (I[fam] + W - 1) / W;
-            nch = std::max(1, std::min(ncb, (2048 + nbatch - 1) / nbatch));
-            const int per = (ncb + nch - 1) / nch;
-            p->chunk[fam] = per * W;
-            nch = (I[fam] + per * W - 1) / (per * W);
+        // chunking of the contraction over the face-normal axis (column-contraction kernel)
+        int pen, nbatch;
+        if (d == 3) {
+            pen = fam == 0 ? 1 : 0;
+            nbatch = fam == 2 ? N[1] : N[2];
+        } else {
+            pen = 1 - fam;
+            nbatch = 1;
         }
-        p->nch[fam] = nch;
-        if ((rc = p->mem.alloc((void **)&p->part[fam], fsz * nch * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&p->F[fam], fsz * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&p->G[fam], 2 * ss * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&p->P[fam], 6 * ss * sizeof(double)))) return rc;
+        const int W = tile_width(N[pen], 2048, I[fam]);
+        const int ncb = (I[fam] + W - 1) / W;
+        int nch = std::max(1, std::min(ncb, (2048 + nbatch - 1) / nbatch));
+        const int per = (ncb + nch - 1) / nch;
+        p->chunk[fam] = per * W;
+        p->nch[fam] = (I[fam] + per * W - 1) / (per * W);
+    }
+    {
+        size_t tp = 0, tf = 0, ts = 0;
+        for (int fam = 0; fam < d; ++fam) {
+            tp += fsz[fam] * p->nch[fam];
+            tf += fsz[fam];
+            ts += ssz[fam];
+        }
+        double *bp, *bf, *bg, *bpk, *bt = nullptr, *bd = nullptr;
+        if ((rc = p->mem.alloc((void **)&bp, tp * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&bf, tf * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&bg, 2 * ts * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&bpk, 6 * ts * sizeof(double)))) return rc;
         if (p->order == 6) {
-            if ((rc = p->mem.alloc((void **)&p->T[fam], 10 * ss * sizeof(double)))) return rc;
-            if ((rc = p->mem.alloc((void **)&p->D[fam], 4 * ss * sizeof(double)))) return rc;
+            if ((rc = p->mem.alloc((void **)&bt, 10 * ts * sizeof(double)))) return rc;
+            if ((rc = p->mem.alloc((void **)&bd, 4 * ts * sizeof(double)))) return rc;
         }
+        size_t op = 0, of = 0, os = 0;
+        for (int fam = 0; fam < d; ++fam) {
+            p->part[fam] = bp + op;
+            p->F[fam] = bf + of;
+            p->G[fam] = bg + 2 * os;
+            p->P[fam] = bpk + 6 * os;
+            if (bt) p->T[fam] = bt + 10 * os;
+            if (bd) p->D[fam] = bd + 4 * os;
+            op += fsz[fam] * p->nch[fam];
+            of += fsz[fam];
+            os += ssz[fam];
+        }
+    }
+    // uniform families: one launch covers the three (two in 2D) families
+    p->cube = true;
+    for (int fam = 1; fam < d; ++fam)
+        if (M[fam] != M[0] || p->nch[fam] != p->nch[0]) p->cube = false;
+    for (int fam = 0; fam < d; ++fam) {
         // kernel spectra: samples then even transforms along the in-face axes
         size_t ksz = (size_t)I[fam];
         for (int b = 0; b < d; ++b)
@@ -589,27 +636,26 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             IPS_HIP(launch_cc(a, p->nch[2], f32s, f32s, st));
         }
         STAGE(IPS_STAGE_FACES);
-        // (6) sum the chunk partials: face spectra F[fam][face][slot_r][slot_c]
-        for (int fam = 0; fam < 3; ++fam) {
-            int64_t len = 2;
-            for (int b = 0; b < 3; ++b)
-                if (b != fam) len *= N[b];
-            IPS_HIP(launch_reduce(p->part[fam], p->F[fam], len, p->nch[fam], st));
-        }
-        // (7) inverse transforms of the face spectra (in place);
-        //     storage [face][row axis r][col axis c], c contiguous
+        // (6) face spectra: sum of the chunk partials, inverse transform along the
+        //     contiguous slot axis c, then along r; F[fam][face][slot_r][slot_c]
         const int fr[3] = {2, 2, 1}, fc[3] = {1, 0, 0};
         for (int fam = 0; fam < 3; ++fam) {
+            if (p->cube && fam > 0) break;
+            const int nfam = p->cube ? 3 : 1;
             const int r = fr[fam], c = fc[fam];
-            const int64_t fstride = (int64_t)N[r] * N[c];
+            const int64_t plane = (int64_t)N[r] * N[c];
             PassArgs a{};
-            a.in = a.out = p->F[fam];
+            a.in = p->part[fam];
+            a.out = p->F[fam];
             a.irs = a.ors = 1;
             a.ics = a.ocs = N[c];
-            a.ibs = a.obs = fstride;
+            a.ibs = (int64_t)p->nch[fam] * plane;
+            a.obs = plane;
+            a.nsum = p->nch[fam];
+            a.sstride = plane;
             a.nrows_in = N[c];
             a.ncols = N[r];
-            a.nbatch = 2;
+            a.nbatch = 2 * nfam;
             a.in_mode = IN_HERM;
             a.out_r0 = 0;
             a.out_nrows = M[c] + 1;
@@ -619,10 +665,10 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             b.in = b.out = p->F[fam];
             b.irs = b.ors = N[c];
             b.ics = b.ocs = 1;
-            b.ibs = b.obs = fstride;
+            b.ibs = b.obs = plane;
             b.nrows_in = N[r];
             b.ncols = M[c] + 1;
-            b.nbatch = 2;
+            b.nbatch = 2 * nfam;
             b.in_mode = IN_HERM;
             b.out_r0 = 0;
             b.out_nrows = M[r] + 1;
@@ -681,15 +727,20 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         }
         STAGE(IPS_STAGE_FACES);
         for (int fam = 0; fam < 2; ++fam) {
+            if (p->cube && fam > 0) break;
+            const int nfam = p->cube ? 2 : 1;
             const int pen = 1 - fam;
-            IPS_HIP(launch_reduce(p->part[fam], p->F[fam], 2 * (int64_t)N[pen], p->nch[fam], st));
             PassArgs a{};
-            a.in = a.out = p->F[fam];
+            a.in = p->part[fam];
+            a.out = p->F[fam];
             a.irs = a.ors = 1;
-            a.ics = a.ocs = N[pen];
+            a.ics = (int64_t)p->nch[fam] * N[pen];
+            a.ocs = N[pen];
             a.ibs = a.obs = 0;
+            a.nsum = p->nch[fam];
+            a.sstride = N[pen];
             a.nrows_in = N[pen];
-            a.ncols = 2;
+            a.ncols = 2 * nfam;
             a.nbatch = 1;
             a.in_mode = IN_HERM;
             a.out_r0 = 0;
@@ -720,8 +771,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         a.phi = phi;
         for (int fam = 0; fam < d; ++fam) a.G[fam] = p->G[fam];
         IPS_HIP(launch_gtilde(a, st));
-        for (int fam = 0; fam < d; ++fam)
-            if ((rc = shell_dst(p, p->G[fam], 2, fam, false, st))) return rc;
+        if ((rc = shell_dst_all(p, p->G, 2, false, st))) return rc;
     }
     ShellSpec sh{};
     PackArgs pk{};
@@ -752,8 +802,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
                 IPS_HIP(launch_h2c(a, st));
             }
         }
-        for (int fam = 0; fam < d; ++fam)
-            if ((rc = shell_dst(p, p->T[fam], 10, fam, true, st))) return rc;
+        if ((rc = shell_dst_all(p, p->T, 10, true, st))) return rc;
         DcorrArgs a{};
         a.geo = p->geo;
         for (int q = 0; q < 3; ++q) a.n[q] = q < d ? n[q] : 1;
@@ -763,8 +812,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.D[fam] = p->D[fam];
         }
         IPS_HIP(launch_dcorr(a, st));
-        for (int fam = 0; fam < d; ++fam)
-            if ((rc = shell_dst(p, p->D[fam], 4, fam, false, st))) return rc;
+        if ((rc = shell_dst_all(p, p->D, 4, false, st))) return rc;
         pk.withD = 1;
         IPS_HIP(launch_pack(pk, st));
     }
