@@ -77,14 +77,17 @@ def stage_bytes(n: int, mode: str, nch: dict) -> dict:
     }
 
 
-def nchunks(n: int) -> dict:
+def nchunks(n: int, mode: str) -> dict:
     """Chunk counts of the column-contraction kernels (mirrors the plan's choice)."""
     M = n - 1
     I, N = M - 1, 2 * M
+    work = int(os.environ.get("IPS_TILE_WORK", "2048"))
+    if work not in (1024, 2048, 4096):
+        work = 2048
 
     def tw(NN, ncols):
         nseq = 1
-        while 2 * nseq * NN <= 2048:
+        while 2 * nseq * NN <= work:
             nseq *= 2
         need = 2
         while need < ncols:
@@ -217,7 +220,7 @@ def main():
     ok = [m for m in modes if m == "fp64" or (res[m]["err"] is not None and res[m]["err"] <= 1e-6)]
     best = min(ok, key=lambda m: res[m]["ms"])
     r = res[best]
-    nch = nchunks(n)
+    nch = nchunks(n, best)
     byts = stage_bytes(n, best, nch)
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in r["stages"].items() if v[1] > 0}
     dom = max((k for k in stage_ms if k in byts), key=lambda k: stage_ms[k])

@@ -80,6 +80,9 @@ struct ShellSpec {
     //   t = 1: D_1 + sg D_{M-1}        (multiplies sin(pi k_a / M_a))
     //   t = 2: D_2 + sg D_{M-2}        (multiplies sin(2 pi k_a / M_a))
     const double *P[3];
+    // 3D: family 1 packed values transposed to [par][t][k2][k0] (k0 contiguous),
+    // for the final pass which walks k0 at fixed k2
+    const double *P1T;
 };
 
 struct PackArgs {
@@ -87,7 +90,8 @@ struct PackArgs {
     const double *G[3];
     const double *D[3];
     double *P[3];
-    int withD; // also pack the deferred-correction layers
+    double *P1T; // 3D only
+    int withD;   // also pack the deferred-correction layers
 };
 
 struct FinalArgs {

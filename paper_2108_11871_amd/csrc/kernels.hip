@@ -113,6 +113,11 @@ static hipError_t launch_pass_t(const PassArgs &a, hipStream_t st)
             launch_pass_k<T, TI, TO, 8, true>(a, nblk, lds, st);
         else
             launch_pass_k<T, TI, TO, 8, false>(a, nblk, lds, st);
+    } else if (work <= 16 * NT) {
+        if (p2)
+            launch_pass_k<T, TI, TO, 16, true>(a, nblk, lds, st);
+        else
+            launch_pass_k<T, TI, TO, 16, false>(a, nblk, lds, st);
     } else {
         return hipErrorInvalidValue;
     }
@@ -214,35 +219,47 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
     }
 }
 
+template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT>
+static void launch_cc_k(const CcArgs &a, int nchunk, hipStream_t st)
+{
+    const size_t lds = tile_lds<T>(a.fd.N, a.W);
+    set_lds((const void *)&k_cc<T, TI, MAXE, WB, P2, RPT>, lds);
+    hipLaunchKernelGGL((k_cc<T, TI, MAXE, WB, P2, RPT>), dim3(nchunk * a.nbatch), dim3(NT), lds, st,
+                       a, nchunk);
+}
+
+template <typename T, typename TI, int MAXE, bool WB>
+static void launch_cc_m(const CcArgs &a, int nchunk, hipStream_t st)
+{
+    const bool p2 = is_pow2(a.fd.N);
+    if (a.fd.N <= 2 * NT) {
+        if (p2)
+            launch_cc_k<T, TI, MAXE, WB, true, 2>(a, nchunk, st);
+        else
+            launch_cc_k<T, TI, MAXE, WB, false, 2>(a, nchunk, st);
+    } else {
+        if (p2)
+            launch_cc_k<T, TI, MAXE, WB, true, 8>(a, nchunk, st);
+        else
+            launch_cc_k<T, TI, MAXE, WB, false, 8>(a, nchunk, st);
+    }
+}
+
 template <typename T, typename TI, bool WB>
 static hipError_t launch_cc_t(const CcArgs &a, int nchunk, hipStream_t st)
 {
-    const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    const dim3 grid(nchunk * a.nbatch);
-    if (a.fd.N <= 2 * NT) {
-        if (is_pow2(a.fd.N)) {
-            set_lds((const void *)&k_cc<T, TI, 8, WB, true, 2>, lds);
-            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, true, 2>), grid, dim3(NT), lds, st, a, nchunk);
-        } else {
-            set_lds((const void *)&k_cc<T, TI, 8, WB, false, 2>, lds);
-            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, false, 2>), grid, dim3(NT), lds, st, a, nchunk);
-        }
-    } else {
-        if (is_pow2(a.fd.N)) {
-            set_lds((const void *)&k_cc<T, TI, 8, WB, true, 8>, lds);
-            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, true, 8>), grid, dim3(NT), lds, st, a, nchunk);
-        } else {
-            set_lds((const void *)&k_cc<T, TI, 8, WB, false, 8>, lds);
-            hipLaunchKernelGGL((k_cc<T, TI, 8, WB, false, 8>), grid, dim3(NT), lds, st, a, nchunk);
-        }
-    }
+    const int work = (a.W / 2) * a.fd.N;
+    if (work <= 8 * NT)
+        launch_cc_m<T, TI, 8, WB>(a, nchunk, st);
+    else
+        launch_cc_m<T, TI, 16, WB>(a, nchunk, st);
     return hipGetLastError();
 }
 
 hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st)
 {
     const int work = (a.W / 2) * a.fd.N;
-    if (work > 8 * NT || a.fd.N > 8 * NT) return hipErrorInvalidValue;
+    if (work > 16 * NT || a.fd.N > 8 * NT) return hipErrorInvalidValue;
     const bool wb = a.Bout != nullptr;
     if (!f32) {
         if (in_f32) return hipErrorInvalidValue;
@@ -519,15 +536,26 @@ __global__ void k_pack(PackArgs a)
             const double *G = a.G[fam];
             double *P = a.P[fam];
             const double g0 = G[e], g1 = G[ss + e];
-            P[e] = g0 - g1;              // par 0 (even k), t 0
-            P[3 * ss + e] = g0 + g1;     // par 1 (odd k), t 0
+            double v[6];
+            v[0] = g0 - g1; // par 0 (even k), t 0
+            v[3] = g0 + g1; // par 1 (odd k), t 0
             if (a.withD) {
                 const double *D = a.D[fam];
                 const double d1 = D[e], d2 = D[ss + e], d3 = D[2 * ss + e], d4 = D[3 * ss + e];
-                P[ss + e] = d1 - d4;
-                P[2 * ss + e] = d2 - d3;
-                P[4 * ss + e] = d1 + d4;
-                P[5 * ss + e] = d2 + d3;
+                v[1] = d1 - d4;
+                v[2] = d2 - d3;
+                v[4] = d1 + d4;
+                v[5] = d2 + d3;
+            }
+            const int nt = a.withD ? 6 : 1;
+            for (int t = 0; t < 6; ++t)
+                if (t % 3 < nt) P[t * ss + e] = v[t];
+            if (fam == 1 && g.d == 3 && a.P1T) {
+                // e = (k0-1) * I2 + (k2-1)  ->  (k2-1) * I0 + (k0-1)
+                const int I0 = g.M[0] - 1, I2 = g.M[2] - 1;
+                const int64_t et = (e % I2) * I0 + e / I2;
+                for (int t = 0; t < 6; ++t)
+                    if (t % 3 < nt) a.P1T[t * ss + et] = v[t];
             }
             return;
         }
@@ -578,8 +606,9 @@ __global__ __launch_bounds__(NT) void k_h2v(H2Args a)
     const int IL = g.M[L] - 1;
     int64_t rows = 1;
     for (int b = 0; b < L; ++b) rows *= g.M[b] - 1;
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    constexpr int LPR = 16; // lanes per row
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t row = (int64_t)blockIdx.x * (NT / LPR) + (threadIdx.x / LPR);
     if (row >= rows) return;
     int k[3] = {1, 1, 1};
     {
@@ -615,7 +644,7 @@ __global__ __launch_bounds__(NT) void k_h2v(H2Args a)
     const double *lamL = a.tab[L].lam;
     double ev[5] = {0, 0, 0, 0, 0}, od[5] = {0, 0, 0, 0, 0};
     double *Vrow = a.V + row * IL;
-    for (int kL = 1 + lane; kL <= IL; kL += 64) {
+    for (int kL = 1 + lane; kL <= IL; kL += LPR) {
         lam[L] = lamL[kL - 1];
         double Lm, Rm;
         lam_symbols(g, lam, Lm, Rm);
@@ -634,7 +663,7 @@ __global__ __launch_bounds__(NT) void k_h2v(H2Args a)
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
+        for (int m = LPR / 2; m >= 1; m >>= 1) {
             od[j] += __shfl_xor(od[j], m);
             ev[j] += __shfl_xor(ev[j], m);
         }
@@ -652,7 +681,7 @@ hipError_t launch_h2v(const H2Args &a, hipStream_t st)
 {
     int64_t rows = 1;
     for (int b = 0; b < a.geo.d - 1; ++b) rows *= a.geo.M[b] - 1;
-    const int64_t nb = (rows + NT / 64 - 1) / (NT / 64);
+    const int64_t nb = (rows + NT / 16 - 1) / (NT / 16);
     hipLaunchKernelGGL(k_h2v, dim3((unsigned)nb), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
@@ -862,7 +891,22 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
     T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
     const int ncb = (a.ncols + W - 1) / W;
     const int lb = xcd_remap(blockIdx.x, ncb * a.nbatch);
-    const int cb = lb % ncb, bt = lb / ncb;
+    // logical order: pairs of neighbouring column blocks, then the batch, then
+    // the pair index -- each XCD sweeps all batches over a narrow band of
+    // columns, so the per-element shell data of that band stays in its L2
+    int cb, bt;
+    {
+        const int pairs = ncb / 2;
+        if (lb < 2 * pairs * a.nbatch) {
+            const int pr = lb / (2 * a.nbatch), rem = lb % (2 * a.nbatch);
+            bt = rem >> 1;
+            cb = 2 * pr + (rem & 1);
+        } else {
+            const int rem = lb - 2 * pairs * a.nbatch; // odd ncb: last column block
+            bt = rem;
+            cb = ncb - 1;
+        }
+    }
     const int c0 = cb * W;
     const int nc = min(W, a.ncols - c0);
     T *g = static_cast<T *>(a.buf) + bt * a.ibs + c0 * a.ics;
@@ -882,8 +926,10 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
     const bool six = a.order == 6;
     const int nt = six ? 3 : 1;
     constexpr int SV = 10;
-    double *rv = reinterpret_cast<double *>(buf + (size_t)N * rs);
-    rv = reinterpret_cast<double *>(((uintptr_t)rv + 7) & ~(uintptr_t)7);
+    // staging area after the tile, 8-byte aligned, addressed from smem so that
+    // it stays in the LDS address space
+    const size_t soff = ((size_t)N * sizeof(cx<T>) + (size_t)N * rs * sizeof(T) + 7) & ~(size_t)7;
+    double *rv = reinterpret_cast<double *>(smem + soff);
     double *cv = rv + (size_t)(M - 1) * SV;
     const int I0 = geo.M[0] - 1, I1 = geo.M[1] - 1, I2 = d == 3 ? geo.M[2] - 1 : 1;
     const int kB = bt + 1;
@@ -894,10 +940,11 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
         r[1] = a.tab[0].q[i];
         r[2] = a.tab[0].s[i];
         r[3] = a.tab[0].s[I0 + i];
-        // family 1: other index (k0, k2) in 3D, (k0) in 2D
-        const int64_t o = d == 3 ? (int64_t)i * I2 + (kB - 1) : i;
+        // family 1: other index (k0, k2) in 3D (transposed copy: k0 contiguous), (k0) in 2D
+        const double *P1 = d == 3 ? a.sh.P1T : a.sh.P[1];
+        const int64_t o = d == 3 ? (int64_t)(kB - 1) * I0 + i : i;
         for (int par = 0; par < 2; ++par)
-            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = a.sh.P[1][(par * 3 + t) * ss1 + o];
+            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = P1[(par * 3 + t) * ss1 + o];
     }
     for (int i = threadIdx.x; i < nc; i += NT) {
         double *r = cv + i * SV;
@@ -968,19 +1015,24 @@ static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
 }
 
 template <typename T>
-static void launch_final_t(const FinalArgs &a, int nblk, bool small, hipStream_t st)
+static void launch_final_t(const FinalArgs &a, int nblk, int work, hipStream_t st)
 {
     const bool p2 = is_pow2(a.fd.N);
-    if (small) {
+    if (work <= 4 * NT) {
         if (p2)
             launch_final_k<T, 4, true>(a, nblk, st);
         else
             launch_final_k<T, 4, false>(a, nblk, st);
-    } else {
+    } else if (work <= 8 * NT) {
         if (p2)
             launch_final_k<T, 8, true>(a, nblk, st);
         else
             launch_final_k<T, 8, false>(a, nblk, st);
+    } else {
+        if (p2)
+            launch_final_k<T, 16, true>(a, nblk, st);
+        else
+            launch_final_k<T, 16, false>(a, nblk, st);
     }
 }
 
@@ -989,11 +1041,11 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st)
     const int ncb = (a.ncols + a.W - 1) / a.W;
     const int nblk = ncb * a.nbatch;
     const int work = (a.W / 2) * a.fd.N;
-    if (work > 8 * NT) return hipErrorInvalidValue;
+    if (work > 16 * NT) return hipErrorInvalidValue;
     if (a.mixed)
-        launch_final_t<float>(a, nblk, work <= 4 * NT, st);
+        launch_final_t<float>(a, nblk, work, st);
     else
-        launch_final_t<double>(a, nblk, work <= 4 * NT, st);
+        launch_final_t<double>(a, nblk, work, st);
     return hipGetLastError();
 }
 

@@ -105,6 +105,20 @@ struct DevBuf {
     }
 };
 
+// Tile budget in complex elements per block (nseq * N), 2048 by default;
+// IPS_TILE_WORK (1024, 2048 or 4096) overrides it.
+int tile_work(bool f32)
+{
+    static const int base = [] {
+        const char *e = getenv("IPS_TILE_WORK");
+        int v = e ? atoi(e) : 2048;
+        if (v != 1024 && v != 2048 && v != 4096) v = 2048;
+        return v;
+    }();
+    (void)f32; // FP32 tiles use the same column count (wider tiles measured slower)
+    return base;
+}
+
 // Columns per tile: a power of two, 2 * nseq with nseq * N <= maxwork,
 // no wider than the columns present (rounded up to a power of two).
 int tile_width(int N, int maxwork, int ncols)
@@ -163,6 +177,7 @@ struct ips_plan_s {
     double *T[3] = {nullptr, nullptr, nullptr};
     double *D[3] = {nullptr, nullptr, nullptr};
     double *P[3] = {nullptr, nullptr, nullptr}; // parity-packed shell spectra
+    double *P1T = nullptr;                      // 3D: transposed family-1 copy
     bool cube = false; // all families share sizes and chunking (batched launches)
     double *V = nullptr; // 2D: sine coefficients of the sixth-order right-hand side
     DevBuf mem;
@@ -199,8 +214,10 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
     if (d >= 2) {
         // LDS of the final pass along axis 0: tile + twiddles + staged row/column tables
         const int N0 = 2 * (int)(n[0] - 1);
-        const int W = tile_width(N0, 2048, (int)(n[1] - 2));
-        const size_t lds = (size_t)N0 * 16 + (size_t)N0 * (W + 1) * 8 + 8 + (size_t)(n[0] - 2 + W) * 80;
+        const bool f32 = precision != IPS_FP64;
+        const size_t tsz = f32 ? 4 : 8;
+        const int W = tile_width(N0, tile_work(f32), (int)(n[1] - 2));
+        const size_t lds = (size_t)N0 * 2 * tsz + (size_t)N0 * (W + 1) * tsz + 8 + (size_t)(n[0] - 2 + W) * 80;
         if (lds > 160 * 1024)
             return fail(IPS_E_UNSUPPORTED, "n[0] too large for the final pass of this build");
     }
@@ -243,7 +260,7 @@ int run_pass(PassArgs a, const FftDesc &fd, const cx<double> *tw, bool in_f32, b
 {
     a.fd = fd;
     a.tw = tw;
-    if (a.W == 0) a.W = tile_width(fd.N, 2048, a.ncols);
+    if (a.W == 0) a.W = tile_width(fd.N, tile_work(in_f32 || out_f32), a.ncols);
     IPS_HIP(launch_pass(a, in_f32, out_f32, st));
     return IPS_OK;
 }
@@ -370,7 +387,7 @@ int plan_build(ips_plan p, hipStream_t st)
             pen = 1 - fam;
             nbatch = 1;
         }
-        const int W = tile_width(N[pen], 2048, I[fam]);
+        const int W = tile_width(N[pen], tile_work(p->precision == IPS_MIXED_FP32_SLICES), I[fam]);
         const int ncb = (I[fam] + W - 1) / W;
         int nch = std::max(1, std::min(ncb, (2048 + nbatch - 1) / nbatch));
         const int per = (ncb + nch - 1) / nch;
@@ -406,6 +423,7 @@ int plan_build(ips_plan p, hipStream_t st)
             os += ssz[fam];
         }
     }
+    if (d == 3 && (rc = p->mem.alloc((void **)&p->P1T, 6 * ssz[1] * sizeof(double)))) return rc;
     // uniform families: one launch covers the three (two in 2D) families
     p->cube = true;
     for (int fam = 1; fam < d; ++fam)
@@ -563,7 +581,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Bcs = I[1];
             a.Brs = 1;
             a.Bbs = vxy;
-            a.W = tile_width(N[1], 2048, a.ncols);
+            a.W = tile_width(N[1], tile_work(f32s), a.ncols);
             a.fd = p->fd[1];
             a.tw = p->tw[1];
             IPS_HIP(launch_cc(a, p->nch[0], f32s, f32s, st));
@@ -586,7 +604,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Ko = M[0] + 1;
             a.part = p->part[1];
             a.Bout = nullptr;
-            a.W = tile_width(N[0], 2048, a.ncols);
+            a.W = tile_width(N[0], tile_work(f32s), a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
             IPS_HIP(launch_cc(a, p->nch[1], f32s, f32s, st));
@@ -630,7 +648,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Ko = M[0] + 1;
             a.part = p->part[2];
             a.Bout = nullptr;
-            a.W = tile_width(N[0], 2048, a.ncols);
+            a.W = tile_width(N[0], tile_work(f32s), a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
             IPS_HIP(launch_cc(a, p->nch[2], f32s, f32s, st));
@@ -720,7 +738,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
                 a.Brs = 1;
                 a.Bbs = 0;
             }
-            a.W = tile_width(N[pen], 2048, a.ncols);
+            a.W = tile_width(N[pen], tile_work(f32s), a.ncols);
             a.fd = p->fd[pen];
             a.tw = p->tw[pen];
             IPS_HIP(launch_cc(a, p->nch[fam], f32s, false, st));
@@ -784,6 +802,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         pk.D[fam] = p->D[fam];
         pk.P[fam] = p->P[fam];
     }
+    sh.P1T = p->P1T;
+    pk.P1T = p->P1T;
     pk.withD = 0;
     IPS_HIP(launch_pack(pk, st));
     if (p->order == 6) {
@@ -840,7 +860,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.bax = -1;
         }
         a.nrows_in = I[0];
-        a.W = tile_width(N[0], 2048, a.ncols);
+        a.W = tile_width(N[0], tile_work(f32), a.ncols);
         a.order = p->order;
         a.mixed = f32;
         a.geo = p->geo;
