@@ -86,6 +86,16 @@ def _quad_lib():
                 ctypes.POINTER(ctypes.c_int64),
                 ctypes.POINTER(ctypes.c_double),
             ]
+            lib.oracle_boundary_adjoint.restype = ctypes.c_int
+            lib.oracle_boundary_adjoint.argtypes = [
+                ctypes.c_int,
+                ctypes.POINTER(ctypes.c_int64),
+                ctypes.POINTER(ctypes.c_double),
+                ctypes.c_int64,
+                ctypes.POINTER(ctypes.c_int64),
+                ctypes.POINTER(ctypes.c_double),
+                ctypes.POINTER(ctypes.c_double),
+            ]
             _quad = lib
     return _quad
 
@@ -451,3 +461,158 @@ def solve(rho: np.ndarray, h, order: int = 6, boundary: str = "direct") -> np.nd
     if d == 1:
         return ps + harmonic_1d(g, h)
     return ps + harmonic(g, h, order)
+
+
+# ----------------------------------------------------------------------------
+# Adjoint of the whole map rho -> phi (for gradients)
+# ----------------------------------------------------------------------------
+# phi = A rho is linear in rho (the boundary entries of rho are ignored).
+# Each forward step above is linear; its transpose is written out below and
+# chained in reverse order.  Pinned by <A v, w> = <v, A^T w> and by dense
+# matrices of A on tiny grids.
+
+
+def boundary_values_T(lam_full: np.ndarray, h) -> np.ndarray:
+    """Transpose of ``boundary_values``: rho_bar(s) = prod(h) sum_b G(|x_b - x_s|) lam(b)
+    over the boundary nodes b, for every interior node s (0 on the boundary)."""
+    lam_full = np.asarray(lam_full, dtype=np.float64)
+    d = lam_full.ndim
+    n = np.ascontiguousarray(lam_full.shape, dtype=np.int64)
+    hh = np.ascontiguousarray(np.broadcast_to(np.asarray(h, np.float64), (d,)))
+    mask = boundary_mask(lam_full.shape)
+    t = np.ascontiguousarray(np.argwhere(mask), dtype=np.int64)
+    lam = np.ascontiguousarray(lam_full[mask])
+    out = np.zeros(lam_full.shape)
+    lib = _quad_lib()
+    rc = lib.oracle_boundary_adjoint(
+        d,
+        n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        hh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        t.shape[0],
+        t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+    )
+    if rc != 0:
+        raise RuntimeError("oracle_boundary_adjoint failed (%d)" % rc)
+    return out
+
+
+def d2_T(v: np.ndarray, axis: int, hax: float) -> np.ndarray:
+    """Transpose of ``d2``: the input's ``axis`` grows by 2."""
+    shape = list(v.shape)
+    shape[axis] += 2
+    out = np.zeros(shape)
+    n = shape[axis]
+
+    def sl(a, b):
+        s = [slice(None)] * v.ndim
+        s[axis] = slice(a, b)
+        return tuple(s)
+
+    w = v / (hax * hax)
+    out[sl(2, n)] += w
+    out[sl(1, n - 1)] -= 2.0 * w
+    out[sl(0, n - 2)] += w
+    return out
+
+
+def _restrict_T(v: np.ndarray, shrink) -> np.ndarray:
+    """Transpose of ``_restrict``: zero padding."""
+    return np.pad(v, [(s, s) for s in shrink])
+
+
+def apply_Lh_T(y: np.ndarray, h) -> np.ndarray:
+    """Transpose of ``apply_Lh`` (interior values -> full grid)."""
+    d = y.ndim
+    out = 0.0
+    for i in range(d):
+        out = out + d2_T(_restrict_T(y, [0 if ax == i else 1 for ax in range(d)]), i, h[i])
+    for i in range(d):
+        for j in range(i + 1, d):
+            v = _restrict_T(y, [0 if ax in (i, j) else 1 for ax in range(d)])
+            out = out + compact_coeff(h, i, j) * d2_T(d2_T(v, i, h[i]), j, h[j])
+    return out
+
+
+def transfer_T(y: np.ndarray, h) -> np.ndarray:
+    """Transpose of ``transfer``: interior values -> boundary nodes (0 inside)."""
+    out = -apply_Lh_T(y, h)
+    out[(slice(1, -1),) * y.ndim] = 0.0
+    return out
+
+
+def rhs6_core_T(core_bar: np.ndarray, h) -> np.ndarray:
+    """Transpose of ``rhs6_core`` (core values -> full grid)."""
+    d = core_bar.ndim
+    out = 0.0
+    for i in range(d):
+        for j in range(i + 1, d):
+            cij = h[i] ** 4 / 240.0 + h[i] ** 2 * h[j] ** 2 / 144.0
+            cji = h[j] ** 4 / 240.0 + h[i] ** 2 * h[j] ** 2 / 144.0
+            t1 = _restrict_T(cij * core_bar, [0 if ax == i else (1 if ax == j else 2) for ax in range(d)])
+            t2 = _restrict_T(cji * core_bar, [0 if ax == j else (1 if ax == i else 2) for ax in range(d)])
+            v1 = d2_T(d2_T(t1, i, h[i]), i, h[i])
+            v2 = d2_T(d2_T(t2, i, h[i]), j, h[j])
+            out = out + d2_T(v1 + v2, j, h[j])
+    return out
+
+
+def extrapolate_T(Rbar: np.ndarray) -> np.ndarray:
+    """Transpose of ``extrapolate`` (interior-size array -> core-size array)."""
+    R = np.array(Rbar, dtype=np.float64)
+    d = R.ndim
+    filled = [True] * d
+    for ax in reversed(range(d)):
+        filled[ax] = False
+        span = []
+        for b in range(d):
+            if b == ax:
+                span.append(None)
+            else:
+                span.append(slice(None) if filled[b] else slice(1, R.shape[b] - 1))
+
+        def at(pos):
+            return tuple(pos if b == ax else span[b] for b in range(d))
+
+        m = R.shape[ax]
+        lo = R[at(0)].copy()
+        hi = R[at(m - 1)].copy()
+        R[at(0)] = 0.0
+        R[at(m - 1)] = 0.0
+        for k, w in zip((1, 2, 3, 4), (4.0, -6.0, 4.0, -1.0)):
+            R[at(k)] += w * lo
+            R[at(m - 1 - k)] += w * hi
+    return R[(slice(1, -1),) * d]
+
+
+def adjoint(w: np.ndarray, h, order: int = 6) -> np.ndarray:
+    """rho_bar = A^T w for the map rho -> phi computed by ``solve`` (boundary of rho_bar = 0)."""
+    w = np.asarray(w, dtype=np.float64)
+    d = w.ndim
+    h = np.asarray(np.broadcast_to(np.asarray(h, np.float64), (d,)))
+    inner = (slice(1, -1),) * d
+    mask = boundary_mask(w.shape)
+    lam = np.where(mask, w, 0.0)  # w on the boundary: phi = g there
+    if d == 1:
+        M = w.shape[0] - 1
+        t = np.arange(1, M, dtype=np.float64) / M
+        lam[0] += np.sum(w[1:-1] * (1.0 - t))
+        lam[-1] += np.sum(w[1:-1] * t)
+    else:
+        wI = w[inner]
+        a = solve_L0(wI, h)  # L_0^-1 is symmetric
+        gt_bar = a
+        if order == 6:
+            core_bar = extrapolate_T(a)
+            u1_bar = rhs6_core_T(core_bar, h)
+            lam = lam + np.where(mask, u1_bar, 0.0)  # R_boundary^T a
+            b = solve_L0(u1_bar[inner], h)  # L_0^-1 R_interior^T a
+            gt_bar = a + b
+        elif order != 4:
+            raise ValueError("order must be 4 or 6")
+        lam = lam + transfer_T(gt_bar, h)
+    out = phi_star(w, h)  # phi_star's map is symmetric on the interior
+    out = out + boundary_values_T(lam, h)
+    out[mask] = 0.0
+    return out

@@ -83,3 +83,62 @@ int oracle_boundary_direct(int d, const int64_t *n, const double *h,
     free(sx);
     return 0;
 }
+
+/*
+ * Transpose of oracle_boundary_direct over the boundary nodes:
+ *     out[s] = prod_i h_i * sum_{t} G(|x_t - x_s|) lam[t]      for every interior node s
+ * where t runs over the listed target nodes with weights lam[t].  out has the
+ * full grid's size; its boundary entries are set to 0.
+ */
+int oracle_boundary_adjoint(int d, const int64_t *n, const double *h, int64_t ntargets,
+                            const int64_t *targets, const double *lam, double *out)
+{
+    if (d < 1 || d > 3 || !n || !h || !targets || !lam || !out) return -1;
+    int64_t nn[3] = {1, 1, 1};
+    double hh[3] = {1.0, 1.0, 1.0};
+    for (int a = 0; a < d; ++a) {
+        if (n[a] < 3 || !(h[a] > 0.0)) return -1;
+        nn[3 - d + a] = n[a];
+        hh[3 - d + a] = h[a];
+    }
+    double vol = 1.0;
+    for (int a = 0; a < d; ++a) vol *= h[a];
+    double *tx = malloc(sizeof(double) * (size_t)(ntargets > 0 ? ntargets : 1) * 4);
+    if (!tx) return -2;
+    int64_t nt = 0;
+    for (int64_t t = 0; t < ntargets; ++t) {
+        if (lam[t] == 0.0) continue;
+        double c[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < d; ++a) c[3 - d + a] = (double)targets[t * d + a];
+        tx[4 * nt + 0] = c[0];
+        tx[4 * nt + 1] = c[1];
+        tx[4 * nt + 2] = c[2];
+        tx[4 * nt + 3] = lam[t];
+        ++nt;
+    }
+    const int64_t total = nn[0] * nn[1] * nn[2];
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t e = 0; e < total; ++e) {
+        const int64_t k = e % nn[2], j = (e / nn[2]) % nn[1], i = e / (nn[1] * nn[2]);
+        int interior = (k > 0 && k < nn[2] - 1);
+        if (nn[1] > 1) interior = interior && j > 0 && j < nn[1] - 1;
+        if (nn[0] > 1) interior = interior && i > 0 && i < nn[0] - 1;
+        if (!interior) {
+            out[e] = 0.0;
+            continue;
+        }
+        const double s[3] = {(double)i, (double)j, (double)k};
+        double acc = 0.0;
+        for (int64_t t = 0; t < nt; ++t) {
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double dx = (tx[4 * t + a] - s[a]) * hh[a];
+                r2 += dx * dx;
+            }
+            acc += green(d, sqrt(r2)) * tx[4 * t + 3];
+        }
+        out[e] = acc * vol;
+    }
+    free(tx);
+    return 0;
+}

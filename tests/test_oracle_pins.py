@@ -341,3 +341,56 @@ def test_discrete_poisson_relation_decays_at_fourth_order():
         )
         res.append(np.abs(lhs - rhs)[3:-3, 3:-3].max())
     assert res[0] / res[1] > 12.0
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the whole map rho -> phi
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,h", [((9,), (0.2,)), ((9, 11), (0.2, 0.13)), ((12, 13), (0.1, 0.07)),
+                                     ((8, 9, 10), (0.2, 0.17, 0.11)), ((10, 11, 12), (0.1, 0.12, 0.09))])
+@pytest.mark.parametrize("order", [4, 6])
+def test_adjoint_dot_product(shape, h, order):
+    rng = np.random.default_rng(hash((shape, order)) % 2**32)
+    v = rng.standard_normal(shape)
+    w = rng.standard_normal(shape)
+    lhs = np.sum(P.solve(v, h, order) * w)
+    rhs = np.sum(v * P.adjoint(w, h, order))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+@pytest.mark.parametrize("shape,h,order", [((8, 9), (0.2, 0.15), 6), ((6, 7), (0.3, 0.2), 4),
+                                           ((8, 8, 9), (0.2, 0.25, 0.15), 6)])
+def test_adjoint_is_the_transpose_of_the_dense_map(shape, h, order):
+    # columns of A from unit vectors on the interior (boundary entries of rho are ignored)
+    nI = int(np.prod([s - 2 for s in shape]))
+    inner = (slice(1, -1),) * len(shape)
+    A = np.zeros((int(np.prod(shape)), nI))
+    for c in range(nI):
+        e = np.zeros(shape)
+        e[inner].flat[c] = 1.0
+        A[:, c] = P.solve(e, h, order).ravel()
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal(shape)
+    ref = A.T @ w.ravel()
+    got = P.adjoint(w, h, order)
+    assert np.abs(got[inner].ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.all(got[P.boundary_mask(shape)] == 0.0)
+
+
+def test_adjoint_pieces_are_transposes():
+    # each transposed building block against its forward counterpart
+    rng = np.random.default_rng(4)
+    h = np.array([0.2, 0.13, 0.17])
+    u = rng.standard_normal((9, 10, 11))
+    y = rng.standard_normal((7, 8, 9))
+    assert abs(np.sum(P.apply_Lh(u, h) * y) - np.sum(u * P.apply_Lh_T(y, h))) < 1e-10
+    core = rng.standard_normal((5, 6, 7))
+    R = rng.standard_normal((7, 8, 9))
+    assert abs(np.sum(P.extrapolate(core) * R) - np.sum(core * P.extrapolate_T(R))) < 1e-11
+    cb = rng.standard_normal((5, 6, 7))
+    assert abs(np.sum(P.rhs6_core(u, h) * cb) - np.sum(u * P.rhs6_core_T(cb, h))) < 1e-6 * np.abs(P.rhs6_core(u, h)).max()
+    rho = rng.standard_normal((9, 10, 11))
+    lam = np.where(P.boundary_mask(rho.shape), rng.standard_normal(rho.shape), 0.0)
+    lhs = np.sum(P.boundary_values(rho, h) * lam)
+    rhs = np.sum(rho[1:-1, 1:-1, 1:-1] * P.boundary_values_T(lam, h)[1:-1, 1:-1, 1:-1])
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
