@@ -110,14 +110,14 @@ struct FinalArgs {
     const cx<double> *tw;
 };
 
-// Sixth-order right-hand side on the depth-5 shell (see k_h2v / k_h2c).
-struct H2Args {
-    int axis;  // contraction axis of k_h2c (a problem axis other than the last)
+// Sixth-order right-hand side on the depth-5 shell layers (see k_r6t).
+struct R6Args {
     Geo geo;
     AxisTabs tab[3];
-    ShellSpec sh;
-    double *V; // sine coefficients of the right-hand side on all interior modes
-    double *T; // [10][I_b][I_c] (3D) or [10][I_b] (2D) for the contracted axis
+    const double *P[3]; // packed shell spectra (ShellSpec::P)
+    const double *P1T;  // 3D: family 1 transposed (ShellSpec::P1T)
+    double *T[3];       // [10][other axes] per axis: layers 1..5, then M-1..M-5
+    int nblk[3];        // filled by the launcher
 };
 
 struct DcorrArgs {
@@ -125,6 +125,7 @@ struct DcorrArgs {
     int64_t n[3];
     const double *phi;     // grid with boundary values already written
     const double *RS[3];   // R_spec on the depth-5 shell layers [10][..][..]
+    double *C[3];          // R on the core layers 2..5, M-5..M-2: [8][..][..]
     double *D[3];          // outputs [4][..][..]
 };
 
@@ -151,8 +152,7 @@ hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchun
 hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st);
 hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);
 hipError_t launch_pack(const PackArgs &a, hipStream_t st);
-hipError_t launch_h2v(const H2Args &a, hipStream_t st);
-hipError_t launch_h2c(const H2Args &a, hipStream_t st);
+hipError_t launch_r6t(R6Args a, hipStream_t st);
 hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);
 // K[dd][ib][ic] (3D) or K[dd][ib] (2D) for faces normal to axis a; (b, c) are

@@ -9,10 +9,10 @@
 //             Trap2Dconvolution, convolution)
 //   k_gtilde  transfer of the boundary values of the compact operator to the
 //             right-hand side next to the boundary (eq. harmonic4thOrderNH2D)
-//   k_h2      sixth-order right-hand side on the nodes near the boundary,
+//   k_r6t     sixth-order right-hand side on the layers near the boundary,
 //             from its sine coefficients (eqs. 6thOrderRelation2D/3D)
-//   k_dcorr   boundary terms of that right-hand side and its cubic
-//             extrapolation next to the boundary (Section 5)
+//   k_rcore,  boundary terms of that right-hand side and its cubic
+//   k_dcorr   extrapolation next to the boundary (Section 5)
 //   k_final   spectral combination phi_star + phi_H and first inverse pass
 #include <hip/hip_runtime.h>
 
@@ -373,154 +373,14 @@ hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// g~ = -(L_h B) on the interior nodes next to the boundary, split into one
-// layer pair per axis (a node belongs to the lowest axis whose index is 1 or
-// M-1 there; other layers hold 0 at that node).
+// Shell layer sizes
 // ---------------------------------------------------------------------------
-__global__ void k_gtilde(GtArgs a)
-{
-    const Geo &g = a.geo;
-    const int d = g.d;
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (int fam = 0; fam < d; ++fam) {
-        int len[2] = {1, 1}, ax[2] = {0, 0}, na = 0;
-        for (int b = 0; b < d; ++b)
-            if (b != fam) {
-                ax[na] = b;
-                len[na] = g.M[b] - 1;
-                ++na;
-            }
-        const int64_t per = (int64_t)len[0] * len[1];
-        if (e < 2 * per) {
-            const int f = (int)(e / per);
-            const int64_t r = e % per;
-            int i[3];
-            i[fam] = f ? g.M[fam] - 1 : 1;
-            i[ax[0]] = 1 + (int)(na == 2 ? r / len[1] : r);
-            if (na == 2) i[ax[1]] = 1 + (int)(r % len[1]);
-            // with M = 2 both layers are the same nodes: keep only the first
-            bool owned = !(f == 1 && g.M[fam] == 2);
-            for (int b = 0; b < fam; ++b)
-                if (i[b] == 1 || i[b] == g.M[b] - 1) owned = false;
-            double s = 0.0;
-            if (owned) {
-                // face neighbours
-                for (int p = 0; p < d; ++p) {
-                    double w = 1.0 / (g.h[p] * g.h[p]);
-                    for (int q = 0; q < d; ++q)
-                        if (q != p) w -= 2.0 * g.c2[p][q] / (g.h[p] * g.h[p] * g.h[q] * g.h[q]);
-                    for (int sg = -1; sg <= 1; sg += 2) {
-                        int j[3] = {i[0], i[1], i[2]};
-                        j[p] += sg;
-                        if (on_boundary(g, j)) s += w * a.phi[node_off(a.n, d, j)];
-                    }
-                }
-                // edge neighbours
-                for (int p = 0; p < d; ++p)
-                    for (int q = p + 1; q < d; ++q) {
-                        const double w = g.c2[p][q] / (g.h[p] * g.h[p] * g.h[q] * g.h[q]);
-                        for (int sp = -1; sp <= 1; sp += 2)
-                            for (int sq = -1; sq <= 1; sq += 2) {
-                                int j[3] = {i[0], i[1], i[2]};
-                                j[p] += sp;
-                                j[q] += sq;
-                                if (on_boundary(g, j)) s += w * a.phi[node_off(a.n, d, j)];
-                            }
-                    }
-                s = -s;
-            }
-            a.G[fam][e] = s;
-            return;
-        }
-        e -= 2 * per;
-    }
-}
-
-hipError_t launch_gtilde(const GtArgs &a, hipStream_t st)
-{
-    const Geo &g = a.geo;
-    int64_t tot = 0;
-    for (int fam = 0; fam < g.d; ++fam) {
-        int64_t c = 2;
-        for (int b = 0; b < g.d; ++b)
-            if (b != fam) c *= g.M[b] - 1;
-        tot += c;
-    }
-    hipLaunchKernelGGL(k_gtilde, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Spectral pieces shared by k_h2 and k_final
-// ---------------------------------------------------------------------------
-struct Spec {
-    double lam[3];
-    double Lambda; // eigenvalue of L_0
-    double mR;     // symbol of the sixth-order right-hand side operator
-};
-
-__device__ __forceinline__ void spec_eval(const Geo &g, const AxisTabs *tab, const int *k, Spec &s)
-{
-    const int d = g.d;
-    for (int a = 0; a < d; ++a) s.lam[a] = tab[a].lam[k[a] - 1];
-    double L = 0.0, R = 0.0;
-    for (int a = 0; a < d; ++a) L += s.lam[a];
-    for (int i = 0; i < d; ++i)
-        for (int j = i + 1; j < d; ++j) {
-            const double p = s.lam[i] * s.lam[j];
-            L += g.c2[i][j] * p;
-            R += p * (g.c4[i][j] * s.lam[i] + g.c4[j][i] * s.lam[j]);
-        }
-    s.Lambda = L;
-    s.mR = R;
-}
-
-// index of the two (or one) other axes of `a` in a shell layer array
-__device__ __forceinline__ int64_t shell_idx(const Geo &g, int a, const int *k)
-{
-    int64_t o = 0;
-    for (int b = 0; b < g.d; ++b)
-        if (b != a) o = o * (g.M[b] - 1) + (k[b] - 1);
-    return o;
-}
-
 __host__ __device__ __forceinline__ int64_t shell_size(const Geo &g, int a)
 {
     int64_t s = 1;
     for (int b = 0; b < g.d; ++b)
         if (b != a) s *= g.M[b] - 1;
     return s;
-}
-
-// raw DST of g~ at wavenumber k
-__device__ __forceinline__ double gt_hat(const Geo &g, const AxisTabs *tab, const ShellSpec &sh,
-                                         const int *k)
-{
-    double v = 0.0;
-    for (int a = 0; a < g.d; ++a) {
-        const int64_t o = shell_idx(g, a, k);
-        const int64_t ss = shell_size(g, a);
-        const double sg = (k[a] & 1) ? 1.0 : -1.0;
-        v += tab[a].s[k[a] - 1] * (sh.G[a][o] + sg * sh.G[a][ss + o]);
-    }
-    return v;
-}
-
-// raw DST of the deferred-correction shell field D at wavenumber k
-__device__ __forceinline__ double d_hat(const Geo &g, const AxisTabs *tab, const ShellSpec &sh,
-                                        const int *k)
-{
-    double v = 0.0;
-    for (int a = 0; a < g.d; ++a) {
-        const int64_t o = shell_idx(g, a, k);
-        const int64_t ss = shell_size(g, a);
-        const double sg = (k[a] & 1) ? 1.0 : -1.0;
-        const int m1 = g.M[a] - 1;
-        const double *D = sh.D[a];
-        v += tab[a].s[k[a] - 1] * (D[o] + sg * D[3 * ss + o]) +
-             tab[a].s[m1 + k[a] - 1] * (D[ss + o] + sg * D[2 * ss + o]);
-    }
-    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -595,281 +455,396 @@ __device__ __forceinline__ void lam_symbols(const Geo &g, const double *lam, dou
 //     T_a[j][k_other] = sum_{k_a} sin(pi k_a j / M_a) V(k)
 // (followed by an inverse sine transform over the other axes).  Parity:
 // sin(pi k (M-j)/M) = (-1)^(k+1) sin(pi k j / M).
-// k_h2v writes V and contracts the last axis (one wave per row of V);
-// k_h2c contracts one of the other axes, streaming V.
+//
+// k_r6t computes the three (two in 2D) contractions in one launch and never
+// stores V: each thread owns one position (k_b, k_c) and sums over a quarter
+// of the k_a, rebuilding V(k) from the packed shell spectra:
+//   gt_hat = sin(pi k_a/M_a) G_a(k_b, k_c) + sin(pi k_l/M_l) G_l(.., k_a, ..)
+//            + sin(pi k_w/M_w) G_w(.., k_a, ..)
+// where l is the axis that varies across the lanes of a wave and w the
+// other one.  The lanes read G_w contiguously (3D: for a = 2 from the
+// transposed family-1 copy) and G_l at one of two addresses (parity of
+// k_l).  With lambda_a the only varying eigenvalue,
+//   Lambda = A0 + A1 lambda_a,  m_R = B0 + lambda_a (B1 + B2 lambda_a).
+// Block: 64 positions x 4 wave groups; group g takes k_a = 1 + g + 4t, so
+// its parity is fixed and the layer pairs split into odd and even sums.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_h2v(H2Args a)
+template <int D>
+__global__ __launch_bounds__(NT) void k_r6t(R6Args a)
 {
-    const Geo &g = a.geo;
-    const int d = g.d;
-    const int L = d - 1; // last axis
-    const int IL = g.M[L] - 1;
-    int64_t rows = 1;
-    for (int b = 0; b < L; ++b) rows *= g.M[b] - 1;
-    constexpr int LPR = 16; // lanes per row
-    const int lane = threadIdx.x & (LPR - 1);
-    const int64_t row = (int64_t)blockIdx.x * (NT / LPR) + (threadIdx.x / LPR);
-    if (row >= rows) return;
-    int k[3] = {1, 1, 1};
-    {
-        int64_t r = row;
-        for (int b = L - 1; b >= 0; --b) {
-            k[b] = 1 + (int)(r % (g.M[b] - 1));
-            r /= (g.M[b] - 1);
-        }
-    }
-    // row invariants: eigenvalues and shell factors of the first d-1 axes,
-    // and the last family's packed g~ values (its other index is the row)
-    double lam[3], s1[3];
-    for (int b = 0; b < L; ++b) {
-        lam[b] = a.tab[b].lam[k[b] - 1];
-        s1[b] = a.tab[b].s[k[b] - 1];
-    }
-    const int64_t ssL = shell_size(g, L);
-    const double gL_even = a.sh.P[L][row], gL_odd = a.sh.P[L][3 * ssL + row];
-    // per-element families b < L: other index includes the last axis
-    const double *Pb[2];
-    int64_t obase[2], ostride[2];
-    for (int b = 0; b < L; ++b) {
-        const int64_t ss = shell_size(g, b);
-        Pb[b] = a.sh.P[b] + ((k[b] & 1) ? 3 * ss : 0);
-        // other index of family b: axes != b in increasing order, last axis fastest
-        int64_t o = 0;
-        for (int c = 0; c < L; ++c)
-            if (c != b) o = o * (g.M[c] - 1) + (k[c] - 1);
-        obase[b] = o * IL;
-        ostride[b] = 1;
-    }
-    const double *sj = a.tab[L].s;
-    const double *lamL = a.tab[L].lam;
-    double ev[5] = {0, 0, 0, 0, 0}, od[5] = {0, 0, 0, 0, 0};
-    double *Vrow = a.V + row * IL;
-    for (int kL = 1 + lane; kL <= IL; kL += LPR) {
-        lam[L] = lamL[kL - 1];
-        double Lm, Rm;
-        lam_symbols(g, lam, Lm, Rm);
-        double gt = sj[kL - 1] * ((kL & 1) ? gL_odd : gL_even);
-        for (int b = 0; b < L; ++b) gt += s1[b] * Pb[b][obase[b] + (kL - 1) * ostride[b]];
-        const double v = g.pref * Rm * gt / Lm;
-        Vrow[kL - 1] = v;
-        if (kL & 1) {
-#pragma unroll
-            for (int j = 0; j < 5; ++j) od[j] += sj[j * IL + kL - 1] * v;
-        } else {
-#pragma unroll
-            for (int j = 0; j < 5; ++j) ev[j] += sj[j * IL + kL - 1] * v;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-#pragma unroll
-        for (int m = LPR / 2; m >= 1; m >>= 1) {
-            od[j] += __shfl_xor(od[j], m);
-            ev[j] += __shfl_xor(ev[j], m);
-        }
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            a.T[j * rows + row] = od[j] + ev[j];
-            a.T[(5 + j) * rows + row] = od[j] - ev[j];
-        }
-    }
-}
-
-hipError_t launch_h2v(const H2Args &a, hipStream_t st)
-{
-    int64_t rows = 1;
-    for (int b = 0; b < a.geo.d - 1; ++b) rows *= a.geo.M[b] - 1;
-    const int64_t nb = (rows + NT / 16 - 1) / (NT / 16);
-    hipLaunchKernelGGL(k_h2v, dim3((unsigned)nb), dim3(NT), 0, st, a);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(NT) void k_h2c(H2Args a)
-{
-    constexpr int PB = 64;   // positions per block
-    constexpr int NG = NT / PB; // groups over k_a (k_a = 1 + g + NG t: fixed parity per group)
-    __shared__ double stab[5 * 1024];
+    constexpr int PB = 64, NG = NT / PB;
     __shared__ double red[NG][5][PB];
     const Geo &g = a.geo;
-    const int d = g.d, ax = a.axis;
+    int ax = 0, blk = blockIdx.x;
+    while (ax < D - 1 && blk >= a.nblk[ax]) {
+        blk -= a.nblk[ax];
+        ++ax;
+    }
+    const int lane = threadIdx.x & (PB - 1);
+    const int grp = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int Ia = g.M[ax] - 1;
-    // positions: other axes flattened (later axis fastest); V stride of axis ax
-    int64_t P = 1, stride = 1;
-    for (int b = 0; b < d; ++b)
-        if (b != ax) P *= g.M[b] - 1;
-    for (int b = ax + 1; b < d; ++b) stride *= g.M[b] - 1;
-    for (int t = threadIdx.x; t < 5 * Ia; t += NT) stab[t] = a.tab[ax].s[t];
-    const int pl = threadIdx.x % PB, grp = threadIdx.x / PB;
-    const int64_t p = (int64_t)blockIdx.x * PB + pl;
-    __syncthreads();
-    double acc[5] = {0, 0, 0, 0, 0};
-    if (p < P) {
-        // base offset of position p in V: split p into (outer, inner) around axis ax
-        const int64_t outer = p / stride, inner = p % stride;
-        const double *v = a.V + outer * stride * Ia + inner;
-        for (int ka = 1 + grp; ka <= Ia; ka += NG) {
-            const double x = v[(int64_t)(ka - 1) * stride];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) acc[j] += stab[j * Ia + ka - 1] * x;
+    int la, wa;
+    if (D == 3) {
+        la = ax == 2 ? 0 : 2;
+        wa = ax == 1 ? 0 : 1;
+    } else {
+        la = 1 - ax;
+        wa = -1;
+    }
+    const int Il = g.M[la] - 1;
+    const int Iw = D == 3 ? g.M[wa] - 1 : 1;
+    const int npos = Il * Iw;
+    const int p = blk * PB + lane;
+    const bool live = p < npos;
+    const int pp = live ? p : 0;
+    const int kl = 1 + pp % Il;
+    const int kw = 1 + pp / Il;
+    const int para = (grp & 1) ? 0 : 1; // parity of k_a in this group
+
+    // symbols as polynomials in lambda_a
+    const double lamL = a.tab[la].lam[kl - 1];
+    double A0 = lamL, A1 = 1.0 + g.c2[ax][la] * lamL;
+    double B0 = 0.0, B1 = g.c4[la][ax] * lamL * lamL, B2 = g.c4[ax][la] * lamL;
+    if (D == 3) {
+        const double lamW = a.tab[wa].lam[kw - 1];
+        A0 += lamW + g.c2[la][wa] * lamL * lamW;
+        A1 += g.c2[ax][wa] * lamW;
+        B0 = g.c4[la][wa] * lamL * lamL * lamW + g.c4[wa][la] * lamL * lamW * lamW;
+        B1 += g.c4[wa][ax] * lamW * lamW;
+        B2 += g.c4[ax][wa] * lamW;
+    }
+    // own family (normal to a): fixed value for this group's parity
+    const int64_t ssa = shell_size(g, ax);
+    int64_t oown;
+    if (D == 3)
+        oown = ax == 2 ? (int64_t)(kl - 1) * Iw + (kw - 1) : (int64_t)(kw - 1) * Il + (kl - 1);
+    else
+        oown = kl - 1;
+    const double gown = a.P[ax][(int64_t)para * 3 * ssa + oown];
+    // family normal to the lane axis: two addresses per wave
+    const int64_t ssl = shell_size(g, la);
+    const double sbl = a.tab[la].s[kl - 1];
+    const double *pb = a.P[la] + (int64_t)(kl & 1) * 3 * ssl;
+    int64_t bs;
+    if (D == 3) {
+        if (ax == 0) {
+            pb += kw - 1; // G_2[k0][k1], k0 = k_a
+            bs = Iw;
+        } else if (ax == 1) {
+            pb += (int64_t)(kw - 1) * (g.M[1] - 1); // G_2[k0][k1], k1 = k_a
+            bs = 1;
+        } else {
+            pb += (int64_t)(kw - 1) * (g.M[2] - 1); // G_0[k1][k2], k2 = k_a
+            bs = 1;
         }
+    } else {
+        bs = 1;
+    }
+    // family normal to the wave axis (3D): contiguous across the lanes
+    const double *pc = nullptr;
+    double scw = 0.0;
+    int64_t cs = 0;
+    if (D == 3) {
+        const int64_t ssw = shell_size(g, wa);
+        scw = a.tab[wa].s[kw - 1];
+        const double *base = ax == 2 ? a.P1T : a.P[wa];
+        pc = base + (int64_t)(kw & 1) * 3 * ssw + (kl - 1);
+        cs = ax == 2 ? (g.M[0] - 1) : (g.M[2] - 1);
+    }
+    const double *tl = a.tab[ax].lam;
+    const double *ts = a.tab[ax].s;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int ka = 1 + grp; ka <= Ia; ka += NG) {
+        const double lk = tl[ka - 1];
+        double gt = ts[ka - 1] * gown + sbl * pb[(int64_t)(ka - 1) * bs];
+        if (D == 3) gt += scw * pc[(int64_t)(ka - 1) * cs];
+        const double L = fma(A1, lk, A0);
+        const double R = fma(fma(B2, lk, B1), lk, B0);
+        const double v = R * gt / L;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc[j] = fma(ts[j * Ia + ka - 1], v, acc[j]);
     }
 #pragma unroll
-    for (int j = 0; j < 5; ++j) red[grp][j][pl] = acc[j];
+    for (int j = 0; j < 5; ++j) red[grp][j][lane] = acc[j];
     __syncthreads();
-    if (grp == 0 && p < P) {
-        // k_a = 1 + grp + NG t is odd for even grp (NG even)
-        double od[5], ev[5];
+    if (grp == 0 && live) {
+        const int64_t pout = (D == 3 && ax == 2) ? (int64_t)(kl - 1) * Iw + (kw - 1) : p;
+        double *T = a.T[ax];
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            od[j] = 0.0;
-            ev[j] = 0.0;
-            for (int q = 0; q < NG; ++q) {
-                if (q % 2 == 0)
-                    od[j] += red[q][j][pl];
-                else
-                    ev[j] += red[q][j][pl];
-            }
-            a.T[j * P + p] = od[j] + ev[j];
-            a.T[(5 + j) * P + p] = od[j] - ev[j];
+            const double od = red[0][j][lane] + red[2][j][lane];
+            const double ev = red[1][j][lane] + red[3][j][lane];
+            T[j * (int64_t)npos + pout] = g.pref * (od + ev);
+            T[(5 + j) * (int64_t)npos + pout] = g.pref * (od - ev);
         }
     }
 }
 
-hipError_t launch_h2c(const H2Args &a, hipStream_t st)
+hipError_t launch_r6t(R6Args a, hipStream_t st)
 {
-    int64_t P = 1;
-    for (int b = 0; b < a.geo.d; ++b)
-        if (b != a.axis) P *= a.geo.M[b] - 1;
-    if (a.geo.M[a.axis] - 1 > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_h2c, dim3((unsigned)((P + 63) / 64)), dim3(NT), 0, st, a);
+    const int d = a.geo.d;
+    int tot = 0;
+    for (int ax = 0; ax < d; ++ax) {
+        const int np = (int)shell_size(a.geo, ax);
+        a.nblk[ax] = (np + 63) / 64;
+        tot += a.nblk[ax];
+    }
+    if (d == 3)
+        hipLaunchKernelGGL(k_r6t<3>, dim3(tot), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_r6t<2>, dim3(tot), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// D = R - R_spec on the nodes with an index in {1, 2, M-2, M-1}:
-//   R_core = R_spec + (boundary terms of the D2^2 D2 stencils, which reach
-//            the faces from core nodes with an index 2 or M-2)
-//   R      = tensor-product cubic extrapolation of R_core to indices 1, M-1
+// D = R - R_spec on the nodes with an index in {1, 2, M-2, M-1}, in two steps.
+//   k_rcore: R on the core nodes with an index along axis a in
+//            {2..5, M-5..M-2}:  R = R_spec + boundary terms, where a
+//            D2^2 D2 stencil centred on index 2 or M-2 of some axis x reaches
+//            the face of x: c4[x][y] D2_y g / h_x^4 for every y != x.
+//            C[a][l][other], l = 0..7 for the layers 2,3,4,5,M-5,..,M-2.
+//   k_dcorr: R at the shell nodes by tensor-product cubic extrapolation
+//            (index 1 <- 4,-6,4,-1 times indices 2..5, mirrored at M-1),
+//            minus R_spec.  A node belongs to the lowest axis that has an
+//            index in {1, 2, M-2, M-1} there; other layers hold 0.
+// Both read R_spec only from the layers of their own axis.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int layer5(int i, int M)
 {
-    if (i >= 1 && i <= 5) return i - 1;
-    if (i >= M - 5 && i <= M - 1) return 5 + (M - 1 - i);
-    return -1;
+    return i <= 5 ? i - 1 : 5 + (M - 1 - i);
 }
 
-__device__ double rs_lookup(const DcorrArgs &a, const int *p)
+template <int D>
+__device__ __forceinline__ void other_axes(int a, int *ob)
+{
+    int q = 0;
+    for (int b = 0; b < D; ++b)
+        if (b != a) ob[q++] = b;
+}
+
+template <int D>
+__global__ __launch_bounds__(NT) void k_rcore(DcorrArgs a)
 {
     const Geo &g = a.geo;
-    for (int ax = 0; ax < g.d; ++ax) {
-        const int jj = layer5(p[ax], g.M[ax]);
-        if (jj >= 0) {
-            const int64_t ss = shell_size(g, ax);
-            return a.RS[ax][jj * ss + shell_idx(g, ax, p)];
+    const int fam = blockIdx.y >> 3, l = blockIdx.y & 7;
+    const int64_t ss = shell_size(g, fam);
+    const int e = blockIdx.x * NT + threadIdx.x;
+    if (e >= ss) return;
+    int ob[2] = {0, 0};
+    other_axes<D>(fam, ob);
+    int i[3] = {0, 0, 0};
+    const int Mf = g.M[fam];
+    i[fam] = l < 4 ? 2 + l : Mf - 2 - (7 - l);
+    if (D == 3) {
+        const int Ic = g.M[ob[1]] - 1;
+        i[ob[0]] = 1 + e / Ic;
+        i[ob[1]] = 1 + e % Ic;
+    } else {
+        i[ob[0]] = 1 + e;
+    }
+    bool core = true;
+    for (int b = 0; b < D; ++b) core = core && i[b] >= 2 && i[b] <= g.M[b] - 2;
+    double v = 0.0;
+    if (core) {
+        v = a.RS[fam][(int64_t)layer5(i[fam], Mf) * ss + e];
+#pragma unroll
+        for (int x = 0; x < D; ++x) {
+            if (i[x] != 2 && i[x] != g.M[x] - 2) continue;
+            int q[3] = {i[0], i[1], i[2]};
+            q[x] = i[x] == 2 ? 0 : g.M[x];
+            double t = 0.0;
+#pragma unroll
+            for (int y = 0; y < D; ++y) {
+                if (y == x) continue;
+                int qm[3] = {q[0], q[1], q[2]}, qp[3] = {q[0], q[1], q[2]};
+                qm[y] -= 1;
+                qp[y] += 1;
+                const double f0 = a.phi[node_off(a.n, D, q)];
+                const double fm = a.phi[node_off(a.n, D, qm)];
+                const double fp = a.phi[node_off(a.n, D, qp)];
+                t += g.c4[x][y] * (fm - 2.0 * f0 + fp) / (g.h[y] * g.h[y]);
+            }
+            const double h2 = g.h[x] * g.h[x];
+            v += t / (h2 * h2);
         }
     }
-    return 0.0; // not reached for the nodes this kernel visits
+    a.C[fam][(int64_t)l * ss + e] = v;
 }
 
-__device__ double rcore(const DcorrArgs &a, const int *p)
+template <int D>
+__global__ __launch_bounds__(NT) void k_dcorr(DcorrArgs a)
 {
     const Geo &g = a.geo;
-    const int d = g.d;
-    double v = rs_lookup(a, p);
-    for (int ax = 0; ax < d; ++ax) {
-        int face;
-        if (p[ax] == 2)
-            face = 0;
-        else if (p[ax] == g.M[ax] - 2)
-            face = g.M[ax];
+    const int fam = blockIdx.y >> 2, jj = blockIdx.y & 3;
+    const int64_t ss = shell_size(g, fam);
+    const int e = blockIdx.x * NT + threadIdx.x;
+    if (e >= ss) return;
+    int ob[2] = {0, 0};
+    other_axes<D>(fam, ob);
+    const int Mf = g.M[fam];
+    const int L4[4] = {1, 2, Mf - 2, Mf - 1};
+    int i[3] = {0, 0, 0};
+    i[fam] = L4[jj];
+    int Ic = 1;
+    if (D == 3) {
+        Ic = g.M[ob[1]] - 1;
+        i[ob[0]] = 1 + e / Ic;
+        i[ob[1]] = 1 + e % Ic;
+    } else {
+        i[ob[0]] = 1 + e;
+    }
+    bool owned = true;
+    for (int b = 0; b < fam; ++b) {
+        const int m = g.M[b];
+        if (i[b] == 1 || i[b] == 2 || i[b] == m - 2 || i[b] == m - 1) owned = false;
+    }
+    double out = 0.0;
+    if (owned) {
+        const double *C = a.C[fam];
+        // along the family axis (uniform over the block)
+        const bool exa = jj == 0 || jj == 3;
+        int l0;
+        if (jj == 0)
+            l0 = 0;
+        else if (jj == 3)
+            l0 = 7;
         else
-            continue;
-        const double h2 = g.h[ax] * g.h[ax];
-        double t = 0.0;
-        for (int b = 0; b < d; ++b) {
-            if (b == ax) continue;
-            int q[3] = {p[0], p[1], p[2]};
-            q[ax] = face;
-            const double f0 = a.phi[node_off(a.n, d, q)];
-            q[b] = p[b] - 1;
-            const double fm = a.phi[node_off(a.n, d, q)];
-            q[b] = p[b] + 1;
-            const double fp = a.phi[node_off(a.n, d, q)];
-            t += g.c4[ax][b] * (fm - 2.0 * f0 + fp) / (g.h[b] * g.h[b]);
+            l0 = jj == 1 ? 0 : 7;
+        const int dl = jj == 3 ? -1 : 1;
+        // in-face axes: 1 or 4 taps each
+        int nt[2] = {1, 1}, p0[2] = {0, 0}, dp[2] = {0, 0};
+        for (int q = 0; q < D - 1; ++q) {
+            const int b = ob[q], m = g.M[b];
+            if (i[b] == 1) {
+                nt[q] = 4;
+                p0[q] = 2;
+                dp[q] = 1;
+            } else if (i[b] == m - 1) {
+                nt[q] = 4;
+                p0[q] = m - 2;
+                dp[q] = -1;
+            } else {
+                p0[q] = i[b];
+            }
         }
-        v += t / (h2 * h2);
-    }
-    return v;
-}
-
-__global__ void k_dcorr(DcorrArgs a)
-{
-    const Geo &g = a.geo;
-    const int d = g.d;
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (int fam = 0; fam < d; ++fam) {
-        const int64_t per = shell_size(g, fam);
-        if (e < 4 * per) {
-            const int jj = (int)(e / per);
-            int64_t r = e % per;
-            int i[3] = {0, 0, 0};
-            const int L[4] = {1, 2, g.M[fam] - 2, g.M[fam] - 1};
-            i[fam] = L[jj];
-            for (int b = d - 1; b >= 0; --b) {
-                if (b == fam) continue;
-                i[b] = 1 + (int)(r % (g.M[b] - 1));
-                r /= (g.M[b] - 1);
-            }
-            bool owned = true;
-            for (int b = 0; b < fam; ++b) {
-                const int m = g.M[b];
-                if (i[b] == 1 || i[b] == 2 || i[b] == m - 2 || i[b] == m - 1) owned = false;
-            }
-            double out = 0.0;
-            if (owned) {
-                // per-axis cubic extrapolation: index 1 <- 4,-6,4,-1 times 2..5
-                // (and mirrored at M-1); other indices map to themselves
-                int cnt[3], sg[3];
-                for (int b = 0; b < 3; ++b) {
-                    const bool ex = b < d && (i[b] == 1 || i[b] == g.M[b] - 1);
-                    cnt[b] = ex ? 4 : 1;
-                    sg[b] = ex ? (i[b] == 1 ? 1 : -1) : 0;
+        const double wt[4] = {4.0, -6.0, 4.0, -1.0};
+        double R = 0.0;
+        for (int t0 = 0; t0 < nt[0]; ++t0) {
+            const double w0 = nt[0] == 1 ? 1.0 : wt[t0];
+            const int pb = p0[0] + dp[0] * t0;
+            for (int t1 = 0; t1 < (D == 3 ? nt[1] : 1); ++t1) {
+                const double w1 = (D == 3 && nt[1] == 4) ? wt[t1] : 1.0;
+                const int pc = D == 3 ? p0[1] + dp[1] * t1 : 1;
+                const int64_t o = D == 3 ? (int64_t)(pb - 1) * Ic + (pc - 1) : pb - 1;
+                double v;
+                if (exa) {
+                    const double c0 = C[(int64_t)(l0)*ss + o], c1 = C[(int64_t)(l0 + dl) * ss + o];
+                    const double c2 = C[(int64_t)(l0 + 2 * dl) * ss + o], c3 = C[(int64_t)(l0 + 3 * dl) * ss + o];
+                    v = 4.0 * c0 - 6.0 * c1 + 4.0 * c2 - c3;
+                } else {
+                    v = C[(int64_t)l0 * ss + o];
                 }
-                double R = 0.0;
-                for (int t0 = 0; t0 < cnt[0]; ++t0) {
-                    const double w0 = cnt[0] == 1 ? 1.0 : (t0 == 1 ? -6.0 : (t0 == 3 ? -1.0 : 4.0));
-                    for (int t1 = 0; t1 < cnt[1]; ++t1) {
-                        const double w1 = cnt[1] == 1 ? 1.0 : (t1 == 1 ? -6.0 : (t1 == 3 ? -1.0 : 4.0));
-                        for (int t2 = 0; t2 < cnt[2]; ++t2) {
-                            const double w2 =
-                                cnt[2] == 1 ? 1.0 : (t2 == 1 ? -6.0 : (t2 == 3 ? -1.0 : 4.0));
-                            const int p[3] = {i[0] + sg[0] * (t0 + 1), i[1] + sg[1] * (t1 + 1),
-                                              d == 3 ? i[2] + sg[2] * (t2 + 1) : 0};
-                            R += w0 * w1 * w2 * rcore(a, p);
-                        }
-                    }
-                }
-                out = R - rs_lookup(a, i);
+                R += w0 * w1 * v;
             }
-            a.D[fam][e] = out;
-            return;
         }
-        e -= 4 * per;
+        out = R - a.RS[fam][(int64_t)layer5(i[fam], Mf) * ss + e];
     }
+    a.D[fam][(int64_t)jj * ss + e] = out;
 }
 
 hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st)
 {
-    int64_t tot = 0;
-    for (int fam = 0; fam < a.geo.d; ++fam) {
-        int64_t c = 4;
-        for (int b = 0; b < a.geo.d; ++b)
-            if (b != fam) c *= a.geo.M[b] - 1;
-        tot += c;
+    const int d = a.geo.d;
+    int64_t mx = 1;
+    for (int fam = 0; fam < d; ++fam) mx = std::max(mx, shell_size(a.geo, fam));
+    const unsigned nb = (unsigned)((mx + NT - 1) / NT);
+    if (d == 3) {
+        hipLaunchKernelGGL(k_rcore<3>, dim3(nb, 8 * d), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(k_dcorr<3>, dim3(nb, 4 * d), dim3(NT), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_rcore<2>, dim3(nb, 8 * d), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(k_dcorr<2>, dim3(nb, 4 * d), dim3(NT), 0, st, a);
     }
-    hipLaunchKernelGGL(k_dcorr, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// g~ = -(L_h B) on the interior nodes next to the boundary, split into one
+// layer pair per axis (a node belongs to the lowest axis whose index is 1 or
+// M-1 there; other layers hold 0 at that node).  Every neighbour of such a
+// node is a grid node, so all are loaded at once and those off the boundary
+// are dropped.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(NT) void k_gtilde(GtArgs a)
+{
+    const Geo &g = a.geo;
+    const int fam = blockIdx.y >> 1, f = blockIdx.y & 1;
+    const int64_t ss = shell_size(g, fam);
+    const int e = blockIdx.x * NT + threadIdx.x;
+    if (e >= ss) return;
+    int ob[2] = {0, 0};
+    other_axes<D>(fam, ob);
+    int i[3] = {0, 0, 0};
+    i[fam] = f ? g.M[fam] - 1 : 1;
+    if (D == 3) {
+        const int Ic = g.M[ob[1]] - 1;
+        i[ob[0]] = 1 + e / Ic;
+        i[ob[1]] = 1 + e % Ic;
+    } else {
+        i[ob[0]] = 1 + e;
+    }
+    // with M = 2 both layers are the same nodes: keep only the first
+    bool owned = !(f == 1 && g.M[fam] == 2);
+    for (int b = 0; b < fam; ++b)
+        if (i[b] == 1 || i[b] == g.M[b] - 1) owned = false;
+    double s = 0.0;
+    if (owned) {
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+            double w = 1.0 / (g.h[p] * g.h[p]);
+#pragma unroll
+            for (int q = 0; q < D; ++q)
+                if (q != p) w -= 2.0 * g.c2[p][q] / (g.h[p] * g.h[p] * g.h[q] * g.h[q]);
+#pragma unroll
+            for (int sg = -1; sg <= 1; sg += 2) {
+                int j[3] = {i[0], i[1], i[2]};
+                j[p] += sg;
+                const double v = a.phi[node_off(a.n, D, j)];
+                s += on_boundary(g, j) ? w * v : 0.0;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < D; ++p)
+#pragma unroll
+            for (int q = p + 1; q < D; ++q) {
+                const double w = g.c2[p][q] / (g.h[p] * g.h[p] * g.h[q] * g.h[q]);
+#pragma unroll
+                for (int sp = -1; sp <= 1; sp += 2)
+#pragma unroll
+                    for (int sq = -1; sq <= 1; sq += 2) {
+                        int j[3] = {i[0], i[1], i[2]};
+                        j[p] += sp;
+                        j[q] += sq;
+                        const double v = a.phi[node_off(a.n, D, j)];
+                        s += on_boundary(g, j) ? w * v : 0.0;
+                    }
+            }
+        s = -s;
+    }
+    a.G[fam][(int64_t)f * ss + e] = s;
+}
+
+hipError_t launch_gtilde(const GtArgs &a, hipStream_t st)
+{
+    const int d = a.geo.d;
+    int64_t mx = 1;
+    for (int fam = 0; fam < d; ++fam) mx = std::max(mx, shell_size(a.geo, fam));
+    const unsigned nb = (unsigned)((mx + NT - 1) / NT);
+    if (d == 3)
+        hipLaunchKernelGGL(k_gtilde<3>, dim3(nb, 2 * d), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_gtilde<2>, dim3(nb, 2 * d), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 

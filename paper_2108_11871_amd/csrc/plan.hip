@@ -179,7 +179,7 @@ struct ips_plan_s {
     double *P[3] = {nullptr, nullptr, nullptr}; // parity-packed shell spectra
     double *P1T = nullptr;                      // 3D: transposed family-1 copy
     bool cube = false; // all families share sizes and chunking (batched launches)
-    double *V = nullptr; // 2D: sine coefficients of the sixth-order right-hand side
+    double *C[3] = {nullptr, nullptr, nullptr}; // sixth-order right-hand side on core layers
     DevBuf mem;
     // stage timing
     bool timing = false;
@@ -360,12 +360,8 @@ int plan_build(ips_plan p, hipStream_t st)
     int rc = p->mem.alloc(&p->B, vol * wsz);
     if (rc) return rc;
     if (d == 3) {
-        // A also holds the FP64 coefficients V of the sixth-order step (vol doubles)
         const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
-        rc = p->mem.alloc(&p->A, std::max(std::max(a1, a2) * asz, vol * sizeof(double)));
-        if (rc) return rc;
-    } else if (p->order == 6) {
-        rc = p->mem.alloc((void **)&p->V, vol * sizeof(double));
+        rc = p->mem.alloc(&p->A, std::max(a1, a2) * asz);
         if (rc) return rc;
     }
     // per-family sizes, then one contiguous buffer per kind (families back to back)
@@ -401,7 +397,7 @@ int plan_build(ips_plan p, hipStream_t st)
             tf += fsz[fam];
             ts += ssz[fam];
         }
-        double *bp, *bf, *bg, *bpk, *bt = nullptr, *bd = nullptr;
+        double *bp, *bf, *bg, *bpk, *bt = nullptr, *bd = nullptr, *bc = nullptr;
         if ((rc = p->mem.alloc((void **)&bp, tp * sizeof(double)))) return rc;
         if ((rc = p->mem.alloc((void **)&bf, tf * sizeof(double)))) return rc;
         if ((rc = p->mem.alloc((void **)&bg, 2 * ts * sizeof(double)))) return rc;
@@ -409,6 +405,7 @@ int plan_build(ips_plan p, hipStream_t st)
         if (p->order == 6) {
             if ((rc = p->mem.alloc((void **)&bt, 10 * ts * sizeof(double)))) return rc;
             if ((rc = p->mem.alloc((void **)&bd, 4 * ts * sizeof(double)))) return rc;
+            if ((rc = p->mem.alloc((void **)&bc, 8 * ts * sizeof(double)))) return rc;
         }
         size_t op = 0, of = 0, os = 0;
         for (int fam = 0; fam < d; ++fam) {
@@ -418,6 +415,7 @@ int plan_build(ips_plan p, hipStream_t st)
             p->P[fam] = bpk + 6 * os;
             if (bt) p->T[fam] = bt + 10 * os;
             if (bd) p->D[fam] = bd + 4 * os;
+            if (bc) p->C[fam] = bc + 8 * os;
             op += fsz[fam] * p->nch[fam];
             of += fsz[fam];
             os += ssz[fam];
@@ -809,18 +807,15 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     if (p->order == 6) {
         STAGE(IPS_STAGE_SHELL_R6);
         {
-            H2Args a{};
+            R6Args a{};
             a.geo = p->geo;
-            for (int q = 0; q < d; ++q) a.tab[q] = p->tab[q];
-            a.sh = sh;
-            a.V = d == 3 ? static_cast<double *>(p->A) : p->V;
-            a.T = p->T[d - 1];
-            IPS_HIP(launch_h2v(a, st));
-            for (int fam = 0; fam < d - 1; ++fam) {
-                a.axis = fam;
-                a.T = p->T[fam];
-                IPS_HIP(launch_h2c(a, st));
+            for (int q = 0; q < d; ++q) {
+                a.tab[q] = p->tab[q];
+                a.P[q] = p->P[q];
+                a.T[q] = p->T[q];
             }
+            a.P1T = p->P1T;
+            IPS_HIP(launch_r6t(a, st));
         }
         if ((rc = shell_dst_all(p, p->T, 10, true, st))) return rc;
         DcorrArgs a{};
@@ -829,6 +824,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         a.phi = phi;
         for (int fam = 0; fam < d; ++fam) {
             a.RS[fam] = p->T[fam];
+            a.C[fam] = p->C[fam];
             a.D[fam] = p->D[fam];
         }
         IPS_HIP(launch_dcorr(a, st));
