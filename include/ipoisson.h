@@ -97,7 +97,7 @@ int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int o
  * Green's-function kernels used by the boundary convolutions (Section 4),
  * and all device workspace.  Arguments as ips_solve, plus:
  *   precision : an ips_precision value
- *   flags     : 0 or IPS_FLAG_STAGE_TIMING
+ *   flags     : bitwise OR of IPS_FLAG_STAGE_TIMING and IPS_FLAG_ADJOINT (or 0)
  * On success *out receives the plan; release it with ips_plan_destroy.
  */
 int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int order,
@@ -117,10 +117,24 @@ int ips_execute(ips_plan p, const double *rho, double *phi, void *stream);
 
 /*
  * ips_execute_adjoint -- enqueue rho_bar = A^T phi_bar, where A is the
- * linear map rho -> phi that ips_execute applies (same plan).  rho_bar has
- * the grid's size; its boundary entries are set to 0 (phi ignores rho there).
+ * linear map rho -> phi of the method (Sections 2-5) at the plan's grid and
+ * order, i.e. the transpose of the FP64 solve.  Every step runs in FP64
+ * whatever the plan's precision.  The steps of the solve are transposed in
+ * reverse order: the sine-transform solves are symmetric; the transfer of
+ * boundary values (eq. harmonic4thOrderNH2D), the sixth-order stencils and
+ * their cubic extrapolation (eqs. 6thOrderRelation2D/3D) are applied
+ * transposed; the boundary sums of Section 4 become sums from the boundary
+ * nodes over the interior, evaluated with the same kernel spectra.
+ *   phi_bar : device array of the grid's size (all nodes, boundary included)
+ *   rho_bar : device array of the same size, must not overlap phi_bar;
+ *             its boundary entries are set to 0 (the solve ignores rho there)
  * Used for gradients: if J depends on phi, dJ/drho = A^T dJ/dphi.
+ * Workspace: a plan created with IPS_FLAG_ADJOINT holds it from the start;
+ * otherwise the first adjoint call allocates it (later calls allocate
+ * nothing).  About four interior volumes plus two grids (order 6) in FP64.
  */
+#define IPS_FLAG_ADJOINT 2u
+
 int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void *stream);
 
 /*
@@ -144,7 +158,8 @@ typedef enum {
     IPS_STAGE_FINAL = 8,  /* spectral combination + inverse along axis 0 (1D: whole solve) */
     IPS_STAGE_INV_Y = 9,  /* inverse sine transform along axis 1 (3D) */
     IPS_STAGE_INV_Z = 10, /* inverse sine transform along the last axis into phi */
-    IPS_STAGE_COUNT = 11
+    IPS_STAGE_ADJOINT = 11, /* one whole ips_execute_adjoint */
+    IPS_STAGE_COUNT = 12
 } ips_stage;
 
 const char *ips_stage_name(int stage);

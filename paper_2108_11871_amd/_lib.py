@@ -25,8 +25,9 @@ IPS_FP64 = 0
 IPS_MIXED_FP32 = 1
 IPS_MIXED_FP32_SLICES = 2
 IPS_FLAG_STAGE_TIMING = 1
+IPS_FLAG_ADJOINT = 2
 STAGES = ["rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces", "shell_gt", "shell_r6",
-          "final", "inv_y", "inv_z"]
+          "final", "inv_y", "inv_z", "adjoint"]
 
 # Every exported symbol with (restype, argtypes).
 _i64p = ctypes.POINTER(ctypes.c_int64)

@@ -11,8 +11,8 @@ from typing import Sequence
 import torch
 
 from . import _lib
-from ._lib import (IPS_FLAG_STAGE_TIMING, IPS_FP64, IPS_MIXED_FP32, IPS_MIXED_FP32_SLICES, STAGES,
-                   check, f64_array, i64_array, library_path, lib)
+from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_STAGE_TIMING, IPS_FP64, IPS_MIXED_FP32,
+                   IPS_MIXED_FP32_SLICES, STAGES, check, f64_array, i64_array, library_path, lib)
 
 PRECISIONS = {"fp64": IPS_FP64, "mixed_fp32": IPS_MIXED_FP32,
               "mixed_fp32_slices": IPS_MIXED_FP32_SLICES}
@@ -41,7 +41,7 @@ class Plan:
     """A reusable solve of one grid geometry (ips_plan_create / ips_execute)."""
 
     def __init__(self, shape: Sequence[int], h, order: int = 6, precision: str = "fp64",
-                 device=None, timing: bool = False):
+                 device=None, timing: bool = False, adjoint: bool = False):
         self.shape = tuple(int(v) for v in shape)
         d = len(self.shape)
         hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
@@ -55,7 +55,8 @@ class Plan:
         with torch.cuda.device(self.device):
             check(lib().ips_plan_create(ctypes.byref(handle), d, i64_array(self.shape),
                                         f64_array(self.h), self.order, PRECISIONS[precision],
-                                        IPS_FLAG_STAGE_TIMING if timing else 0))
+                                        (IPS_FLAG_STAGE_TIMING if timing else 0)
+                                        | (IPS_FLAG_ADJOINT if adjoint else 0)))
         self._h = handle
 
     @property
@@ -77,7 +78,10 @@ class Plan:
         return out
 
     def adjoint(self, phi_bar: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """rho_bar = A^T phi_bar for the map A: rho -> phi of this plan (FP64)."""
         _check_grid(phi_bar)
+        if tuple(phi_bar.shape) != self.shape:
+            raise ValueError("phi_bar shape %s does not match the plan %s" % (tuple(phi_bar.shape), self.shape))
         if out is None:
             out = torch.empty_like(phi_bar)
         with torch.cuda.device(phi_bar.device):

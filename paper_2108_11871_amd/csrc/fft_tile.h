@@ -456,6 +456,27 @@ __device__ void tile_store(const T *buf, int rs, int row0, TO *dst, int nrows, i
     }
 }
 
+// As tile_store, but the scaled values are added to the destination.
+template <typename T, typename TO, int NT>
+__device__ void tile_store_acc(const T *buf, int rs, int row0, TO *dst, int nrows, int ncols,
+                               int64_t rsd, int64_t csd, T scale, int lgW)
+{
+    if (rsd == 1 && csd != 1) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int c = wave; c < ncols; c += NT / 64) {
+            TO *col = dst + c * csd;
+            for (int r = lane; r < nrows; r += 64) col[r] += (TO)(scale * buf[(row0 + r) * rs + c]);
+        }
+    } else {
+        const int cm = (1 << lgW) - 1;
+        const int tot = nrows << lgW;
+        for (int e = threadIdx.x; e < tot; e += NT) {
+            const int c = e & cm, r = e >> lgW;
+            if (c < ncols) dst[r * rsd + c * csd] += (TO)(scale * buf[(row0 + r) * rs + c]);
+        }
+    }
+}
+
 // Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD works on
 // one contiguous range of logical tiles (neighbouring tiles share its L2).
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks)

@@ -8,7 +8,12 @@
 
 namespace ips {
 
-enum InMode { IN_ZPAD = 0, IN_EVEN = 1, IN_HERM = 2, IN_SPECS = 3 };
+// IN_ZPAD  : f_1..f_{M-1} at positions 1..M-1 of a zero-padded length-N sequence
+// IN_ZPAD0 : f_0..f_M at positions 0..M (zeros at M+1..N-1)
+// IN_EVEN  : f_0..f_M mirrored to length N
+// IN_HERM  : slot rows C_0..C_M, S_1..S_{M-1} -> hermitian synthesis
+// IN_SPECS : S rows only (C = 0) -> hermitian synthesis (inverse DST-I)
+enum InMode { IN_ZPAD = 0, IN_EVEN = 1, IN_HERM = 2, IN_SPECS = 3, IN_ZPAD0 = 4 };
 
 // Generic pencil pass: one transform along the tile rows, tile columns are a
 // block of W consecutive columns, grid.y runs over a batch index.
@@ -28,6 +33,7 @@ struct PassArgs {
     const cx<double> *tw; // N twiddles exp(-2 pi i t / N)
     int nsum;             // IN_HERM: input element = sum of nsum copies (0/1: plain load)
     int64_t sstride;      // spacing of those copies
+    int accum;            // add the result into the output instead of storing it
 };
 
 // Boundary convolution, contraction over the tile columns (faces normal to
@@ -144,6 +150,42 @@ struct BwriteArgs {
     double scale[3];
     double *phi;
 };
+
+// Adjoint (rho_bar = A^T phi_bar), FP64.
+struct AdjArgs {
+    Geo geo;
+    int64_t n[3];
+    AxisTabs tab[3];
+    double *LF[3];       // boundary weights per face family [2][M_b + 1][M_c + 1]
+    int64_t lf_size[3];  // entries of LF[fam]
+    int fb[3], fc[3];    // in-face axes (b, c) of each family, c contiguous (3D)
+};
+
+// Face-to-slice expansion (first transform), see k_expand.
+struct ExpandArgs {
+    int d;
+    const double *LH0, *LH1; // slot spectra of the two faces
+    const double *K;         // kernel spectra K_hat[dd][kb][kc] (2D: [dd][k])
+    int64_t Kd, Kb;
+    int Ms; // M of the face-normal axis
+    int Mb; // M of the column axis (3D)
+    double *out;
+    int64_t ors, ocs, obs;
+    int ncols, nbatch, W;
+    double scale;
+    int accum;
+    FftDesc fd;
+    const cx<double> *tw;
+};
+
+hipError_t launch_adj_spec(const AdjArgs &a, double *X, double *Y, hipStream_t st);
+hipError_t launch_adj_r6(const AdjArgs &a, const double *A, double *F, double *U, hipStream_t st);
+hipError_t launch_adj_lambda(const AdjArgs &a, const double *w, const double *y1, const double *y2,
+                             const double *U, hipStream_t st);
+hipError_t launch_zero_boundary(const AdjArgs &a, double *out, hipStream_t st);
+hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
+hipError_t launch_adj_1d(const double *w, double *out, int M, double h, const FftDesc &fd,
+                         const cx<double> *tw, const AxisTabs &tab, hipStream_t st);
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
 // in_f32: input data in FP32 (else FP64); f32: transform type

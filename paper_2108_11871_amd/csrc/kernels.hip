@@ -61,6 +61,10 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a)
         zero_rows<T, NT>(buf, rs, lgW, 1 + a.nrows_in, N);
         tile_load<T, TI, NT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
+    } else if (a.in_mode == IN_ZPAD0) {
+        zero_rows<T, NT>(buf, rs, lgW, a.nrows_in, N);
+        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        __syncthreads();
     } else if (a.in_mode == IN_EVEN) {
         tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
@@ -81,8 +85,11 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a)
         inv = true;
     }
     fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, inv);
-    if (a.in_mode == IN_ZPAD) post_cs<T, MAXE, NT>(buf, rs, lgs, M);
-    tile_store<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+    if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NT>(buf, rs, lgs, M);
+    if (a.accum)
+        tile_store_acc<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+    else
+        tile_store<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
 }
 
 static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }

@@ -181,6 +181,13 @@ struct ips_plan_s {
     bool cube = false; // all families share sizes and chunking (batched launches)
     double *C[3] = {nullptr, nullptr, nullptr}; // sixth-order right-hand side on core layers
     DevBuf mem;
+    // adjoint workspace (allocated by IPS_FLAG_ADJOINT or the first adjoint call)
+    bool adj_ready = false;
+    double *AX = nullptr, *AY = nullptr, *AX2 = nullptr; // interior volumes
+    double *AF = nullptr, *AU = nullptr;                 // grid-shaped (order 6)
+    double *AZ = nullptr;                                // 3D expansion scratch
+    double *LF[3] = {nullptr, nullptr, nullptr};         // face weights
+    double *LH[3] = {nullptr, nullptr, nullptr};         // their slot spectra
     // stage timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -196,7 +203,7 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
 {
     if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
     if (!n || !h) return fail(IPS_E_INVALID_ARG, "n and h must not be NULL");
-    if (flags & ~IPS_FLAG_STAGE_TIMING) return fail(IPS_E_INVALID_ARG, "unknown flag bits");
+    if (flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_ADJOINT)) return fail(IPS_E_INVALID_ARG, "unknown flag bits");
     if (precision != IPS_FP64 && precision != IPS_MIXED_FP32 && precision != IPS_MIXED_FP32_SLICES)
         return fail(IPS_E_INVALID_ARG, "unknown precision");
     if (d >= 2 && order != 4 && order != 6) return fail(IPS_E_INVALID_ARG, "order must be 4 or 6");
@@ -926,6 +933,346 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     return IPS_OK;
 }
 
+// ---- adjoint ---------------------------------------------------------------------------
+
+int adj_alloc(ips_plan p)
+{
+    if (p->adj_ready || p->d == 1) {
+        p->adj_ready = true;
+        return IPS_OK;
+    }
+    const int d = p->d;
+    size_t vol = 1, grid = 1;
+    for (int a = 0; a < d; ++a) {
+        vol *= (size_t)p->I[a];
+        grid *= (size_t)p->n[a];
+    }
+    int rc;
+    if ((rc = p->mem.alloc((void **)&p->AX, vol * sizeof(double)))) return rc;
+    if ((rc = p->mem.alloc((void **)&p->AY, vol * sizeof(double)))) return rc;
+    if (p->order == 6) {
+        if ((rc = p->mem.alloc((void **)&p->AX2, vol * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&p->AF, grid * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&p->AU, grid * sizeof(double)))) return rc;
+    }
+    size_t zmax = 0;
+    for (int fam = 0; fam < d; ++fam) {
+        int b, c;
+        kaxes(d, fam, b, c);
+        const size_t lf = 2 * (size_t)(p->M[b] + 1) * (d == 3 ? (size_t)(p->M[c] + 1) : 1);
+        const size_t lh = 2 * (size_t)p->N[b] * (d == 3 ? (size_t)p->N[c] : 1);
+        if ((rc = p->mem.alloc((void **)&p->LF[fam], lf * sizeof(double)))) return rc;
+        if ((rc = p->mem.alloc((void **)&p->LH[fam], lh * sizeof(double)))) return rc;
+        if (d == 3) zmax = std::max(zmax, (size_t)p->I[fam] * p->N[b] * p->I[c]);
+    }
+    if (d == 3 && (rc = p->mem.alloc((void **)&p->AZ, zmax * sizeof(double)))) return rc;
+    p->adj_ready = true;
+    return IPS_OK;
+}
+
+// Raw DST-I of an interior field over all axes.  src points at node (1, 1, 1)
+// of an array with strides sst[] (a grid or a packed interior); X receives
+// the packed coefficients [k0][k1][k2].
+int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStream_t st)
+{
+    const int *I = p->I, *M = p->M;
+    PassArgs a{};
+    a.in_mode = IN_ZPAD;
+    a.scale = 1.0;
+    if (p->d == 3) {
+        a.in = src;
+        a.out = X;
+        a.irs = sst[2];
+        a.ics = sst[1];
+        a.ibs = sst[0];
+        a.ors = 1;
+        a.ocs = I[2];
+        a.obs = (int64_t)I[1] * I[2];
+        a.nrows_in = I[2];
+        a.ncols = I[1];
+        a.nbatch = I[0];
+        a.out_r0 = M[2] + 1;
+        a.out_nrows = I[2];
+        int rc = run_pass(a, p->fd[2], p->tw[2], false, false, st);
+        if (rc) return rc;
+        PassArgs b = a;
+        b.in = X;
+        b.irs = b.ors = I[2];
+        b.ics = b.ocs = 1;
+        b.ibs = b.obs = (int64_t)I[1] * I[2];
+        b.nrows_in = I[1];
+        b.ncols = I[2];
+        b.nbatch = I[0];
+        b.out_r0 = M[1] + 1;
+        b.out_nrows = I[1];
+        b.W = 0;
+        if ((rc = run_pass(b, p->fd[1], p->tw[1], false, false, st))) return rc;
+        PassArgs c = b;
+        c.irs = c.ors = (int64_t)I[1] * I[2];
+        c.ics = c.ocs = 1;
+        c.ibs = c.obs = I[2];
+        c.nrows_in = I[0];
+        c.ncols = I[2];
+        c.nbatch = I[1];
+        c.out_r0 = M[0] + 1;
+        c.out_nrows = I[0];
+        c.W = 0;
+        return run_pass(c, p->fd[0], p->tw[0], false, false, st);
+    }
+    a.in = src;
+    a.out = X;
+    a.irs = sst[1];
+    a.ics = sst[0];
+    a.ors = 1;
+    a.ocs = I[1];
+    a.nrows_in = I[1];
+    a.ncols = I[0];
+    a.nbatch = 1;
+    a.out_r0 = M[1] + 1;
+    a.out_nrows = I[1];
+    int rc = run_pass(a, p->fd[1], p->tw[1], false, false, st);
+    if (rc) return rc;
+    PassArgs b = a;
+    b.in = X;
+    b.irs = b.ors = I[1];
+    b.ics = b.ocs = 1;
+    b.nrows_in = I[0];
+    b.ncols = I[1];
+    b.out_r0 = M[0] + 1;
+    b.out_nrows = I[0];
+    b.W = 0;
+    return run_pass(b, p->fd[0], p->tw[0], false, false, st);
+}
+
+// Inverse of vol_fwd's coefficients (raw DST-I again, scaled by 1/2 per axis
+// as the synthesis returns twice the sine sum): X is overwritten, the result
+// goes to dst (node (1, 1, 1), strides dst_st[]).
+int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream_t st)
+{
+    const int *I = p->I, *M = p->M;
+    PassArgs a{};
+    a.in_mode = IN_SPECS;
+    a.scale = 0.5;
+    a.out_r0 = 1;
+    if (p->d == 3) {
+        a.in = a.out = X;
+        a.irs = a.ors = (int64_t)I[1] * I[2];
+        a.ics = a.ocs = 1;
+        a.ibs = a.obs = I[2];
+        a.nrows_in = I[0];
+        a.ncols = I[2];
+        a.nbatch = I[1];
+        a.out_nrows = I[0];
+        int rc = run_pass(a, p->fd[0], p->tw[0], false, false, st);
+        if (rc) return rc;
+        PassArgs b = a;
+        b.irs = b.ors = I[2];
+        b.ics = b.ocs = 1;
+        b.ibs = b.obs = (int64_t)I[1] * I[2];
+        b.nrows_in = I[1];
+        b.ncols = I[2];
+        b.nbatch = I[0];
+        b.out_nrows = I[1];
+        b.W = 0;
+        if ((rc = run_pass(b, p->fd[1], p->tw[1], false, false, st))) return rc;
+        PassArgs c = b;
+        c.out = dst;
+        c.irs = 1;
+        c.ics = I[2];
+        c.ibs = (int64_t)I[1] * I[2];
+        c.ors = dst_st[2];
+        c.ocs = dst_st[1];
+        c.obs = dst_st[0];
+        c.nrows_in = I[2];
+        c.ncols = I[1];
+        c.nbatch = I[0];
+        c.out_nrows = I[2];
+        c.W = 0;
+        (void)M;
+        return run_pass(c, p->fd[2], p->tw[2], false, false, st);
+    }
+    a.in = a.out = X;
+    a.irs = a.ors = I[1];
+    a.ics = a.ocs = 1;
+    a.nrows_in = I[0];
+    a.ncols = I[1];
+    a.nbatch = 1;
+    a.out_nrows = I[0];
+    int rc = run_pass(a, p->fd[0], p->tw[0], false, false, st);
+    if (rc) return rc;
+    PassArgs b = a;
+    b.out = dst;
+    b.irs = 1;
+    b.ics = I[1];
+    b.ors = dst_st[1];
+    b.ocs = dst_st[0];
+    b.nrows_in = I[1];
+    b.ncols = I[0];
+    b.out_nrows = I[1];
+    b.W = 0;
+    return run_pass(b, p->fd[1], p->tw[1], false, false, st);
+}
+
+int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
+{
+    const int d = p->d;
+    const int *I = p->I, *M = p->M, *N = p->N;
+    if (d == 1) {
+        IPS_HIP(launch_adj_1d(w, out, M[0], p->h[0], p->fd[0], p->tw[0], p->tab[0], st));
+        return IPS_OK;
+    }
+    int64_t gst[3] = {1, 1, 1}, pst[3] = {1, 1, 1};
+    for (int a = d - 2; a >= 0; --a) {
+        gst[a] = gst[a + 1] * p->n[a + 1];
+        pst[a] = pst[a + 1] * I[a + 1];
+    }
+    int64_t off = 0;
+    for (int a = 0; a < d; ++a) off += gst[a];
+    AdjArgs aa{};
+    aa.geo = p->geo;
+    for (int a = 0; a < 3; ++a) aa.n[a] = a < d ? p->n[a] : 1;
+    for (int a = 0; a < d; ++a) aa.tab[a] = p->tab[a];
+    for (int fam = 0; fam < d; ++fam) {
+        int b, c;
+        kaxes(d, fam, b, c);
+        aa.fb[fam] = b;
+        aa.fc[fam] = c;
+        aa.LF[fam] = p->LF[fam];
+        aa.lf_size[fam] = 2 * (int64_t)(M[b] + 1) * (d == 3 ? (M[c] + 1) : 1);
+    }
+    const bool six = p->order == 6;
+    int rc;
+    // phi_star part and a = L0^-1 w_I from one forward transform
+    if ((rc = vol_fwd(p, w + off, gst, p->AX, st))) return rc;
+    IPS_HIP(launch_adj_spec(aa, p->AX, p->AY, st));
+    if ((rc = vol_inv(p, p->AY, out + off, gst, st))) return rc;
+    if ((rc = vol_inv(p, p->AX, p->AX, pst, st))) return rc;
+    if (six) {
+        IPS_HIP(launch_adj_r6(aa, p->AX, p->AF, p->AU, st));
+        if ((rc = vol_fwd(p, p->AU + off, gst, p->AX2, st))) return rc;
+        IPS_HIP(launch_adj_spec(aa, p->AX2, nullptr, st));
+        if ((rc = vol_inv(p, p->AX2, p->AX2, pst, st))) return rc;
+    }
+    IPS_HIP(launch_zero_boundary(aa, out, st));
+    IPS_HIP(launch_adj_lambda(aa, w, p->AX, six ? p->AX2 : nullptr, six ? p->AU : nullptr, st));
+    double vh = 1.0;
+    for (int a = 0; a < d; ++a) vh *= p->h[a];
+    for (int fam = 0; fam < d; ++fam) {
+        const int b = aa.fb[fam], c = aa.fc[fam];
+        // slot spectra of the two faces
+        if (d == 3) {
+            PassArgs a{};
+            a.in = p->LF[fam];
+            a.out = p->LH[fam];
+            a.irs = 1;
+            a.ics = M[c] + 1;
+            a.ibs = (int64_t)(M[b] + 1) * (M[c] + 1);
+            a.ors = 1;
+            a.ocs = N[c];
+            a.obs = (int64_t)N[b] * N[c];
+            a.nrows_in = M[c] + 1;
+            a.ncols = M[b] + 1;
+            a.nbatch = 2;
+            a.in_mode = IN_ZPAD0;
+            a.out_r0 = 0;
+            a.out_nrows = N[c];
+            a.scale = 1.0;
+            if ((rc = run_pass(a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            PassArgs b2{};
+            b2.in = b2.out = p->LH[fam];
+            b2.irs = b2.ors = N[c];
+            b2.ics = b2.ocs = 1;
+            b2.ibs = b2.obs = (int64_t)N[b] * N[c];
+            b2.nrows_in = M[b] + 1;
+            b2.ncols = N[c];
+            b2.nbatch = 2;
+            b2.in_mode = IN_ZPAD0;
+            b2.out_r0 = 0;
+            b2.out_nrows = N[b];
+            b2.scale = 1.0;
+            if ((rc = run_pass(b2, p->fd[b], p->tw[b], false, false, st))) return rc;
+            // slices: product with the kernel spectra, synthesis along c, then along b
+            ExpandArgs e{};
+            e.d = 3;
+            e.LH0 = p->LH[fam];
+            e.LH1 = p->LH[fam] + (int64_t)N[b] * N[c];
+            e.K = p->K[fam];
+            e.Kd = (int64_t)(M[b] + 1) * (M[c] + 1);
+            e.Kb = M[c] + 1;
+            e.Ms = M[fam];
+            e.Mb = M[b];
+            e.out = p->AZ;
+            e.ors = 1;
+            e.ocs = I[c];
+            e.obs = (int64_t)N[b] * I[c];
+            e.ncols = N[b];
+            e.nbatch = I[fam];
+            e.W = tile_width(N[c], tile_work(false), N[b]);
+            e.scale = 1.0 / N[c];
+            e.accum = 0;
+            e.fd = p->fd[c];
+            e.tw = p->tw[c];
+            IPS_HIP(launch_expand(e, st));
+            PassArgs z{};
+            z.in = p->AZ;
+            z.out = out + off;
+            z.irs = I[c];
+            z.ics = 1;
+            z.ibs = (int64_t)N[b] * I[c];
+            z.ors = gst[b];
+            z.ocs = gst[c];
+            z.obs = gst[fam];
+            z.nrows_in = N[b];
+            z.ncols = I[c];
+            z.nbatch = I[fam];
+            z.in_mode = IN_HERM;
+            z.out_r0 = 1;
+            z.out_nrows = I[b];
+            z.scale = vh / N[b];
+            z.accum = 1;
+            if ((rc = run_pass(z, p->fd[b], p->tw[b], false, false, st))) return rc;
+        } else {
+            PassArgs a{};
+            a.in = p->LF[fam];
+            a.out = p->LH[fam];
+            a.irs = 1;
+            a.ics = M[b] + 1;
+            a.ors = 1;
+            a.ocs = N[b];
+            a.nrows_in = M[b] + 1;
+            a.ncols = 2;
+            a.nbatch = 1;
+            a.in_mode = IN_ZPAD0;
+            a.out_r0 = 0;
+            a.out_nrows = N[b];
+            a.scale = 1.0;
+            if ((rc = run_pass(a, p->fd[b], p->tw[b], false, false, st))) return rc;
+            ExpandArgs e{};
+            e.d = 2;
+            e.LH0 = p->LH[fam];
+            e.LH1 = p->LH[fam] + N[b];
+            e.K = p->K[fam];
+            e.Kd = M[b] + 1;
+            e.Kb = 0;
+            e.Ms = M[fam];
+            e.Mb = 0;
+            e.out = out + off;
+            e.ors = gst[b];
+            e.ocs = gst[fam];
+            e.obs = 0;
+            e.ncols = I[fam];
+            e.nbatch = 1;
+            e.W = tile_width(N[b], tile_work(false), I[fam]);
+            e.scale = vh / N[b];
+            e.accum = 1;
+            e.fd = p->fd[b];
+            e.tw = p->tw[b];
+            IPS_HIP(launch_expand(e, st));
+        }
+    }
+    return IPS_OK;
+}
+
 int flush_timing(ips_plan p)
 {
     for (auto &r : p->ev_rec) {
@@ -1006,6 +1353,7 @@ int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int
         return fail(IPS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
     rc = plan_build(p, nullptr);
+    if (rc == IPS_OK && (flags & IPS_FLAG_ADJOINT)) rc = adj_alloc(p);
     if (rc == IPS_OK) {
         e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("plan build: ") + hipGetErrorString(e));
@@ -1042,16 +1390,28 @@ int ips_execute(ips_plan p, const double *rho, double *phi, void *stream)
 
 int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void *stream)
 {
-    (void)stream;
-    if (!p || !phi_bar || !rho_bar) return fail(IPS_E_INVALID_ARG, "NULL argument");
-    return fail(IPS_E_UNSUPPORTED, "adjoint not available in this build");
+    if (!p) return fail(IPS_E_INVALID_ARG, "plan must not be NULL");
+    if (!phi_bar || !rho_bar) return fail(IPS_E_INVALID_ARG, "phi_bar and rho_bar must not be NULL");
+    size_t cnt = 1;
+    for (int a = 0; a < p->d; ++a) cnt *= (size_t)p->n[a];
+    const char *r0 = reinterpret_cast<const char *>(phi_bar), *p0 = reinterpret_cast<const char *>(rho_bar);
+    if (r0 < p0 + cnt * sizeof(double) && p0 < r0 + cnt * sizeof(double))
+        return fail(IPS_E_INVALID_ARG, "phi_bar and rho_bar must not overlap");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
+    int rc = adj_alloc(p);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    STAGE(IPS_STAGE_ADJOINT);
+    return execute_adjoint(p, phi_bar, rho_bar, st);
 }
 
 const char *ips_stage_name(int stage)
 {
     static const char *names[IPS_STAGE_COUNT] = {
         "rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces",
-        "shell_gt", "shell_r6", "final", "inv_y", "inv_z"};
+        "shell_gt", "shell_r6", "final", "inv_y", "inv_z", "adjoint"};
     if (stage < 0 || stage >= IPS_STAGE_COUNT) return "unknown";
     return names[stage];
 }

@@ -1,0 +1,150 @@
+"""The HIP adjoint rho_bar = A^T phi_bar (ips_execute_adjoint) and the
+autograd function built on it.
+
+Bars:
+* parity with the oracle's adjoint (a separate transposed chain, itself
+  pinned by dot-product and dense-transpose tests): 1e-12 relative, max norm;
+* dot-product identity <A v, w> = <v, A^T w> between the HIP forward and the
+  HIP adjoint at sizes the oracle cannot reach: 1e-12 relative;
+* gradients of J(rho) = 1/2 |phi(rho) - phi_target|^2 through SolveFn
+  against central differences, which are exact for a quadratic J
+  (rounding only): 1e-10 relative in FP64.
+"""
+import numpy as np
+import pytest
+
+from oracle import poisson as P
+from paper_2108_11871_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _gpu_adjoint(w, h, order, precision="fp64", flag=False):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import to_dev
+
+    plan = api.Plan(w.shape, h, order=order, precision=precision, adjoint=flag)
+    out = plan.adjoint(to_dev(w))
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    plan.close()
+    return res
+
+
+@pytest.mark.parametrize("shape,h,order", [
+    ((17,), (0.1,), 4), ((64,), (0.03,), 4), ((257,), (2.0 / 256,), 4),
+    ((9, 11), (0.2, 0.13), 4), ((9, 11), (0.2, 0.13), 6), ((12, 13), (0.1, 0.07), 6),
+    ((33, 41), (0.06, 0.05), 6), ((50, 38), (0.04, 0.05), 4), ((3, 5), (0.5, 0.3), 4),
+    ((8, 9, 10), (0.2, 0.17, 0.11), 4), ((8, 9, 10), (0.2, 0.17, 0.11), 6),
+    ((10, 11, 12), (0.1, 0.12, 0.09), 6), ((17, 21, 19), (0.1, 0.08, 0.09), 6),
+    ((24, 17, 31), (0.05, 0.07, 0.04), 4), ((3, 4, 5), (0.4, 0.3, 0.2), 4),
+])
+def test_adjoint_matches_oracle(shape, h, order):
+    from gpu_util import banner, rel_err
+
+    banner("adjoint shape=%s order=%d" % (shape, order))
+    rng = np.random.default_rng(sum(shape) * 7 + order)
+    w = rng.standard_normal(shape)
+    ref = P.adjoint(w, h, order)
+    got = _gpu_adjoint(w, h, order)
+    err = rel_err(got, ref)
+    print("  rel err %.3e" % err, flush=True)
+    assert err < TOL
+    assert np.all(got[P.boundary_mask(shape)] == 0.0)
+
+
+def test_adjoint_33_cube_order6():
+    from gpu_util import banner, rel_err
+
+    banner("adjoint 33^3 order 6")
+    n = 33
+    rho, h, _ = I.workload_bumps_3d(n, seed=11)
+    w = rho + 0.1 * np.random.default_rng(2).standard_normal(rho.shape)
+    ref = P.adjoint(w, h, 6)
+    got = _gpu_adjoint(w, h, 6)
+    err = rel_err(got, ref)
+    print("  rel err %.3e" % err, flush=True)
+    assert err < TOL
+
+
+def test_adjoint_independent_of_precision_and_preallocation():
+    """The adjoint runs in FP64 whatever the plan's precision; the workspace
+    flag changes only when it is allocated."""
+    shape, h = (20, 18, 22), (0.1, 0.11, 0.09)
+    w = np.random.default_rng(5).standard_normal(shape)
+    ref = _gpu_adjoint(w, h, 6)
+    assert np.array_equal(_gpu_adjoint(w, h, 6, flag=True), ref)
+    assert np.array_equal(_gpu_adjoint(w, h, 6, precision="mixed_fp32_slices"), ref)
+
+
+@pytest.mark.parametrize("shape,order", [((65, 65, 65), 6), ((129, 97, 113), 6), ((129, 129, 129), 4),
+                                         ((513, 385), 6)])
+def test_dot_product_identity_large(shape, order):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner
+
+    banner("dot product shape=%s order=%d" % (shape, order))
+    h = tuple(2.0 / (s - 1) for s in shape)
+    plan = api.Plan(shape, h, order=order)
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    v = torch.randn(shape, dtype=torch.float64, device="cuda:0", generator=g)
+    w = torch.randn(shape, dtype=torch.float64, device="cuda:0", generator=g)
+    Av = plan(v)
+    Atw = plan.adjoint(w)
+    inner = tuple(slice(1, -1) for _ in shape)
+    lhs = float((Av * w).sum())
+    rhs = float((v[inner] * Atw[inner]).sum())
+    # scale of the sums: sum |Av| |w|
+    scale = float((Av.abs() * w.abs()).sum())
+    plan.close()
+    print("  <Av,w> %.15e  <v,A^T w> %.15e  rel %.2e" % (lhs, rhs, abs(lhs - rhs) / scale), flush=True)
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("shape,precision", [((33, 33, 33), "fp64"), ((65, 49, 57), "fp64"),
+                                             ((65, 65), "fp64"), ((33, 33, 33), "mixed_fp32_slices")])
+def test_autograd_gradient_matches_central_differences(shape, precision):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner, to_dev
+
+    banner("autograd shape=%s %s" % (shape, precision))
+    d = len(shape)
+    rho_np, h, _ = I.workload_bumps(shape, seed=4)
+    tgt_np, _, _ = I.workload_bumps(shape, seed=5)
+    plan = api.Plan(shape, h, order=6, precision=precision)
+    target = plan(to_dev(tgt_np)).detach()
+    rho = to_dev(rho_np).requires_grad_(True)
+    phi = api.SolveFn.apply(rho, plan)
+    J = 0.5 * ((phi - target) ** 2).sum()
+    J.backward()
+    grad = rho.grad.detach()
+
+    def Jof(r):
+        with torch.no_grad():
+            p = plan(r)
+            return 0.5 * float(((p - target) ** 2).sum())
+
+    rng = np.random.default_rng(6)
+    inner = tuple(slice(1, -1) for _ in range(d))
+    worst = 0.0
+    for t in range(4):
+        if t % 2 == 0:
+            v_np, _, _ = I.workload_bumps(shape, seed=100 + t)
+        else:
+            v_np = np.zeros(shape)
+            v_np[inner] = rng.standard_normal(tuple(s - 2 for s in shape))
+        v = to_dev(v_np)
+        tau = float(rho.detach().abs().max() / v.abs().max())
+        fd = (Jof(rho.detach() + tau * v) - Jof(rho.detach() - tau * v)) / (2.0 * tau)
+        an = float((grad * v).sum())
+        rel = abs(fd - an) / max(abs(fd), abs(an), 1e-300)
+        worst = max(worst, rel)
+        print("  direction %d: <grad,v> %.12e  FD %.12e  rel %.2e" % (t, an, fd, rel), flush=True)
+    plan.close()
+    # FP64: only rounding separates the two; the mixed forward perturbs J by ~1e-7 relative
+    assert worst < (1e-10 if precision == "fp64" else 1e-4)
