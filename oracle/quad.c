@@ -12,7 +12,10 @@
  * distance to every interior node with nonzero rho is positive.
  *
  * Interior nodes whose rho is exactly zero contribute exactly zero and are
- * skipped; every other term is summed in plain double precision.
+ * skipped.  Each term is evaluated in double precision and accumulated in
+ * long double (x87 extended precision): a sum of ~1e7 double terms rounded
+ * step by step drifts by ~1e-12 relative, which is the size of the parity
+ * bar, while the extended accumulator keeps the sum exact to ~1e-16.
  *
  * Layout: rho is row-major over n[0] x ... x n[d-1], last axis fastest.
  * targets holds ntargets * d node indices.  out receives ntargets values.
@@ -69,16 +72,16 @@ int oracle_boundary_direct(int d, const int64_t *n, const double *h,
     for (int64_t t = 0; t < ntargets; ++t) {
         double tx[3] = {0.0, 0.0, 0.0};
         for (int a = 0; a < d; ++a) tx[3 - d + a] = (double)targets[t * d + a];
-        double acc = 0.0;
+        long double acc = 0.0L;
         for (int64_t s = 0; s < ns; ++s) {
             double r2 = 0.0;
             for (int a = 0; a < 3; ++a) {
                 double dx = (tx[a] - sx[4 * s + a]) * hh[a];
                 r2 += dx * dx;
             }
-            acc += green(d, sqrt(r2)) * sx[4 * s + 3];
+            acc += (long double)(green(d, sqrt(r2)) * sx[4 * s + 3]);
         }
-        out[t] = acc * vol;
+        out[t] = (double)acc * vol;
     }
     free(sx);
     return 0;
@@ -88,7 +91,8 @@ int oracle_boundary_direct(int d, const int64_t *n, const double *h,
  * Transpose of oracle_boundary_direct over the boundary nodes:
  *     out[s] = prod_i h_i * sum_{t} G(|x_t - x_s|) lam[t]      for every interior node s
  * where t runs over the listed target nodes with weights lam[t].  out has the
- * full grid's size; its boundary entries are set to 0.
+ * full grid's size; its boundary entries are set to 0.  Accumulated in long
+ * double like oracle_boundary_direct.
  */
 int oracle_boundary_adjoint(int d, const int64_t *n, const double *h, int64_t ntargets,
                             const int64_t *targets, const double *lam, double *out)
@@ -128,16 +132,16 @@ int oracle_boundary_adjoint(int d, const int64_t *n, const double *h, int64_t nt
             continue;
         }
         const double s[3] = {(double)i, (double)j, (double)k};
-        double acc = 0.0;
+        long double acc = 0.0L;
         for (int64_t t = 0; t < nt; ++t) {
             double r2 = 0.0;
             for (int a = 0; a < 3; ++a) {
                 double dx = (tx[4 * t + a] - s[a]) * hh[a];
                 r2 += dx * dx;
             }
-            acc += green(d, sqrt(r2)) * tx[4 * t + 3];
+            acc += (long double)(green(d, sqrt(r2)) * tx[4 * t + 3]);
         }
-        out[e] = acc * vol;
+        out[e] = (double)acc * vol;
     }
     free(tx);
     return 0;
