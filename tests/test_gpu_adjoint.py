@@ -148,3 +148,52 @@ def test_autograd_gradient_matches_central_differences(shape, precision):
     plan.close()
     # FP64: only rounding separates the two; the mixed forward perturbs J by ~1e-7 relative
     assert worst < (1e-10 if precision == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32_slices"])
+def test_autograd_257_cube_sixteen_directions(precision):
+    """J = 1/2 |phi(rho) - phi_target|^2 on 257^3 (rho seed 4, phi_target the
+    FP64 solve of the bump sum with seed 5): <dJ/drho, v> against central
+    differences along 8 bump-sum and 8 white-noise directions."""
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner, to_dev
+
+    banner("autograd 257^3 %s" % precision)
+    n = 257
+    rho_np, h, _ = I.workload_bumps_3d(n, seed=4)
+    tgt_np, _, _ = I.workload_bumps_3d(n, seed=5)
+    ref_plan = api.Plan(rho_np.shape, h, order=6)
+    target = ref_plan(to_dev(tgt_np)).detach()
+    ref_plan.close()
+    del tgt_np
+    plan = api.Plan(rho_np.shape, h, order=6, precision=precision)
+    rho = to_dev(rho_np).requires_grad_(True)
+    phi = api.SolveFn.apply(rho, plan)
+    J = 0.5 * ((phi - target) ** 2).sum()
+    J.backward()
+    grad = rho.grad.detach()
+    r0 = rho.detach()
+
+    def Jof(r):
+        with torch.no_grad():
+            return 0.5 * float(((plan(r) - target) ** 2).sum())
+
+    gen = torch.Generator(device="cuda:0").manual_seed(6)
+    worst = 0.0
+    for t in range(16):
+        if t < 8:
+            c, w, a = I.bump_params(600 + t, 3)
+            v = to_dev(I.bump_sum((n, n, n), c, w, a, 10))
+        else:
+            v = torch.zeros_like(r0)
+            v[1:-1, 1:-1, 1:-1] = torch.randn((n - 2,) * 3, dtype=torch.float64, device="cuda:0",
+                                              generator=gen)
+        tau = float(r0.abs().max() / v.abs().max())
+        fd = (Jof(r0 + tau * v) - Jof(r0 - tau * v)) / (2.0 * tau)
+        an = float((grad * v).sum())
+        rel = abs(fd - an) / max(abs(fd), abs(an), 1e-300)
+        worst = max(worst, rel)
+        print("  direction %2d: <grad,v> %.12e  FD %.12e  rel %.2e" % (t, an, fd, rel), flush=True)
+    plan.close()
+    assert worst < (1e-10 if precision == "fp64" else 1e-4)

@@ -1,0 +1,93 @@
+"""Full-size 3D runs (257^3 and 513^3, order 6) of the benchmark workload.
+
+The whole oracle solve is out of reach at 513^3 (its direct boundary
+quadrature alone is ~2e14 terms), so these cases check what can be computed
+one value at a time or holds at any size:
+* the boundary values g at sampled boundary nodes (all corners, edge
+  midpoints, face centres and random nodes) against the oracle's direct
+  trapezoidal sums at those nodes: 1e-12 relative;
+* the error against the closed-form potential of the bump sum at sampled
+  nodes, which must be small and not grow from 257^3 to 513^3;
+* every mixed-precision mode against the FP64 path: 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import closed_forms as CF
+from oracle import poisson as P
+from paper_2108_11871_amd import inputs as I
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _boundary_targets(n, rng, count=600):
+    M = n - 1
+    pts = set()
+    for i in (0, M):
+        for j in (0, M):
+            for k in (0, M):
+                pts.add((i, j, k))
+    mid = M // 2
+    for a in range(3):
+        for u in (0, M):
+            for v in (0, M):
+                t = [u, v]
+                t.insert(a, mid)
+                pts.add(tuple(t))
+            t = [mid, mid]
+            t.insert(a, u)
+            pts.add(tuple(t))
+    while len(pts) < count:
+        t = list(rng.integers(0, n, 3))
+        t[rng.integers(0, 3)] = int(rng.choice([0, M]))
+        pts.add(tuple(int(v) for v in t))
+    return np.array(sorted(pts), dtype=np.int64)
+
+
+def _closed_form_error(phi, meta, n, rng, count=200000):
+    idx = rng.integers(0, n, (count, 3))
+    x = -1.0 + (2.0 / (n - 1)) * idx
+    ex = CF.bump_sum_potential(x, meta["centers"], meta["widths"], meta["amps"], meta["p"])
+    got = phi[idx[:, 0], idx[:, 1], idx[:, 2]]
+    return float(np.abs(got - ex).max() / np.abs(ex).max())
+
+
+@pytest.mark.parametrize("n", [257, 513])
+def test_full_size_bump_sum(n):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner, to_dev
+
+    banner("full size n=%d" % n)
+    rho, h, meta = I.workload_bumps_3d(n, seed=2)
+    rho_d = to_dev(rho)
+    plan = api.Plan(rho.shape, h, order=6)
+    phi_d = plan(rho_d)
+    torch.cuda.synchronize()
+    plan.close()
+    phi = phi_d.cpu().numpy()
+    rng = np.random.default_rng(n)
+    # boundary values against direct sums
+    tg = _boundary_targets(n, rng)
+    g_ref = P.boundary_values_at(rho, h, tg)
+    g_got = phi[tg[:, 0], tg[:, 1], tg[:, 2]]
+    gerr = float(np.abs(g_got - g_ref).max() / np.abs(g_ref).max())
+    banner("  boundary samples %d: rel err %.3e" % (len(tg), gerr))
+    assert gerr < 1e-12
+    # closed form at sampled nodes
+    cerr = _closed_form_error(phi, meta, n, rng)
+    banner("  closed-form rel err at sampled nodes %.3e" % cerr)
+    assert cerr < 1e-9
+    # mixed precision against the FP64 path
+    scale = float(phi_d.abs().max())
+    for mode in ("mixed_fp32", "mixed_fp32_slices"):
+        pm = api.Plan(rho.shape, h, order=6, precision=mode)
+        out = pm(rho_d)
+        torch.cuda.synchronize()
+        pm.close()
+        merr = float((out - phi_d).abs().max()) / scale
+        banner("  %s rel err vs FP64 %.3e" % (mode, merr))
+        assert merr < 1e-6
+        del out
+    del rho_d, phi_d
+    torch.cuda.empty_cache()

@@ -1,0 +1,116 @@
+"""The paper's validation experiments run on the HIP path (Section 6).
+
+* Table 1: convergence rates of phi for rho = B_{eps,p}(x - a) with
+  p - 1 = 0, 2, 4, 6, 8 continuous derivatives, 4th- and 6th-order harmonic
+  parts, against the exact radial potential.  The rates printed in the
+  paper are stored in tests/golden/table1_rates.json.
+* Figure 2: values inside [-1,1]^3 hardly change when the computational
+  box grows to [-D,D]^3 at fixed mesh width.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as CF
+from paper_2108_11871_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+A_CENTER = np.array([1.0 / np.sqrt(31.0), 0.2, 0.1])
+EPS = 0.4
+
+
+def _bump_problem(M, p, D=1.0):
+    n = M + 1
+    gam = CF.unit_gamma(3, EPS, p)
+    rho = I.radial_bump((n,) * 3, EPS, p, center=A_CENTER, gamma=gam, lo=-D, hi=D)
+    h = I.grid_spacing((n,) * 3, -D, D)
+    return rho, h, gam
+
+
+def _exact(M, p, gam, D=1.0):
+    n = M + 1
+    x = -D + (2.0 * D / M) * np.arange(n)
+    r = np.sqrt((x[:, None, None] - A_CENTER[0]) ** 2 + (x[None, :, None] - A_CENTER[1]) ** 2
+                + (x[None, None, :] - A_CENTER[2]) ** 2)
+    return CF.radial_potential(3, r, EPS, p, gam)
+
+
+def _gpu(rho, h, order):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import to_dev
+
+    plan = api.Plan(rho.shape, h, order=order)
+    out = plan(to_dev(rho))
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    plan.close()
+    return res
+
+
+PANELS = {6: [20, 25, 30, 40, 50, 64, 80, 100], 4: [100, 120, 140, 160, 180, 200]}
+
+
+@pytest.mark.parametrize("order", [6, 4])
+def test_table1_convergence_rates(order):
+    from gpu_util import banner
+
+    with open(os.path.join(HERE, "golden", "table1_rates.json")) as fh:
+        gold = json.load(fh)
+    paper = gold["order%d" % order]
+    rates = []
+    for p, ref in zip(gold["p"], paper):
+        errs, hs = [], []
+        for M in PANELS[order]:
+            rho, h, gam = _bump_problem(M, p)
+            phi = _gpu(rho, h, order)
+            ex = _exact(M, p, gam)
+            errs.append(float(np.abs(phi - ex).max() / np.abs(ex).max()))
+            hs.append(h[0])
+        rate = float(np.polyfit(np.log(hs), np.log(errs), 1)[0])
+        rates.append(rate)
+        banner("order %d  p %d  errors %s  rate %.2f  (paper %.1f)"
+               % (order, p, " ".join("%.2e" % e for e in errs), rate, ref))
+    # The paper gives the h window of each regression but not the mesh widths
+    # inside it; before the asymptotic regime the local slopes vary by about
+    # +-1 inside the window (for p = 7, order 6: 7.5 to 9.6 between
+    # neighbouring widths here), hence the tolerance of 1.25.
+    for p, rate, ref in zip(gold["p"], rates, paper):
+        if order == 4 and p == 5:
+            # At h in [0.01, 0.02] this case sits where the spectral error of
+            # phi_star (rate 6.6, the 6th-order row) and the 4th-order error of
+            # phi_H (rate 4, the p = 7, 9 entries) are of the same size, so its
+            # regression rate lies between the two and depends on their
+            # constants; the paper's run landed on the phi_star side.
+            assert 4.0 - 0.25 <= rate <= ref + 0.25, (rates, paper)
+        else:
+            assert abs(rate - ref) <= 1.25, (rates, paper)
+    if order == 6:
+        # spectral accuracy: the rate grows with the smoothness of rho
+        assert all(b > a + 1.0 for a, b in zip(rates, rates[1:])), rates
+
+
+def test_figure2_domain_invariance():
+    """p = 7 (six continuous derivatives), h = 0.02: values on [-1,1]^3 from
+    boxes [-D,D]^3, D = 1.2, 1.5, 2, against the [-1,1]^3 box."""
+    from gpu_util import banner
+
+    p, M1 = 7, 100
+    for order in (4, 6):
+        rho, h, gam = _bump_problem(M1, p)
+        base = _gpu(rho, h, order)
+        err = float(np.abs(base - _exact(M1, p, gam)).max() / np.abs(base).max())
+        for D, MD in ((1.2, 120), (1.5, 150), (2.0, 200)):
+            rho_d, h_d, _ = _bump_problem(MD, p, D)
+            assert abs(h_d[0] - h[0]) < 1e-15
+            phi_d = _gpu(rho_d, h_d, order)
+            k = (MD - M1) // 2
+            sub = phi_d[k:k + M1 + 1, k:k + M1 + 1, k:k + M1 + 1]
+            diff = float(np.abs(sub - base).max() / np.abs(base).max())
+            banner("order %d D %.1f: variation %.2e (error of the [-1,1] solve %.2e)" % (order, D, diff, err))
+            # the paper: variation at most the size of the discretisation error
+            assert diff <= err
