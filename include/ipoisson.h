@@ -97,7 +97,8 @@ int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int o
  * Green's-function kernels used by the boundary convolutions (Section 4),
  * and all device workspace.  Arguments as ips_solve, plus:
  *   precision : an ips_precision value
- *   flags     : bitwise OR of IPS_FLAG_STAGE_TIMING and IPS_FLAG_ADJOINT (or 0)
+ *   flags     : bitwise OR of IPS_FLAG_STAGE_TIMING, IPS_FLAG_ADJOINT and
+ *               IPS_FLAG_AUTOTUNE (or 0)
  * On success *out receives the plan; release it with ips_plan_destroy.
  */
 int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int order,
@@ -171,18 +172,42 @@ int ips_plan_reset_stage_times(ips_plan p);
 int ips_plan_destroy(ips_plan p);
 
 /*
- * ips_batch_create -- plans for `count` independent problems of possibly
- * different sizes and spacings, executed together.
- *   d[b], n[b][0..d[b]-1], h[b][0..d[b]-1] describe problem b
- *   order, precision, flags as ips_plan_create
+ * Tile autotuning.  A plan created with IPS_FLAG_AUTOTUNE times complete
+ * solves of its geometry with every admissible LDS tile budget (1024, 2048
+ * and 4096 complex elements per block) on scratch memory and keeps the
+ * fastest; the choice is cached per (device, geometry, order, precision) for
+ * the life of the process.  Without the flag the budget is 2048, or the
+ * value of the environment variable IPS_TILE_WORK.
  */
+#define IPS_FLAG_AUTOTUNE 4u
+
+/*
+ * ips_batch_create -- plans for `count` independent problems of possibly
+ * different sizes and spacings, executed together (the batched form of the
+ * solve of Sections 2-5; nothing is shared between problems).
+ *   d[b], n[b][0..d[b]-1], h[b][0..d[b]-1] describe problem b
+ *   order, precision : as ips_plan_create, for every problem
+ *   flags : IPS_FLAG_ADJOINT and IPS_FLAG_AUTOTUNE apply to every problem's
+ *           plan (IPS_FLAG_STAGE_TIMING is ignored); IPS_FLAG_BATCH_EAGER
+ *           makes ips_batch_execute launch the problems one after another
+ *           on the caller's stream instead of through a graph.
+ */
+#define IPS_FLAG_BATCH_EAGER 8u
+
 int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)[3],
                      const double (*h)[3], int order, int precision, unsigned flags);
 
 /*
  * ips_batch_execute -- enqueue all problems of the batch on `stream`.
- *   rho[b], phi[b] : device arrays of problem b (host array of pointers)
- * Problems are independent; the call allocates nothing.
+ *   rho[b], phi[b] : device arrays of problem b (host array of pointers);
+ *                    rho[b] and phi[b] must not overlap
+ * The first call (and any call with different array pointers) solves the
+ * problems one after another on `stream` and then captures the same solves
+ * into one HIP graph, spread over four internal streams so that independent
+ * problems can run side by side, largest first; later calls with the same
+ * pointers replay that graph with a single launch on `stream`.  Capturing
+ * creates the graph and, on first use, the internal streams; replays
+ * allocate nothing.  One batch must not execute concurrently on two streams.
  */
 int ips_batch_execute(ips_batch b, const double *const *rho, double *const *phi, void *stream);
 

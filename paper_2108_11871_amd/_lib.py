@@ -26,6 +26,8 @@ IPS_MIXED_FP32 = 1
 IPS_MIXED_FP32_SLICES = 2
 IPS_FLAG_STAGE_TIMING = 1
 IPS_FLAG_ADJOINT = 2
+IPS_FLAG_AUTOTUNE = 4
+IPS_FLAG_BATCH_EAGER = 8
 STAGES = ["rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces", "shell_gt", "shell_r6",
           "final", "inv_y", "inv_z", "adjoint"]
 

@@ -11,8 +11,9 @@ from typing import Sequence
 import torch
 
 from . import _lib
-from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_STAGE_TIMING, IPS_FP64, IPS_MIXED_FP32,
-                   IPS_MIXED_FP32_SLICES, STAGES, check, f64_array, i64_array, library_path, lib)
+from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_AUTOTUNE, IPS_FLAG_BATCH_EAGER, IPS_FLAG_STAGE_TIMING,
+                   IPS_FP64, IPS_MIXED_FP32, IPS_MIXED_FP32_SLICES, STAGES, check, f64_array,
+                   i64_array, library_path, lib)
 
 PRECISIONS = {"fp64": IPS_FP64, "mixed_fp32": IPS_MIXED_FP32,
               "mixed_fp32_slices": IPS_MIXED_FP32_SLICES}
@@ -41,7 +42,7 @@ class Plan:
     """A reusable solve of one grid geometry (ips_plan_create / ips_execute)."""
 
     def __init__(self, shape: Sequence[int], h, order: int = 6, precision: str = "fp64",
-                 device=None, timing: bool = False, adjoint: bool = False):
+                 device=None, timing: bool = False, adjoint: bool = False, autotune: bool = False):
         self.shape = tuple(int(v) for v in shape)
         d = len(self.shape)
         hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
@@ -56,7 +57,8 @@ class Plan:
             check(lib().ips_plan_create(ctypes.byref(handle), d, i64_array(self.shape),
                                         f64_array(self.h), self.order, PRECISIONS[precision],
                                         (IPS_FLAG_STAGE_TIMING if timing else 0)
-                                        | (IPS_FLAG_ADJOINT if adjoint else 0)))
+                                        | (IPS_FLAG_ADJOINT if adjoint else 0)
+                                        | (IPS_FLAG_AUTOTUNE if autotune else 0)))
         self._h = handle
 
     @property
@@ -132,8 +134,10 @@ def solve(rho: torch.Tensor, h, order: int = 6) -> torch.Tensor:
 class Batch:
     """Many independent problems of uneven size (ips_batch_create / ips_batch_execute)."""
 
-    def __init__(self, shapes, hs, order: int = 6, precision: str = "fp64"):
+    def __init__(self, shapes, hs, order: int = 6, precision: str = "fp64", eager: bool = False,
+                 autotune: bool = False, device=None):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         count = len(self.shapes)
         dims = (ctypes.c_int * count)(*[len(s) for s in self.shapes])
         nn = (ctypes.c_int64 * (3 * count))()
@@ -143,12 +147,20 @@ class Batch:
                 nn[3 * b + a] = s[a]
                 hh[3 * b + a] = float(h[a])
         handle = ctypes.c_void_p()
-        check(lib().ips_batch_create(ctypes.byref(handle), count, dims, nn, hh, int(order),
-                                     PRECISIONS[precision], 0))
+        flags = (IPS_FLAG_BATCH_EAGER if eager else 0) | (IPS_FLAG_AUTOTUNE if autotune else 0)
+        with torch.cuda.device(self.device):
+            check(lib().ips_batch_create(ctypes.byref(handle), count, dims, nn, hh, int(order),
+                                         PRECISIONS[precision], flags))
         self._h = handle
         self.count = count
 
     def __call__(self, rhos, outs=None):
+        if len(rhos) != self.count:
+            raise ValueError("expected %d right-hand sides" % self.count)
+        for r, s in zip(rhos, self.shapes):
+            _check_grid(r)
+            if tuple(r.shape) != s:
+                raise ValueError("rho shape %s does not match %s" % (tuple(r.shape), s))
         if outs is None:
             outs = [torch.empty_like(r) for r in rhos]
         rp = (ctypes.c_void_p * self.count)(*[r.data_ptr() for r in rhos])

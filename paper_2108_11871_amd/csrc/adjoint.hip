@@ -407,14 +407,10 @@ template <int MAXE>
 static void launch_expand_m(const ExpandArgs &a, unsigned nblk, size_t lds, hipStream_t st)
 {
     if (pow2(a.fd.N)) {
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)&k_expand<MAXE, true>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        set_lds((const void *)&k_expand<MAXE, true>, lds);
         hipLaunchKernelGGL((k_expand<MAXE, true>), dim3(nblk), dim3(NTA), lds, st, a);
     } else {
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)&k_expand<MAXE, false>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        set_lds((const void *)&k_expand<MAXE, false>, lds);
         hipLaunchKernelGGL((k_expand<MAXE, false>), dim3(nblk), dim3(NTA), lds, st, a);
     }
 }
@@ -490,14 +486,10 @@ hipError_t launch_adj_1d(const double *w, double *out, int M, double h, const Ff
 {
     const size_t lds = (size_t)fd.N * sizeof(cx<double>) + (size_t)fd.N * 3 * sizeof(double);
     if (fd.N <= 4 * NTA) {
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)&k_adj_1d<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds);
+        set_lds((const void *)&k_adj_1d<4>, lds);
         hipLaunchKernelGGL((k_adj_1d<4>), dim3(1), dim3(NTA), lds, st, w, out, M, h, fd, tw, tab);
     } else if (fd.N <= 8 * NTA) {
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)&k_adj_1d<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds);
+        set_lds((const void *)&k_adj_1d<8>, lds);
         hipLaunchKernelGGL((k_adj_1d<8>), dim3(1), dim3(NTA), lds, st, w, out, M, h, fd, tw, tab);
     } else {
         return hipErrorInvalidValue;

@@ -187,6 +187,9 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_adj_1d(const double *w, double *out, int M, double h, const FftDesc &fd,
                          const cx<double> *tw, const AxisTabs &tab, hipStream_t st);
 
+// Raise a kernel's dynamic LDS limit above 64 KiB (once per size, cached).
+void set_lds(const void *fn, size_t bytes);
+
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
 // in_f32: input data in FP32 (else FP64); f32: transform type
 hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st);

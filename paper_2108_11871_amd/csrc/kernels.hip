@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -24,10 +26,22 @@ namespace ips {
 
 constexpr int NT = 256;
 
-// Allow more than 64 KiB of dynamic LDS where a tile needs it (gfx950 has 160 KiB).
-static void set_lds(const void *fn, size_t bytes)
+// Allow more than 64 KiB of dynamic LDS where a tile needs it (gfx950 has
+// 160 KiB).  Each kernel's limit is raised once per process, to the largest
+// size requested so far, so that launches inside a stream capture make no
+// further attribute calls.
+void set_lds(const void *fn, size_t bytes)
 {
-    if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (bytes <= 65536) return;
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = done.find(fn);
+    if (it != done.end() && it->second >= bytes) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        done[fn] = bytes;
+    else
+        (void)hipGetLastError();
 }
 
 template <typename T>

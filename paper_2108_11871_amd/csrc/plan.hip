@@ -105,9 +105,10 @@ struct DevBuf {
     }
 };
 
-// Tile budget in complex elements per block (nseq * N), 2048 by default;
-// IPS_TILE_WORK (1024, 2048 or 4096) overrides it.
-int tile_work(bool f32)
+// Tile budget in complex elements per block (nseq * N): 2048 by default,
+// IPS_TILE_WORK (1024, 2048 or 4096) overrides it for every plan, and plans
+// created with IPS_FLAG_AUTOTUNE pick their own by measurement.
+int tile_work_default()
 {
     static const int base = [] {
         const char *e = getenv("IPS_TILE_WORK");
@@ -115,7 +116,6 @@ int tile_work(bool f32)
         if (v != 1024 && v != 2048 && v != 4096) v = 2048;
         return v;
     }();
-    (void)f32; // FP32 tiles use the same column count (wider tiles measured slower)
     return base;
 }
 
@@ -161,6 +161,7 @@ struct ips_plan_s {
     double h[3] = {1, 1, 1};
     int order = 6, precision = 0;
     int device = 0;
+    int work = 2048; // tile budget (complex elements per block)
     Geo geo{};
     int M[3] = {0, 0, 0}, I[3] = {0, 0, 0}, N[3] = {0, 0, 0};
     FftDesc fd[3]{};
@@ -199,11 +200,23 @@ struct ips_plan_s {
 
 namespace {
 
+// LDS bytes of the final pass along axis 0 (tile, twiddles, staged row and
+// column tables) for tile budget `work`.
+size_t final_pass_lds(int d, const int64_t *n, int precision, int work)
+{
+    if (d < 2) return 0;
+    const int N0 = 2 * (int)(n[0] - 1);
+    const size_t tsz = precision != IPS_FP64 ? 4 : 8;
+    const int W = tile_width(N0, work, (int)(n[1] - 2));
+    return (size_t)N0 * 2 * tsz + (size_t)N0 * (W + 1) * tsz + 8 + (size_t)(n[0] - 2 + W) * 80;
+}
+
 int validate(int d, const int64_t *n, const double *h, int order, int precision, unsigned flags)
 {
     if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
     if (!n || !h) return fail(IPS_E_INVALID_ARG, "n and h must not be NULL");
-    if (flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_ADJOINT)) return fail(IPS_E_INVALID_ARG, "unknown flag bits");
+    if (flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_ADJOINT | IPS_FLAG_AUTOTUNE | IPS_FLAG_BATCH_EAGER))
+        return fail(IPS_E_INVALID_ARG, "unknown flag bits");
     if (precision != IPS_FP64 && precision != IPS_MIXED_FP32 && precision != IPS_MIXED_FP32_SLICES)
         return fail(IPS_E_INVALID_ARG, "unknown precision");
     if (d >= 2 && order != 4 && order != 6) return fail(IPS_E_INVALID_ARG, "order must be 4 or 6");
@@ -218,16 +231,8 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
     }
     if (d == 1 && precision != IPS_FP64)
         return fail(IPS_E_UNSUPPORTED, "d = 1 runs in FP64 only");
-    if (d >= 2) {
-        // LDS of the final pass along axis 0: tile + twiddles + staged row/column tables
-        const int N0 = 2 * (int)(n[0] - 1);
-        const bool f32 = precision != IPS_FP64;
-        const size_t tsz = f32 ? 4 : 8;
-        const int W = tile_width(N0, tile_work(f32), (int)(n[1] - 2));
-        const size_t lds = (size_t)N0 * 2 * tsz + (size_t)N0 * (W + 1) * tsz + 8 + (size_t)(n[0] - 2 + W) * 80;
-        if (lds > 160 * 1024)
-            return fail(IPS_E_UNSUPPORTED, "n[0] too large for the final pass of this build");
-    }
+    if (d >= 2 && final_pass_lds(d, n, precision, tile_work_default()) > 160 * 1024)
+        return fail(IPS_E_UNSUPPORTED, "n[0] too large for the final pass of this build");
     return IPS_OK;
 }
 
@@ -262,12 +267,12 @@ std::vector<cx<double>> twiddles(int N)
     return w;
 }
 
-int run_pass(PassArgs a, const FftDesc &fd, const cx<double> *tw, bool in_f32, bool out_f32,
-             hipStream_t st)
+int run_pass(ips_plan p, PassArgs a, const FftDesc &fd, const cx<double> *tw, bool in_f32,
+             bool out_f32, hipStream_t st)
 {
     a.fd = fd;
     a.tw = tw;
-    if (a.W == 0) a.W = tile_width(fd.N, tile_work(in_f32 || out_f32), a.ncols);
+    if (a.W == 0) a.W = tile_width(fd.N, p->work, a.ncols);
     IPS_HIP(launch_pass(a, in_f32, out_f32, st));
     return IPS_OK;
 }
@@ -296,7 +301,7 @@ int shell_dst(ips_plan p, double *buf, int nl, int fam, bool inverse, hipStream_
         a.out_r0 = inverse ? 1 : p->M[axis] + 1;
         a.out_nrows = p->I[axis];
         a.scale = inverse ? 0.5 : 1.0;
-        return run_pass(a, p->fd[axis], p->tw[axis], false, false, st);
+        return run_pass(p, a, p->fd[axis], p->tw[axis], false, false, st);
     };
     int rc;
     if (na == 2) {
@@ -390,7 +395,7 @@ int plan_build(ips_plan p, hipStream_t st)
             pen = 1 - fam;
             nbatch = 1;
         }
-        const int W = tile_width(N[pen], tile_work(p->precision == IPS_MIXED_FP32_SLICES), I[fam]);
+        const int W = tile_width(N[pen], p->work, I[fam]);
         const int ncb = (I[fam] + W - 1) / W;
         int nch = std::max(1, std::min(ncb, (2048 + nbatch - 1) / nbatch));
         const int per = (ncb + nch - 1) / nch;
@@ -454,7 +459,7 @@ int plan_build(ips_plan p, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = M[kb] + 1;
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[kb], p->tw[kb], false, false, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[kb], p->tw[kb], false, false, st))) return rc;
         } else {
             const int64_t plane = (int64_t)(M[kb] + 1) * (M[kc] + 1);
             PassArgs a{};
@@ -469,7 +474,7 @@ int plan_build(ips_plan p, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = M[kc] + 1;
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[kc], p->tw[kc], false, false, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[kc], p->tw[kc], false, false, st))) return rc;
             PassArgs b2{};
             b2.in = b2.out = p->K[fam];
             b2.irs = b2.ors = M[kc] + 1;
@@ -482,7 +487,7 @@ int plan_build(ips_plan p, hipStream_t st)
             b2.out_r0 = 0;
             b2.out_nrows = M[kb] + 1;
             b2.scale = 1.0;
-            if ((rc = run_pass(b2, p->fd[kb], p->tw[kb], false, false, st))) return rc;
+            if ((rc = run_pass(p, b2, p->fd[kb], p->tw[kb], false, false, st))) return rc;
         }
     }
     return IPS_OK;
@@ -561,7 +566,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = N[2];
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[2], p->tw[2], false, f32s, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[2], p->tw[2], false, f32s, st))) return rc;
         }
         {
             // (2) transform along y, sum over x-slices: faces x = 0, M0;
@@ -586,7 +591,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Bcs = I[1];
             a.Brs = 1;
             a.Bbs = vxy;
-            a.W = tile_width(N[1], tile_work(f32s), a.ncols);
+            a.W = tile_width(N[1], p->work, a.ncols);
             a.fd = p->fd[1];
             a.tw = p->tw[1];
             IPS_HIP(launch_cc(a, p->nch[0], f32s, f32s, st));
@@ -609,7 +614,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Ko = M[0] + 1;
             a.part = p->part[1];
             a.Bout = nullptr;
-            a.W = tile_width(N[0], tile_work(f32s), a.ncols);
+            a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
             IPS_HIP(launch_cc(a, p->nch[1], f32s, f32s, st));
@@ -633,7 +638,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = N[1];
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[1], p->tw[1], false, f32s, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[1], p->tw[1], false, f32s, st))) return rc;
         }
         {
             // (5) transform along x, sum over z-slices: faces z = 0, M2
@@ -653,7 +658,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.Ko = M[0] + 1;
             a.part = p->part[2];
             a.Bout = nullptr;
-            a.W = tile_width(N[0], tile_work(f32s), a.ncols);
+            a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
             IPS_HIP(launch_cc(a, p->nch[2], f32s, f32s, st));
@@ -683,7 +688,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = M[c] + 1;
             a.scale = 1.0 / N[c];
-            if ((rc = run_pass(a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) return rc;
             PassArgs b{};
             b.in = b.out = p->F[fam];
             b.irs = b.ors = N[c];
@@ -696,7 +701,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             b.out_r0 = 0;
             b.out_nrows = M[r] + 1;
             b.scale = 1.0 / N[r];
-            if ((rc = run_pass(b, p->fd[r], p->tw[r], false, false, st))) return rc;
+            if ((rc = run_pass(p, b, p->fd[r], p->tw[r], false, false, st))) return rc;
         }
         // (8) boundary values into phi; F[fam][face][j_r][j_c] -> strides of the in-face
         //     axes in increasing order
@@ -743,7 +748,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
                 a.Brs = 1;
                 a.Bbs = 0;
             }
-            a.W = tile_width(N[pen], tile_work(f32s), a.ncols);
+            a.W = tile_width(N[pen], p->work, a.ncols);
             a.fd = p->fd[pen];
             a.tw = p->tw[pen];
             IPS_HIP(launch_cc(a, p->nch[fam], f32s, false, st));
@@ -769,7 +774,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = M[pen] + 1;
             a.scale = 1.0 / N[pen];
-            if ((rc = run_pass(a, p->fd[pen], p->tw[pen], false, false, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[pen], p->tw[pen], false, false, st))) return rc;
         }
         BwriteArgs a{};
         a.geo = p->geo;
@@ -863,7 +868,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.bax = -1;
         }
         a.nrows_in = I[0];
-        a.W = tile_width(N[0], tile_work(f32), a.ncols);
+        a.W = tile_width(N[0], p->work, a.ncols);
         a.order = p->order;
         a.mixed = f32;
         a.geo = p->geo;
@@ -889,7 +894,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 1;
             a.out_nrows = I[1];
             a.scale = 0.5;
-            if ((rc = run_pass(a, p->fd[1], p->tw[1], f32, f32, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[1], p->tw[1], f32, f32, st))) return rc;
         }
         STAGE(IPS_STAGE_INV_Z);
         // B[kz][x][y] -> phi[x][y][z]
@@ -909,7 +914,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         b.out_r0 = 1;
         b.out_nrows = I[2];
         b.scale = 0.5;
-        if ((rc = run_pass(b, p->fd[2], p->tw[2], f32, false, st))) return rc;
+        if ((rc = run_pass(p, b, p->fd[2], p->tw[2], f32, false, st))) return rc;
     } else {
         STAGE(IPS_STAGE_INV_Z);
         PassArgs b{};
@@ -928,7 +933,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         b.out_r0 = 1;
         b.out_nrows = I[1];
         b.scale = 0.5;
-        if ((rc = run_pass(b, p->fd[1], p->tw[1], f32, false, st))) return rc;
+        if ((rc = run_pass(p, b, p->fd[1], p->tw[1], f32, false, st))) return rc;
     }
     return IPS_OK;
 }
@@ -993,7 +998,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
         a.nbatch = I[0];
         a.out_r0 = M[2] + 1;
         a.out_nrows = I[2];
-        int rc = run_pass(a, p->fd[2], p->tw[2], false, false, st);
+        int rc = run_pass(p, a, p->fd[2], p->tw[2], false, false, st);
         if (rc) return rc;
         PassArgs b = a;
         b.in = X;
@@ -1006,7 +1011,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
         b.out_r0 = M[1] + 1;
         b.out_nrows = I[1];
         b.W = 0;
-        if ((rc = run_pass(b, p->fd[1], p->tw[1], false, false, st))) return rc;
+        if ((rc = run_pass(p, b, p->fd[1], p->tw[1], false, false, st))) return rc;
         PassArgs c = b;
         c.irs = c.ors = (int64_t)I[1] * I[2];
         c.ics = c.ocs = 1;
@@ -1017,7 +1022,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
         c.out_r0 = M[0] + 1;
         c.out_nrows = I[0];
         c.W = 0;
-        return run_pass(c, p->fd[0], p->tw[0], false, false, st);
+        return run_pass(p, c, p->fd[0], p->tw[0], false, false, st);
     }
     a.in = src;
     a.out = X;
@@ -1030,7 +1035,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
     a.nbatch = 1;
     a.out_r0 = M[1] + 1;
     a.out_nrows = I[1];
-    int rc = run_pass(a, p->fd[1], p->tw[1], false, false, st);
+    int rc = run_pass(p, a, p->fd[1], p->tw[1], false, false, st);
     if (rc) return rc;
     PassArgs b = a;
     b.in = X;
@@ -1041,7 +1046,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
     b.out_r0 = M[0] + 1;
     b.out_nrows = I[0];
     b.W = 0;
-    return run_pass(b, p->fd[0], p->tw[0], false, false, st);
+    return run_pass(p, b, p->fd[0], p->tw[0], false, false, st);
 }
 
 // Inverse of vol_fwd's coefficients (raw DST-I again, scaled by 1/2 per axis
@@ -1063,7 +1068,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
         a.ncols = I[2];
         a.nbatch = I[1];
         a.out_nrows = I[0];
-        int rc = run_pass(a, p->fd[0], p->tw[0], false, false, st);
+        int rc = run_pass(p, a, p->fd[0], p->tw[0], false, false, st);
         if (rc) return rc;
         PassArgs b = a;
         b.irs = b.ors = I[2];
@@ -1074,7 +1079,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
         b.nbatch = I[0];
         b.out_nrows = I[1];
         b.W = 0;
-        if ((rc = run_pass(b, p->fd[1], p->tw[1], false, false, st))) return rc;
+        if ((rc = run_pass(p, b, p->fd[1], p->tw[1], false, false, st))) return rc;
         PassArgs c = b;
         c.out = dst;
         c.irs = 1;
@@ -1089,7 +1094,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
         c.out_nrows = I[2];
         c.W = 0;
         (void)M;
-        return run_pass(c, p->fd[2], p->tw[2], false, false, st);
+        return run_pass(p, c, p->fd[2], p->tw[2], false, false, st);
     }
     a.in = a.out = X;
     a.irs = a.ors = I[1];
@@ -1098,7 +1103,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
     a.ncols = I[1];
     a.nbatch = 1;
     a.out_nrows = I[0];
-    int rc = run_pass(a, p->fd[0], p->tw[0], false, false, st);
+    int rc = run_pass(p, a, p->fd[0], p->tw[0], false, false, st);
     if (rc) return rc;
     PassArgs b = a;
     b.out = dst;
@@ -1110,7 +1115,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
     b.ncols = I[0];
     b.out_nrows = I[1];
     b.W = 0;
-    return run_pass(b, p->fd[1], p->tw[1], false, false, st);
+    return run_pass(p, b, p->fd[1], p->tw[1], false, false, st);
 }
 
 int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
@@ -1177,7 +1182,7 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = N[c];
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) return rc;
             PassArgs b2{};
             b2.in = b2.out = p->LH[fam];
             b2.irs = b2.ors = N[c];
@@ -1190,7 +1195,7 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
             b2.out_r0 = 0;
             b2.out_nrows = N[b];
             b2.scale = 1.0;
-            if ((rc = run_pass(b2, p->fd[b], p->tw[b], false, false, st))) return rc;
+            if ((rc = run_pass(p, b2, p->fd[b], p->tw[b], false, false, st))) return rc;
             // slices: product with the kernel spectra, synthesis along c, then along b
             ExpandArgs e{};
             e.d = 3;
@@ -1207,7 +1212,7 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
             e.obs = (int64_t)N[b] * I[c];
             e.ncols = N[b];
             e.nbatch = I[fam];
-            e.W = tile_width(N[c], tile_work(false), N[b]);
+            e.W = tile_width(N[c], p->work, N[b]);
             e.scale = 1.0 / N[c];
             e.accum = 0;
             e.fd = p->fd[c];
@@ -1230,7 +1235,7 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
             z.out_nrows = I[b];
             z.scale = vh / N[b];
             z.accum = 1;
-            if ((rc = run_pass(z, p->fd[b], p->tw[b], false, false, st))) return rc;
+            if ((rc = run_pass(p, z, p->fd[b], p->tw[b], false, false, st))) return rc;
         } else {
             PassArgs a{};
             a.in = p->LF[fam];
@@ -1246,7 +1251,7 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = N[b];
             a.scale = 1.0;
-            if ((rc = run_pass(a, p->fd[b], p->tw[b], false, false, st))) return rc;
+            if ((rc = run_pass(p, a, p->fd[b], p->tw[b], false, false, st))) return rc;
             ExpandArgs e{};
             e.d = 2;
             e.LH0 = p->LH[fam];
@@ -1262,7 +1267,7 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
             e.obs = 0;
             e.ncols = I[fam];
             e.nbatch = 1;
-            e.W = tile_width(N[b], tile_work(false), I[fam]);
+            e.W = tile_width(N[b], p->work, I[fam]);
             e.scale = vh / N[b];
             e.accum = 1;
             e.fd = p->fd[b];
@@ -1304,6 +1309,118 @@ std::map<std::tuple<int, int, int64_t, int64_t, int64_t, double, double, double,
 
 } // namespace
 
+// Plan with a given tile budget (arguments already validated).
+int plan_create_work(ips_plan *out, int d, const int64_t *n, const double *h, int order,
+                     int precision, unsigned flags, int work)
+{
+    ips_plan p = new (std::nothrow) ips_plan_s();
+    if (!p) return fail(IPS_E_NO_MEMORY, "host allocation failed");
+    p->d = d;
+    p->order = d == 1 ? 4 : order;
+    p->precision = precision;
+    p->work = work;
+    p->timing = (flags & IPS_FLAG_STAGE_TIMING) != 0;
+    for (int a = 0; a < d; ++a) {
+        p->n[a] = n[a];
+        p->h[a] = h[a];
+        p->M[a] = (int)(n[a] - 1);
+        p->I[a] = p->M[a] - 1;
+        p->N[a] = 2 * p->M[a];
+    }
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(IPS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    int rc = plan_build(p, nullptr);
+    if (rc == IPS_OK && (flags & IPS_FLAG_ADJOINT)) rc = adj_alloc(p);
+    if (rc == IPS_OK) {
+        e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("plan build: ") + hipGetErrorString(e));
+    }
+    if (rc) {
+        plan_free(p);
+        return rc;
+    }
+    *out = p;
+    return IPS_OK;
+}
+
+// Autotuner of the tile budget: every admissible budget is timed on a full
+// solve of this geometry (two warm-up solves, then the best of three timed
+// ones, HIP events on a private stream); the fastest wins.  Results are
+// cached per (device, geometry, order, precision) for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t, int64_t, int64_t, double, double, double, int, int>, int> g_tune;
+
+int autotune_work(int d, const int64_t *n, const double *h, int order, int precision, int *best)
+{
+    int dev = 0;
+    IPS_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, d, n[0], d > 1 ? n[1] : 0, d > 2 ? n[2] : 0, h[0],
+                                     d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0, order, precision);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *best = it->second;
+            return IPS_OK;
+        }
+    }
+    size_t cnt = 1;
+    for (int a = 0; a < d; ++a) cnt *= (size_t)n[a];
+    DevBuf mem;
+    double *rho = nullptr, *phi = nullptr;
+    int rc = mem.alloc((void **)&rho, cnt * sizeof(double));
+    if (!rc) rc = mem.alloc((void **)&phi, cnt * sizeof(double));
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(IPS_E_DEVICE, "autotune: hipStreamCreate failed");
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(IPS_E_DEVICE, "autotune: hipEventCreate failed");
+    if (!rc && launch_fill(rho, (int64_t)cnt, 1.0, st) != hipSuccess)
+        rc = fail(IPS_E_DEVICE, "autotune: fill failed");
+    int pick = tile_work_default();
+    float pick_ms = 1e30f;
+    const int cand[3] = {1024, 2048, 4096};
+    for (int ci = 0; ci < 3 && !rc; ++ci) {
+        if (final_pass_lds(d, n, precision, cand[ci]) > 160 * 1024) continue;
+        ips_plan p = nullptr;
+        rc = plan_create_work(&p, d, n, h, order, precision, 0, cand[ci]);
+        if (rc) break;
+        float tbest = 1e30f;
+        for (int it = 0; it < 5 && !rc; ++it) {
+            if (hipEventRecord(e0, st) != hipSuccess) rc = fail(IPS_E_DEVICE, "autotune: event");
+            if (!rc) rc = execute(p, rho, phi, st);
+            if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(IPS_E_DEVICE, "autotune: event");
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(IPS_E_DEVICE, "autotune: sync");
+            float ms = 0.f;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(IPS_E_DEVICE, "autotune: time");
+            if (!rc && it >= 2) tbest = std::min(tbest, ms);
+        }
+        plan_free(p);
+        if (!rc && tbest < pick_ms) {
+            pick_ms = tbest;
+            pick = cand[ci];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    mem.release();
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = pick;
+    }
+    *best = pick;
+    return IPS_OK;
+}
+
 extern "C" {
 
 const char *ips_status_string(int status)
@@ -1334,36 +1451,12 @@ int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int
     *out = nullptr;
     int rc = validate(d, n, h, order, precision, flags);
     if (rc) return rc;
-    ips_plan p = new (std::nothrow) ips_plan_s();
-    if (!p) return fail(IPS_E_NO_MEMORY, "host allocation failed");
-    p->d = d;
-    p->order = d == 1 ? 4 : order;
-    p->precision = precision;
-    p->timing = (flags & IPS_FLAG_STAGE_TIMING) != 0;
-    for (int a = 0; a < d; ++a) {
-        p->n[a] = n[a];
-        p->h[a] = h[a];
-        p->M[a] = (int)(n[a] - 1);
-        p->I[a] = p->M[a] - 1;
-        p->N[a] = 2 * p->M[a];
+    int work = tile_work_default();
+    if ((flags & IPS_FLAG_AUTOTUNE) && d >= 2) {
+        rc = autotune_work(d, n, h, order, precision, &work);
+        if (rc) return rc;
     }
-    hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) {
-        delete p;
-        return fail(IPS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
-    }
-    rc = plan_build(p, nullptr);
-    if (rc == IPS_OK && (flags & IPS_FLAG_ADJOINT)) rc = adj_alloc(p);
-    if (rc == IPS_OK) {
-        e = hipStreamSynchronize(nullptr);
-        if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("plan build: ") + hipGetErrorString(e));
-    }
-    if (rc) {
-        plan_free(p);
-        return rc;
-    }
-    *out = p;
-    return IPS_OK;
+    return plan_create_work(out, d, n, h, order, precision, flags, work);
 }
 
 int ips_plan_workspace_size(ips_plan p, size_t *bytes)
@@ -1481,9 +1574,88 @@ int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int o
     return IPS_OK;
 }
 
+} // extern "C"
+
 struct ips_batch_s {
     std::vector<ips_plan> plans;
+    std::vector<int> order; // execution order: largest problems first
+    bool eager = false;
+    int device = 0;
+    // graph of the last capture and the buffers it was captured with
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const double *> rho_key;
+    std::vector<double *> phi_key;
 };
+
+namespace {
+
+constexpr int kBatchStreams = 4;
+
+void batch_release_graph(ips_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->rho_key.clear();
+    b->phi_key.clear();
+}
+
+// Capture every problem's solve into one graph: the problems are spread over
+// kBatchStreams branches (fork from one stream, join back), so independent
+// solves may run side by side on the device.
+int batch_capture(ips_batch b, const double *const *rho, double *const *phi)
+{
+    if (b->streams.empty()) {
+        for (int k = 0; k < kBatchStreams; ++k) {
+            hipStream_t s = nullptr;
+            IPS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            b->streams.push_back(s);
+        }
+        for (int k = 0; k < kBatchStreams; ++k) {
+            hipEvent_t e = nullptr;
+            IPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->events.push_back(e);
+        }
+    }
+    hipStream_t s0 = b->streams[0];
+    IPS_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    int rc = IPS_OK;
+    hipError_t e = hipEventRecord(b->events[0], s0);
+    for (int k = 1; k < kBatchStreams && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->streams[k], b->events[0], 0);
+    if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("batch capture fork: ") + hipGetErrorString(e));
+    for (size_t j = 0; j < b->order.size() && !rc; ++j) {
+        const int i = b->order[j];
+        rc = execute(b->plans[i], rho[i], phi[i], b->streams[j % kBatchStreams]);
+    }
+    for (int k = 1; k < kBatchStreams && !rc; ++k) {
+        e = hipEventRecord(b->events[k], b->streams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s0, b->events[k], 0);
+        if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("batch capture join: ") + hipGetErrorString(e));
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s0, &graph);
+    if (!rc && e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (!rc) {
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            rc = fail(IPS_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) {
+        (void)hipGetLastError();
+        return rc;
+    }
+    b->rho_key.assign(rho, rho + b->plans.size());
+    b->phi_key.assign(phi, phi + b->plans.size());
+    return IPS_OK;
+}
+
+} // namespace
+
+extern "C" {
 
 int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)[3],
                      const double (*h)[3], int order, int precision, unsigned flags)
@@ -1493,16 +1665,26 @@ int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)
     if (count <= 0 || !d || !n || !h) return fail(IPS_E_INVALID_ARG, "bad batch description");
     ips_batch b = new (std::nothrow) ips_batch_s();
     if (!b) return fail(IPS_E_NO_MEMORY, "host allocation failed");
+    b->eager = (flags & IPS_FLAG_BATCH_EAGER) != 0;
+    (void)hipGetDevice(&b->device);
+    // per-problem plans: no stage timing inside a batch
+    const unsigned pflags = flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_BATCH_EAGER);
+    std::vector<std::pair<int64_t, int>> sz;
     for (int i = 0; i < count; ++i) {
         ips_plan p = nullptr;
-        int rc = ips_plan_create(&p, d[i], n[i], h[i], order, precision, flags);
+        int rc = ips_plan_create(&p, d[i], n[i], h[i], order, precision, pflags);
         if (rc) {
             for (ips_plan q : b->plans) plan_free(q);
             delete b;
             return rc;
         }
         b->plans.push_back(p);
+        int64_t c = 1;
+        for (int a = 0; a < d[i]; ++a) c *= n[i][a];
+        sz.emplace_back(-c, i);
     }
+    std::stable_sort(sz.begin(), sz.end());
+    for (auto &v : sz) b->order.push_back(v.second);
     *out = b;
     return IPS_OK;
 }
@@ -1510,16 +1692,49 @@ int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)
 int ips_batch_execute(ips_batch b, const double *const *rho, double *const *phi, void *stream)
 {
     if (!b || !rho || !phi) return fail(IPS_E_INVALID_ARG, "NULL argument");
-    for (size_t i = 0; i < b->plans.size(); ++i) {
-        int rc = ips_execute(b->plans[i], rho[i], phi[i], stream);
+    const size_t cnt = b->plans.size();
+    for (size_t i = 0; i < cnt; ++i) {
+        if (!rho[i] || !phi[i]) return fail(IPS_E_INVALID_ARG, "NULL problem array");
+        size_t m = 1;
+        for (int a = 0; a < b->plans[i]->d; ++a) m *= (size_t)b->plans[i]->n[a];
+        const char *r0 = reinterpret_cast<const char *>(rho[i]), *p0 = reinterpret_cast<const char *>(phi[i]);
+        if (r0 < p0 + m * sizeof(double) && p0 < r0 + m * sizeof(double))
+            return fail(IPS_E_INVALID_ARG, "rho and phi of a problem must not overlap");
+    }
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != b->device)
+        return fail(IPS_E_INVALID_ARG, "batch belongs to another device than the current one");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (b->eager) {
+        for (int i : b->order) {
+            int rc = execute(b->plans[i], rho[i], phi[i], st);
+            if (rc) return rc;
+        }
+        return IPS_OK;
+    }
+    const bool same = b->exec && std::equal(b->rho_key.begin(), b->rho_key.end(), rho) &&
+                      std::equal(b->phi_key.begin(), b->phi_key.end(), phi);
+    if (same) {
+        IPS_HIP(hipGraphLaunch(b->exec, st));
+        return IPS_OK;
+    }
+    // new buffers: solve directly on the caller's stream (which also sets every
+    // kernel attribute outside any capture), then capture the graph that later
+    // calls with these buffers replay
+    batch_release_graph(b);
+    for (int i : b->order) {
+        int rc = execute(b->plans[i], rho[i], phi[i], st);
         if (rc) return rc;
     }
-    return IPS_OK;
+    return batch_capture(b, rho, phi);
 }
 
 int ips_batch_destroy(ips_batch b)
 {
     if (!b) return IPS_OK;
+    batch_release_graph(b);
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     for (ips_plan p : b->plans) plan_free(p);
     delete b;
     return IPS_OK;

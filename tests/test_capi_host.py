@@ -66,7 +66,7 @@ def test_plan_create_rejects_bad_geometry(args, code):
 def test_plan_create_rejects_bad_order_precision_flags():
     assert _create(2, [9, 9], [0.1, 0.1], order=5)[0] == -1
     assert _create(2, [9, 9], [0.1, 0.1], precision=7)[0] == -1
-    assert _create(2, [9, 9], [0.1, 0.1], flags=4)[0] == -1
+    assert _create(2, [9, 9], [0.1, 0.1], flags=16)[0] == -1
     assert _create(1, [9], [0.1], precision=1)[0] == -2
 
 

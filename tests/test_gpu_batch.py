@@ -1,0 +1,144 @@
+"""Batched solves of independent boxes of uneven size (ips_batch_*) and the
+tile autotuner.
+
+Workload: 64 problems (seed 3); per problem and axis n = round(exp(U(ln 33,
+ln 193))), box [-s, s] with s ~ U(0.5, 2), a 5-bump sum; order 6.
+Bars:
+* every problem of a batch equals the same problem solved by its own plan:
+  bit for bit (same kernels, same inputs), FP64 and mixed;
+* the smallest problems against the FP64 oracle: 1e-12;
+* graph replays, with the program's own eager work and synchronisations in
+  between, reproduce the eager result every time;
+* mixed batches within 1e-6 of the FP64 batch.
+"""
+import numpy as np
+import pytest
+
+from oracle import poisson as P
+from paper_2108_11871_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _workload(count=64):
+    return I.batched_problems(seed=3, count=count)
+
+
+def _single(rho_d, h, precision):
+    from paper_2108_11871_amd import api
+
+    plan = api.Plan(tuple(rho_d.shape), h, order=6, precision=precision)
+    out = plan(rho_d)
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32_slices"])
+def test_batch_equals_single_plans(precision):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner, to_dev
+
+    probs = _workload()
+    banner("batch of %d problems, %s, %.2e nodes" % (len(probs), precision,
+                                                     sum(p[0].size for p in probs)))
+    rhos = [to_dev(p[0]) for p in probs]
+    batch = api.Batch([r.shape for r in rhos], [p[1] for p in probs], order=6, precision=precision)
+    outs = batch(rhos)
+    torch.cuda.synchronize()
+    for i, (r, p) in enumerate(zip(rhos, probs)):
+        ref = _single(r, p[1], precision)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), "problem %d %s" % (i, tuple(r.shape))
+    batch.close()
+
+
+def test_batch_smallest_problems_match_oracle():
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner, rel_err, to_dev
+
+    probs = sorted(_workload(), key=lambda p: p[0].size)[:4]
+    rhos = [to_dev(p[0]) for p in probs]
+    batch = api.Batch([r.shape for r in rhos], [p[1] for p in probs], order=6)
+    outs = batch(rhos)
+    torch.cuda.synchronize()
+    for (rho, h, _), o in zip(probs, outs):
+        ref = P.solve(rho, h, 6)
+        err = rel_err(o.cpu().numpy(), ref)
+        banner("batch problem %s: rel err vs oracle %.3e" % (rho.shape, err))
+        assert err < 1e-12
+    batch.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import to_dev
+
+    probs = _workload(16)
+    rhos = [to_dev(p[0]) for p in probs]
+    shapes = [r.shape for r in rhos]
+    hs = [p[1] for p in probs]
+    eager = api.Batch(shapes, hs, order=6, eager=True)
+    ref = eager(rhos)
+    torch.cuda.synchronize()
+    graph = api.Batch(shapes, hs, order=6)
+    outs = [torch.empty_like(r) for r in rhos]
+    other = torch.randn(1 << 20, dtype=torch.float64, device="cuda:0")
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        graph(rhos, outs)
+        other = torch.sin(other) * 1.0001 + other.sum() * 1e-9  # unrelated eager work
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), "replay %d" % rep
+    # new output buffers: the batch captures a new graph
+    outs2 = graph(rhos)
+    torch.cuda.synchronize()
+    for o, r in zip(outs2, ref):
+        assert torch.equal(o, r)
+    eager.close()
+    graph.close()
+
+
+def test_mixed_batch_within_1e6_of_fp64():
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import to_dev
+
+    probs = _workload()
+    rhos = [to_dev(p[0]) for p in probs]
+    shapes = [r.shape for r in rhos]
+    hs = [p[1] for p in probs]
+    b64 = api.Batch(shapes, hs, order=6)
+    ref = b64(rhos)
+    for mode in ("mixed_fp32", "mixed_fp32_slices"):
+        bm = api.Batch(shapes, hs, order=6, precision=mode)
+        got = bm(rhos)
+        torch.cuda.synchronize()
+        worst = max(float((g - r).abs().max() / r.abs().max()) for g, r in zip(got, ref))
+        print("  %s worst rel err vs FP64 %.3e" % (mode, worst), flush=True)
+        assert worst < 1e-6
+        bm.close()
+    b64.close()
+
+
+@pytest.mark.parametrize("shape,precision", [((65, 65, 65), "fp64"), ((97, 81, 113), "mixed_fp32_slices"),
+                                             ((257, 257), "fp64")])
+def test_autotuned_plan_matches_default(shape, precision):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import to_dev
+
+    rho, h, _ = I.workload_bumps(shape, seed=9)
+    r = to_dev(rho)
+    ref = _single(r, h, precision)
+    plan = api.Plan(shape, h, order=6, precision=precision, autotune=True)
+    got = plan(r)
+    torch.cuda.synchronize()
+    plan.close()
+    err = float((got - ref).abs().max() / ref.abs().max())
+    print("  autotuned vs default rel diff %.2e" % err, flush=True)
+    assert err < (1e-12 if precision == "fp64" else 1e-6)
