@@ -15,7 +15,9 @@ Prints ONE JSON line.  Besides the contract fields it carries
                 stream) and, when counters for the current sources exist
                 under profiles/, the HBM traffic they measured;
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample;
-  modes         per-precision throughput, error vs FP64 and stage times.
+  modes         per-precision throughput, error vs FP64 and stage times;
+  adjoint       time of one FP64 adjoint solve on the same grid;
+  batched       64 uneven boxes per batch, graph replay against eager launches.
 
 Profiling helpers (same file, so that every profile is taken on committed code):
   --copy-calibration MIB   after the timed work, one plain device copy of MIB MiB
@@ -251,6 +253,62 @@ def ingest_stats(stats_csv, bench_json, title, cmd, out_name, top=20):
     print("\n".join(lines))
 
 
+def time_batched(api, torch, steps, warmup, modes=("fp64", "mixed_fp32_slices")):
+    """64 independent boxes of uneven size (seed 3), order 6: graph replays
+    and eager launches, whole-batch nodes per second."""
+    from paper_2108_11871_amd import inputs
+
+    probs = inputs.batched_problems(seed=3, count=64)
+    rhos = [torch.from_numpy(p[0]).to("cuda:0") for p in probs]
+    shapes = [tuple(r.shape) for r in rhos]
+    hs = [p[1] for p in probs]
+    nodes = sum(r.numel() for r in rhos)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "64 boxes, n per axis log-uniform in [33, 193], box [-s, s] with s ~ U(0.5, 2) "
+                       "per axis, 5-bump sums, order 6, seed 3",
+           "nodes": nodes, "modes": {}}
+    for mode in modes:
+        res = {}
+        for kind in ("graph", "eager"):
+            b = api.Batch(shapes, hs, order=6, precision=mode, eager=(kind == "eager"))
+            outs = [torch.empty_like(r) for r in rhos]
+            for _ in range(max(warmup, 1) + 1):
+                b(rhos, outs)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                b(rhos, outs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            res[kind] = {"ms_per_batch": ms, "mpoints_per_s": nodes / (ms * 1e-3) / 1e6}
+            b.close()
+        out["modes"][mode] = res
+    return out
+
+
+def time_adjoint(api, torch, rho_d, h, steps, warmup):
+    """One FP64 adjoint rho_bar = A^T phi_bar per step on the same grid."""
+    plan = api.Plan(tuple(rho_d.shape), h, order=6, adjoint=True)
+    out = torch.empty_like(rho_d)
+    for _ in range(max(warmup, 1)):
+        plan.adjoint(rho_d, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.adjoint(rho_d, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.close()
+    return {"ms_per_step": ms, "mpoints_per_s": rho_d.numel() / (ms * 1e-3) / 1e6, "precision": "fp64"}
+
+
 def load_traffic(kernel_stage: str, n: int, mode: str):
     """HBM bytes per launch measured by rocprofv3 counters, if taken on these sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -278,6 +336,7 @@ def main():
     ap.add_argument("--modes", default=",".join(MODES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint timings")
     ap.add_argument("--ingest", nargs="+", metavar="ARG")
     args = ap.parse_args()
 
@@ -393,6 +452,9 @@ def main():
         },
         "source_hash": source_hash(),
     }
+    if not args.no_extras:
+        out["adjoint"] = time_adjoint(api, torch, rho_d, h, max(args.steps // 2, 1), args.warmup)
+        out["batched"] = time_batched(api, torch, max(args.steps // 2, 1), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.seed)
     print(json.dumps(out), flush=True)
