@@ -351,21 +351,22 @@ hipError_t launch_zero_boundary(const AdjArgs &a, double *out, hipStream_t st)
 // followed by the hermitian synthesis along the rows.  Rows 1..M-1 of the
 // result, times `scale`, are stored (3D) or added (2D) to out[(row-1)*ors +
 // col*ocs + batch*obs].
-template <int MAXE, bool P2>
-__global__ __launch_bounds__(NTA) void k_expand(ExpandArgs a)
+template <int MAXE, bool P2, int NTT>
+__global__ __launch_bounds__(NTT) void k_expand(ExpandArgs a)
 {
+    constexpr bool BIG = NTT != NTA;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1;
-    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
-    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
+    const cx<double> *tw = BIG ? a.tw : reinterpret_cast<const cx<double> *>(smem);
+    double *buf = reinterpret_cast<double *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<double>)));
     const int ncb = (a.ncols + W - 1) / W;
     const int cb = blockIdx.x % ncb, bt = blockIdx.x / ncb;
     const int c0 = cb * W;
     const int nc = min(W, a.ncols - c0);
-    load_twiddles<double, NTA>(tw, a.tw, N);
+    if (!BIG) load_twiddles<double, NTT>(reinterpret_cast<cx<double> *>(smem), a.tw, N);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = wave; c < W; c += NTA / 64) {
+    for (int c = wave; c < W; c += NTT / 64) {
         const int col = c0 + c;
         int s, kb;
         const double *l0, *l1;
@@ -392,26 +393,26 @@ __global__ __launch_bounds__(NTA) void k_expand(ExpandArgs a)
         }
     }
     __syncthreads();
-    pre_herm<double, MAXE, NTA>(buf, rs, lgs, M, false);
-    fft_tile<double, MAXE, NTA, P2>(buf, rs, lgs, a.fd, tw, true);
+    pre_herm<double, MAXE, NTT>(buf, rs, lgs, M, false);
+    fft_tile<double, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, true);
     double *out = a.out + (int64_t)bt * a.obs + (int64_t)c0 * a.ocs;
     if (a.accum)
-        tile_store_acc<double, double, NTA>(buf, rs, 1, out, M - 1, nc, a.ors, a.ocs, a.scale, lgW);
+        tile_store_acc<double, double, NTT>(buf, rs, 1, out, M - 1, nc, a.ors, a.ocs, a.scale, lgW);
     else
-        tile_store<double, double, NTA>(buf, rs, 1, out, M - 1, nc, a.ors, a.ocs, a.scale, lgW);
+        tile_store<double, double, NTT>(buf, rs, 1, out, M - 1, nc, a.ors, a.ocs, a.scale, lgW);
 }
 
 static bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
-template <int MAXE>
+template <int MAXE, int NTT = NTA>
 static void launch_expand_m(const ExpandArgs &a, unsigned nblk, size_t lds, hipStream_t st)
 {
     if (pow2(a.fd.N)) {
-        set_lds((const void *)&k_expand<MAXE, true>, lds);
-        hipLaunchKernelGGL((k_expand<MAXE, true>), dim3(nblk), dim3(NTA), lds, st, a);
+        set_lds((const void *)&k_expand<MAXE, true, NTT>, lds);
+        hipLaunchKernelGGL((k_expand<MAXE, true, NTT>), dim3(nblk), dim3(NTT), lds, st, a);
     } else {
-        set_lds((const void *)&k_expand<MAXE, false>, lds);
-        hipLaunchKernelGGL((k_expand<MAXE, false>), dim3(nblk), dim3(NTA), lds, st, a);
+        set_lds((const void *)&k_expand<MAXE, false, NTT>, lds);
+        hipLaunchKernelGGL((k_expand<MAXE, false, NTT>), dim3(nblk), dim3(NTT), lds, st, a);
     }
 }
 
@@ -419,9 +420,19 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t st)
 {
     const int ncb = (a.ncols + a.W - 1) / a.W;
     const unsigned nblk = (unsigned)ncb * (unsigned)a.nbatch;
-    const size_t lds = (size_t)a.fd.N * sizeof(cx<double>) + (size_t)a.fd.N * (a.W + 1) * sizeof(double);
     const int work = (a.W / 2) * a.fd.N;
     if (nblk == 0) return hipSuccess;
+    if (a.fd.N > 2048) {
+        // long transforms: one complex sequence per tile, global twiddles
+        const size_t lds = (size_t)a.fd.N * a.W * sizeof(double);
+        if (a.W != 2 || work > 8 * 1024) return hipErrorInvalidValue;
+        if (work <= 4 * 1024)
+            launch_expand_m<4, 1024>(a, nblk, lds, st);
+        else
+            launch_expand_m<8, 1024>(a, nblk, lds, st);
+        return hipGetLastError();
+    }
+    const size_t lds = (size_t)a.fd.N * sizeof(cx<double>) + (size_t)a.fd.N * (a.W + 1) * sizeof(double);
     if (work <= 4 * NTA)
         launch_expand_m<4>(a, nblk, lds, st);
     else if (work <= 8 * NTA)
@@ -437,28 +448,29 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t st)
 //   lambda_0 = w_0 + sum_j w_j (1 - j/M),  lambda_M = w_M + sum_j w_j j/M,
 //   rho_bar_s = phi_star(w_I)_s + h (G(s h) lambda_0 + G((M - s) h) lambda_M),
 // G(r) = r/2, rho_bar on the two end nodes = 0.
-template <int MAXE>
-__global__ __launch_bounds__(NTA) void k_adj_1d(const double *w, double *out, int M, double h,
+template <int MAXE, int NTT>
+__global__ __launch_bounds__(NTT) void k_adj_1d(const double *w, double *out, int M, double h,
                                                 FftDesc fd, const cx<double> *twg, AxisTabs tab)
 {
+    constexpr bool BIG = NTT != NTA;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = fd.N, rs = 3, lgW = 1;
-    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
-    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
-    __shared__ double red[2][NTA];
-    load_twiddles<double, NTA>(tw, twg, N);
+    const int N = fd.N, rs = BIG ? 2 : 3, lgW = 1;
+    const cx<double> *tw = BIG ? twg : reinterpret_cast<const cx<double> *>(smem);
+    double *buf = reinterpret_cast<double *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<double>)));
+    __shared__ double red[2][NTT];
+    if (!BIG) load_twiddles<double, NTT>(reinterpret_cast<cx<double> *>(smem), twg, N);
     double s0 = 0.0, s1 = 0.0;
-    for (int j = 1 + threadIdx.x; j < M; j += NTA) {
+    for (int j = 1 + threadIdx.x; j < M; j += NTT) {
         s0 += w[j] * ((double)(M - j) / M);
         s1 += w[j] * ((double)j / M);
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;
-    zero_rows<double, NTA>(buf, rs, lgW, 0, 1);
-    zero_rows<double, NTA>(buf, rs, lgW, M, N);
-    tile_load<double, double, NTA>(buf, rs, 1, w + 1, M - 1, 1, 1, 1, lgW);
+    zero_rows<double, NTT>(buf, rs, lgW, 0, 1);
+    zero_rows<double, NTT>(buf, rs, lgW, M, N);
+    tile_load<double, double, NTT>(buf, rs, 1, w + 1, M - 1, 1, 1, 1, lgW);
     __syncthreads();
-    for (int k = NTA / 2; k > 0; k >>= 1) {
+    for (int k = NTT / 2; k > 0; k >>= 1) {
         if (threadIdx.x < k) {
             red[0][threadIdx.x] += red[0][threadIdx.x + k];
             red[1][threadIdx.x] += red[1][threadIdx.x + k];
@@ -466,14 +478,14 @@ __global__ __launch_bounds__(NTA) void k_adj_1d(const double *w, double *out, in
         __syncthreads();
     }
     const double l0 = w[0] + red[0][0], l1 = w[M] + red[1][0];
-    fft_tile<double, MAXE, NTA>(buf, rs, 0, fd, tw, false);
-    post_cs<double, MAXE, NTA>(buf, rs, 0, M);
-    for (int k = 1 + threadIdx.x; k < M; k += NTA)
+    fft_tile<double, MAXE, NTT>(buf, rs, 0, fd, tw, false);
+    post_cs<double, MAXE, NTT>(buf, rs, 0, M);
+    for (int k = 1 + threadIdx.x; k < M; k += NTT)
         buf[(M + k) * rs] = -(2.0 / M) * buf[(M + k) * rs] / tab.q[k - 1];
     __syncthreads();
-    pre_herm<double, MAXE, NTA>(buf, rs, 0, M, true);
-    fft_tile<double, MAXE, NTA>(buf, rs, 0, fd, tw, true);
-    for (int j = threadIdx.x; j <= M; j += NTA) {
+    pre_herm<double, MAXE, NTT>(buf, rs, 0, M, true);
+    fft_tile<double, MAXE, NTT>(buf, rs, 0, fd, tw, true);
+    for (int j = threadIdx.x; j <= M; j += NTT) {
         double v = 0.0;
         if (j > 0 && j < M)
             v = 0.5 * buf[j * rs] + h * (0.5 * (j * h) * l0 + 0.5 * ((M - j) * h) * l1);
@@ -484,13 +496,25 @@ __global__ __launch_bounds__(NTA) void k_adj_1d(const double *w, double *out, in
 hipError_t launch_adj_1d(const double *w, double *out, int M, double h, const FftDesc &fd,
                          const cx<double> *tw, const AxisTabs &tab, hipStream_t st)
 {
+    if (fd.N > 2048) {
+        const size_t lds = (size_t)fd.N * 2 * sizeof(double);
+        if (fd.N > 8 * 1024) return hipErrorInvalidValue;
+        if (fd.N <= 4 * 1024) {
+            set_lds((const void *)&k_adj_1d<4, 1024>, lds);
+            hipLaunchKernelGGL((k_adj_1d<4, 1024>), dim3(1), dim3(1024), lds, st, w, out, M, h, fd, tw, tab);
+        } else {
+            set_lds((const void *)&k_adj_1d<8, 1024>, lds);
+            hipLaunchKernelGGL((k_adj_1d<8, 1024>), dim3(1), dim3(1024), lds, st, w, out, M, h, fd, tw, tab);
+        }
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)fd.N * sizeof(cx<double>) + (size_t)fd.N * 3 * sizeof(double);
     if (fd.N <= 4 * NTA) {
-        set_lds((const void *)&k_adj_1d<4>, lds);
-        hipLaunchKernelGGL((k_adj_1d<4>), dim3(1), dim3(NTA), lds, st, w, out, M, h, fd, tw, tab);
+        set_lds((const void *)&k_adj_1d<4, NTA>, lds);
+        hipLaunchKernelGGL((k_adj_1d<4, NTA>), dim3(1), dim3(NTA), lds, st, w, out, M, h, fd, tw, tab);
     } else if (fd.N <= 8 * NTA) {
-        set_lds((const void *)&k_adj_1d<8>, lds);
-        hipLaunchKernelGGL((k_adj_1d<8>), dim3(1), dim3(NTA), lds, st, w, out, M, h, fd, tw, tab);
+        set_lds((const void *)&k_adj_1d<8, NTA>, lds);
+        hipLaunchKernelGGL((k_adj_1d<8, NTA>), dim3(1), dim3(NTA), lds, st, w, out, M, h, fd, tw, tab);
     } else {
         return hipErrorInvalidValue;
     }

@@ -31,6 +31,7 @@ struct PassArgs {
     int W; // columns per block (even)
     FftDesc fd;
     const cx<double> *tw; // N twiddles exp(-2 pi i t / N)
+    const cx<float> *twf; // the same in FP32 (transforms longer than 2048 in FP32)
     int nsum;             // IN_HERM: input element = sum of nsum copies (0/1: plain load)
     int64_t sstride;      // spacing of those copies
     int accum;            // add the result into the output instead of storing it
@@ -56,6 +57,7 @@ struct CcArgs {
     int W;
     FftDesc fd;
     const cx<double> *tw;
+    const cx<float> *twf;
 };
 
 // Per-axis tables of a plan (device pointers, index k-1 for k = 1..M-1).
@@ -114,6 +116,8 @@ struct FinalArgs {
     ShellSpec sh;
     FftDesc fd;
     const cx<double> *tw;
+    const cx<float> *twf;
+    double *rowtab; // 2D, transforms longer than 2048: row table [M0 - 1][12]
 };
 
 // Sixth-order right-hand side on the depth-5 shell layers (see k_r6t).

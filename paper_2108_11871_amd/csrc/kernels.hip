@@ -44,23 +44,49 @@ void set_lds(const void *fn, size_t bytes)
         (void)hipGetLastError();
 }
 
+// Transforms longer than kLdsTwMaxN run in blocks of NTB threads whose tile
+// holds one complex sequence without row padding (W = 2) and whose twiddles
+// are read from the global table (the LDS holds only the tile).
+constexpr int NTB = 1024;
+constexpr int kLdsTwMaxN = 2048;
+
+static bool big_fft(int N) { return N > kLdsTwMaxN; }
+
 template <typename T>
 static size_t tile_lds(int N, int W)
 {
+    if (big_fft(N)) return (size_t)N * W * sizeof(T);
     return (size_t)N * sizeof(cx<T>) + (size_t)N * (W + 1) * sizeof(T);
+}
+
+// Twiddle table of the transform type: LDS copy (short transforms) or the
+// plan's global table (long ones).
+template <typename T, bool BIG>
+__device__ __forceinline__ const cx<T> *tw_table(unsigned char *smem, const cx<double> *twd,
+                                                const cx<float> *twf)
+{
+    if constexpr (BIG) {
+        if constexpr (sizeof(T) == sizeof(float))
+            return reinterpret_cast<const cx<T> *>(twf);
+        else
+            return reinterpret_cast<const cx<T> *>(twd);
+    } else {
+        return reinterpret_cast<const cx<T> *>(smem);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Generic pencil pass
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, typename TO, int MAXE, bool P2>
-__global__ __launch_bounds__(NT) void k_pass(PassArgs a)
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT>
+__global__ __launch_bounds__(NTT) void k_pass(PassArgs a)
 {
+    constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1;
-    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
-    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
+    const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
+    T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
     const int ncb = (a.ncols + W - 1) / W;
     const int lb = xcd_remap(blockIdx.x, ncb * a.nbatch);
     const int cb = lb % ncb, bt = lb / ncb;
@@ -68,51 +94,51 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a)
     const int nc = min(W, a.ncols - c0);
     const TI *in = static_cast<const TI *>(a.in) + bt * a.ibs + c0 * a.ics;
     TO *out = static_cast<TO *>(a.out) + bt * a.obs + c0 * a.ocs;
-    load_twiddles<T, NT>(tw, a.tw, N);
+    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
     bool inv = false;
     if (a.in_mode == IN_ZPAD) {
-        zero_rows<T, NT>(buf, rs, lgW, 0, 1);
-        zero_rows<T, NT>(buf, rs, lgW, 1 + a.nrows_in, N);
-        tile_load<T, TI, NT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
+        zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
+        tile_load<T, TI, NTT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
     } else if (a.in_mode == IN_ZPAD0) {
-        zero_rows<T, NT>(buf, rs, lgW, a.nrows_in, N);
-        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        zero_rows<T, NTT>(buf, rs, lgW, a.nrows_in, N);
+        tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
     } else if (a.in_mode == IN_EVEN) {
-        tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
-        pre_even<T, NT>(buf, rs, lgW, M);
+        pre_even<T, NTT>(buf, rs, lgW, M);
     } else if (a.in_mode == IN_HERM) {
         if (a.nsum > 1)
-            tile_load_sum<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW, a.nsum,
-                                     a.sstride);
+            tile_load_sum<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW, a.nsum,
+                                      a.sstride);
         else
-            tile_load<T, TI, NT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+            tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
-        pre_herm<T, MAXE, NT>(buf, rs, lgs, M, false);
+        pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, false);
         inv = true;
     } else {
-        tile_load<T, TI, NT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        tile_load<T, TI, NTT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
         __syncthreads();
-        pre_herm<T, MAXE, NT>(buf, rs, lgs, M, true);
+        pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, true);
         inv = true;
     }
-    fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, inv);
-    if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NT>(buf, rs, lgs, M);
+    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv);
+    if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
     if (a.accum)
-        tile_store_acc<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+        tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
     else
-        tile_store<T, TO, NT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+        tile_store<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
 }
 
 static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
-template <typename T, typename TI, typename TO, int MAXE, bool P2>
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT = NT>
 static void launch_pass_k(const PassArgs &a, int64_t nblk, size_t lds, hipStream_t st)
 {
-    set_lds((const void *)&k_pass<T, TI, TO, MAXE, P2>, lds);
-    hipLaunchKernelGGL((k_pass<T, TI, TO, MAXE, P2>), dim3((unsigned)nblk), dim3(NT), lds, st, a);
+    set_lds((const void *)&k_pass<T, TI, TO, MAXE, P2, NTT>, lds);
+    hipLaunchKernelGGL((k_pass<T, TI, TO, MAXE, P2, NTT>), dim3((unsigned)nblk), dim3(NTT), lds, st, a);
 }
 
 template <typename T, typename TI, typename TO>
@@ -124,6 +150,21 @@ static hipError_t launch_pass_t(const PassArgs &a, hipStream_t st)
     const int work = (a.W / 2) * a.fd.N;
     const bool p2 = is_pow2(a.fd.N);
     if (nblk <= 0) return hipSuccess;
+    if (big_fft(a.fd.N)) {
+        if (a.W != 2 || work > 8 * NTB) return hipErrorInvalidValue;
+        if (work <= 4 * NTB) {
+            if (p2)
+                launch_pass_k<T, TI, TO, 4, true, NTB>(a, nblk, lds, st);
+            else
+                launch_pass_k<T, TI, TO, 4, false, NTB>(a, nblk, lds, st);
+        } else {
+            if (p2)
+                launch_pass_k<T, TI, TO, 8, true, NTB>(a, nblk, lds, st);
+            else
+                launch_pass_k<T, TI, TO, 8, false, NTB>(a, nblk, lds, st);
+        }
+        return hipGetLastError();
+    }
     if (work <= 4 * NT) {
         if (p2)
             launch_pass_k<T, TI, TO, 4, true>(a, nblk, lds, st);
@@ -156,14 +197,15 @@ hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t
 // ---------------------------------------------------------------------------
 // Boundary convolution, contraction over the tile columns (3D and 2D)
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT>
-__global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
+template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT>
+__global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
 {
+    constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1;
-    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
-    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
+    const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
+    T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
     // Logical order: for each wavenumber k_b of the other axis, its cos slot
     // and its sin slot are neighbours, so the blocks reading the same kernel
     // spectra K[.][k_b][.] run together on one XCD (shared L2).
@@ -185,22 +227,22 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
     double acc0[RPT], acc1[RPT]; // rows per thread: RPT * NT >= N
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc0[i] = acc1[i] = 0.0;
-    load_twiddles<T, NT>(tw, a.tw, N);
+    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
     const int cbeg = ch * a.cols_per_chunk;
     const int cend = min(a.ncols, cbeg + a.cols_per_chunk);
     for (int c0 = cbeg; c0 < cend; c0 += W) {
         const int nc = min(W, cend - c0);
-        zero_rows<T, NT>(buf, rs, lgW, 0, 1);
-        zero_rows<T, NT>(buf, rs, lgW, 1 + a.nrows_in, N);
-        tile_load<T, TI, NT>(buf, rs, 1, in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc, a.irs,
+        zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
+        zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
+        tile_load<T, TI, NTT>(buf, rs, 1, in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc, a.irs,
                              a.ics, lgW);
         __syncthreads();
-        fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, false);
-        post_cs<T, MAXE, NT>(buf, rs, lgs, M);
+        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false);
+        post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
         if (WB && (a.Mo == 0 || bt > a.Mo)) {
             const int64_t bb = a.Mo == 0 ? 0 : (int64_t)(bt - a.Mo - 1) * a.Bbs;
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-            for (int c = wave; c < nc; c += NT / 64) {
+            for (int c = wave; c < nc; c += NTT / 64) {
                 const int64_t cb = (int64_t)(c0 + c) * a.Bcs + bb;
                 for (int r = lane; r < M - 1; r += 64) {
                     const T v = buf[(M + 1 + r) * rs + c];
@@ -213,7 +255,7 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
         }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            const int row = threadIdx.x + i * NT;
+            const int row = threadIdx.x + i * NTT;
             if (row < N) {
                 const int kp = row <= M ? row : row - M;
                 const double *Kr = a.K + (int64_t)kb * a.Ko + kp;
@@ -232,7 +274,7 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
     double *p1 = p0 + (int64_t)nchunk * a.nbatch * N;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-        const int row = threadIdx.x + i * NT;
+        const int row = threadIdx.x + i * NTT;
         if (row < N) {
             p0[row] = acc0[i];
             p1[row] = acc1[i];
@@ -240,13 +282,13 @@ __global__ __launch_bounds__(NT) void k_cc(CcArgs a, int nchunk)
     }
 }
 
-template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT>
+template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT = NT>
 static void launch_cc_k(const CcArgs &a, int nchunk, hipStream_t st)
 {
     const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    set_lds((const void *)&k_cc<T, TI, MAXE, WB, P2, RPT>, lds);
-    hipLaunchKernelGGL((k_cc<T, TI, MAXE, WB, P2, RPT>), dim3(nchunk * a.nbatch), dim3(NT), lds, st,
-                       a, nchunk);
+    set_lds((const void *)&k_cc<T, TI, MAXE, WB, P2, RPT, NTT>, lds);
+    hipLaunchKernelGGL((k_cc<T, TI, MAXE, WB, P2, RPT, NTT>), dim3(nchunk * a.nbatch), dim3(NTT), lds,
+                       st, a, nchunk);
 }
 
 template <typename T, typename TI, int MAXE, bool WB>
@@ -270,6 +312,23 @@ template <typename T, typename TI, bool WB>
 static hipError_t launch_cc_t(const CcArgs &a, int nchunk, hipStream_t st)
 {
     const int work = (a.W / 2) * a.fd.N;
+    if (big_fft(a.fd.N)) {
+        // one complex sequence per tile; rows per thread = N / NTB <= 8
+        const bool p2 = is_pow2(a.fd.N);
+        if (a.W != 2 || a.fd.N > 8 * NTB) return hipErrorInvalidValue;
+        if (a.fd.N <= 4 * NTB) {
+            if (p2)
+                launch_cc_k<T, TI, 4, WB, true, 4, NTB>(a, nchunk, st);
+            else
+                launch_cc_k<T, TI, 4, WB, false, 4, NTB>(a, nchunk, st);
+        } else {
+            if (p2)
+                launch_cc_k<T, TI, 8, WB, true, 8, NTB>(a, nchunk, st);
+            else
+                launch_cc_k<T, TI, 8, WB, false, 8, NTB>(a, nchunk, st);
+        }
+        return hipGetLastError();
+    }
     if (work <= 8 * NT)
         launch_cc_m<T, TI, 8, WB>(a, nchunk, st);
     else
@@ -280,7 +339,7 @@ static hipError_t launch_cc_t(const CcArgs &a, int nchunk, hipStream_t st)
 hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st)
 {
     const int work = (a.W / 2) * a.fd.N;
-    if (work > 16 * NT || a.fd.N > 8 * NT) return hipErrorInvalidValue;
+    if (!big_fft(a.fd.N) && (work > 16 * NT || a.fd.N > 8 * NT)) return hipErrorInvalidValue;
     const bool wb = a.Bout != nullptr;
     if (!f32) {
         if (in_f32) return hipErrorInvalidValue;
@@ -452,19 +511,17 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-// Lambda(k) and m_R(k) from the eigenvalues lam of D2 along each axis.
-__device__ __forceinline__ void lam_symbols(const Geo &g, const double *lam, double &L, double &R)
+// 1/x from the hardware reciprocal refined by two Newton steps
+// (each doubles the correct bits: the result is within an ulp or two of 1/x).
+__device__ __forceinline__ double recip(double x)
 {
-    L = 0.0;
-    R = 0.0;
-    for (int a = 0; a < g.d; ++a) L += lam[a];
-    for (int i = 0; i < g.d; ++i)
-        for (int j = i + 1; j < g.d; ++j) {
-            const double p = lam[i] * lam[j];
-            L += g.c2[i][j] * p;
-            R += p * (g.c4[i][j] * lam[i] + g.c4[j][i] * lam[j]);
-        }
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
+
 
 // ---------------------------------------------------------------------------
 // Sixth-order right-hand side of the harmonic part, interior contribution.
@@ -581,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
         if (D == 3) gt += scw * pc[(int64_t)(ka - 1) * cs];
         const double L = fma(A1, lk, A0);
         const double R = fma(fma(B2, lk, B1), lk, B0);
-        const double v = R * gt / L;
+        const double v = R * gt * recip(L);
 #pragma unroll
         for (int j = 0; j < 5; ++j) acc[j] = fma(ts[j * Ia + ka - 1], v, acc[j]);
     }
@@ -877,14 +934,44 @@ hipError_t launch_gtilde(const GtArgs &a, hipStream_t st)
 //   c(k) = prod(2/M) [ -beta / (pi^2 sum k^2/L^2) + gt_hat / Lambda ]     (order 4)
 // then the inverse sine transform along axis 0, written back in place.
 // ---------------------------------------------------------------------------
-template <typename T, int MAXE, bool P2>
-__global__ __launch_bounds__(NT) void k_final(FinalArgs a)
+// Staged row kx-1 = i of the final pass (see k_final for the layout).
+__device__ __forceinline__ void final_row(const FinalArgs &a, int i, int kB, double lamB, double qB,
+                                          double *r)
 {
+    const Geo &geo = a.geo;
+    const int d = geo.d;
+    const int I0 = geo.M[0] - 1;
+    const int nt = a.order == 6 ? 3 : 1;
+    const double c2xz = d == 3 ? geo.c2[0][2] : 0.0;
+    const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
+    const double lx = a.tab[0].lam[i];
+    r[0] = lx;
+    r[1] = a.tab[0].q[i] + qB;
+    r[2] = a.tab[0].s[i];
+    r[3] = a.tab[0].s[I0 + i];
+    r[10] = lx + c2xz * lx * lamB;
+    r[11] = lx * lamB * (c4xz * lx + c4zx * lamB);
+    // family 1: other index (k0, k2) in 3D (transposed copy: k0 contiguous), (k0) in 2D
+    const int64_t ss1 = shell_size(geo, 1);
+    const double *P1 = d == 3 ? a.sh.P1T : a.sh.P[1];
+    const int64_t o = d == 3 ? (int64_t)(kB - 1) * I0 + i : i;
+    for (int par = 0; par < 2; ++par)
+        for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = P1[(par * 3 + t) * ss1 + o];
+    for (int par = 0; par < 2; ++par)
+        for (int t = nt; t < 3; ++t) r[4 + par * 3 + t] = 0.0;
+}
+
+template <typename T, int MAXE, bool P2, int WC, int NTT>
+__global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
+{
+    constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = W + 1;
-    const int lgW = 31 - __clz(W), lgs = lgW - 1;
-    cx<T> *tw = reinterpret_cast<cx<T> *>(smem);
-    T *buf = reinterpret_cast<T *>(smem + (size_t)N * sizeof(cx<T>));
+    // WC > 0: tile width known at compile time (row offsets become shifts)
+    const int N = a.fd.N, M = a.fd.M, W = WC > 0 ? WC : a.W, rs = BIG ? W : W + 1;
+    const int lgW = WC > 0 ? __builtin_ctz(WC > 0 ? WC : 1) : 31 - __clz(W), lgs = lgW - 1;
+    const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
+    const size_t twb = BIG ? 0 : (size_t)N * sizeof(cx<T>);
+    T *buf = reinterpret_cast<T *>(smem + twb);
     const int ncb = (a.ncols + W - 1) / W;
     const int lb = xcd_remap(blockIdx.x, ncb * a.nbatch);
     // logical order: pairs of neighbouring column blocks, then the batch, then
@@ -906,54 +993,33 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
     const int c0 = cb * W;
     const int nc = min(W, a.ncols - c0);
     T *g = static_cast<T *>(a.buf) + bt * a.ibs + c0 * a.ics;
-    load_twiddles<T, NT>(tw, a.tw, N);
-    zero_rows<T, NT>(buf, rs, lgW, 0, 1);
-    zero_rows<T, NT>(buf, rs, lgW, 1 + a.nrows_in, N);
-    tile_load<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, lgW);
-    __syncthreads();
-    fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, false);
-    post_cs<T, MAXE, NT>(buf, rs, lgs, M);
-    // Row (axis 0) and column (axis 1) invariants staged in LDS:
-    //   [lam, q, s1, s2, packed shell values of the family whose other index
-    //    is fixed along the row/column, for both parities of the crossing axis]
+    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
+    zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
+    zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
+    tile_load<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, lgW);
     const Geo &geo = a.geo;
     const int d = geo.d;
-    const int tot = (M - 1) << lgW;
     const bool six = a.order == 6;
     const int nt = six ? 3 : 1;
-    constexpr int SV = 10;
+    // Staged per row kx and per column ky (12 doubles each):
+    //   [0] lambda  [1] q (rows: + q_z)  [2] sin(pi k/M)  [3] sin(2 pi k/M)
+    //   [4..9] packed shell values of the family whose other index is fixed
+    //          along the row/column, parity 0 then 1, three kinds each
+    //   [10] lambda + c2[.][2] lambda lambda_z   (part of Lambda)
+    //   [11] c4[.][2] lambda^2 lambda_z + c4[2][.] lambda lambda_z^2   (part of m_R)
+    // so that per element Lambda = r10 + c10 + lambda_z + c2[0][1] lx ly and
+    // m_R = r11 + c11 + lx ly (c4[0][1] lx + c4[1][0] ly).
+    constexpr int SV = 12;
     // staging area after the tile, 8-byte aligned, addressed from smem so that
     // it stays in the LDS address space
-    const size_t soff = ((size_t)N * sizeof(cx<T>) + (size_t)N * rs * sizeof(T) + 7) & ~(size_t)7;
-    double *rv = reinterpret_cast<double *>(smem + soff);
-    double *cv = rv + (size_t)(M - 1) * SV;
+    // (transforms longer than 2048: the row table lives in global memory,
+    // written for the solve by k_final_rows; only the columns are staged)
+    const size_t soff = (twb + (size_t)N * rs * sizeof(T) + 7) & ~(size_t)7;
+    double *rv = BIG ? a.rowtab : reinterpret_cast<double *>(smem + soff);
+    double *cv = BIG ? reinterpret_cast<double *>(smem + soff) : rv + (size_t)(M - 1) * SV;
     const int I0 = geo.M[0] - 1, I1 = geo.M[1] - 1, I2 = d == 3 ? geo.M[2] - 1 : 1;
     const int kB = bt + 1;
     const int64_t ss0 = shell_size(geo, 0), ss1 = shell_size(geo, 1);
-    for (int i = threadIdx.x; i < I0; i += NT) {
-        double *r = rv + i * SV;
-        r[0] = a.tab[0].lam[i];
-        r[1] = a.tab[0].q[i];
-        r[2] = a.tab[0].s[i];
-        r[3] = a.tab[0].s[I0 + i];
-        // family 1: other index (k0, k2) in 3D (transposed copy: k0 contiguous), (k0) in 2D
-        const double *P1 = d == 3 ? a.sh.P1T : a.sh.P[1];
-        const int64_t o = d == 3 ? (int64_t)(kB - 1) * I0 + i : i;
-        for (int par = 0; par < 2; ++par)
-            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = P1[(par * 3 + t) * ss1 + o];
-    }
-    for (int i = threadIdx.x; i < nc; i += NT) {
-        double *r = cv + i * SV;
-        const int j = c0 + i; // k1 - 1
-        r[0] = a.tab[1].lam[j];
-        r[1] = a.tab[1].q[j];
-        r[2] = a.tab[1].s[j];
-        r[3] = a.tab[1].s[I1 + j];
-        // family 0: other index (k1, k2) in 3D, (k1) in 2D
-        const int64_t o = d == 3 ? (int64_t)j * I2 + (kB - 1) : j;
-        for (int par = 0; par < 2; ++par)
-            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = a.sh.P[0][(par * 3 + t) * ss0 + o];
-    }
     // batch (axis 2) constants and the per-element family 2
     double lamB = 0.0, qB = 0.0, s1B = 0.0, s2B = 0.0;
     const double *Pz = nullptr;
@@ -966,54 +1032,130 @@ __global__ __launch_bounds__(NT) void k_final(FinalArgs a)
         ss2 = shell_size(geo, 2);
         Pz = a.sh.P[2] + ((kB & 1) ? 3 * ss2 : 0);
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < tot; e += NT) {
-        const int c = e & (W - 1), kx = 1 + (e >> lgW);
-        double cval = 0.0;
-        if (c < nc) {
-            const int ky = 1 + c0 + c;
-            const double *r = rv + (kx - 1) * SV;
-            const double *q1 = cv + c * SV;
-            const double beta = (double)buf[(M + kx) * rs + c];
-            const double *Pr = r + 4 + ((ky & 1) ? 3 : 0);  // family 1 at (kx, kz)
-            const double *Pc = q1 + 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz)
-            double lam[3] = {r[0], q1[0], lamB};
-            double q = r[1] + q1[1] + qB;
-            double gt = r[2] * Pc[0] + q1[2] * Pr[0];
-            double dh = 0.0;
-            if (six) dh = r[2] * Pc[1] + r[3] * Pc[2] + q1[2] * Pr[1] + q1[3] * Pr[2];
-            if (d == 3) {
-                const double *Pe = Pz + (int64_t)(kx - 1) * I1 + (ky - 1);
-                gt += s1B * Pe[0];
-                if (six) dh += s1B * Pe[ss2] + s2B * Pe[2 * ss2];
-            }
-            double Lm, Rm;
-            lam_symbols(geo, lam, Lm, Rm);
-            const double iL = 1.0 / Lm;
-            const double harm = six ? (gt * (1.0 + Rm * iL) + dh) * iL : gt * iL;
-            cval = geo.pref * (harm - beta / q);
-        }
-        buf[(M + kx) * rs + c] = (T)cval;
+    const double c2xz = d == 3 ? geo.c2[0][2] : 0.0, c2yz = d == 3 ? geo.c2[1][2] : 0.0;
+    const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
+    const double c4yz = d == 3 ? geo.c4[1][2] : 0.0, c4zy = d == 3 ? geo.c4[2][1] : 0.0;
+    if (!BIG)
+        for (int i = threadIdx.x; i < I0; i += NTT) final_row(a, i, kB, lamB, qB, rv + i * SV);
+    for (int i = threadIdx.x; i < nc; i += NTT) {
+        double *r = cv + i * SV;
+        const int j = c0 + i; // k1 - 1
+        const double ly = a.tab[1].lam[j];
+        r[0] = ly;
+        r[1] = a.tab[1].q[j];
+        r[2] = a.tab[1].s[j];
+        r[3] = a.tab[1].s[I1 + j];
+        r[10] = ly + c2yz * ly * lamB;
+        r[11] = ly * lamB * (c4yz * ly + c4zy * lamB);
+        // family 0: other index (k1, k2) in 3D, (k1) in 2D
+        const int64_t o = d == 3 ? (int64_t)j * I2 + (kB - 1) : j;
+        for (int par = 0; par < 2; ++par)
+            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = a.sh.P[0][(par * 3 + t) * ss0 + o];
     }
     __syncthreads();
-    pre_herm<T, MAXE, NT>(buf, rs, lgs, M, true);
-    fft_tile<T, MAXE, NT, P2>(buf, rs, lgs, a.fd, tw, true);
-    tile_store<T, T, NT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW);
+    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false);
+    // One sweep over the row pairs (k, N-k) of every complex sequence s
+    // (real columns 2s and 2s+1):
+    //   sine coefficients  S_a = (z(N-k).y - z(k).y)/2,  S_b = (z(k).x - z(N-k).x)/2
+    //   (raw DST of rho along axis 0 at kx = k; the cosine part is not needed),
+    //   spectral combination of each column into its coefficient c(k),
+    //   and the hermitian input of the inverse sine transform:
+    //   z(k) = (c_b, -c_a), z(N-k) = (-c_b, c_a), rows 0 and M zero.
+    // Each thread owns both rows of its pair, so no barrier is needed between
+    // the reads and the writes.
+    const double c2xy = geo.c2[0][1], c4xy = geo.c4[0][1], c4yx = geo.c4[1][0];
+    const int smask = (1 << lgs) - 1;
+    const int npair = (M + 1) << lgs;
+    for (int e = threadIdx.x; e < npair; e += NTT) {
+        const int sq = e & smask, k = e >> lgs;
+        if (k == 0 || k == M) {
+            lds_cs(buf, rs, k, sq, cx<T>{(T)0, (T)0});
+            continue;
+        }
+        const cx<T> z1 = lds_c(buf, rs, k, sq), z2 = lds_c(buf, rs, N - k, sq);
+        double cab[2];
+        const double beta2[2] = {0.5 * ((double)z2.y - (double)z1.y), 0.5 * ((double)z1.x - (double)z2.x)};
+        const double *r = rv + (k - 1) * SV;
+        const int kx = k;
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int c = 2 * sq + h2;
+            double cval = 0.0;
+            if (c < nc) {
+                const int ky = 1 + c0 + c;
+                const double *q1 = cv + c * SV;
+                const double *Pr = r + 4 + ((ky & 1) ? 3 : 0);  // family 1 at (kx, kz)
+                const double *Pc = q1 + 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz)
+                const double lx = r[0], ly = q1[0], lxy = lx * ly;
+                const double Lm = r[10] + q1[10] + lamB + c2xy * lxy;
+                double gt = r[2] * Pc[0] + q1[2] * Pr[0];
+                double dh = 0.0;
+                if (six) dh = r[2] * Pc[1] + r[3] * Pc[2] + q1[2] * Pr[1] + q1[3] * Pr[2];
+                if (d == 3) {
+                    const double *Pe = Pz + (int64_t)(kx - 1) * I1 + (ky - 1);
+                    gt += s1B * Pe[0];
+                    if (six) dh += s1B * Pe[ss2] + s2B * Pe[2 * ss2];
+                }
+                const double iL = recip(Lm);
+                double harm;
+                if (six) {
+                    const double Rm = r[11] + q1[11] + lxy * (c4xy * lx + c4yx * ly);
+                    harm = (gt * (1.0 + Rm * iL) + dh) * iL;
+                } else {
+                    harm = gt * iL;
+                }
+                cval = geo.pref * (harm - beta2[h2] * recip(r[1] + q1[1]));
+            }
+            cab[h2] = cval;
+        }
+        lds_cs(buf, rs, k, sq, cx<T>{(T)cab[1], (T)(-cab[0])});
+        lds_cs(buf, rs, N - k, sq, cx<T>{(T)(-cab[1]), (T)cab[0]});
+    }
+    __syncthreads();
+    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, true);
+    tile_store<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW);
+}
+
+template <typename T, int MAXE, bool P2, int WC, int NTT = NT>
+static void launch_final_w(const FinalArgs &a, int nblk, size_t lds, hipStream_t st)
+{
+    set_lds((const void *)&k_final<T, MAXE, P2, WC, NTT>, lds);
+    hipLaunchKernelGGL((k_final<T, MAXE, P2, WC, NTT>), dim3(nblk), dim3(NTT), lds, st, a);
 }
 
 template <typename T, int MAXE, bool P2>
 static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
 {
-    // tile + staged row (M0-1 rows) and column (W) invariants, 10 doubles each
-    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)(a.fd.M - 1 + a.W) * 10 * sizeof(double);
-    set_lds((const void *)&k_final<T, MAXE, P2>, lds);
-    hipLaunchKernelGGL((k_final<T, MAXE, P2>), dim3(nblk), dim3(NT), lds, st, a);
+    // tile + staged row (M0-1 rows) and column (W) invariants, 12 doubles each
+    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)(a.fd.M - 1 + a.W) * 12 * sizeof(double);
+    if (a.W == 8)
+        launch_final_w<T, MAXE, P2, 8>(a, nblk, lds, st);
+    else if (a.W == 16)
+        launch_final_w<T, MAXE, P2, 16>(a, nblk, lds, st);
+    else
+        launch_final_w<T, MAXE, P2, 0>(a, nblk, lds, st);
 }
 
 template <typename T>
 static void launch_final_t(const FinalArgs &a, int nblk, int work, hipStream_t st)
 {
     const bool p2 = is_pow2(a.fd.N);
+    if (big_fft(a.fd.N)) {
+        // tile + staged columns only (the rows come from the global table)
+        const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)a.W * 12 * sizeof(double);
+        if (work <= 4 * NTB) {
+            if (p2)
+                launch_final_w<T, 4, true, 2, NTB>(a, nblk, lds, st);
+            else
+                launch_final_w<T, 4, false, 2, NTB>(a, nblk, lds, st);
+        } else {
+            if (p2)
+                launch_final_w<T, 8, true, 2, NTB>(a, nblk, lds, st);
+            else
+                launch_final_w<T, 8, false, 2, NTB>(a, nblk, lds, st);
+        }
+        return;
+    }
     if (work <= 4 * NT) {
         if (p2)
             launch_final_k<T, 4, true>(a, nblk, st);
@@ -1032,12 +1174,25 @@ static void launch_final_t(const FinalArgs &a, int nblk, int work, hipStream_t s
     }
 }
 
+// Row table of the final pass for transforms longer than 2048 (2D: one
+// table per solve, the batch axis is absent).
+__global__ void k_final_rows(FinalArgs a)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.geo.M[0] - 1; i += gridDim.x * blockDim.x)
+        final_row(a, i, 1, 0.0, 0.0, a.rowtab + (int64_t)i * 12);
+}
+
 hipError_t launch_final(const FinalArgs &a, hipStream_t st)
 {
     const int ncb = (a.ncols + a.W - 1) / a.W;
     const int nblk = ncb * a.nbatch;
     const int work = (a.W / 2) * a.fd.N;
-    if (work > 16 * NT) return hipErrorInvalidValue;
+    if (big_fft(a.fd.N)) {
+        if (a.geo.d != 2 || !a.rowtab || a.W != 2 || work > 8 * NTB) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_final_rows, dim3((a.geo.M[0] + NT - 1) / NT), dim3(NT), 0, st, a);
+    } else if (work > 16 * NT) {
+        return hipErrorInvalidValue;
+    }
     if (a.mixed)
         launch_final_t<float>(a, nblk, work, st);
     else
@@ -1085,29 +1240,30 @@ hipError_t launch_ksample(double *out, int d, int a, int b, int c, const int *M,
 // 1D: phi* by one sine-transform pencil, end values by direct sums of
 // G(r) = r/2, phi_H linear between them.
 // ---------------------------------------------------------------------------
-template <int MAXE>
-__global__ __launch_bounds__(NT) void k_1d(const double *rho, double *phi, int M, double h,
-                                           FftDesc fd, const cx<double> *twg, AxisTabs tab)
+template <int MAXE, int NTT>
+__global__ __launch_bounds__(NTT) void k_1d(const double *rho, double *phi, int M, double h,
+                                            FftDesc fd, const cx<double> *twg, AxisTabs tab)
 {
+    constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = fd.N, rs = 3, lgW = 1;
-    cx<double> *tw = reinterpret_cast<cx<double> *>(smem);
-    double *buf = reinterpret_cast<double *>(smem + (size_t)N * sizeof(cx<double>));
-    __shared__ double red[2][NT];
-    load_twiddles<double, NT>(tw, twg, N);
+    const int N = fd.N, rs = BIG ? 2 : 3, lgW = 1;
+    const cx<double> *tw = BIG ? twg : reinterpret_cast<const cx<double> *>(smem);
+    double *buf = reinterpret_cast<double *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<double>)));
+    __shared__ double red[2][NTT];
+    if (!BIG) load_twiddles<double, NTT>(reinterpret_cast<cx<double> *>(smem), twg, N);
     // end values
     double s0 = 0.0, s1 = 0.0;
-    for (int j = 1 + threadIdx.x; j < M; j += NT) {
+    for (int j = 1 + threadIdx.x; j < M; j += NTT) {
         s0 += (0.5 * j * h) * rho[j];
         s1 += (0.5 * (M - j) * h) * rho[j];
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;
-    zero_rows<double, NT>(buf, rs, lgW, 0, 1);
-    zero_rows<double, NT>(buf, rs, lgW, M, N);
-    tile_load<double, double, NT>(buf, rs, 1, rho + 1, M - 1, 1, 1, 1, lgW);
+    zero_rows<double, NTT>(buf, rs, lgW, 0, 1);
+    zero_rows<double, NTT>(buf, rs, lgW, M, N);
+    tile_load<double, double, NTT>(buf, rs, 1, rho + 1, M - 1, 1, 1, 1, lgW);
     __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
+    for (int w = NTT / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
             red[0][threadIdx.x] += red[0][threadIdx.x + w];
             red[1][threadIdx.x] += red[1][threadIdx.x + w];
@@ -1115,14 +1271,14 @@ __global__ __launch_bounds__(NT) void k_1d(const double *rho, double *phi, int M
         __syncthreads();
     }
     const double g0 = h * red[0][0], g1 = h * red[1][0];
-    fft_tile<double, MAXE, NT>(buf, rs, 0, fd, tw, false);
-    post_cs<double, MAXE, NT>(buf, rs, 0, M);
-    for (int k = 1 + threadIdx.x; k < M; k += NT)
+    fft_tile<double, MAXE, NTT>(buf, rs, 0, fd, tw, false);
+    post_cs<double, MAXE, NTT>(buf, rs, 0, M);
+    for (int k = 1 + threadIdx.x; k < M; k += NTT)
         buf[(M + k) * rs] = -(2.0 / M) * buf[(M + k) * rs] / tab.q[k - 1];
     __syncthreads();
-    pre_herm<double, MAXE, NT>(buf, rs, 0, M, true);
-    fft_tile<double, MAXE, NT>(buf, rs, 0, fd, tw, true);
-    for (int j = threadIdx.x; j <= M; j += NT) {
+    pre_herm<double, MAXE, NTT>(buf, rs, 0, M, true);
+    fft_tile<double, MAXE, NTT>(buf, rs, 0, fd, tw, true);
+    for (int j = threadIdx.x; j <= M; j += NTT) {
         double v;
         if (j == 0)
             v = g0;
@@ -1139,12 +1295,21 @@ hipError_t launch_1d(const double *rho, double *phi, int M, double h, const FftD
                      hipStream_t st)
 {
     const size_t lds = tile_lds<double>(fd.N, 2);
-    if (fd.N <= 4 * NT) {
-        set_lds((const void *)&k_1d<4>, lds);
-        hipLaunchKernelGGL((k_1d<4>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
+    if (big_fft(fd.N)) {
+        if (fd.N > 8 * NTB) return hipErrorInvalidValue;
+        if (fd.N <= 4 * NTB) {
+            set_lds((const void *)&k_1d<4, NTB>, lds);
+            hipLaunchKernelGGL((k_1d<4, NTB>), dim3(1), dim3(NTB), lds, st, rho, phi, M, h, fd, tw, tab);
+        } else {
+            set_lds((const void *)&k_1d<8, NTB>, lds);
+            hipLaunchKernelGGL((k_1d<8, NTB>), dim3(1), dim3(NTB), lds, st, rho, phi, M, h, fd, tw, tab);
+        }
+    } else if (fd.N <= 4 * NT) {
+        set_lds((const void *)&k_1d<4, NT>, lds);
+        hipLaunchKernelGGL((k_1d<4, NT>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
     } else if (fd.N <= 8 * NT) {
-        set_lds((const void *)&k_1d<8>, lds);
-        hipLaunchKernelGGL((k_1d<8>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
+        set_lds((const void *)&k_1d<8, NT>, lds);
+        hipLaunchKernelGGL((k_1d<8, NT>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
     } else {
         return hipErrorInvalidValue;
     }

@@ -34,7 +34,9 @@ int fail(int code, const std::string &msg)
             return fail(IPS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
     } while (0)
 
-constexpr int kMaxN = 2048; // longest transform (2M) held in one LDS tile
+constexpr int kLdsMaxN = 2048; // longest transform whose twiddles are staged in LDS
+constexpr int kMaxN3 = 2048;   // 3D: longest transform (2M) per axis
+constexpr int kMaxN12 = 8192;  // 1D and 2D: longest transform (one sequence per tile)
 
 // FFT length N = 2M as a list of Stockham radices (8, 4, 2, 3, 5, 7, other primes)
 bool factor_fft(int N, FftDesc &fd)
@@ -166,6 +168,8 @@ struct ips_plan_s {
     int M[3] = {0, 0, 0}, I[3] = {0, 0, 0}, N[3] = {0, 0, 0};
     FftDesc fd[3]{};
     cx<double> *tw[3] = {nullptr, nullptr, nullptr};
+    cx<float> *twf[3] = {nullptr, nullptr, nullptr}; // FP32 twiddles (transforms longer than 2048)
+    double *rowtab = nullptr;                          // 2D final pass, long axis 0
     AxisTabs tab[3]{};
     double *K[3] = {nullptr, nullptr, nullptr};
     void *A = nullptr; // slot transforms of rho along one axis (3D)
@@ -208,7 +212,8 @@ size_t final_pass_lds(int d, const int64_t *n, int precision, int work)
     const int N0 = 2 * (int)(n[0] - 1);
     const size_t tsz = precision != IPS_FP64 ? 4 : 8;
     const int W = tile_width(N0, work, (int)(n[1] - 2));
-    return (size_t)N0 * 2 * tsz + (size_t)N0 * (W + 1) * tsz + 8 + (size_t)(n[0] - 2 + W) * 80;
+    if (N0 > kLdsMaxN) return (size_t)N0 * W * tsz + 8 + (size_t)W * 96; // rows in global memory
+    return (size_t)N0 * 2 * tsz + (size_t)N0 * (W + 1) * tsz + 8 + (size_t)(n[0] - 2 + W) * 96;
 }
 
 int validate(int d, const int64_t *n, const double *h, int order, int precision, unsigned flags)
@@ -226,8 +231,10 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
             return fail(IPS_E_INVALID_ARG, "every h[i] must be finite and > 0");
         if (d >= 2 && order == 6 && n[a] < 8)
             return fail(IPS_E_INVALID_ARG, "order 6 needs n[i] >= 8 (extrapolation stencil)");
-        if (2 * (n[a] - 1) > kMaxN)
-            return fail(IPS_E_UNSUPPORTED, "n[i] - 1 must not exceed " + std::to_string(kMaxN / 2));
+        const int maxN = d == 3 ? kMaxN3 : kMaxN12;
+        if (2 * (n[a] - 1) > maxN)
+            return fail(IPS_E_UNSUPPORTED, "n[i] - 1 must not exceed " + std::to_string(maxN / 2) +
+                                               (d == 3 ? " in 3D" : " in 1D and 2D"));
     }
     if (d == 1 && precision != IPS_FP64)
         return fail(IPS_E_UNSUPPORTED, "d = 1 runs in FP64 only");
@@ -272,6 +279,9 @@ int run_pass(ips_plan p, PassArgs a, const FftDesc &fd, const cx<double> *tw, bo
 {
     a.fd = fd;
     a.tw = tw;
+    a.twf = nullptr;
+    for (int ax = 0; ax < p->d; ++ax)
+        if (p->tw[ax] == tw) a.twf = p->twf[ax];
     if (a.W == 0) a.W = tile_width(fd.N, p->work, a.ncols);
     IPS_HIP(launch_pass(a, in_f32, out_f32, st));
     return IPS_OK;
@@ -351,6 +361,14 @@ int plan_build(ips_plan p, hipStream_t st)
         int rc = p->mem.alloc((void **)&p->tw[a], w.size() * sizeof(cx<double>));
         if (rc) return rc;
         IPS_HIP(hipMemcpy(p->tw[a], w.data(), w.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
+        if (p->N[a] > kLdsMaxN) {
+            // long transforms read their twiddles from global memory: FP32 copy
+            std::vector<cx<float>> wf(w.size());
+            for (size_t t = 0; t < w.size(); ++t) wf[t] = {(float)w[t].x, (float)w[t].y};
+            rc = p->mem.alloc((void **)&p->twf[a], wf.size() * sizeof(cx<float>));
+            if (rc) return rc;
+            IPS_HIP(hipMemcpy(p->twf[a], wf.data(), wf.size() * sizeof(cx<float>), hipMemcpyHostToDevice));
+        }
         std::vector<double> t = axis_tables(p->M[a], p->h[a]);
         double *dt = nullptr;
         rc = p->mem.alloc((void **)&dt, t.size() * sizeof(double));
@@ -371,6 +389,8 @@ int plan_build(ips_plan p, hipStream_t st)
     const size_t asz = p->precision == IPS_MIXED_FP32_SLICES ? sizeof(float) : sizeof(double);
     int rc = p->mem.alloc(&p->B, vol * wsz);
     if (rc) return rc;
+    if (d == 2 && N[0] > kLdsMaxN && (rc = p->mem.alloc((void **)&p->rowtab, (size_t)I[0] * 12 * sizeof(double))))
+        return rc;
     if (d == 3) {
         const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
         rc = p->mem.alloc(&p->A, std::max(a1, a2) * asz);
@@ -397,7 +417,9 @@ int plan_build(ips_plan p, hipStream_t st)
         }
         const int W = tile_width(N[pen], p->work, I[fam]);
         const int ncb = (I[fam] + W - 1) / W;
-        int nch = std::max(1, std::min(ncb, (2048 + nbatch - 1) / nbatch));
+        // about 2048 blocks of 256 threads; 256 blocks of 1024 for long transforms
+        const int target = N[pen] > kLdsMaxN ? 256 : 2048;
+        int nch = std::max(1, std::min(ncb, (target + nbatch - 1) / nbatch));
         const int per = (ncb + nch - 1) / nch;
         p->chunk[fam] = per * W;
         p->nch[fam] = (I[fam] + per * W - 1) / (per * W);
@@ -594,6 +616,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.W = tile_width(N[1], p->work, a.ncols);
             a.fd = p->fd[1];
             a.tw = p->tw[1];
+            a.twf = p->twf[1];
             IPS_HIP(launch_cc(a, p->nch[0], f32s, f32s, st));
         }
         {
@@ -617,6 +640,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
+            a.twf = p->twf[0];
             IPS_HIP(launch_cc(a, p->nch[1], f32s, f32s, st));
         }
         {
@@ -661,6 +685,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
             a.tw = p->tw[0];
+            a.twf = p->twf[0];
             IPS_HIP(launch_cc(a, p->nch[2], f32s, f32s, st));
         }
         STAGE(IPS_STAGE_FACES);
@@ -751,6 +776,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.W = tile_width(N[pen], p->work, a.ncols);
             a.fd = p->fd[pen];
             a.tw = p->tw[pen];
+            a.twf = p->twf[pen];
             IPS_HIP(launch_cc(a, p->nch[fam], f32s, false, st));
         }
         STAGE(IPS_STAGE_FACES);
@@ -876,6 +902,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         a.sh = sh;
         a.fd = p->fd[0];
         a.tw = p->tw[0];
+        a.twf = p->twf[0];
+        a.rowtab = p->rowtab;
         IPS_HIP(launch_final(a, st));
     }
     if (d == 3) {

@@ -53,7 +53,8 @@ def _create(d, n, h, order=6, precision=0, flags=0):
         ((2, [9, 9], [float("nan"), 0.1]), -1),
         ((2, [9, 9], [float("inf"), 0.1]), -1),
         ((3, [9, 9, 7], [0.1] * 3), -1),  # order 6 needs n >= 8
-        ((2, [9, 2049], [0.1, 0.1]), -2),  # longer than one LDS tile
+        ((2, [9, 4098], [0.1, 0.1]), -2),  # 2D: transforms longer than 8192
+        ((3, [9, 9, 1026], [0.1, 0.1, 0.1]), -2),  # 3D: transforms longer than 2048
     ],
 )
 def test_plan_create_rejects_bad_geometry(args, code):
