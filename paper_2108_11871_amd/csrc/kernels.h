@@ -117,7 +117,8 @@ struct FinalArgs {
     FftDesc fd;
     const cx<double> *tw;
     const cx<float> *twf;
-    double *rowtab; // 2D, transforms longer than 2048: row table [M0 - 1][12]
+    double *rowtab; // if set: row table [nbatch][M0 - 1][12] in global memory, written by
+                    // launch_final before the pass (required for transforms longer than 2048)
 };
 
 // Sixth-order right-hand side on the depth-5 shell layers (see k_r6t).

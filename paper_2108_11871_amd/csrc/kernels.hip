@@ -224,9 +224,14 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
     const int kb = a.Mo > 0 ? (bt <= a.Mo ? bt : bt - a.Mo) : 0;
     const TI *in = static_cast<const TI *>(a.in);
     T *Bout = static_cast<T *>(a.Bout);
-    double acc0[RPT], acc1[RPT]; // rows per thread: RPT * NT >= N
+    // Wavenumbers per thread: kp = threadIdx.x + i NTT, i < KPT (KPT NTT >= M + 1).
+    // A thread owns both slot rows of its wavenumbers, C at row kp and S at
+    // row M + kp, which share the kernel spectrum value: one load of each
+    // face's K feeds four products.
+    constexpr int KPT = RPT / 2 + 1;
+    double aC0[KPT], aS0[KPT], aC1[KPT], aS1[KPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) acc0[i] = acc1[i] = 0.0;
+    for (int i = 0; i < KPT; ++i) aC0[i] = aS0[i] = aC1[i] = aS1[i] = 0.0;
     if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
     const int cbeg = ch * a.cols_per_chunk;
     const int cend = min(a.ncols, cbeg + a.cols_per_chunk);
@@ -254,16 +259,22 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
             }
         }
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int row = threadIdx.x + i * NTT;
-            if (row < N) {
-                const int kp = row <= M ? row : row - M;
+        for (int i = 0; i < KPT; ++i) {
+            const int kp = threadIdx.x + i * NTT;
+            if (kp <= M) {
+                const bool hs = kp >= 1 && kp < M; // has a sine slot
+                const int srow = hs ? M + kp : kp;
                 const double *Kr = a.K + (int64_t)kb * a.Ko + kp;
+                const double *K0 = Kr + (int64_t)c0 * a.Kd;
+                const double *K1 = Kr + (int64_t)(a.ncols - 1 - c0) * a.Kd;
                 for (int c = 0; c < nc; ++c) {
-                    const double v = (double)buf[row * rs + c];
-                    const int dd = c0 + c;
-                    acc0[i] += Kr[(int64_t)dd * a.Kd] * v;
-                    acc1[i] += Kr[(int64_t)(a.ncols - 1 - dd) * a.Kd] * v;
+                    const double k0 = K0[(int64_t)c * a.Kd], k1 = K1[-(int64_t)c * a.Kd];
+                    const double vc = (double)buf[kp * rs + c];
+                    const double vs = hs ? (double)buf[srow * rs + c] : 0.0;
+                    aC0[i] += k0 * vc;
+                    aC1[i] += k1 * vc;
+                    aS0[i] += k0 * vs;
+                    aS1[i] += k1 * vs;
                 }
             }
         }
@@ -273,11 +284,15 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
     double *p0 = a.part + ((int64_t)ch * a.nbatch + bt) * N;
     double *p1 = p0 + (int64_t)nchunk * a.nbatch * N;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int row = threadIdx.x + i * NTT;
-        if (row < N) {
-            p0[row] = acc0[i];
-            p1[row] = acc1[i];
+    for (int i = 0; i < KPT; ++i) {
+        const int kp = threadIdx.x + i * NTT;
+        if (kp <= M) {
+            p0[kp] = aC0[i];
+            p1[kp] = aC1[i];
+            if (kp >= 1 && kp < M) {
+                p0[M + kp] = aS0[i];
+                p1[M + kp] = aS1[i];
+            }
         }
     }
 }
@@ -1015,8 +1030,9 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     // (transforms longer than 2048: the row table lives in global memory,
     // written for the solve by k_final_rows; only the columns are staged)
     const size_t soff = (twb + (size_t)N * rs * sizeof(T) + 7) & ~(size_t)7;
-    double *rv = BIG ? a.rowtab : reinterpret_cast<double *>(smem + soff);
-    double *cv = BIG ? reinterpret_cast<double *>(smem + soff) : rv + (size_t)(M - 1) * SV;
+    const bool grows = BIG || a.rowtab != nullptr; // row table in global memory
+    double *rv = grows ? a.rowtab + (BIG ? 0 : (int64_t)bt * (M - 1) * SV) : reinterpret_cast<double *>(smem + soff);
+    double *cv = grows ? reinterpret_cast<double *>(smem + soff) : rv + (size_t)(M - 1) * SV;
     const int I0 = geo.M[0] - 1, I1 = geo.M[1] - 1, I2 = d == 3 ? geo.M[2] - 1 : 1;
     const int kB = bt + 1;
     const int64_t ss0 = shell_size(geo, 0), ss1 = shell_size(geo, 1);
@@ -1035,7 +1051,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     const double c2xz = d == 3 ? geo.c2[0][2] : 0.0, c2yz = d == 3 ? geo.c2[1][2] : 0.0;
     const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
     const double c4yz = d == 3 ? geo.c4[1][2] : 0.0, c4zy = d == 3 ? geo.c4[2][1] : 0.0;
-    if (!BIG)
+    if (!grows)
         for (int i = threadIdx.x; i < I0; i += NTT) final_row(a, i, kB, lamB, qB, rv + i * SV);
     for (int i = threadIdx.x; i < nc; i += NTT) {
         double *r = cv + i * SV;
@@ -1126,12 +1142,16 @@ static void launch_final_w(const FinalArgs &a, int nblk, size_t lds, hipStream_t
 template <typename T, int MAXE, bool P2>
 static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
 {
-    // tile + staged row (M0-1 rows) and column (W) invariants, 12 doubles each
-    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)(a.fd.M - 1 + a.W) * 12 * sizeof(double);
+    // tile + staged column (W) invariants and, unless the row table is in
+    // global memory, the row (M0-1) invariants, 12 doubles each
+    const size_t rows = a.rowtab ? 0 : (size_t)(a.fd.M - 1);
+    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (rows + a.W) * 12 * sizeof(double);
     if (a.W == 8)
         launch_final_w<T, MAXE, P2, 8>(a, nblk, lds, st);
     else if (a.W == 16)
         launch_final_w<T, MAXE, P2, 16>(a, nblk, lds, st);
+    else if (a.W == 32)
+        launch_final_w<T, MAXE, P2, 32>(a, nblk, lds, st);
     else
         launch_final_w<T, MAXE, P2, 0>(a, nblk, lds, st);
 }
@@ -1166,20 +1186,36 @@ static void launch_final_t(const FinalArgs &a, int nblk, int work, hipStream_t s
             launch_final_k<T, 8, true>(a, nblk, st);
         else
             launch_final_k<T, 8, false>(a, nblk, st);
-    } else {
+    } else if (work <= 16 * NT) {
         if (p2)
             launch_final_k<T, 16, true>(a, nblk, st);
         else
             launch_final_k<T, 16, false>(a, nblk, st);
+    } else {
+        if (p2)
+            launch_final_k<T, 32, true>(a, nblk, st);
+        else
+            launch_final_k<T, 32, false>(a, nblk, st);
     }
 }
 
-// Row table of the final pass for transforms longer than 2048 (2D: one
-// table per solve, the batch axis is absent).
+// Row table of the final pass in global memory, one per batch index
+// (rowtab[kB - 1][kx - 1][12]); 2D has a single batch index.
 __global__ void k_final_rows(FinalArgs a)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.geo.M[0] - 1; i += gridDim.x * blockDim.x)
-        final_row(a, i, 1, 0.0, 0.0, a.rowtab + (int64_t)i * 12);
+    const int I0 = a.geo.M[0] - 1;
+    const int64_t tot = (int64_t)I0 * a.nbatch;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % I0), b = (int)(e / I0);
+        const int kB = b + 1;
+        double lamB = 0.0, qB = 0.0;
+        if (a.geo.d == 3) {
+            lamB = a.tab[2].lam[kB - 1];
+            qB = a.tab[2].q[kB - 1];
+        }
+        final_row(a, i, kB, lamB, qB, a.rowtab + e * 12);
+    }
 }
 
 hipError_t launch_final(const FinalArgs &a, hipStream_t st)
@@ -1187,11 +1223,13 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st)
     const int ncb = (a.ncols + a.W - 1) / a.W;
     const int nblk = ncb * a.nbatch;
     const int work = (a.W / 2) * a.fd.N;
-    if (big_fft(a.fd.N)) {
-        if (a.geo.d != 2 || !a.rowtab || a.W != 2 || work > 8 * NTB) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_final_rows, dim3((a.geo.M[0] + NT - 1) / NT), dim3(NT), 0, st, a);
-    } else if (work > 16 * NT) {
+    if (big_fft(a.fd.N) && (a.geo.d != 2 || !a.rowtab || a.W != 2 || work > 8 * NTB))
         return hipErrorInvalidValue;
+    if (!big_fft(a.fd.N) && work > 32 * NT) return hipErrorInvalidValue;
+    if (a.rowtab) {
+        const int64_t tot = (int64_t)(a.geo.M[0] - 1) * a.nbatch;
+        const unsigned nb = (unsigned)std::min<int64_t>((tot + NT - 1) / NT, 4096);
+        hipLaunchKernelGGL(k_final_rows, dim3(nb), dim3(NT), 0, st, a);
     }
     if (a.mixed)
         launch_final_t<float>(a, nblk, work, st);

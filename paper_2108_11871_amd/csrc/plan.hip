@@ -169,7 +169,7 @@ struct ips_plan_s {
     FftDesc fd[3]{};
     cx<double> *tw[3] = {nullptr, nullptr, nullptr};
     cx<float> *twf[3] = {nullptr, nullptr, nullptr}; // FP32 twiddles (transforms longer than 2048)
-    double *rowtab = nullptr;                          // 2D final pass, long axis 0
+    double *rowtab = nullptr;                          // final pass row table [batch][M0 - 1][12]
     AxisTabs tab[3]{};
     double *K[3] = {nullptr, nullptr, nullptr};
     void *A = nullptr; // slot transforms of rho along one axis (3D)
@@ -204,16 +204,28 @@ struct ips_plan_s {
 
 namespace {
 
-// LDS bytes of the final pass along axis 0 (tile, twiddles, staged row and
-// column tables) for tile budget `work`.
+// Tile budget of the final pass.  Its row invariants live in global memory,
+// so the LDS holds only the tile: 2048 complex elements (8 columns at
+// 2M = 512) measured fastest -- wider tiles (128-byte row segments) lose more
+// to occupancy than they gain in coalescing, narrower ones lose coalescing.
+int final_work(int precision)
+{
+    (void)precision;
+    return 2048;
+}
+
+// LDS bytes of the final pass along axis 0 (tile, twiddles, staged column
+// table).
 size_t final_pass_lds(int d, const int64_t *n, int precision, int work)
 {
     if (d < 2) return 0;
     const int N0 = 2 * (int)(n[0] - 1);
     const size_t tsz = precision != IPS_FP64 ? 4 : 8;
-    const int W = tile_width(N0, work, (int)(n[1] - 2));
-    if (N0 > kLdsMaxN) return (size_t)N0 * W * tsz + 8 + (size_t)W * 96; // rows in global memory
-    return (size_t)N0 * 2 * tsz + (size_t)N0 * (W + 1) * tsz + 8 + (size_t)(n[0] - 2 + W) * 96;
+    const int W = tile_width(N0, N0 > kLdsMaxN ? work : final_work(precision), (int)(n[1] - 2));
+    // tile (+ twiddles for short transforms) and staged columns; the row
+    // invariants live in global memory
+    if (N0 > kLdsMaxN) return (size_t)N0 * W * tsz + 8 + (size_t)W * 96;
+    return (size_t)N0 * 2 * tsz + (size_t)N0 * (W + 1) * tsz + 8 + (size_t)W * 96;
 }
 
 int validate(int d, const int64_t *n, const double *h, int order, int precision, unsigned flags)
@@ -389,8 +401,10 @@ int plan_build(ips_plan p, hipStream_t st)
     const size_t asz = p->precision == IPS_MIXED_FP32_SLICES ? sizeof(float) : sizeof(double);
     int rc = p->mem.alloc(&p->B, vol * wsz);
     if (rc) return rc;
-    if (d == 2 && N[0] > kLdsMaxN && (rc = p->mem.alloc((void **)&p->rowtab, (size_t)I[0] * 12 * sizeof(double))))
-        return rc;
+    {
+        const size_t nb = d == 3 ? (size_t)I[2] : 1;
+        if ((rc = p->mem.alloc((void **)&p->rowtab, nb * I[0] * 12 * sizeof(double)))) return rc;
+    }
     if (d == 3) {
         const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
         rc = p->mem.alloc(&p->A, std::max(a1, a2) * asz);
@@ -894,7 +908,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.bax = -1;
         }
         a.nrows_in = I[0];
-        a.W = tile_width(N[0], p->work, a.ncols);
+        a.W = tile_width(N[0], N[0] > kLdsMaxN ? p->work : final_work(p->precision), a.ncols);
         a.order = p->order;
         a.mixed = f32;
         a.geo = p->geo;
