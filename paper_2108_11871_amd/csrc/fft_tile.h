@@ -232,11 +232,83 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftD
     __syncthreads();
 }
 
+// Stockham stage with every size known at compile time: transform length
+// N, radix R, product of the earlier radices NS (a power of two), row pitch
+// RS and 2^LGS sequences.  Same data movement as stage_bfly; the index and
+// twiddle arithmetic folds to shifts and constants.
+template <typename T, int R, int NT, int N, int NS, int RS, int LGS>
+__device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv)
+{
+    constexpr int NR = N / R, NBF = NR << LGS, TSTEP = N / (NS * R), SMASK = (1 << LGS) - 1;
+    constexpr int BPT = (NBF + NT - 1) / NT;
+    cx<T> v[BPT][R];
+    int base[BPT];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        if (NBF % NT == 0 || b < NBF) {
+            const int sq = b & SMASK, j = b >> LGS;
+            const int jm = j & (NS - 1);
+            base[i] = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = lds_c(buf, RS, j + r * NR, sq);
+            if (NS > 1 && jm != 0) {
+                const int e = jm * TSTEP;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid(tw, e * r, inv));
+            }
+            dft_small<T, R>(v[i], tw, N, inv);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = threadIdx.x + i * NT;
+        if (NBF % NT == 0 || b < NBF) {
+            const int sq = b & SMASK;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_cs(buf, RS, base[i] + r * NS, sq, v[i][r]);
+        }
+    }
+    __syncthreads();
+}
+
+// Compile-time transforms for the common power-of-two lengths at the
+// default tile widths (radix-8 stages first, as factor_fft orders them).
+template <typename T, int NT, int N, int RS, int LGS>
+__device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, bool inv)
+{
+    if constexpr (N == 256) {
+        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 4, NT, N, 64, RS, LGS>(buf, tw, inv);
+    } else if constexpr (N == 512) {
+        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv);
+    } else if constexpr (N == 1024) {
+        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 2, NT, N, 512, RS, LGS>(buf, tw, inv);
+    }
+}
+
 // Full length-N complex FFT of 2^lgs sequences held in LDS (in place).
 // P2: N is a power of two (only radix-2/4/8 stages are compiled in).
-template <typename T, int MAXE, int NT, bool P2 = false>
+// CT = false keeps the generic stages (kernels that run several transforms
+// per block, where hoisted constant twiddles would cost occupancy).
+template <typename T, int MAXE, int NT, bool P2 = false, bool CT = true>
 __device__ void fft_tile(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, bool inv)
 {
+    if constexpr (P2 && CT && NT == 256) {
+        // (N, tile width) pairs of the default tile budget: N * W / 2 = MAXE * NT
+        if constexpr (MAXE == 8) {
+            if (fd.N == 512 && rs == 9) return fft_ct<T, NT, 512, 9, 2>(buf, tw, inv);
+            if (fd.N == 256 && rs == 17) return fft_ct<T, NT, 256, 17, 3>(buf, tw, inv);
+            if (fd.N == 1024 && rs == 5) return fft_ct<T, NT, 1024, 5, 1>(buf, tw, inv);
+        }
+    }
     if constexpr (P2) {
         for (int st = 0; st < fd.nst; ++st) {
             const int R = fd.rad[st];

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
         tile_load<T, TI, NTT>(buf, rs, 1, in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc, a.irs,
                              a.ics, lgW);
         __syncthreads();
-        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false);
+        fft_tile<T, MAXE, NTT, P2, false>(buf, rs, lgs, a.fd, tw, false);
         post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
         if (WB && (a.Mo == 0 || bt > a.Mo)) {
             const int64_t bb = a.Mo == 0 ? 0 : (int64_t)(bt - a.Mo - 1) * a.Bbs;
