@@ -70,7 +70,7 @@ def stage_bytes(n: int, mode: str, nch: dict) -> dict:
     vol = I ** 3
     wa = 4 if mode == "mixed_fp32_slices" else 8  # slot data of rho
     wb = 4 if mode != "fp64" else 8  # sine-space volume
-    kt = I * (M + 1) ** 2 * 8  # kernel spectra of one face family
+    kt = I * (M + 1) ** 2 * wa  # kernel spectra of one face family (FP32 with FP32 slots)
     A = I * I * N * wa
     part = 2 * N * N * 8
     return {

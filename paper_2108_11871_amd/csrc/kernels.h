@@ -47,7 +47,7 @@ struct CcArgs {
     int nbatch;        // slots of the remaining in-face axis (1 if none)
     int Mo;            // M of that axis (slot -> wavenumber), 0 if none
     int cols_per_chunk;
-    const double *K;   // K[d][k_o][k_p], k_p contiguous
+    const void *K;     // K[d][k_o][k_p], k_p contiguous: FP32 when the slot input is FP32, else FP64
     int64_t Kd, Ko;
     double *part;      // [2][nchunk][nbatch][2 M_p]
     void *Bout;        // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + (k_o-1)*Bbs],
@@ -212,5 +212,6 @@ hipError_t launch_ksample(double *out, int d, int a, int b, int c, const int *M,
 hipError_t launch_1d(const double *rho, double *phi, int M, double h, const FftDesc &fd,
                      const cx<double> *tw, const AxisTabs &tab, double *scratch, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 
 } // namespace ips

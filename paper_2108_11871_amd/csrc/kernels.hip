@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include "kernels.h"
@@ -264,11 +265,13 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
             if (kp <= M) {
                 const bool hs = kp >= 1 && kp < M; // has a sine slot
                 const int srow = hs ? M + kp : kp;
-                const double *Kr = a.K + (int64_t)kb * a.Ko + kp;
-                const double *K0 = Kr + (int64_t)c0 * a.Kd;
-                const double *K1 = Kr + (int64_t)(a.ncols - 1 - c0) * a.Kd;
+                // kernel spectra in the slot type: FP32 when the slots are FP32
+                using TK = typename std::conditional<std::is_same<TI, float>::value, float, double>::type;
+                const TK *Kr = static_cast<const TK *>(a.K) + (int64_t)kb * a.Ko + kp;
+                const TK *K0 = Kr + (int64_t)c0 * a.Kd;
+                const TK *K1 = Kr + (int64_t)(a.ncols - 1 - c0) * a.Kd;
                 for (int c = 0; c < nc; ++c) {
-                    const double k0 = K0[(int64_t)c * a.Kd], k1 = K1[-(int64_t)c * a.Kd];
+                    const double k0 = (double)K0[(int64_t)c * a.Kd], k1 = (double)K1[-(int64_t)c * a.Kd];
                     const double vc = (double)buf[kp * rs + c];
                     const double vs = hs ? (double)buf[srow * rs + c] : 0.0;
                     aC0[i] += k0 * vc;
@@ -392,6 +395,20 @@ __global__ void k_fill(double *p, int64_t n, double v)
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+__global__ void k_to_f32(const double *src, float *dst, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st)
+{
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + NT - 1) / NT, 8192));
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(NT), 0, st, src, dst, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st)

@@ -172,6 +172,7 @@ struct ips_plan_s {
     double *rowtab = nullptr;                          // final pass row table [batch][M0 - 1][12]
     AxisTabs tab[3]{};
     double *K[3] = {nullptr, nullptr, nullptr};
+    float *K32[3] = {nullptr, nullptr, nullptr}; // FP32 copies (3D slices in FP32)
     void *A = nullptr; // slot transforms of rho along one axis (3D)
     void *B = nullptr; // raw DST of rho along the last d-1 axes, then phi in sine space
     double *part[3] = {nullptr, nullptr, nullptr};
@@ -525,6 +526,11 @@ int plan_build(ips_plan p, hipStream_t st)
             b2.scale = 1.0;
             if ((rc = run_pass(p, b2, p->fd[kb], p->tw[kb], false, false, st))) return rc;
         }
+        if (d == 3 && p->precision == IPS_MIXED_FP32_SLICES) {
+            // the FP32 slot data are contracted with FP32 kernel spectra
+            if ((rc = p->mem.alloc((void **)&p->K32[fam], ksz * sizeof(float)))) return rc;
+            IPS_HIP(launch_to_f32(p->K[fam], p->K32[fam], (int64_t)ksz, st));
+        }
     }
     return IPS_OK;
 }
@@ -618,7 +624,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[2];
             a.Mo = M[2];
             a.cols_per_chunk = p->chunk[0];
-            a.K = p->K[0];
+            a.K = f32s ? (const void *)p->K32[0] : (const void *)p->K[0];
             a.Kd = (int64_t)(M[2] + 1) * (M[1] + 1);
             a.Ko = M[1] + 1;
             a.part = p->part[0];
@@ -646,7 +652,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[2];
             a.Mo = M[2];
             a.cols_per_chunk = p->chunk[1];
-            a.K = p->K[1];
+            a.K = f32s ? (const void *)p->K32[1] : (const void *)p->K[1];
             a.Kd = (int64_t)(M[2] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
             a.part = p->part[1];
@@ -691,7 +697,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[1];
             a.Mo = M[1];
             a.cols_per_chunk = p->chunk[2];
-            a.K = p->K[2];
+            a.K = f32s ? (const void *)p->K32[2] : (const void *)p->K[2];
             a.Kd = (int64_t)(M[1] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
             a.part = p->part[2];
@@ -727,6 +733,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.out_r0 = 0;
             a.out_nrows = M[c] + 1;
             a.scale = 1.0 / N[c];
+            // few faces: narrow tiles give enough blocks to fill the device
+            a.W = tile_width(N[c], std::min(p->work, 512), a.ncols);
             if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) return rc;
             PassArgs b{};
             b.in = b.out = p->F[fam];
@@ -740,6 +748,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             b.out_r0 = 0;
             b.out_nrows = M[r] + 1;
             b.scale = 1.0 / N[r];
+            b.W = tile_width(N[r], std::min(p->work, 512), b.ncols);
             if ((rc = run_pass(p, b, p->fd[r], p->tw[r], false, false, st))) return rc;
         }
         // (8) boundary values into phi; F[fam][face][j_r][j_c] -> strides of the in-face
