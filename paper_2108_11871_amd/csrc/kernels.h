@@ -117,7 +117,7 @@ struct FinalArgs {
     FftDesc fd;
     const cx<double> *tw;
     const cx<float> *twf;
-    double *rowtab; // if set: row table [nbatch][M0 - 1][12] in global memory, written by
+    void *rowtab;   // if set: row table [nbatch][M0 - 1][12] (transform type) in global memory, written by
                     // launch_final before the pass (required for transforms longer than 2048)
 };
 

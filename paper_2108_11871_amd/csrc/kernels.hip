@@ -554,6 +554,13 @@ __device__ __forceinline__ double recip(double x)
     return fma(r, e, r);
 }
 
+// FP32: one Newton step on the hardware reciprocal.
+__device__ __forceinline__ float recip(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 
 // ---------------------------------------------------------------------------
 // Sixth-order right-hand side of the harmonic part, interior contribution.
@@ -967,8 +974,9 @@ hipError_t launch_gtilde(const GtArgs &a, hipStream_t st)
 // then the inverse sine transform along axis 0, written back in place.
 // ---------------------------------------------------------------------------
 // Staged row kx-1 = i of the final pass (see k_final for the layout).
+template <typename TR>
 __device__ __forceinline__ void final_row(const FinalArgs &a, int i, int kB, double lamB, double qB,
-                                          double *r)
+                                          TR *r)
 {
     const Geo &geo = a.geo;
     const int d = geo.d;
@@ -977,20 +985,20 @@ __device__ __forceinline__ void final_row(const FinalArgs &a, int i, int kB, dou
     const double c2xz = d == 3 ? geo.c2[0][2] : 0.0;
     const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
     const double lx = a.tab[0].lam[i];
-    r[0] = lx;
-    r[1] = a.tab[0].q[i] + qB;
-    r[2] = a.tab[0].s[i];
-    r[3] = a.tab[0].s[I0 + i];
-    r[10] = lx + c2xz * lx * lamB;
-    r[11] = lx * lamB * (c4xz * lx + c4zx * lamB);
+    r[0] = (TR)lx;
+    r[1] = (TR)(a.tab[0].q[i] + qB);
+    r[2] = (TR)a.tab[0].s[i];
+    r[3] = (TR)a.tab[0].s[I0 + i];
+    r[10] = (TR)(lx + c2xz * lx * lamB);
+    r[11] = (TR)(lx * lamB * (c4xz * lx + c4zx * lamB));
     // family 1: other index (k0, k2) in 3D (transposed copy: k0 contiguous), (k0) in 2D
     const int64_t ss1 = shell_size(geo, 1);
     const double *P1 = d == 3 ? a.sh.P1T : a.sh.P[1];
     const int64_t o = d == 3 ? (int64_t)(kB - 1) * I0 + i : i;
     for (int par = 0; par < 2; ++par)
-        for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = P1[(par * 3 + t) * ss1 + o];
+        for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = (TR)P1[(par * 3 + t) * ss1 + o];
     for (int par = 0; par < 2; ++par)
-        for (int t = nt; t < 3; ++t) r[4 + par * 3 + t] = 0.0;
+        for (int t = nt; t < 3; ++t) r[4 + par * 3 + t] = (TR)0;
 }
 
 template <typename T, int MAXE, bool P2, int WC, int NTT>
@@ -1047,9 +1055,12 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     // (transforms longer than 2048: the row table lives in global memory,
     // written for the solve by k_final_rows; only the columns are staged)
     const size_t soff = (twb + (size_t)N * rs * sizeof(T) + 7) & ~(size_t)7;
+    // staged values and the per-element combination are in the transform
+    // type (FP32 in the mixed modes, FP64 otherwise)
     const bool grows = BIG || a.rowtab != nullptr; // row table in global memory
-    double *rv = grows ? a.rowtab + (BIG ? 0 : (int64_t)bt * (M - 1) * SV) : reinterpret_cast<double *>(smem + soff);
-    double *cv = grows ? reinterpret_cast<double *>(smem + soff) : rv + (size_t)(M - 1) * SV;
+    T *rv = grows ? static_cast<T *>(a.rowtab) + (BIG ? 0 : (int64_t)bt * (M - 1) * SV)
+                  : reinterpret_cast<T *>(smem + soff);
+    T *cv = grows ? reinterpret_cast<T *>(smem + soff) : rv + (size_t)(M - 1) * SV;
     const int I0 = geo.M[0] - 1, I1 = geo.M[1] - 1, I2 = d == 3 ? geo.M[2] - 1 : 1;
     const int kB = bt + 1;
     const int64_t ss0 = shell_size(geo, 0), ss1 = shell_size(geo, 1);
@@ -1069,21 +1080,21 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
     const double c4yz = d == 3 ? geo.c4[1][2] : 0.0, c4zy = d == 3 ? geo.c4[2][1] : 0.0;
     if (!grows)
-        for (int i = threadIdx.x; i < I0; i += NTT) final_row(a, i, kB, lamB, qB, rv + i * SV);
+        for (int i = threadIdx.x; i < I0; i += NTT) final_row<T>(a, i, kB, lamB, qB, rv + i * SV);
     for (int i = threadIdx.x; i < nc; i += NTT) {
-        double *r = cv + i * SV;
+        T *r = cv + i * SV;
         const int j = c0 + i; // k1 - 1
         const double ly = a.tab[1].lam[j];
-        r[0] = ly;
-        r[1] = a.tab[1].q[j];
-        r[2] = a.tab[1].s[j];
-        r[3] = a.tab[1].s[I1 + j];
-        r[10] = ly + c2yz * ly * lamB;
-        r[11] = ly * lamB * (c4yz * ly + c4zy * lamB);
+        r[0] = (T)ly;
+        r[1] = (T)a.tab[1].q[j];
+        r[2] = (T)a.tab[1].s[j];
+        r[3] = (T)a.tab[1].s[I1 + j];
+        r[10] = (T)(ly + c2yz * ly * lamB);
+        r[11] = (T)(ly * lamB * (c4yz * ly + c4zy * lamB));
         // family 0: other index (k1, k2) in 3D, (k1) in 2D
         const int64_t o = d == 3 ? (int64_t)j * I2 + (kB - 1) : j;
         for (int par = 0; par < 2; ++par)
-            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = a.sh.P[0][(par * 3 + t) * ss0 + o];
+            for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = (T)a.sh.P[0][(par * 3 + t) * ss0 + o];
     }
     __syncthreads();
     fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false);
@@ -1096,7 +1107,8 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     //   z(k) = (c_b, -c_a), z(N-k) = (-c_b, c_a), rows 0 and M zero.
     // Each thread owns both rows of its pair, so no barrier is needed between
     // the reads and the writes.
-    const double c2xy = geo.c2[0][1], c4xy = geo.c4[0][1], c4yx = geo.c4[1][0];
+    const T c2xy = (T)geo.c2[0][1], c4xy = (T)geo.c4[0][1], c4yx = (T)geo.c4[1][0];
+    const T lamBt = (T)lamB, s1Bt = (T)s1B, s2Bt = (T)s2B, preft = (T)geo.pref;
     const int smask = (1 << lgs) - 1;
     const int npair = (M + 1) << lgs;
     for (int e = threadIdx.x; e < npair; e += NTT) {
@@ -1106,43 +1118,43 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
             continue;
         }
         const cx<T> z1 = lds_c(buf, rs, k, sq), z2 = lds_c(buf, rs, N - k, sq);
-        double cab[2];
-        const double beta2[2] = {0.5 * ((double)z2.y - (double)z1.y), 0.5 * ((double)z1.x - (double)z2.x)};
-        const double *r = rv + (k - 1) * SV;
+        T cab[2];
+        const T beta2[2] = {(T)0.5 * (z2.y - z1.y), (T)0.5 * (z1.x - z2.x)};
+        const T *r = rv + (k - 1) * SV;
         const int kx = k;
 #pragma unroll
         for (int h2 = 0; h2 < 2; ++h2) {
             const int c = 2 * sq + h2;
-            double cval = 0.0;
+            T cval = (T)0;
             if (c < nc) {
                 const int ky = 1 + c0 + c;
-                const double *q1 = cv + c * SV;
-                const double *Pr = r + 4 + ((ky & 1) ? 3 : 0);  // family 1 at (kx, kz)
-                const double *Pc = q1 + 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz)
-                const double lx = r[0], ly = q1[0], lxy = lx * ly;
-                const double Lm = r[10] + q1[10] + lamB + c2xy * lxy;
-                double gt = r[2] * Pc[0] + q1[2] * Pr[0];
-                double dh = 0.0;
+                const T *q1 = cv + c * SV;
+                const T *Pr = r + 4 + ((ky & 1) ? 3 : 0);  // family 1 at (kx, kz)
+                const T *Pc = q1 + 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz)
+                const T lx = r[0], ly = q1[0], lxy = lx * ly;
+                const T Lm = r[10] + q1[10] + lamBt + c2xy * lxy;
+                T gt = r[2] * Pc[0] + q1[2] * Pr[0];
+                T dh = (T)0;
                 if (six) dh = r[2] * Pc[1] + r[3] * Pc[2] + q1[2] * Pr[1] + q1[3] * Pr[2];
                 if (d == 3) {
                     const double *Pe = Pz + (int64_t)(kx - 1) * I1 + (ky - 1);
-                    gt += s1B * Pe[0];
-                    if (six) dh += s1B * Pe[ss2] + s2B * Pe[2 * ss2];
+                    gt += s1Bt * (T)Pe[0];
+                    if (six) dh += s1Bt * (T)Pe[ss2] + s2Bt * (T)Pe[2 * ss2];
                 }
-                const double iL = recip(Lm);
-                double harm;
+                const T iL = recip(Lm);
+                T harm;
                 if (six) {
-                    const double Rm = r[11] + q1[11] + lxy * (c4xy * lx + c4yx * ly);
-                    harm = (gt * (1.0 + Rm * iL) + dh) * iL;
+                    const T Rm = r[11] + q1[11] + lxy * (c4xy * lx + c4yx * ly);
+                    harm = (gt * ((T)1 + Rm * iL) + dh) * iL;
                 } else {
                     harm = gt * iL;
                 }
-                cval = geo.pref * (harm - beta2[h2] * recip(r[1] + q1[1]));
+                cval = preft * (harm - beta2[h2] * recip(r[1] + q1[1]));
             }
             cab[h2] = cval;
         }
-        lds_cs(buf, rs, k, sq, cx<T>{(T)cab[1], (T)(-cab[0])});
-        lds_cs(buf, rs, N - k, sq, cx<T>{(T)(-cab[1]), (T)cab[0]});
+        lds_cs(buf, rs, k, sq, cx<T>{cab[1], -cab[0]});
+        lds_cs(buf, rs, N - k, sq, cx<T>{-cab[1], cab[0]});
     }
     __syncthreads();
     fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, true);
@@ -1160,9 +1172,9 @@ template <typename T, int MAXE, bool P2>
 static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
 {
     // tile + staged column (W) invariants and, unless the row table is in
-    // global memory, the row (M0-1) invariants, 12 doubles each
+    // global memory, the row (M0-1) invariants, 12 values of type T each
     const size_t rows = a.rowtab ? 0 : (size_t)(a.fd.M - 1);
-    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (rows + a.W) * 12 * sizeof(double);
+    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (rows + a.W) * 12 * sizeof(T);
     if (a.W == 8)
         launch_final_w<T, MAXE, P2, 8>(a, nblk, lds, st);
     else if (a.W == 16)
@@ -1179,7 +1191,7 @@ static void launch_final_t(const FinalArgs &a, int nblk, int work, hipStream_t s
     const bool p2 = is_pow2(a.fd.N);
     if (big_fft(a.fd.N)) {
         // tile + staged columns only (the rows come from the global table)
-        const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)a.W * 12 * sizeof(double);
+        const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)a.W * 12 * sizeof(T);
         if (work <= 4 * NTB) {
             if (p2)
                 launch_final_w<T, 4, true, 2, NTB>(a, nblk, lds, st);
@@ -1231,7 +1243,10 @@ __global__ void k_final_rows(FinalArgs a)
             lamB = a.tab[2].lam[kB - 1];
             qB = a.tab[2].q[kB - 1];
         }
-        final_row(a, i, kB, lamB, qB, a.rowtab + e * 12);
+        if (a.mixed)
+            final_row<float>(a, i, kB, lamB, qB, static_cast<float *>(a.rowtab) + e * 12);
+        else
+            final_row<double>(a, i, kB, lamB, qB, static_cast<double *>(a.rowtab) + e * 12);
     }
 }
 
