@@ -153,7 +153,7 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool
 // (nseq * N <= MAXE * NT).
 template <typename T, int R, int MAXE, int NT>
 __device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDesc &fd, int st,
-                                           const cx<T> *tw, bool inv)
+                                           const cx<T> *tw, bool inv, int tid)
 {
     constexpr int BPT = (MAXE + R - 1) / R;
     const int N = fd.N, Ns = fd.ns[st];
@@ -165,7 +165,7 @@ __device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDes
     int base[BPT];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-        const int b = threadIdx.x + i * NT;
+        const int b = tid + i * NT;
         if (b < nbf) {
             const int s = b & smask, j = b >> lgs;
             const int jm = fmod_ns(j, Ns, fd.nsmag[st], fd.nslg[st]);
@@ -183,7 +183,7 @@ __device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDes
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-        const int b = threadIdx.x + i * NT;
+        const int b = tid + i * NT;
         if (b < nbf) {
             const int s = b & smask;
 #pragma unroll
@@ -196,7 +196,7 @@ __device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDes
 // Stockham stage of arbitrary radix R computed output by output.
 template <typename T, int MAXE, int NT>
 __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftDesc &fd, int st,
-                                             const cx<T> *tw, bool inv)
+                                             const cx<T> *tw, bool inv, int tid)
 {
     const int N = fd.N, Ns = fd.ns[st], R = fd.rad[st];
     const int NR = N / R;
@@ -206,7 +206,7 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftD
     cx<T> out[MAXE];
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
-        const int e = threadIdx.x + i * NT;
+        const int e = tid + i * NT;
         if (e < tot) {
             const int s = e & smask, o = e >> lgs;
             const int jm = fmod_ns(o, Ns, fd.nsmag[st], fd.nslg[st]);
@@ -226,7 +226,7 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftD
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
-        const int e = threadIdx.x + i * NT;
+        const int e = tid + i * NT;
         if (e < tot) lds_cs(buf, rs, e >> lgs, e & smask, out[i]);
     }
     __syncthreads();
@@ -237,7 +237,7 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftD
 // RS and 2^LGS sequences.  Same data movement as stage_bfly; the index and
 // twiddle arithmetic folds to shifts and constants.
 template <typename T, int R, int NT, int N, int NS, int RS, int LGS>
-__device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv)
+__device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv, int tid)
 {
     constexpr int NR = N / R, NBF = NR << LGS, TSTEP = N / (NS * R), SMASK = (1 << LGS) - 1;
     constexpr int BPT = (NBF + NT - 1) / NT;
@@ -245,7 +245,7 @@ __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv)
     int base[BPT];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-        const int b = threadIdx.x + i * NT;
+        const int b = tid + i * NT;
         if (NBF % NT == 0 || b < NBF) {
             const int sq = b & SMASK, j = b >> LGS;
             const int jm = j & (NS - 1);
@@ -263,7 +263,7 @@ __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv)
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-        const int b = threadIdx.x + i * NT;
+        const int b = tid + i * NT;
         if (NBF % NT == 0 || b < NBF) {
             const int sq = b & SMASK;
 #pragma unroll
@@ -275,68 +275,74 @@ __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv)
 
 // Compile-time transforms for the common power-of-two lengths at the
 // default tile widths (radix-8 stages first, as factor_fft orders them).
+// tid: the thread index (a caller that runs several transforms in a loop
+// may pass one the compiler cannot see through, so that the per-thread index
+// and twiddle values are recomputed for each transform instead of being held
+// in registers across the loop).
 template <typename T, int NT, int N, int RS, int LGS>
-__device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, bool inv)
+__device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, bool inv, int tid)
 {
     if constexpr (N == 256) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv);
-        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv);
-        stage_ct<T, 4, NT, N, 64, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 4, NT, N, 64, RS, LGS>(buf, tw, inv, tid);
     } else if constexpr (N == 512) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv);
-        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv);
-        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv, tid);
     } else if constexpr (N == 1024) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv);
-        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv);
-        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv);
-        stage_ct<T, 2, NT, N, 512, RS, LGS>(buf, tw, inv);
+        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 2, NT, N, 512, RS, LGS>(buf, tw, inv, tid);
     }
 }
 
 // Full length-N complex FFT of 2^lgs sequences held in LDS (in place).
 // P2: N is a power of two (only radix-2/4/8 stages are compiled in).
-// CT = false keeps the generic stages (kernels that run several transforms
-// per block, where hoisted constant twiddles would cost occupancy).
+// CT = false keeps the generic stages only.  tid: see fft_ct (-1: threadIdx.x).
 template <typename T, int MAXE, int NT, bool P2 = false, bool CT = true>
-__device__ void fft_tile(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, bool inv)
+__device__ __forceinline__ void fft_tile(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, bool inv,
+                                         int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     if constexpr (P2 && CT && NT == 256) {
         // (N, tile width) pairs of the default tile budget: N * W / 2 = MAXE * NT
         if constexpr (MAXE == 8) {
-            if (fd.N == 512 && rs == 9) return fft_ct<T, NT, 512, 9, 2>(buf, tw, inv);
-            if (fd.N == 256 && rs == 17) return fft_ct<T, NT, 256, 17, 3>(buf, tw, inv);
-            if (fd.N == 1024 && rs == 5) return fft_ct<T, NT, 1024, 5, 1>(buf, tw, inv);
+            if (fd.N == 512 && rs == 9) return fft_ct<T, NT, 512, 9, 2>(buf, tw, inv, tid);
+            if (fd.N == 256 && rs == 17) return fft_ct<T, NT, 256, 17, 3>(buf, tw, inv, tid);
+            if (fd.N == 1024 && rs == 5) return fft_ct<T, NT, 1024, 5, 1>(buf, tw, inv, tid);
         }
     }
     if constexpr (P2) {
         for (int st = 0; st < fd.nst; ++st) {
             const int R = fd.rad[st];
             if (R == 8)
-                stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv);
+                stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid);
             else if (R == 4)
-                stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv);
+                stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid);
             else
-                stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv);
+                stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid);
         }
         return;
     }
     for (int st = 0; st < fd.nst; ++st) {
         switch (fd.rad[st]) {
-        case 2: stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
-        case 3: stage_bfly<T, 3, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
-        case 4: stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
-        case 5: stage_bfly<T, 5, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
-        case 8: stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
-        default: stage_direct<T, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv); break;
+        case 2: stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
+        case 3: stage_bfly<T, 3, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
+        case 4: stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
+        case 5: stage_bfly<T, 5, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
+        case 8: stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
+        default: stage_direct<T, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
         }
     }
 }
 
 // After a forward zero-padded FFT: write C and S in slot layout (in place).
 template <typename T, int MAXE, int NT>
-__device__ void post_cs(T *buf, int rs, int lgs, int M)
+__device__ __forceinline__ void post_cs(T *buf, int rs, int lgs, int M, int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     constexpr int PPT = MAXE / 2 + 1;
     const int N = 2 * M;
     const int tot = (M + 1) << lgs;
@@ -344,7 +350,7 @@ __device__ void post_cs(T *buf, int rs, int lgs, int M)
     T ca[PPT], cb[PPT], sa[PPT], sb[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int e = threadIdx.x + i * NT;
+        const int e = tid + i * NT;
         if (e < tot) {
             const int s = e & smask, k = e >> lgs;
             const cx<T> z1 = lds_c(buf, rs, k, s);
@@ -358,7 +364,7 @@ __device__ void post_cs(T *buf, int rs, int lgs, int M)
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int e = threadIdx.x + i * NT;
+        const int e = tid + i * NT;
         if (e < tot) {
             const int s = e & smask, k = e >> lgs;
             buf[k * rs + 2 * s] = ca[i];
@@ -426,11 +432,12 @@ __device__ void pre_even(T *buf, int rs, int lgW, int M)
 }
 
 template <typename T, int NT>
-__device__ void zero_rows(T *buf, int rs, int lgW, int r0, int r1)
+__device__ __forceinline__ void zero_rows(T *buf, int rs, int lgW, int r0, int r1, int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     const int tot = (r1 - r0) << lgW;
     const int cm = (1 << lgW) - 1;
-    for (int e = threadIdx.x; e < tot; e += NT) buf[(r0 + (e >> lgW)) * rs + (e & cm)] = (T)0;
+    for (int e = tid; e < tot; e += NT) buf[(r0 + (e >> lgW)) * rs + (e & cm)] = (T)0;
 }
 
 template <typename T, int NT>
@@ -469,6 +476,51 @@ __device__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, in
             if (c < ncols) v = (T)src[r * rsd + c * csd];
             buf[(row0 + r) * rs + c] = v;
         }
+    }
+}
+
+// Global -> LDS for a tile of two column sets: tile column j < W/2 holds
+// source column cA + j (if j < nA), tile column W/2 + j holds source column
+// cB - j (if j < nB); every other column is zero.  Element (r, col) is
+// src[r*rsd + col*csd].  Rows-contiguous sources are read by whole waves per
+// column (several waves per column when the tile has fewer columns than the
+// block has waves).
+template <typename T, typename TI, int NT>
+__device__ void tile_load_pair(T *buf, int rs, int row0, const TI *src, int nrows, int64_t rsd, int64_t csd,
+                               int lgW, int cA, int nA, int cB, int nB, int tid = -1)
+{
+    if (tid < 0) tid = tid;
+    const int W = 1 << lgW, Wh = W >> 1;
+    auto src_col = [&](int c) -> int {
+        const int j = c < Wh ? c : c - Wh;
+        return c < Wh ? (j < nA ? cA + j : -1) : (j < nB ? cB - j : -1);
+    };
+    if (rsd == 1 && csd != 1) {
+        constexpr int NW = NT / 64;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int cstep = NW < W ? NW : W;
+        const int rstep = (NW / cstep) * 64;
+        const int rbeg = (wave / cstep) * 64 + lane;
+        for (int c = wave % cstep; c < W; c += cstep) {
+            const int sc = src_col(c);
+            T *dst = buf + row0 * rs + c;
+            if (sc >= 0) {
+                const TI *col = src + sc * csd;
+                for (int r = rbeg; r < nrows; r += rstep) dst[r * rs] = (T)col[r];
+            } else {
+                for (int r = rbeg; r < nrows; r += rstep) dst[r * rs] = (T)0;
+            }
+        }
+        return;
+    }
+    const int cm = W - 1;
+    const int tot = nrows << lgW;
+    for (int e = tid; e < tot; e += NT) {
+        const int c = e & cm, r = e >> lgW;
+        const int sc = src_col(c);
+        T v = (T)0;
+        if (sc >= 0) v = (T)src[r * rsd + sc * csd];
+        buf[(row0 + r) * rs + c] = v;
     }
 }
 

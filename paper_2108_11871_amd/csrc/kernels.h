@@ -46,7 +46,7 @@ struct CcArgs {
     int ncols;         // interior length of the contracted axis
     int nbatch;        // slots of the remaining in-face axis (1 if none)
     int Mo;            // M of that axis (slot -> wavenumber), 0 if none
-    int cols_per_chunk;
+    int cols_per_chunk; // first-half columns per chunk (a tile pairs column c with ncols-1-c)
     const void *K;     // K[d][k_o][k_p], k_p contiguous: FP32 when the slot input is FP32, else FP64
     int64_t Kd, Ko;
     double *part;      // [2][nchunk][nbatch][2 M_p]

@@ -3,7 +3,7 @@
 // Stage map (paper sections):
 //   k_pass    pencil transforms: DST-I / zero-padded cos+sin / even (DCT-I) /
 //             hermitian synthesis along one axis (Sections 3, 4, 5)
-//   k_cc      boundary values as sums over slices of 2D (3D problems) or 1D
+//   k_cc      (conv.hip) boundary values as sums over slices of 2D (3D problems) or 1D
 //             (2D problems) discrete convolutions, accumulated in Fourier
 //             space with the kernel spectra (Section 4, eqs. Trap2D,
 //             Trap2Dconvolution, convolution)
@@ -21,11 +21,10 @@
 #include <type_traits>
 #include <mutex>
 
+#include "common.h"
 #include "kernels.h"
 
 namespace ips {
-
-constexpr int NT = 256;
 
 // Allow more than 64 KiB of dynamic LDS where a tile needs it (gfx950 has
 // 160 KiB).  Each kernel's limit is raised once per process, to the largest
@@ -43,37 +42,6 @@ void set_lds(const void *fn, size_t bytes)
         done[fn] = bytes;
     else
         (void)hipGetLastError();
-}
-
-// Transforms longer than kLdsTwMaxN run in blocks of NTB threads whose tile
-// holds one complex sequence without row padding (W = 2) and whose twiddles
-// are read from the global table (the LDS holds only the tile).
-constexpr int NTB = 1024;
-constexpr int kLdsTwMaxN = 2048;
-
-static bool big_fft(int N) { return N > kLdsTwMaxN; }
-
-template <typename T>
-static size_t tile_lds(int N, int W)
-{
-    if (big_fft(N)) return (size_t)N * W * sizeof(T);
-    return (size_t)N * sizeof(cx<T>) + (size_t)N * (W + 1) * sizeof(T);
-}
-
-// Twiddle table of the transform type: LDS copy (short transforms) or the
-// plan's global table (long ones).
-template <typename T, bool BIG>
-__device__ __forceinline__ const cx<T> *tw_table(unsigned char *smem, const cx<double> *twd,
-                                                const cx<float> *twf)
-{
-    if constexpr (BIG) {
-        if constexpr (sizeof(T) == sizeof(float))
-            return reinterpret_cast<const cx<T> *>(twf);
-        else
-            return reinterpret_cast<const cx<T> *>(twd);
-    } else {
-        return reinterpret_cast<const cx<T> *>(smem);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -133,7 +101,6 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a)
         tile_store<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
 }
 
-static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT = NT>
 static void launch_pass_k(const PassArgs &a, int64_t nblk, size_t lds, hipStream_t st)
@@ -193,181 +160,6 @@ hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t
     if (in_f32 && out_f32) return launch_pass_t<float, float, float>(a, st);
     if (!in_f32 && out_f32) return launch_pass_t<float, double, float>(a, st);
     return launch_pass_t<float, float, double>(a, st);
-}
-
-// ---------------------------------------------------------------------------
-// Boundary convolution, contraction over the tile columns (3D and 2D)
-// ---------------------------------------------------------------------------
-template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT>
-__global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
-{
-    constexpr bool BIG = NTT != NT;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
-    const int lgW = 31 - __clz(W), lgs = lgW - 1;
-    const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
-    T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
-    // Logical order: for each wavenumber k_b of the other axis, its cos slot
-    // and its sin slot are neighbours, so the blocks reading the same kernel
-    // spectra K[.][k_b][.] run together on one XCD (shared L2).
-    const int lb = xcd_remap(blockIdx.x, nchunk * a.nbatch);
-    const int ch = lb % nchunk, q = lb / nchunk;
-    int bt = q;
-    if (a.Mo > 0) {
-        // q = 0 -> slot 0; q = 2kb-1 -> slot kb; q = 2kb -> slot Mo+kb (kb < Mo); q = 2Mo-1 -> slot Mo
-        if (q == 0)
-            bt = 0;
-        else if (q == 2 * a.Mo - 1)
-            bt = a.Mo;
-        else
-            bt = (q & 1) ? (q + 1) / 2 : a.Mo + q / 2;
-    }
-    const int kb = a.Mo > 0 ? (bt <= a.Mo ? bt : bt - a.Mo) : 0;
-    const TI *in = static_cast<const TI *>(a.in);
-    T *Bout = static_cast<T *>(a.Bout);
-    // Wavenumbers per thread: kp = threadIdx.x + i NTT, i < KPT (KPT NTT >= M + 1).
-    // A thread owns both slot rows of its wavenumbers, C at row kp and S at
-    // row M + kp, which share the kernel spectrum value: one load of each
-    // face's K feeds four products.
-    constexpr int KPT = RPT / 2 + 1;
-    double aC0[KPT], aS0[KPT], aC1[KPT], aS1[KPT];
-#pragma unroll
-    for (int i = 0; i < KPT; ++i) aC0[i] = aS0[i] = aC1[i] = aS1[i] = 0.0;
-    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
-    const int cbeg = ch * a.cols_per_chunk;
-    const int cend = min(a.ncols, cbeg + a.cols_per_chunk);
-    for (int c0 = cbeg; c0 < cend; c0 += W) {
-        const int nc = min(W, cend - c0);
-        zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
-        zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
-        tile_load<T, TI, NTT>(buf, rs, 1, in + bt * a.ibs + c0 * a.ics, a.nrows_in, nc, a.irs,
-                             a.ics, lgW);
-        __syncthreads();
-        fft_tile<T, MAXE, NTT, P2, false>(buf, rs, lgs, a.fd, tw, false);
-        post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
-        if (WB && (a.Mo == 0 || bt > a.Mo)) {
-            const int64_t bb = a.Mo == 0 ? 0 : (int64_t)(bt - a.Mo - 1) * a.Bbs;
-            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-            for (int c = wave; c < nc; c += NTT / 64) {
-                const int64_t cb = (int64_t)(c0 + c) * a.Bcs + bb;
-                for (int r = lane; r < M - 1; r += 64) {
-                    const T v = buf[(M + 1 + r) * rs + c];
-                    if (a.Bf32)
-                        static_cast<float *>(a.Bout)[cb + (int64_t)r * a.Brs] = (float)v;
-                    else
-                        Bout[cb + (int64_t)r * a.Brs] = v;
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < KPT; ++i) {
-            const int kp = threadIdx.x + i * NTT;
-            if (kp <= M) {
-                const bool hs = kp >= 1 && kp < M; // has a sine slot
-                const int srow = hs ? M + kp : kp;
-                // kernel spectra in the slot type: FP32 when the slots are FP32
-                using TK = typename std::conditional<std::is_same<TI, float>::value, float, double>::type;
-                const TK *Kr = static_cast<const TK *>(a.K) + (int64_t)kb * a.Ko + kp;
-                const TK *K0 = Kr + (int64_t)c0 * a.Kd;
-                const TK *K1 = Kr + (int64_t)(a.ncols - 1 - c0) * a.Kd;
-                for (int c = 0; c < nc; ++c) {
-                    const double k0 = (double)K0[(int64_t)c * a.Kd], k1 = (double)K1[-(int64_t)c * a.Kd];
-                    const double vc = (double)buf[kp * rs + c];
-                    const double vs = hs ? (double)buf[srow * rs + c] : 0.0;
-                    aC0[i] += k0 * vc;
-                    aC1[i] += k1 * vc;
-                    aS0[i] += k0 * vs;
-                    aS1[i] += k1 * vs;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // partials [face][chunk][batch][slot]
-    double *p0 = a.part + ((int64_t)ch * a.nbatch + bt) * N;
-    double *p1 = p0 + (int64_t)nchunk * a.nbatch * N;
-#pragma unroll
-    for (int i = 0; i < KPT; ++i) {
-        const int kp = threadIdx.x + i * NTT;
-        if (kp <= M) {
-            p0[kp] = aC0[i];
-            p1[kp] = aC1[i];
-            if (kp >= 1 && kp < M) {
-                p0[M + kp] = aS0[i];
-                p1[M + kp] = aS1[i];
-            }
-        }
-    }
-}
-
-template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT = NT>
-static void launch_cc_k(const CcArgs &a, int nchunk, hipStream_t st)
-{
-    const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    set_lds((const void *)&k_cc<T, TI, MAXE, WB, P2, RPT, NTT>, lds);
-    hipLaunchKernelGGL((k_cc<T, TI, MAXE, WB, P2, RPT, NTT>), dim3(nchunk * a.nbatch), dim3(NTT), lds,
-                       st, a, nchunk);
-}
-
-template <typename T, typename TI, int MAXE, bool WB>
-static void launch_cc_m(const CcArgs &a, int nchunk, hipStream_t st)
-{
-    const bool p2 = is_pow2(a.fd.N);
-    if (a.fd.N <= 2 * NT) {
-        if (p2)
-            launch_cc_k<T, TI, MAXE, WB, true, 2>(a, nchunk, st);
-        else
-            launch_cc_k<T, TI, MAXE, WB, false, 2>(a, nchunk, st);
-    } else {
-        if (p2)
-            launch_cc_k<T, TI, MAXE, WB, true, 8>(a, nchunk, st);
-        else
-            launch_cc_k<T, TI, MAXE, WB, false, 8>(a, nchunk, st);
-    }
-}
-
-template <typename T, typename TI, bool WB>
-static hipError_t launch_cc_t(const CcArgs &a, int nchunk, hipStream_t st)
-{
-    const int work = (a.W / 2) * a.fd.N;
-    if (big_fft(a.fd.N)) {
-        // one complex sequence per tile; rows per thread = N / NTB <= 8
-        const bool p2 = is_pow2(a.fd.N);
-        if (a.W != 2 || a.fd.N > 8 * NTB) return hipErrorInvalidValue;
-        if (a.fd.N <= 4 * NTB) {
-            if (p2)
-                launch_cc_k<T, TI, 4, WB, true, 4, NTB>(a, nchunk, st);
-            else
-                launch_cc_k<T, TI, 4, WB, false, 4, NTB>(a, nchunk, st);
-        } else {
-            if (p2)
-                launch_cc_k<T, TI, 8, WB, true, 8, NTB>(a, nchunk, st);
-            else
-                launch_cc_k<T, TI, 8, WB, false, 8, NTB>(a, nchunk, st);
-        }
-        return hipGetLastError();
-    }
-    if (work <= 8 * NT)
-        launch_cc_m<T, TI, 8, WB>(a, nchunk, st);
-    else
-        launch_cc_m<T, TI, 16, WB>(a, nchunk, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st)
-{
-    const int work = (a.W / 2) * a.fd.N;
-    if (!big_fft(a.fd.N) && (work > 16 * NT || a.fd.N > 8 * NT)) return hipErrorInvalidValue;
-    const bool wb = a.Bout != nullptr;
-    if (!f32) {
-        if (in_f32) return hipErrorInvalidValue;
-        return wb ? launch_cc_t<double, double, true>(a, nchunk, st)
-                  : launch_cc_t<double, double, false>(a, nchunk, st);
-    }
-    if (in_f32) return wb ? launch_cc_t<float, float, true>(a, nchunk, st)
-                          : launch_cc_t<float, float, false>(a, nchunk, st);
-    return wb ? launch_cc_t<float, double, true>(a, nchunk, st)
-              : launch_cc_t<float, double, false>(a, nchunk, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -430,14 +430,17 @@ int plan_build(ips_plan p, hipStream_t st)
             pen = 1 - fam;
             nbatch = 1;
         }
+        // a tile holds W/2 columns of the first half of the axis and their
+        // mirrors: the chunks split the (I + 1)/2 first-half columns
         const int W = tile_width(N[pen], p->work, I[fam]);
-        const int ncb = (I[fam] + W - 1) / W;
+        const int hc = (I[fam] + 1) / 2, Wh = W / 2;
+        const int ncb = (hc + Wh - 1) / Wh;
         // about 2048 blocks of 256 threads; 256 blocks of 1024 for long transforms
         const int target = N[pen] > kLdsMaxN ? 256 : 2048;
         int nch = std::max(1, std::min(ncb, (target + nbatch - 1) / nbatch));
         const int per = (ncb + nch - 1) / nch;
-        p->chunk[fam] = per * W;
-        p->nch[fam] = (I[fam] + per * W - 1) / (per * W);
+        p->chunk[fam] = per * Wh;
+        p->nch[fam] = (hc + per * Wh - 1) / (per * Wh);
     }
     {
         size_t tp = 0, tf = 0, ts = 0;
