@@ -15,6 +15,9 @@ inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // Raise a kernel's dynamic LDS limit above 64 KiB when a launch needs it.
 void set_lds(const void *fn, size_t bytes);
 
+// Blocks of a kernel that fit on the device at once (0 if unknown).
+int resident_blocks(const void *fn, int nthreads, size_t lds);
+
 // Transforms longer than kLdsTwMaxN run in blocks of NTB threads whose tile
 // holds one complex sequence without row padding (W = 2) and whose twiddles
 // are read from the global table (the LDS holds only the tile).

@@ -60,18 +60,39 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
     const int cbeg = ch * a.cols_per_chunk;
     const int cend = min(hc, cbeg + a.cols_per_chunk);
     using TK = typename std::conditional<std::is_same<TI, float>::value, float, double>::type;
+    // PF (compile-time width): the next tile is fetched into registers while
+    // the current one is transformed and contracted
+    constexpr bool PF = WHC > 0;
+    constexpr int WCF = PF ? 2 * WHC : 2;
+    const bool rcont = a.irs == 1 && a.ics != 1;
+    auto n_a = [&](int c) { return min(Wh, cend - c); };
+    auto n_b = [&](int c) { return min(n_a(c), max(0, (a.ncols - 2 * c) >> 1)); };
+    TI pf[MAXE];
+    if constexpr (PF)
+        if (cbeg < cend)
+            fetch_pair<TI, NTT, WCF, MAXE>(pf, in, a.nrows_in, a.irs, a.ics, cbeg, n_a(cbeg), a.ncols - 1 - cbeg,
+                                          n_b(cbeg), threadIdx.x);
     for (int c0 = cbeg; c0 < cend; c0 += Wh) {
-        const int nA = min(Wh, cend - c0);
-        const int m0 = a.ncols - 1 - c0;                       // mirror of c0
-        const int nB = min(nA, max(0, (a.ncols - 2 * c0) >> 1)); // mirrors distinct from their column
+        const int nA = n_a(c0);
+        const int m0 = a.ncols - 1 - c0; // mirror of c0
+        const int nB = n_b(c0);          // mirrors distinct from their column
         // the thread index, opaque to the compiler: per-thread index and
         // twiddle values are recomputed for each tile rather than held in
         // registers across the loop
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
+        tid &= NTT - 1; // the range (known bits) of the thread index
         zero_rows<T, NTT>(buf, rs, lgW, 0, 1, tid);
         zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N, tid);
-        tile_load_pair<T, TI, NTT>(buf, rs, 1, in, a.nrows_in, a.irs, a.ics, lgW, c0, nA, m0, nB, tid);
+        if constexpr (PF) {
+            put_pair<T, TI, NTT, WCF, MAXE>(buf, rs, 1, pf, a.nrows_in, rcont, tid);
+            const int c1 = c0 + Wh;
+            if (c1 < cend)
+                fetch_pair<TI, NTT, WCF, MAXE>(pf, in, a.nrows_in, a.irs, a.ics, c1, n_a(c1), a.ncols - 1 - c1,
+                                              n_b(c1), tid);
+        } else {
+            tile_load_pair<T, TI, NTT>(buf, rs, 1, in, a.nrows_in, a.irs, a.ics, lgW, c0, nA, m0, nB, tid);
+        }
         __syncthreads();
         fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
         post_cs<T, MAXE, NTT>(buf, rs, lgs, M, tid);
@@ -161,8 +182,14 @@ static void launch_cc_k(const CcArgs &a, int nchunk, hipStream_t st)
                        st, a, nchunk);
 }
 
-// Full tiles of the default widths (W = 16, 8, 4 for 2M = 256, 512, 1024)
-// get a fully unrolled contraction.
+// The default widths (W = 16, 8, 4 for 2M = 256, 512, 1024) get a fully
+// unrolled contraction and the register prefetch of the next tile.
+template <int WHC, int MAXE, int NTT = NT>
+static bool prefetch_fits(const CcArgs &a)
+{
+    return a.W == 2 * WHC && PairMap<NTT, 2 * WHC, MAXE>::covers(a.nrows_in, a.irs == 1 && a.ics != 1);
+}
+
 template <typename T, typename TI, int MAXE, bool WB>
 static void launch_cc_m(const CcArgs &a, int nchunk, hipStream_t st)
 {
@@ -170,16 +197,16 @@ static void launch_cc_m(const CcArgs &a, int nchunk, hipStream_t st)
     if (a.fd.N <= 2 * NT) {
         if (!p2)
             launch_cc_k<T, TI, MAXE, WB, false, 2>(a, nchunk, st);
-        else if (a.W == 16)
+        else if (prefetch_fits<8, MAXE>(a))
             launch_cc_k<T, TI, MAXE, WB, true, 2, NT, 8>(a, nchunk, st);
-        else if (a.W == 8)
+        else if (prefetch_fits<4, MAXE>(a))
             launch_cc_k<T, TI, MAXE, WB, true, 2, NT, 4>(a, nchunk, st);
         else
             launch_cc_k<T, TI, MAXE, WB, true, 2>(a, nchunk, st);
     } else if (a.fd.N <= 4 * NT) {
         if (!p2)
             launch_cc_k<T, TI, MAXE, WB, false, 4>(a, nchunk, st);
-        else if (a.W == 4)
+        else if (prefetch_fits<2, MAXE>(a))
             launch_cc_k<T, TI, MAXE, WB, true, 4, NT, 2>(a, nchunk, st);
         else
             launch_cc_k<T, TI, MAXE, WB, true, 4>(a, nchunk, st);

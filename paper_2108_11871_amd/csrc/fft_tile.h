@@ -380,8 +380,9 @@ __device__ __forceinline__ void post_cs(T *buf, int rs, int lgs, int M, int tid 
 
 // Before an inverse FFT: slots (C, S) -> hermitian-packed complex sequences.
 template <typename T, int MAXE, int NT>
-__device__ void pre_herm(T *buf, int rs, int lgs, int M, bool c_zero)
+__device__ __forceinline__ void pre_herm(T *buf, int rs, int lgs, int M, bool c_zero, int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     constexpr int PPT = MAXE / 2 + 1;
     const int N = 2 * M;
     const int tot = (M + 1) << lgs;
@@ -389,7 +390,7 @@ __device__ void pre_herm(T *buf, int rs, int lgs, int M, bool c_zero)
     cx<T> z1[PPT], z2[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int e = threadIdx.x + i * NT;
+        const int e = tid + i * NT;
         if (e < tot) {
             const int s = e & smask, k = e >> lgs;
             T ca = 0, cb = 0, sa = 0, sb = 0;
@@ -408,7 +409,7 @@ __device__ void pre_herm(T *buf, int rs, int lgs, int M, bool c_zero)
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int e = threadIdx.x + i * NT;
+        const int e = tid + i * NT;
         if (e < tot) {
             const int s = e & smask, k = e >> lgs;
             lds_cs(buf, rs, k, s, z1[i]);
@@ -420,11 +421,12 @@ __device__ void pre_herm(T *buf, int rs, int lgs, int M, bool c_zero)
 
 // Even extension: rows 1..M-1 copied to rows N-1..M+1.
 template <typename T, int NT>
-__device__ void pre_even(T *buf, int rs, int lgW, int M)
+__device__ __forceinline__ void pre_even(T *buf, int rs, int lgW, int M, int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     const int N = 2 * M;
     const int tot = (M - 1) << lgW;
-    for (int e = threadIdx.x; e < tot; e += NT) {
+    for (int e = tid; e < tot; e += NT) {
         const int c = e & ((1 << lgW) - 1), j = 1 + (e >> lgW);
         buf[(N - j) * rs + c] = buf[j * rs + c];
     }
@@ -453,12 +455,13 @@ __device__ void load_twiddles(cx<T> *dst, const cx<double> *src, int N)
 // LDS rows row0.. ; columns >= ncols are zero.  Element (r, c) is
 // src[r*rsd + c*csd].  Rows-contiguous sources are read one column per wave.
 template <typename T, typename TI, int NT>
-__device__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, int ncols,
-                          int64_t rsd, int64_t csd, int lgW)
+__device__ __forceinline__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, int ncols,
+                                          int64_t rsd, int64_t csd, int lgW, int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     const int W = 1 << lgW;
     if (rsd == 1 && csd != 1) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int lane = tid & 63, wave = tid >> 6;
         for (int c = wave; c < W; c += NT / 64) {
             if (c < ncols) {
                 const TI *col = src + c * csd;
@@ -470,7 +473,7 @@ __device__ void tile_load(T *buf, int rs, int row0, const TI *src, int nrows, in
     } else {
         const int cm = W - 1;
         const int tot = nrows << lgW;
-        for (int e = threadIdx.x; e < tot; e += NT) {
+        for (int e = tid; e < tot; e += NT) {
             const int c = e & cm, r = e >> lgW;
             T v = (T)0;
             if (c < ncols) v = (T)src[r * rsd + c * csd];
@@ -524,15 +527,106 @@ __device__ void tile_load_pair(T *buf, int rs, int row0, const TI *src, int nrow
     }
 }
 
+// The element mapping of tile_load_pair for a compile-time width WC, split
+// in two halves so that a loop over tiles can fetch the next tile into
+// registers (fetch_pair) while it transforms the current one, and write them
+// to LDS afterwards (put_pair).  Each thread holds EPT elements; covers()
+// tells whether that is enough for nrows rows.
+template <int NT, int WC, int EPT>
+struct PairMap {
+    static constexpr int NW = NT / 64;
+    static constexpr int CSTEP = NW < WC ? NW : WC;  // rows-contiguous: columns per sweep of the waves
+    static constexpr int CPT = WC / CSTEP;           // columns per thread
+    static constexpr int RB = EPT / CPT;             // rows per column per thread
+    static constexpr int RSTEP = (NW / CSTEP) * 64;
+    __host__ __device__ static bool covers(int nrows, bool rows_contiguous)
+    {
+        return rows_contiguous ? RB * RSTEP >= nrows : EPT * NT >= nrows * WC;
+    }
+};
+
+template <int WC>
+__device__ __forceinline__ int pair_src_col(int c, int cA, int nA, int cB, int nB)
+{
+    constexpr int Wh = WC / 2;
+    const int j = c < Wh ? c : c - Wh;
+    return c < Wh ? (j < nA ? cA + j : -1) : (j < nB ? cB - j : -1);
+}
+
+// MIR = false: plain tile, tile column c holds source column cA + c (c < nA).
+template <typename TI, int NT, int WC, int EPT, bool MIR = true>
+__device__ __forceinline__ void fetch_pair(TI (&v)[EPT], const TI *src, int nrows, int64_t rsd, int64_t csd,
+                                           int cA, int nA, int cB, int nB, int tid)
+{
+    auto src_col = [&](int c) {
+        if constexpr (MIR)
+            return pair_src_col<WC>(c, cA, nA, cB, nB);
+        else
+            return c < nA ? cA + c : -1;
+    };
+    using PM = PairMap<NT, WC, EPT>;
+    if (rsd == 1 && csd != 1) {
+        const int lane = tid & 63, wave = tid >> 6;
+        const int rbeg = (wave / PM::CSTEP) * 64 + lane;
+#pragma unroll
+        for (int kc = 0; kc < PM::CPT; ++kc) {
+            const int sc = src_col(wave % PM::CSTEP + kc * PM::CSTEP);
+            const TI *col = src + (int64_t)(sc < 0 ? 0 : sc) * csd;
+#pragma unroll
+            for (int kr = 0; kr < PM::RB; ++kr) {
+                const int r = rbeg + kr * PM::RSTEP;
+                v[kc * PM::RB + kr] = (sc >= 0 && r < nrows) ? col[r] : (TI)0;
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = tid + k * NT;
+        const int c = e & (WC - 1), r = e / WC;
+        const int sc = src_col(c);
+        v[k] = (sc >= 0 && r < nrows) ? src[r * rsd + (int64_t)sc * csd] : (TI)0;
+    }
+}
+
+template <typename T, typename TI, int NT, int WC, int EPT>
+__device__ __forceinline__ void put_pair(T *buf, int rs, int row0, const TI (&v)[EPT], int nrows, bool rows_contiguous,
+                                         int tid)
+{
+    using PM = PairMap<NT, WC, EPT>;
+    if (rows_contiguous) {
+        const int lane = tid & 63, wave = tid >> 6;
+        const int rbeg = (wave / PM::CSTEP) * 64 + lane;
+#pragma unroll
+        for (int kc = 0; kc < PM::CPT; ++kc) {
+            const int c = wave % PM::CSTEP + kc * PM::CSTEP;
+#pragma unroll
+            for (int kr = 0; kr < PM::RB; ++kr) {
+                const int r = rbeg + kr * PM::RSTEP;
+                if (r < nrows) buf[(row0 + r) * rs + c] = (T)v[kc * PM::RB + kr];
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = tid + k * NT;
+        const int c = e & (WC - 1), r = e / WC;
+        if (r < nrows) buf[(row0 + r) * rs + c] = (T)v[k];
+    }
+}
+
 // As tile_load (columns contiguous or generic), but every element is the sum
 // of nsum copies spaced sstride apart (summing partial results on the fly).
 template <typename T, typename TI, int NT>
-__device__ void tile_load_sum(T *buf, int rs, int row0, const TI *src, int nrows, int ncols,
-                              int64_t rsd, int64_t csd, int lgW, int nsum, int64_t sstride)
+__device__ __forceinline__ void tile_load_sum(T *buf, int rs, int row0, const TI *src, int nrows, int ncols,
+                                              int64_t rsd, int64_t csd, int lgW, int nsum, int64_t sstride,
+                                              int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     const int W = 1 << lgW;
     if (rsd == 1 && csd != 1) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int lane = tid & 63, wave = tid >> 6;
         for (int c = wave; c < W; c += NT / 64) {
             for (int r = lane; r < nrows; r += 64) {
                 T v = (T)0;
@@ -547,7 +641,7 @@ __device__ void tile_load_sum(T *buf, int rs, int row0, const TI *src, int nrows
     }
     const int cm = W - 1;
     const int tot = nrows << lgW;
-    for (int e = threadIdx.x; e < tot; e += NT) {
+    for (int e = tid; e < tot; e += NT) {
         const int c = e & cm, r = e >> lgW;
         T v = (T)0;
         if (c < ncols) {
@@ -561,11 +655,12 @@ __device__ void tile_load_sum(T *buf, int rs, int row0, const TI *src, int nrows
 // LDS -> global: LDS rows row0..row0+nrows-1, cols [0, ncols) go to
 // dst[r*rsd + c*csd] scaled by `scale`.
 template <typename T, typename TO, int NT>
-__device__ void tile_store(const T *buf, int rs, int row0, TO *dst, int nrows, int ncols,
-                           int64_t rsd, int64_t csd, T scale, int lgW)
+__device__ __forceinline__ void tile_store(const T *buf, int rs, int row0, TO *dst, int nrows, int ncols,
+                                           int64_t rsd, int64_t csd, T scale, int lgW, int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     if (rsd == 1 && csd != 1) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int lane = tid & 63, wave = tid >> 6;
         for (int c = wave; c < ncols; c += NT / 64) {
             TO *col = dst + c * csd;
             for (int r = lane; r < nrows; r += 64) col[r] = (TO)(scale * buf[(row0 + r) * rs + c]);
@@ -573,7 +668,7 @@ __device__ void tile_store(const T *buf, int rs, int row0, TO *dst, int nrows, i
     } else {
         const int cm = (1 << lgW) - 1;
         const int tot = nrows << lgW;
-        for (int e = threadIdx.x; e < tot; e += NT) {
+        for (int e = tid; e < tot; e += NT) {
             const int c = e & cm, r = e >> lgW;
             if (c < ncols) dst[r * rsd + c * csd] = (TO)(scale * buf[(row0 + r) * rs + c]);
         }
@@ -582,11 +677,12 @@ __device__ void tile_store(const T *buf, int rs, int row0, TO *dst, int nrows, i
 
 // As tile_store, but the scaled values are added to the destination.
 template <typename T, typename TO, int NT>
-__device__ void tile_store_acc(const T *buf, int rs, int row0, TO *dst, int nrows, int ncols,
-                               int64_t rsd, int64_t csd, T scale, int lgW)
+__device__ __forceinline__ void tile_store_acc(const T *buf, int rs, int row0, TO *dst, int nrows, int ncols,
+                                               int64_t rsd, int64_t csd, T scale, int lgW, int tid = -1)
 {
+    if (tid < 0) tid = threadIdx.x;
     if (rsd == 1 && csd != 1) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int lane = tid & 63, wave = tid >> 6;
         for (int c = wave; c < ncols; c += NT / 64) {
             TO *col = dst + c * csd;
             for (int r = lane; r < nrows; r += 64) col[r] += (TO)(scale * buf[(row0 + r) * rs + c]);
@@ -594,7 +690,7 @@ __device__ void tile_store_acc(const T *buf, int rs, int row0, TO *dst, int nrow
     } else {
         const int cm = (1 << lgW) - 1;
         const int tot = nrows << lgW;
-        for (int e = threadIdx.x; e < tot; e += NT) {
+        for (int e = tid; e < tot; e += NT) {
             const int c = e & cm, r = e >> lgW;
             if (c < ncols) dst[r * rsd + c * csd] += (TO)(scale * buf[(row0 + r) * rs + c]);
         }

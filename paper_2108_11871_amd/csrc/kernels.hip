@@ -1,7 +1,7 @@
 // HIP kernels of the infinite-domain Poisson solver (gfx950).
 //
 // Stage map (paper sections):
-//   k_pass    pencil transforms: DST-I / zero-padded cos+sin / even (DCT-I) /
+//   k_pass    (pass.hip) pencil transforms: DST-I / zero-padded cos+sin / even (DCT-I) /
 //             hermitian synthesis along one axis (Sections 3, 4, 5)
 //   k_cc      (conv.hip) boundary values as sums over slices of 2D (3D problems) or 1D
 //             (2D problems) discrete convolutions, accumulated in Fourier
@@ -20,6 +20,7 @@
 #include <map>
 #include <type_traits>
 #include <mutex>
+#include <tuple>
 
 #include "common.h"
 #include "kernels.h"
@@ -44,122 +45,28 @@ void set_lds(const void *fn, size_t bytes)
         (void)hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Generic pencil pass
-// ---------------------------------------------------------------------------
-template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT>
-__global__ __launch_bounds__(NTT) void k_pass(PassArgs a)
+
+// Blocks of a kernel that fit on the device at once (occupancy times the
+// number of compute units), cached per kernel, block size and LDS size.
+int resident_blocks(const void *fn, int nthreads, size_t lds)
 {
-    constexpr bool BIG = NTT != NT;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
-    const int lgW = 31 - __clz(W), lgs = lgW - 1;
-    const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
-    T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
-    const int ncb = (a.ncols + W - 1) / W;
-    const int lb = xcd_remap(blockIdx.x, ncb * a.nbatch);
-    const int cb = lb % ncb, bt = lb / ncb;
-    const int c0 = cb * W;
-    const int nc = min(W, a.ncols - c0);
-    const TI *in = static_cast<const TI *>(a.in) + bt * a.ibs + c0 * a.ics;
-    TO *out = static_cast<TO *>(a.out) + bt * a.obs + c0 * a.ocs;
-    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
-    bool inv = false;
-    if (a.in_mode == IN_ZPAD) {
-        zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
-        zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
-        tile_load<T, TI, NTT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-        __syncthreads();
-    } else if (a.in_mode == IN_ZPAD0) {
-        zero_rows<T, NTT>(buf, rs, lgW, a.nrows_in, N);
-        tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-        __syncthreads();
-    } else if (a.in_mode == IN_EVEN) {
-        tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-        __syncthreads();
-        pre_even<T, NTT>(buf, rs, lgW, M);
-    } else if (a.in_mode == IN_HERM) {
-        if (a.nsum > 1)
-            tile_load_sum<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW, a.nsum,
-                                      a.sstride);
-        else
-            tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-        __syncthreads();
-        pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, false);
-        inv = true;
-    } else {
-        tile_load<T, TI, NTT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-        __syncthreads();
-        pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, true);
-        inv = true;
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t, int>, int> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_tuple(fn, nthreads, lds, dev);
+    auto it = done.find(key);
+    if (it != done.end()) return it->second;
+    int per = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, nthreads, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
     }
-    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv);
-    if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
-    if (a.accum)
-        tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
-    else
-        tile_store<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
-}
-
-
-template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT = NT>
-static void launch_pass_k(const PassArgs &a, int64_t nblk, size_t lds, hipStream_t st)
-{
-    set_lds((const void *)&k_pass<T, TI, TO, MAXE, P2, NTT>, lds);
-    hipLaunchKernelGGL((k_pass<T, TI, TO, MAXE, P2, NTT>), dim3((unsigned)nblk), dim3(NTT), lds, st, a);
-}
-
-template <typename T, typename TI, typename TO>
-static hipError_t launch_pass_t(const PassArgs &a, hipStream_t st)
-{
-    const int ncb = (a.ncols + a.W - 1) / a.W;
-    const int64_t nblk = (int64_t)ncb * a.nbatch;
-    const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    const int work = (a.W / 2) * a.fd.N;
-    const bool p2 = is_pow2(a.fd.N);
-    if (nblk <= 0) return hipSuccess;
-    if (big_fft(a.fd.N)) {
-        if (a.W != 2 || work > 8 * NTB) return hipErrorInvalidValue;
-        if (work <= 4 * NTB) {
-            if (p2)
-                launch_pass_k<T, TI, TO, 4, true, NTB>(a, nblk, lds, st);
-            else
-                launch_pass_k<T, TI, TO, 4, false, NTB>(a, nblk, lds, st);
-        } else {
-            if (p2)
-                launch_pass_k<T, TI, TO, 8, true, NTB>(a, nblk, lds, st);
-            else
-                launch_pass_k<T, TI, TO, 8, false, NTB>(a, nblk, lds, st);
-        }
-        return hipGetLastError();
-    }
-    if (work <= 4 * NT) {
-        if (p2)
-            launch_pass_k<T, TI, TO, 4, true>(a, nblk, lds, st);
-        else
-            launch_pass_k<T, TI, TO, 4, false>(a, nblk, lds, st);
-    } else if (work <= 8 * NT) {
-        if (p2)
-            launch_pass_k<T, TI, TO, 8, true>(a, nblk, lds, st);
-        else
-            launch_pass_k<T, TI, TO, 8, false>(a, nblk, lds, st);
-    } else if (work <= 16 * NT) {
-        if (p2)
-            launch_pass_k<T, TI, TO, 16, true>(a, nblk, lds, st);
-        else
-            launch_pass_k<T, TI, TO, 16, false>(a, nblk, lds, st);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st)
-{
-    if (!in_f32 && !out_f32) return launch_pass_t<double, double, double>(a, st);
-    if (in_f32 && out_f32) return launch_pass_t<float, float, float>(a, st);
-    if (!in_f32 && out_f32) return launch_pass_t<float, double, float>(a, st);
-    return launch_pass_t<float, float, double>(a, st);
+    const int r = per * ncu;
+    done[key] = r;
+    return r;
 }
 
 // ---------------------------------------------------------------------------
