@@ -435,8 +435,10 @@ int plan_build(ips_plan p, hipStream_t st)
         const int W = tile_width(N[pen], p->work, I[fam]);
         const int hc = (I[fam] + 1) / 2, Wh = W / 2;
         const int ncb = (hc + Wh - 1) / Wh;
-        // about 2048 blocks of 256 threads; 256 blocks of 1024 for long transforms
-        const int target = N[pen] > kLdsMaxN ? 256 : 2048;
+        // about 6144 blocks of 256 threads (a few tiles each: measured faster
+        // than fewer, longer blocks, although the face pass then sums more
+        // chunk partials); 256 blocks of 1024 for long transforms
+        const int target = N[pen] > kLdsMaxN ? 256 : 6144;
         int nch = std::max(1, std::min(ncb, (target + nbatch - 1) / nbatch));
         const int per = (ncb + nch - 1) / nch;
         p->chunk[fam] = per * Wh;
