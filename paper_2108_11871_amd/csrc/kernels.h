@@ -91,6 +91,9 @@ struct ShellSpec {
     // 3D: family 1 packed values transposed to [par][t][k2][k0] (k0 contiguous),
     // for the final pass which walks k0 at fixed k2
     const double *P1T;
+    // 3D: family 2 packed values transposed to [par][t][k1][k0] (k0 contiguous),
+    // for the final pass, whose lanes walk k0
+    const double *P2T;
 };
 
 struct PackArgs {
@@ -99,6 +102,7 @@ struct PackArgs {
     const double *D[3];
     double *P[3];
     double *P1T; // 3D only
+    double *P2T; // 3D only
     int withD;   // also pack the deferred-correction layers
 };
 

@@ -221,6 +221,13 @@ __global__ void k_pack(PackArgs a)
             const int nt = a.withD ? 6 : 1;
             for (int t = 0; t < 6; ++t)
                 if (t % 3 < nt) P[t * ss + e] = v[t];
+            if (fam == 2 && g.d == 3 && a.P2T) {
+                // e = (k0-1) * I1 + (k1-1)  ->  (k1-1) * I0 + (k0-1)
+                const int I0 = g.M[0] - 1, I1 = g.M[1] - 1;
+                const int64_t et = (e % I1) * I0 + e / I1;
+                for (int t = 0; t < 6; ++t)
+                    if (t % 3 < nt) a.P2T[t * ss + et] = v[t];
+            }
             if (fam == 1 && g.d == 3 && a.P1T) {
                 // e = (k0-1) * I2 + (k2-1)  ->  (k2-1) * I0 + (k0-1)
                 const int I0 = g.M[0] - 1, I2 = g.M[2] - 1;
@@ -282,13 +289,15 @@ __device__ __forceinline__ float recip(float x)
 // transposed family-1 copy) and G_l at one of two addresses (parity of
 // k_l).  With lambda_a the only varying eigenvalue,
 //   Lambda = A0 + A1 lambda_a,  m_R = B0 + lambda_a (B1 + B2 lambda_a).
-// Block: 64 positions x 4 wave groups; group g takes k_a = 1 + g + 4t, so
-// its parity is fixed and the layer pairs split into odd and even sums.
+// Block: 64 PPT positions x 4 wave groups; group g takes k_a = 1 + g + 4t,
+// so its parity is fixed and the layer pairs split into odd and even sums.
+// Each thread carries PPT positions (64 apart) through the k_a loop: their
+// loads and reciprocals are independent, which hides more latency per wave.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int PPT>
 __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
 {
-    constexpr int PB = 64, NG = NT / PB;
+    constexpr int PB = 64 * PPT, NG = NT / 64;
     __shared__ double red[NG][5][PB];
     const Geo &g = a.geo;
     int ax = 0, blk = blockIdx.x;
@@ -296,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
         blk -= a.nblk[ax];
         ++ax;
     }
-    const int lane = threadIdx.x & (PB - 1);
+    const int lane = threadIdx.x & 63;
     const int grp = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int Ia = g.M[ax] - 1;
     int la, wa;
@@ -310,107 +319,128 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
     const int Il = g.M[la] - 1;
     const int Iw = D == 3 ? g.M[wa] - 1 : 1;
     const int npos = Il * Iw;
-    const int p = blk * PB + lane;
-    const bool live = p < npos;
-    const int pp = live ? p : 0;
-    const int kl = 1 + pp % Il;
-    const int kw = 1 + pp / Il;
     const int para = (grp & 1) ? 0 : 1; // parity of k_a in this group
-
-    // symbols as polynomials in lambda_a
-    const double lamL = a.tab[la].lam[kl - 1];
-    double A0 = lamL, A1 = 1.0 + g.c2[ax][la] * lamL;
-    double B0 = 0.0, B1 = g.c4[la][ax] * lamL * lamL, B2 = g.c4[ax][la] * lamL;
-    if (D == 3) {
-        const double lamW = a.tab[wa].lam[kw - 1];
-        A0 += lamW + g.c2[la][wa] * lamL * lamW;
-        A1 += g.c2[ax][wa] * lamW;
-        B0 = g.c4[la][wa] * lamL * lamL * lamW + g.c4[wa][la] * lamL * lamW * lamW;
-        B1 += g.c4[wa][ax] * lamW * lamW;
-        B2 += g.c4[ax][wa] * lamW;
-    }
-    // own family (normal to a): fixed value for this group's parity
-    const int64_t ssa = shell_size(g, ax);
-    int64_t oown;
-    if (D == 3)
-        oown = ax == 2 ? (int64_t)(kl - 1) * Iw + (kw - 1) : (int64_t)(kw - 1) * Il + (kl - 1);
-    else
-        oown = kl - 1;
-    const double gown = a.P[ax][(int64_t)para * 3 * ssa + oown];
-    // family normal to the lane axis: two addresses per wave
-    const int64_t ssl = shell_size(g, la);
-    const double sbl = a.tab[la].s[kl - 1];
-    const double *pb = a.P[la] + (int64_t)(kl & 1) * 3 * ssl;
-    int64_t bs;
-    if (D == 3) {
-        if (ax == 0) {
-            pb += kw - 1; // G_2[k0][k1], k0 = k_a
-            bs = Iw;
-        } else if (ax == 1) {
-            pb += (int64_t)(kw - 1) * (g.M[1] - 1); // G_2[k0][k1], k1 = k_a
-            bs = 1;
-        } else {
-            pb += (int64_t)(kw - 1) * (g.M[2] - 1); // G_0[k1][k2], k2 = k_a
-            bs = 1;
+    const int64_t ssa = shell_size(g, ax), ssl = shell_size(g, la);
+    // per position q (PPT independent positions per thread, 64 apart)
+    double A0[PPT], A1[PPT], B0[PPT], B1[PPT], B2[PPT], gown[PPT], sbl[PPT], scw[PPT];
+    const double *pb[PPT], *pc[PPT];
+    int64_t bs = 1, cs = 0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int p = blk * PB + q * 64 + lane;
+        const int pp = p < npos ? p : 0;
+        const int kl = 1 + pp % Il;
+        const int kw = 1 + pp / Il;
+        // symbols as polynomials in lambda_a
+        const double lamL = a.tab[la].lam[kl - 1];
+        A0[q] = lamL;
+        A1[q] = 1.0 + g.c2[ax][la] * lamL;
+        B0[q] = 0.0;
+        B1[q] = g.c4[la][ax] * lamL * lamL;
+        B2[q] = g.c4[ax][la] * lamL;
+        if (D == 3) {
+            const double lamW = a.tab[wa].lam[kw - 1];
+            A0[q] += lamW + g.c2[la][wa] * lamL * lamW;
+            A1[q] += g.c2[ax][wa] * lamW;
+            B0[q] = g.c4[la][wa] * lamL * lamL * lamW + g.c4[wa][la] * lamL * lamW * lamW;
+            B1[q] += g.c4[wa][ax] * lamW * lamW;
+            B2[q] += g.c4[ax][wa] * lamW;
         }
-    } else {
-        bs = 1;
-    }
-    // family normal to the wave axis (3D): contiguous across the lanes
-    const double *pc = nullptr;
-    double scw = 0.0;
-    int64_t cs = 0;
-    if (D == 3) {
-        const int64_t ssw = shell_size(g, wa);
-        scw = a.tab[wa].s[kw - 1];
-        const double *base = ax == 2 ? a.P1T : a.P[wa];
-        pc = base + (int64_t)(kw & 1) * 3 * ssw + (kl - 1);
-        cs = ax == 2 ? (g.M[0] - 1) : (g.M[2] - 1);
+        // own family (normal to a): fixed value for this group's parity
+        int64_t oown;
+        if (D == 3)
+            oown = ax == 2 ? (int64_t)(kl - 1) * Iw + (kw - 1) : (int64_t)(kw - 1) * Il + (kl - 1);
+        else
+            oown = kl - 1;
+        gown[q] = a.P[ax][(int64_t)para * 3 * ssa + oown];
+        // family normal to the lane axis: two addresses per wave
+        sbl[q] = a.tab[la].s[kl - 1];
+        pb[q] = a.P[la] + (int64_t)(kl & 1) * 3 * ssl;
+        if (D == 3) {
+            if (ax == 0) {
+                pb[q] += kw - 1; // G_2[k0][k1], k0 = k_a
+                bs = Iw;
+            } else if (ax == 1) {
+                pb[q] += (int64_t)(kw - 1) * (g.M[1] - 1); // G_2[k0][k1], k1 = k_a
+            } else {
+                pb[q] += (int64_t)(kw - 1) * (g.M[2] - 1); // G_0[k1][k2], k2 = k_a
+            }
+        }
+        // family normal to the wave axis (3D): contiguous across the lanes
+        pc[q] = nullptr;
+        scw[q] = 0.0;
+        if (D == 3) {
+            const int64_t ssw = shell_size(g, wa);
+            scw[q] = a.tab[wa].s[kw - 1];
+            const double *base = ax == 2 ? a.P1T : a.P[wa];
+            pc[q] = base + (int64_t)(kw & 1) * 3 * ssw + (kl - 1);
+            cs = ax == 2 ? (g.M[0] - 1) : (g.M[2] - 1);
+        }
     }
     const double *tl = a.tab[ax].lam;
     const double *ts = a.tab[ax].s;
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int ka = 1 + grp; ka <= Ia; ka += NG) {
-        const double lk = tl[ka - 1];
-        double gt = ts[ka - 1] * gown + sbl * pb[(int64_t)(ka - 1) * bs];
-        if (D == 3) gt += scw * pc[(int64_t)(ka - 1) * cs];
-        const double L = fma(A1, lk, A0);
-        const double R = fma(fma(B2, lk, B1), lk, B0);
-        const double v = R * gt * recip(L);
+    double acc[PPT][5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) acc[j] = fma(ts[j * Ia + ka - 1], v, acc[j]);
+    for (int q = 0; q < PPT; ++q)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc[q][j] = 0.0;
+    for (int ka = 1 + grp; ka <= Ia; ka += NG) {
+        const double lk = tl[ka - 1], sk = ts[ka - 1];
+        double sj[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) sj[j] = ts[j * Ia + ka - 1];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            double gt = sk * gown[q] + sbl[q] * pb[q][(int64_t)(ka - 1) * bs];
+            if (D == 3) gt += scw[q] * pc[q][(int64_t)(ka - 1) * cs];
+            const double L = fma(A1[q], lk, A0[q]);
+            const double R = fma(fma(B2[q], lk, B1[q]), lk, B0[q]);
+            const double v = R * gt * recip(L);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) acc[q][j] = fma(sj[j], v, acc[q][j]);
+        }
     }
 #pragma unroll
-    for (int j = 0; j < 5; ++j) red[grp][j][lane] = acc[j];
+    for (int q = 0; q < PPT; ++q)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) red[grp][j][q * 64 + lane] = acc[q][j];
     __syncthreads();
-    if (grp == 0 && live) {
+    // group g finishes positions g*64/...: every thread of the block writes
+    // its share of the PB positions
+    double *T = a.T[ax];
+    for (int i = threadIdx.x; i < PB; i += NT) {
+        const int p = blk * PB + i;
+        if (p >= npos) continue;
+        const int kl = 1 + p % Il, kw = 1 + p / Il;
         const int64_t pout = (D == 3 && ax == 2) ? (int64_t)(kl - 1) * Iw + (kw - 1) : p;
-        double *T = a.T[ax];
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            const double od = red[0][j][lane] + red[2][j][lane];
-            const double ev = red[1][j][lane] + red[3][j][lane];
+            const double od = red[0][j][i] + red[2][j][i];
+            const double ev = red[1][j][i] + red[3][j][i];
             T[j * (int64_t)npos + pout] = g.pref * (od + ev);
             T[(5 + j) * (int64_t)npos + pout] = g.pref * (od - ev);
         }
     }
 }
 
-hipError_t launch_r6t(R6Args a, hipStream_t st)
+template <int PPT>
+static hipError_t launch_r6t_p(R6Args a, hipStream_t st)
 {
     const int d = a.geo.d;
     int tot = 0;
     for (int ax = 0; ax < d; ++ax) {
         const int np = (int)shell_size(a.geo, ax);
-        a.nblk[ax] = (np + 63) / 64;
+        a.nblk[ax] = (np + 64 * PPT - 1) / (64 * PPT);
         tot += a.nblk[ax];
     }
     if (d == 3)
-        hipLaunchKernelGGL(k_r6t<3>, dim3(tot), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((k_r6t<3, PPT>), dim3(tot), dim3(NT), 0, st, a);
     else
-        hipLaunchKernelGGL(k_r6t<2>, dim3(tot), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((k_r6t<2, PPT>), dim3(tot), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
+
+hipError_t launch_r6t(R6Args a, hipStream_t st) { return launch_r6t_p<2>(a, st); }
 
 // ---------------------------------------------------------------------------
 // D = R - R_spec on the nodes with an index in {1, 2, M-2, M-1}, in two steps.
@@ -765,7 +795,6 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     const int64_t ss0 = shell_size(geo, 0), ss1 = shell_size(geo, 1);
     // batch (axis 2) constants and the per-element family 2
     double lamB = 0.0, qB = 0.0, s1B = 0.0, s2B = 0.0;
-    const double *Pz = nullptr;
     int64_t ss2 = 0;
     if (d == 3) {
         lamB = a.tab[2].lam[kB - 1];
@@ -773,7 +802,6 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
         s1B = a.tab[2].s[kB - 1];
         s2B = a.tab[2].s[I2 + kB - 1];
         ss2 = shell_size(geo, 2);
-        Pz = a.sh.P[2] + ((kB & 1) ? 3 * ss2 : 0);
     }
     const double c2xz = d == 3 ? geo.c2[0][2] : 0.0, c2yz = d == 3 ? geo.c2[1][2] : 0.0;
     const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
@@ -808,52 +836,60 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     // the reads and the writes.
     const T c2xy = (T)geo.c2[0][1], c4xy = (T)geo.c4[0][1], c4yx = (T)geo.c4[1][0];
     const T lamBt = (T)lamB, s1Bt = (T)s1B, s2Bt = (T)s2B, preft = (T)geo.pref;
-    const int smask = (1 << lgs) - 1;
-    const int npair = (M + 1) << lgs;
-    for (int e = threadIdx.x; e < npair; e += NTT) {
-        const int sq = e & smask, k = e >> lgs;
+    const int nseq = 1 << lgs;
+    // Row k per thread (consecutive k across the lanes): the row invariants
+    // are read once and serve every column of the tile; the family-2 values
+    // come from the transposed copy [par][t][k1][k0], contiguous in k0 = kx.
+    const double *Pt = d == 3 ? a.sh.P2T + ((kB & 1) ? 3 * ss2 : 0) : nullptr;
+    for (int k = threadIdx.x; k <= M; k += NTT) {
         if (k == 0 || k == M) {
-            lds_cs(buf, rs, k, sq, cx<T>{(T)0, (T)0});
+            for (int sq = 0; sq < nseq; ++sq) lds_cs(buf, rs, k, sq, cx<T>{(T)0, (T)0});
             continue;
         }
-        const cx<T> z1 = lds_c(buf, rs, k, sq), z2 = lds_c(buf, rs, N - k, sq);
-        T cab[2];
-        const T beta2[2] = {(T)0.5 * (z2.y - z1.y), (T)0.5 * (z1.x - z2.x)};
         const T *r = rv + (k - 1) * SV;
+        const T lx = r[0], rq = r[1], rs1 = r[2], rs2 = r[3], r10 = r[10], r11 = r[11];
+        // family 1 at (kx, kz) for even / odd ky
+        const T Pe0 = r[4], Pe1 = r[5], Pe2 = r[6], Po0 = r[7], Po1 = r[8], Po2 = r[9];
         const int kx = k;
+        const int pco = 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz): parity of kx
+        for (int sq = 0; sq < nseq; ++sq) {
+            const cx<T> z1 = lds_c(buf, rs, k, sq), z2 = lds_c(buf, rs, N - k, sq);
+            T cab[2];
+            const T beta2[2] = {(T)0.5 * (z2.y - z1.y), (T)0.5 * (z1.x - z2.x)};
 #pragma unroll
-        for (int h2 = 0; h2 < 2; ++h2) {
-            const int c = 2 * sq + h2;
-            T cval = (T)0;
-            if (c < nc) {
-                const int ky = 1 + c0 + c;
-                const T *q1 = cv + c * SV;
-                const T *Pr = r + 4 + ((ky & 1) ? 3 : 0);  // family 1 at (kx, kz)
-                const T *Pc = q1 + 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz)
-                const T lx = r[0], ly = q1[0], lxy = lx * ly;
-                const T Lm = r[10] + q1[10] + lamBt + c2xy * lxy;
-                T gt = r[2] * Pc[0] + q1[2] * Pr[0];
-                T dh = (T)0;
-                if (six) dh = r[2] * Pc[1] + r[3] * Pc[2] + q1[2] * Pr[1] + q1[3] * Pr[2];
-                if (d == 3) {
-                    const double *Pe = Pz + (int64_t)(kx - 1) * I1 + (ky - 1);
-                    gt += s1Bt * (T)Pe[0];
-                    if (six) dh += s1Bt * (T)Pe[ss2] + s2Bt * (T)Pe[2 * ss2];
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int c = 2 * sq + h2;
+                T cval = (T)0;
+                if (c < nc) {
+                    const int ky = 1 + c0 + c; // c0 is even: ky is odd for h2 = 0
+                    const T *q1 = cv + c * SV;
+                    const T P0 = h2 ? Pe0 : Po0, P1v = h2 ? Pe1 : Po1, P2v = h2 ? Pe2 : Po2;
+                    const T *Pc = q1 + pco;
+                    const T ly = q1[0], lxy = lx * ly;
+                    const T Lm = r10 + q1[10] + lamBt + c2xy * lxy;
+                    T gt = rs1 * Pc[0] + q1[2] * P0;
+                    T dh = (T)0;
+                    if (six) dh = rs1 * Pc[1] + rs2 * Pc[2] + q1[2] * P1v + q1[3] * P2v;
+                    if (d == 3) {
+                        const double *Pe = Pt + (int64_t)(ky - 1) * I0 + (kx - 1);
+                        gt += s1Bt * (T)Pe[0];
+                        if (six) dh += s1Bt * (T)Pe[ss2] + s2Bt * (T)Pe[2 * ss2];
+                    }
+                    const T iL = recip(Lm);
+                    T harm;
+                    if (six) {
+                        const T Rm = r11 + q1[11] + lxy * (c4xy * lx + c4yx * ly);
+                        harm = (gt * ((T)1 + Rm * iL) + dh) * iL;
+                    } else {
+                        harm = gt * iL;
+                    }
+                    cval = preft * (harm - beta2[h2] * recip(rq + q1[1]));
                 }
-                const T iL = recip(Lm);
-                T harm;
-                if (six) {
-                    const T Rm = r[11] + q1[11] + lxy * (c4xy * lx + c4yx * ly);
-                    harm = (gt * ((T)1 + Rm * iL) + dh) * iL;
-                } else {
-                    harm = gt * iL;
-                }
-                cval = preft * (harm - beta2[h2] * recip(r[1] + q1[1]));
+                cab[h2] = cval;
             }
-            cab[h2] = cval;
+            lds_cs(buf, rs, k, sq, cx<T>{cab[1], -cab[0]});
+            lds_cs(buf, rs, N - k, sq, cx<T>{-cab[1], cab[0]});
         }
-        lds_cs(buf, rs, k, sq, cx<T>{cab[1], -cab[0]});
-        lds_cs(buf, rs, N - k, sq, cx<T>{-cab[1], cab[0]});
     }
     __syncthreads();
     fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, true);
