@@ -159,18 +159,24 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
         __syncthreads();
     }
     // partials [face][chunk][batch][slot]: slot rows t and M + t
-    double *p0 = a.part + ((int64_t)ch * a.nbatch + bt) * N;
-    double *p1 = p0 + (int64_t)nchunk * a.nbatch * N;
+    const int64_t o0 = ((int64_t)ch * a.nbatch + bt) * N, o1 = o0 + (int64_t)nchunk * a.nbatch * N;
+    auto put = [&](auto *pp) {
 #pragma unroll
-    for (int i = 0; i < TPT; ++i) {
-        const int t = threadIdx.x + i * NTT;
-        if (t < M) {
-            p0[t] = a10[i];
-            p1[t] = a11[i];
-            p0[M + t] = a20[i];
-            p1[M + t] = a21[i];
+        for (int i = 0; i < TPT; ++i) {
+            const int t = threadIdx.x + i * NTT;
+            if (t < M) {
+                using P = std::remove_reference_t<decltype(*pp)>;
+                pp[o0 + t] = (P)a10[i];
+                pp[o1 + t] = (P)a11[i];
+                pp[o0 + M + t] = (P)a20[i];
+                pp[o1 + M + t] = (P)a21[i];
+            }
         }
-    }
+    };
+    if (a.part_f32)
+        put(static_cast<float *>(a.part));
+    else
+        put(static_cast<double *>(a.part));
 }
 
 template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT = NT, int WHC = 0>

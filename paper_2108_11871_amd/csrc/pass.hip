@@ -174,9 +174,9 @@ static void launch_pass_k(const PassArgs &a, int ntiles, size_t lds, hipStream_t
 
 // Default tile widths (W = 8, 16, 4 for 2M = 512, 256, 1024 at 2048 complex
 // points per tile) with plain loads get the register prefetch when EPT
-// registers per thread cover the loaded rows (FP32 tiles: only when MAXE
-// registers do, i.e. not for the full-length inputs of the inverse passes,
-// where the prefetching loop measured slower than one tile per block).
+// registers per thread cover the loaded rows.  FP32 tiles: only the forward
+// zero-padded transforms (EPT = MAXE); for the inverse passes the
+// prefetching loop measured slower than one tile per block.
 template <int WC, int EPT>
 static bool pass_fits(const PassArgs &a)
 {
@@ -188,7 +188,9 @@ static void launch_pass_m(const PassArgs &a, int ntiles, size_t lds, hipStream_t
 {
     if constexpr (P2 && MAXE == 8) {
         if (!(a.in_mode == IN_HERM && a.nsum > 1)) {
-            constexpr bool wide = sizeof(T) == 8; // EPT = 2 MAXE pays off for FP64 tiles only
+            constexpr bool wide = sizeof(T) == 8; // FP64 tiles: every mode, EPT up to 2 MAXE
+            if (!wide && a.in_mode != IN_ZPAD && a.in_mode != IN_ZPAD0)
+                return launch_pass_k<T, TI, TO, MAXE, P2>(a, ntiles, lds, st);
             if (pass_fits<8, 8>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 8, 8>(a, ntiles, lds, st);
             if (pass_fits<16, 8>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 16, 8>(a, ntiles, lds, st);
             if (pass_fits<4, 8>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 4, 8>(a, ntiles, lds, st);
@@ -248,6 +250,8 @@ static hipError_t launch_pass_t(const PassArgs &a, hipStream_t st)
     }
     return hipGetLastError();
 }
+
+hipError_t launch_pass_in32(const PassArgs &a, hipStream_t st) { return launch_pass_t<double, float, double>(a, st); }
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st)
 {

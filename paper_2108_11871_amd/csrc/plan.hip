@@ -176,6 +176,7 @@ struct ips_plan_s {
     void *A = nullptr; // slot transforms of rho along one axis (3D)
     void *B = nullptr; // raw DST of rho along the last d-1 axes, then phi in sine space
     double *part[3] = {nullptr, nullptr, nullptr};
+    float *partf[3] = {nullptr, nullptr, nullptr}; // the same buffer, FP32 partials (3D, FP32 slices)
     int nch[3] = {1, 1, 1};
     int chunk[3] = {1, 1, 1};
     double *F[3] = {nullptr, nullptr, nullptr};
@@ -465,6 +466,7 @@ int plan_build(ips_plan p, hipStream_t st)
         size_t op = 0, of = 0, os = 0;
         for (int fam = 0; fam < d; ++fam) {
             p->part[fam] = bp + op;
+            p->partf[fam] = reinterpret_cast<float *>(bp) + op;
             p->F[fam] = bf + of;
             p->G[fam] = bg + 2 * os;
             p->P[fam] = bpk + 6 * os;
@@ -634,7 +636,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.K = f32s ? (const void *)p->K32[0] : (const void *)p->K[0];
             a.Kd = (int64_t)(M[2] + 1) * (M[1] + 1);
             a.Ko = M[1] + 1;
-            a.part = p->part[0];
+            a.part = f32s ? (void *)p->partf[0] : (void *)p->part[0];
+            a.part_f32 = f32s;
             a.Bout = p->B;
             a.Bf32 = f32;
             a.Bcs = I[1];
@@ -662,7 +665,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.K = f32s ? (const void *)p->K32[1] : (const void *)p->K[1];
             a.Kd = (int64_t)(M[2] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
-            a.part = p->part[1];
+            a.part = f32s ? (void *)p->partf[1] : (void *)p->part[1];
+            a.part_f32 = f32s;
             a.Bout = nullptr;
             a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
@@ -707,7 +711,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.K = f32s ? (const void *)p->K32[2] : (const void *)p->K[2];
             a.Kd = (int64_t)(M[1] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
-            a.part = p->part[2];
+            a.part = f32s ? (void *)p->partf[2] : (void *)p->part[2];
+            a.part_f32 = f32s;
             a.Bout = nullptr;
             a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
@@ -725,7 +730,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             const int r = fr[fam], c = fc[fam];
             const int64_t plane = (int64_t)N[r] * N[c];
             PassArgs a{};
-            a.in = p->part[fam];
+            a.in = f32s ? (const void *)p->partf[fam] : (const void *)p->part[fam];
             a.out = p->F[fam];
             a.irs = a.ors = 1;
             a.ics = a.ocs = N[c];
@@ -742,7 +747,15 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.scale = 1.0 / N[c];
             // few faces: narrow tiles give enough blocks to fill the device
             a.W = tile_width(N[c], std::min(p->work, 512), a.ncols);
-            if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            if (f32s) {
+                // FP32 chunk partials, summed and transformed in FP64
+                a.fd = p->fd[c];
+                a.tw = p->tw[c];
+                a.twf = p->twf[c];
+                IPS_HIP(launch_pass_in32(a, st));
+            } else if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) {
+                return rc;
+            }
             PassArgs b{};
             b.in = b.out = p->F[fam];
             b.irs = b.ors = N[c];
