@@ -616,6 +616,23 @@ __device__ __forceinline__ void put_pair(T *buf, int rs, int row0, const TI (&v)
     }
 }
 
+// q[0] + q[s] + ... + q[(n-1) s] with four independent partial sums, so that
+// four loads are in flight at a time: ((a0 + a1) + (a2 + a3)).
+template <typename T, typename TI>
+__device__ __forceinline__ T sum_strided(const TI *q, int n, int64_t s)
+{
+    T a0 = (T)0, a1 = (T)0, a2 = (T)0, a3 = (T)0;
+    int k = 0;
+    for (; k + 4 <= n; k += 4) {
+        a0 += (T)q[k * s];
+        a1 += (T)q[(k + 1) * s];
+        a2 += (T)q[(k + 2) * s];
+        a3 += (T)q[(k + 3) * s];
+    }
+    for (; k < n; ++k) a0 += (T)q[k * s];
+    return (a0 + a1) + (a2 + a3);
+}
+
 // As tile_load (columns contiguous or generic), but every element is the sum
 // of nsum copies spaced sstride apart (summing partial results on the fly).
 template <typename T, typename TI, int NT>
@@ -630,10 +647,7 @@ __device__ __forceinline__ void tile_load_sum(T *buf, int rs, int row0, const TI
         for (int c = wave; c < W; c += NT / 64) {
             for (int r = lane; r < nrows; r += 64) {
                 T v = (T)0;
-                if (c < ncols) {
-                    const TI *q = src + c * csd + r;
-                    for (int k = 0; k < nsum; ++k) v += (T)q[k * sstride];
-                }
+                if (c < ncols) v = sum_strided<T>(src + c * csd + r, nsum, sstride);
                 buf[(row0 + r) * rs + c] = v;
             }
         }
@@ -644,10 +658,7 @@ __device__ __forceinline__ void tile_load_sum(T *buf, int rs, int row0, const TI
     for (int e = tid; e < tot; e += NT) {
         const int c = e & cm, r = e >> lgW;
         T v = (T)0;
-        if (c < ncols) {
-            const TI *q = src + r * rsd + c * csd;
-            for (int k = 0; k < nsum; ++k) v += (T)q[k * sstride];
-        }
+        if (c < ncols) v = sum_strided<T>(src + r * rsd + c * csd, nsum, sstride);
         buf[(row0 + r) * rs + c] = v;
     }
 }

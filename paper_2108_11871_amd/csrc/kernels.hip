@@ -731,9 +731,13 @@ __device__ __forceinline__ void final_row(const FinalArgs &a, int i, int kB, dou
 }
 
 template <typename T, int MAXE, bool P2, int WC, int NTT>
-__global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
+__global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
 {
     constexpr bool BIG = NTT != NT;
+    // FP64 tiles of a compile-time width (short transforms): persistent blocks
+    // that fetch the next tile into registers while the current one is
+    // processed (for FP32 tiles one tile per block measured faster)
+    constexpr bool PF = WC > 0 && !BIG && sizeof(T) == 8;
     extern __shared__ __align__(16) unsigned char smem[];
     // WC > 0: tile width known at compile time (row offsets become shifts)
     const int N = a.fd.N, M = a.fd.M, W = WC > 0 ? WC : a.W, rs = BIG ? W : W + 1;
@@ -742,12 +746,11 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     const size_t twb = BIG ? 0 : (size_t)N * sizeof(cx<T>);
     T *buf = reinterpret_cast<T *>(smem + twb);
     const int ncb = (a.ncols + W - 1) / W;
-    const int lb = xcd_remap(blockIdx.x, ncb * a.nbatch);
+    const int grid = gridDim.x;
     // logical order: pairs of neighbouring column blocks, then the batch, then
     // the pair index -- each XCD sweeps all batches over a narrow band of
     // columns, so the per-element shell data of that band stays in its L2
-    int cb, bt;
-    {
+    auto decode = [&](int lb, int &cb, int &bt) {
         const int pairs = ncb / 2;
         if (lb < 2 * pairs * a.nbatch) {
             const int pr = lb / (2 * a.nbatch), rem = lb % (2 * a.nbatch);
@@ -758,14 +761,48 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
             bt = rem;
             cb = ncb - 1;
         }
+    };
+    const int lb0 = xcd_remap(blockIdx.x, grid);
+    const bool rcont = a.irs == 1 && a.ics != 1;
+    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
+    T pf[PF ? MAXE : 1];
+    if constexpr (PF) {
+        if (lb0 < ntiles) {
+            int cb, bt;
+            decode(lb0, cb, bt);
+            const int c0 = cb * W;
+            fetch_pair<T, NTT, (PF ? WC : 2), MAXE, false>(pf, static_cast<const T *>(a.buf) + bt * a.ibs + c0 * a.ics,
+                                                          a.nrows_in, a.irs, a.ics, 0, min(W, a.ncols - c0), 0, 0,
+                                                          threadIdx.x);
+        }
     }
+    for (int it = lb0; it < ntiles; it += grid) {
+    int tid = threadIdx.x;
+    if constexpr (PF) {
+        asm volatile("" : "+v"(tid));
+        tid &= NTT - 1;
+    }
+    int cb, bt;
+    decode(it, cb, bt);
     const int c0 = cb * W;
     const int nc = min(W, a.ncols - c0);
     T *g = static_cast<T *>(a.buf) + bt * a.ibs + c0 * a.ics;
-    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
-    zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
-    zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
-    tile_load<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, lgW);
+    zero_rows<T, NTT>(buf, rs, lgW, 0, 1, tid);
+    zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N, tid);
+    if constexpr (PF) {
+        put_pair<T, T, NTT, (PF ? WC : 2), MAXE>(buf, rs, 1, pf, a.nrows_in, rcont, tid);
+        const int nx = it + grid;
+        if (nx < ntiles) {
+            int cb1, bt1;
+            decode(nx, cb1, bt1);
+            const int c1 = cb1 * W;
+            fetch_pair<T, NTT, (PF ? WC : 2), MAXE, false>(pf, static_cast<const T *>(a.buf) + bt1 * a.ibs + c1 * a.ics,
+                                                          a.nrows_in, a.irs, a.ics, 0, min(W, a.ncols - c1), 0, 0,
+                                                          tid);
+        }
+    } else {
+        tile_load<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, lgW, tid);
+    }
     const Geo &geo = a.geo;
     const int d = geo.d;
     const bool six = a.order == 6;
@@ -807,8 +844,8 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
     const double c4yz = d == 3 ? geo.c4[1][2] : 0.0, c4zy = d == 3 ? geo.c4[2][1] : 0.0;
     if (!grows)
-        for (int i = threadIdx.x; i < I0; i += NTT) final_row<T>(a, i, kB, lamB, qB, rv + i * SV);
-    for (int i = threadIdx.x; i < nc; i += NTT) {
+        for (int i = tid; i < I0; i += NTT) final_row<T>(a, i, kB, lamB, qB, rv + i * SV);
+    for (int i = tid; i < nc; i += NTT) {
         T *r = cv + i * SV;
         const int j = c0 + i; // k1 - 1
         const double ly = a.tab[1].lam[j];
@@ -824,7 +861,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
             for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = (T)a.sh.P[0][(par * 3 + t) * ss0 + o];
     }
     __syncthreads();
-    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false);
+    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
     // One sweep over the row pairs (k, N-k) of every complex sequence s
     // (real columns 2s and 2s+1):
     //   sine coefficients  S_a = (z(N-k).y - z(k).y)/2,  S_b = (z(k).x - z(N-k).x)/2
@@ -841,7 +878,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
     // are read once and serve every column of the tile; the family-2 values
     // come from the transposed copy [par][t][k1][k0], contiguous in k0 = kx.
     const double *Pt = d == 3 ? a.sh.P2T + ((kB & 1) ? 3 * ss2 : 0) : nullptr;
-    for (int k = threadIdx.x; k <= M; k += NTT) {
+    for (int k = tid; k <= M; k += NTT) {
         if (k == 0 || k == M) {
             for (int sq = 0; sq < nseq; ++sq) lds_cs(buf, rs, k, sq, cx<T>{(T)0, (T)0});
             continue;
@@ -892,15 +929,24 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a)
         }
     }
     __syncthreads();
-    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, true);
-    tile_store<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW);
+    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, true, tid);
+    tile_store<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW, tid);
+    if constexpr (!PF) break; // one tile per block: no loop for the compiler to hoist out of
+    __syncthreads();          // the next tile reuses the LDS
+    }
 }
 
 template <typename T, int MAXE, bool P2, int WC, int NTT = NT>
 static void launch_final_w(const FinalArgs &a, int nblk, size_t lds, hipStream_t st)
 {
-    set_lds((const void *)&k_final<T, MAXE, P2, WC, NTT>, lds);
-    hipLaunchKernelGGL((k_final<T, MAXE, P2, WC, NTT>), dim3(nblk), dim3(NTT), lds, st, a);
+    const void *fn = (const void *)&k_final<T, MAXE, P2, WC, NTT>;
+    set_lds(fn, lds);
+    int grid = nblk;
+    if (WC > 0 && NTT == NT && sizeof(T) == 8) {
+        const int r = resident_blocks(fn, NTT, lds);
+        if (r > 0 && r < nblk) grid = r;
+    }
+    hipLaunchKernelGGL((k_final<T, MAXE, P2, WC, NTT>), dim3(grid), dim3(NTT), lds, st, a, nblk);
 }
 
 template <typename T, int MAXE, bool P2>
@@ -910,11 +956,14 @@ static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
     // global memory, the row (M0-1) invariants, 12 values of type T each
     const size_t rows = a.rowtab ? 0 : (size_t)(a.fd.M - 1);
     const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (rows + a.W) * 12 * sizeof(T);
-    if (a.W == 8)
+    // compile-time widths also prefetch the next tile: MAXE registers per
+    // thread must cover the tile's rows
+    const bool rc = a.irs == 1 && a.ics != 1;
+    if (a.W == 8 && PairMap<NT, 8, MAXE>::covers(a.nrows_in, rc))
         launch_final_w<T, MAXE, P2, 8>(a, nblk, lds, st);
-    else if (a.W == 16)
+    else if (a.W == 16 && PairMap<NT, 16, MAXE>::covers(a.nrows_in, rc))
         launch_final_w<T, MAXE, P2, 16>(a, nblk, lds, st);
-    else if (a.W == 32)
+    else if (a.W == 32 && PairMap<NT, 32, MAXE>::covers(a.nrows_in, rc))
         launch_final_w<T, MAXE, P2, 32>(a, nblk, lds, st);
     else
         launch_final_w<T, MAXE, P2, 0>(a, nblk, lds, st);
