@@ -55,10 +55,14 @@ STAGE_KERNEL = {
 
 
 def source_hash() -> str:
+    """Hash of every kernel and plan source (counters taken on other sources are stale)."""
     h = hashlib.sha256()
-    for f in ("fft_tile.h", "kernels.h", "kernels.hip", "plan.hip"):
-        with open(os.path.join(ROOT, "paper_2108_11871_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2108_11871_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -72,7 +76,7 @@ def stage_bytes(n: int, mode: str, nch: dict) -> dict:
     wb = 4 if mode != "fp64" else 8  # sine-space volume
     kt = I * (M + 1) ** 2 * wa  # kernel spectra of one face family (FP32 with FP32 slots)
     A = I * I * N * wa
-    part = 2 * N * N * 8
+    part = 2 * N * N * wa  # chunk partials of both faces (FP32 with FP32 slots)
     return {
         "rho_z": vol * 8 + A,
         "conv_x": A + kt + vol * wb + nch.get("x", 1) * part,
@@ -104,11 +108,13 @@ def nchunks(n: int, mode: str) -> dict:
 
     out = {}
     for key in ("x", "y", "z"):
+        # a tile holds W/2 first-half columns and their mirrors
         W = tw(N, I)
-        ncb = (I + W - 1) // W
-        nch = max(1, min(ncb, (2048 + N - 1) // N))
+        hc, Wh = (I + 1) // 2, W // 2
+        ncb = (hc + Wh - 1) // Wh
+        nch = max(1, min(ncb, (6144 + N - 1) // N))
         per = (ncb + nch - 1) // nch
-        out[key] = (I + per * W - 1) // (per * W)
+        out[key] = (hc + per * Wh - 1) // (per * Wh)
     return out
 
 
@@ -181,7 +187,7 @@ def cpu_baseline(seed: int):
 
 # stage -> (kernel-name substring, occurrence within one solve) in dispatch order
 STAGE_DISPATCH = {
-    "final": ("k_final", 0),
+    "final": ("k_final<", 0),
     "conv_x": ("k_cc", 0),
     "conv_y": ("k_cc", 1),
     "conv_z": ("k_cc", 2),
