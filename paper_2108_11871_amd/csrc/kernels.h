@@ -123,7 +123,7 @@ struct FinalArgs {
     const cx<double> *tw;
     const cx<float> *twf;
     void *rowtab;   // if set: row table [nbatch][M0 - 1][12] (transform type) in global memory, written by
-                    // launch_final before the pass (required for transforms longer than 2048)
+                    // launch_final_rows before the pass (required for transforms longer than 2048)
 };
 
 // Sixth-order right-hand side on the depth-5 shell layers (see k_r6t).
@@ -211,6 +211,8 @@ hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);
 hipError_t launch_pack(const PackArgs &a, hipStream_t st);
 hipError_t launch_r6t(R6Args a, hipStream_t st);
 hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st);
+// Row table of the final pass (if a.rowtab): once per solve, before launch_final.
+hipError_t launch_final_rows(const FinalArgs &a, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);
 // K[dd][ib][ic] (3D) or K[dd][ib] (2D) for faces normal to axis a; (b, c) are
 // the in-face axes in storage order (c contiguous).

@@ -1034,6 +1034,15 @@ __global__ void k_final_rows(FinalArgs a)
     }
 }
 
+hipError_t launch_final_rows(const FinalArgs &a, hipStream_t st)
+{
+    if (!a.rowtab) return hipSuccess;
+    const int64_t tot = (int64_t)(a.geo.M[0] - 1) * a.nbatch;
+    const unsigned nb = (unsigned)std::min<int64_t>((tot + NT - 1) / NT, 4096);
+    hipLaunchKernelGGL(k_final_rows, dim3(nb), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_final(const FinalArgs &a, hipStream_t st)
 {
     const int ncb = (a.ncols + a.W - 1) / a.W;
@@ -1042,11 +1051,6 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st)
     if (big_fft(a.fd.N) && (a.geo.d != 2 || !a.rowtab || a.W != 2 || work > 8 * NTB))
         return hipErrorInvalidValue;
     if (!big_fft(a.fd.N) && work > 32 * NT) return hipErrorInvalidValue;
-    if (a.rowtab) {
-        const int64_t tot = (int64_t)(a.geo.M[0] - 1) * a.nbatch;
-        const unsigned nb = (unsigned)std::min<int64_t>((tot + NT - 1) / NT, 4096);
-        hipLaunchKernelGGL(k_final_rows, dim3(nb), dim3(NT), 0, st, a);
-    }
     if (a.mixed)
         launch_final_t<float>(a, nblk, work, st);
     else

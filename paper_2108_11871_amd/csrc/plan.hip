@@ -917,7 +917,6 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     }
     // ---- combination and inverse transforms ------------------------------------------
     {
-        STAGE(IPS_STAGE_FINAL);
         FinalArgs a{};
         a.buf = p->B;
         if (d == 3) {
@@ -949,6 +948,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         a.tw = p->tw[0];
         a.twf = p->twf[0];
         a.rowtab = p->rowtab;
+        IPS_HIP(launch_final_rows(a, st));
+        STAGE(IPS_STAGE_FINAL);
         IPS_HIP(launch_final(a, st));
     }
     if (d == 3) {
