@@ -93,8 +93,9 @@ struct ShellSpec {
     // for the final pass which walks k0 at fixed k2
     const double *P1T;
     // 3D: family 2 packed values transposed to [par][t][k1][k0] (k0 contiguous),
-    // for the final pass, whose lanes walk k0
-    const double *P2T;
+    // for the final pass, whose lanes walk k0; stored in the final pass's
+    // transform type (FP32 in the mixed modes)
+    const void *P2T;
 };
 
 struct PackArgs {
@@ -103,7 +104,8 @@ struct PackArgs {
     const double *D[3];
     double *P[3];
     double *P1T; // 3D only
-    double *P2T; // 3D only
+    void *P2T;   // 3D only: FP32 if p2t_f32, else FP64
+    int p2t_f32;
     int withD;   // also pack the deferred-correction layers
 };
 

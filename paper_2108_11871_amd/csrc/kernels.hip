@@ -226,7 +226,12 @@ __global__ void k_pack(PackArgs a)
                 const int I0 = g.M[0] - 1, I1 = g.M[1] - 1;
                 const int64_t et = (e % I1) * I0 + e / I1;
                 for (int t = 0; t < 6; ++t)
-                    if (t % 3 < nt) a.P2T[t * ss + et] = v[t];
+                    if (t % 3 < nt) {
+                        if (a.p2t_f32)
+                            static_cast<float *>(a.P2T)[t * ss + et] = (float)v[t];
+                        else
+                            static_cast<double *>(a.P2T)[t * ss + et] = v[t];
+                    }
             }
             if (fam == 1 && g.d == 3 && a.P1T) {
                 // e = (k0-1) * I2 + (k2-1)  ->  (k2-1) * I0 + (k0-1)
@@ -877,7 +882,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     // Row k per thread (consecutive k across the lanes): the row invariants
     // are read once and serve every column of the tile; the family-2 values
     // come from the transposed copy [par][t][k1][k0], contiguous in k0 = kx.
-    const double *Pt = d == 3 ? a.sh.P2T + ((kB & 1) ? 3 * ss2 : 0) : nullptr;
+    const T *Pt = d == 3 ? static_cast<const T *>(a.sh.P2T) + ((kB & 1) ? 3 * ss2 : 0) : nullptr;
     for (int k = tid; k <= M; k += NTT) {
         if (k == 0 || k == M) {
             for (int sq = 0; sq < nseq; ++sq) lds_cs(buf, rs, k, sq, cx<T>{(T)0, (T)0});
@@ -908,9 +913,9 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
                     T dh = (T)0;
                     if (six) dh = rs1 * Pc[1] + rs2 * Pc[2] + q1[2] * P1v + q1[3] * P2v;
                     if (d == 3) {
-                        const double *Pe = Pt + (int64_t)(ky - 1) * I0 + (kx - 1);
-                        gt += s1Bt * (T)Pe[0];
-                        if (six) dh += s1Bt * (T)Pe[ss2] + s2Bt * (T)Pe[2 * ss2];
+                        const T *Pe = Pt + (int64_t)(ky - 1) * I0 + (kx - 1);
+                        gt += s1Bt * Pe[0];
+                        if (six) dh += s1Bt * Pe[ss2] + s2Bt * Pe[2 * ss2];
                     }
                     const T iL = recip(Lm);
                     T harm;

@@ -185,7 +185,7 @@ struct ips_plan_s {
     double *D[3] = {nullptr, nullptr, nullptr};
     double *P[3] = {nullptr, nullptr, nullptr}; // parity-packed shell spectra
     double *P1T = nullptr;                      // 3D: transposed family-1 copy
-    double *P2T = nullptr;                      // 3D: transposed family-2 copy
+    void *P2T = nullptr;                        // 3D: transposed family-2 copy (final pass type)
     bool cube = false; // all families share sizes and chunking (batched launches)
     double *C[3] = {nullptr, nullptr, nullptr}; // sixth-order right-hand side on core layers
     DevBuf mem;
@@ -479,7 +479,7 @@ int plan_build(ips_plan p, hipStream_t st)
         }
     }
     if (d == 3 && (rc = p->mem.alloc((void **)&p->P1T, 6 * ssz[1] * sizeof(double)))) return rc;
-    if (d == 3 && (rc = p->mem.alloc((void **)&p->P2T, 6 * ssz[2] * sizeof(double)))) return rc;
+    if (d == 3 && (rc = p->mem.alloc(&p->P2T, 6 * ssz[2] * sizeof(double)))) return rc;
     // uniform families: one launch covers the three (two in 2D) families
     p->cube = true;
     for (int fam = 1; fam < d; ++fam)
@@ -885,6 +885,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     sh.P2T = p->P2T;
     pk.P1T = p->P1T;
     pk.P2T = p->P2T;
+    pk.p2t_f32 = f32;
     pk.withD = 0;
     IPS_HIP(launch_pack(pk, st));
     if (p->order == 6) {
