@@ -123,18 +123,29 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
                 const TK *Kr = static_cast<const TK *>(a.K) + (int64_t)kb * a.Ko;
                 const TK *KA = Kr + t + (int64_t)c0 * a.Kd; // K at column c0 + j
                 const TK *KB = Kr + t + (int64_t)m0 * a.Kd; // K at column m0 - j
+                // per-tile sums in the slot type (FP32 products of FP32 data and
+                // FP32 spectra, W/2 column pairs), added to the FP64 accumulators
+                // once per tile; FP64 slots accumulate directly
+                using TA = TK;
+                TA s10 = 0, s11 = 0, s20 = 0, s21 = 0;
+                if constexpr (std::is_same<TA, double>::value) {
+                    s10 = a10[i];
+                    s11 = a11[i];
+                    s20 = a20[i];
+                    s21 = a21[i];
+                }
                 auto col_pair = [&](int j) {
-                    const double kA = (double)KA[(int64_t)j * a.Kd], kB = (double)KB[-(int64_t)j * a.Kd];
-                    const double ud = (double)r1[j], um = (double)r1[Wh + j];
-                    const double vd = two ? (double)r2[j] : 0.0, vm = two ? (double)r2[Wh + j] : 0.0;
-                    a10[i] = fma(kA, ud, a10[i]);
-                    a10[i] = fma(kB, um, a10[i]);
-                    a11[i] = fma(kB, ud, a11[i]);
-                    a11[i] = fma(kA, um, a11[i]);
-                    a20[i] = fma(kA, vd, a20[i]);
-                    a20[i] = fma(kB, vm, a20[i]);
-                    a21[i] = fma(kB, vd, a21[i]);
-                    a21[i] = fma(kA, vm, a21[i]);
+                    const TA kA = KA[(int64_t)j * a.Kd], kB = KB[-(int64_t)j * a.Kd];
+                    const TA ud = (TA)r1[j], um = (TA)r1[Wh + j];
+                    const TA vd = two ? (TA)r2[j] : (TA)0, vm = two ? (TA)r2[Wh + j] : (TA)0;
+                    s10 = fma(kA, ud, s10);
+                    s10 = fma(kB, um, s10);
+                    s11 = fma(kB, ud, s11);
+                    s11 = fma(kA, um, s11);
+                    s20 = fma(kA, vd, s20);
+                    s20 = fma(kB, vm, s20);
+                    s21 = fma(kB, vd, s21);
+                    s21 = fma(kA, vm, s21);
                 };
                 if (WHC > 0 && nA == WHC) {
 #pragma unroll
@@ -146,13 +157,24 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
                     // C_M (no sine partner) with its own kernel spectrum
                     const TK *MA = Kr + M + (int64_t)c0 * a.Kd, *MB = Kr + M + (int64_t)m0 * a.Kd;
                     for (int j = 0; j < nA; ++j) {
-                        const double kA = (double)MA[(int64_t)j * a.Kd], kB = (double)MB[-(int64_t)j * a.Kd];
-                        const double vd = (double)r2[j], vm = (double)r2[Wh + j];
-                        a20[i] = fma(kA, vd, a20[i]);
-                        a20[i] = fma(kB, vm, a20[i]);
-                        a21[i] = fma(kB, vd, a21[i]);
-                        a21[i] = fma(kA, vm, a21[i]);
+                        const TA kA = MA[(int64_t)j * a.Kd], kB = MB[-(int64_t)j * a.Kd];
+                        const TA vd = (TA)r2[j], vm = (TA)r2[Wh + j];
+                        s20 = fma(kA, vd, s20);
+                        s20 = fma(kB, vm, s20);
+                        s21 = fma(kB, vd, s21);
+                        s21 = fma(kA, vm, s21);
                     }
+                }
+                if constexpr (std::is_same<TA, double>::value) {
+                    a10[i] = s10;
+                    a11[i] = s11;
+                    a20[i] = s20;
+                    a21[i] = s21;
+                } else {
+                    a10[i] += (double)s10;
+                    a11[i] += (double)s11;
+                    a20[i] += (double)s20;
+                    a21[i] += (double)s21;
                 }
             }
         }
