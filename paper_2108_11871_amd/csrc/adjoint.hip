@@ -201,12 +201,67 @@ __global__ __launch_bounds__(NTA) void k_adj_sop(AdjArgs a, const double *F, dou
     }
 }
 
-hipError_t launch_adj_r6(const AdjArgs &a, const double *A, double *F, double *U, hipStream_t st)
+// 3D: the same sums in separable form, one axis x at a time,
+//   T_x = sum_{y != x} c4[x][y] / (h_x^4 h_y^2) D2_y F      (k_adj_d2y)
+//   U  += D4_x T_x                                         (k_adj_d4x)
+// with F and T_x taken as zero off the grid (F is zero outside the core: the
+// extrapolation writes every node), which is the tap set of k_adj_sop.  One
+// wave per grid line along the last axis; the lanes walk it contiguously.
+__global__ __launch_bounds__(NTA) void k_adj_d2y(AdjArgs a, int x, const double *F, double *T)
+{
+    const Geo &g = a.geo;
+    const int n[3] = {(int)a.n[0], (int)a.n[1], (int)a.n[2]};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i0 = blockIdx.y, i1 = blockIdx.x * (NTA / 64) + wave;
+    if (i1 >= n[1]) return;
+    const int64_t st[3] = {(int64_t)n[1] * n[2], n[2], 1};
+    const double hx2 = g.h[x] * g.h[x];
+    for (int i2 = lane; i2 < n[2]; i2 += 64) {
+        const int i[3] = {i0, i1, i2};
+        const int64_t e = i0 * st[0] + i1 * st[1] + i2;
+        double v = 0.0;
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            if (y == x) continue;
+            const double fm = i[y] > 0 ? F[e - st[y]] : 0.0;
+            const double fp = i[y] < n[y] - 1 ? F[e + st[y]] : 0.0;
+            v += g.c4[x][y] / (hx2 * hx2 * g.h[y] * g.h[y]) * (fm - 2.0 * F[e] + fp);
+        }
+        T[e] = v;
+    }
+}
+
+__global__ __launch_bounds__(NTA) void k_adj_d4x(AdjArgs a, int x, const double *T, double *U)
+{
+    const int n[3] = {(int)a.n[0], (int)a.n[1], (int)a.n[2]};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i0 = blockIdx.y, i1 = blockIdx.x * (NTA / 64) + wave;
+    if (i1 >= n[1]) return;
+    const int64_t st[3] = {(int64_t)n[1] * n[2], n[2], 1};
+    const double a4[5] = {1.0, -4.0, 6.0, -4.0, 1.0};
+    for (int i2 = lane; i2 < n[2]; i2 += 64) {
+        const int i[3] = {i0, i1, i2};
+        const int64_t e = i0 * st[0] + i1 * st[1] + i2;
+        double v = 0.0;
+#pragma unroll
+        for (int dx = -2; dx <= 2; ++dx) {
+            const int j = i[x] + dx;
+            if (j >= 0 && j < n[x]) v += a4[dx + 2] * T[e + dx * st[x]];
+        }
+        U[e] = x == 0 ? v : U[e] + v;
+    }
+}
+
+hipError_t launch_adj_r6(const AdjArgs &a, const double *A, double *F, double *U, double *T, hipStream_t st)
 {
     const int nb = 4096;
     if (a.geo.d == 3) {
         hipLaunchKernelGGL(k_adj_etrans<3>, dim3(nb), dim3(NTA), 0, st, a, A, F);
-        hipLaunchKernelGGL(k_adj_sop<3>, dim3(nb), dim3(NTA), 0, st, a, F, U);
+        const dim3 grid((unsigned)((a.n[1] + NTA / 64 - 1) / (NTA / 64)), (unsigned)a.n[0]);
+        for (int x = 0; x < 3; ++x) {
+            hipLaunchKernelGGL(k_adj_d2y, grid, dim3(NTA), 0, st, a, x, F, T);
+            hipLaunchKernelGGL(k_adj_d4x, grid, dim3(NTA), 0, st, a, x, T, U);
+        }
     } else {
         hipLaunchKernelGGL(k_adj_etrans<2>, dim3(nb), dim3(NTA), 0, st, a, A, F);
         hipLaunchKernelGGL(k_adj_sop<2>, dim3(nb), dim3(NTA), 0, st, a, F, U);

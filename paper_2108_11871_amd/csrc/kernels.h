@@ -191,7 +191,8 @@ struct ExpandArgs {
 };
 
 hipError_t launch_adj_spec(const AdjArgs &a, double *X, double *Y, hipStream_t st);
-hipError_t launch_adj_r6(const AdjArgs &a, const double *A, double *F, double *U, hipStream_t st);
+// T: 3D scratch of one grid-shaped array (unused in 2D)
+hipError_t launch_adj_r6(const AdjArgs &a, const double *A, double *F, double *U, double *T, hipStream_t st);
 hipError_t launch_adj_lambda(const AdjArgs &a, const double *w, const double *y1, const double *y2,
                              const double *U, hipStream_t st);
 hipError_t launch_zero_boundary(const AdjArgs &a, double *out, hipStream_t st);

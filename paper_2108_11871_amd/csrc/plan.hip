@@ -1045,6 +1045,8 @@ int adj_alloc(ips_plan p)
         if ((rc = p->mem.alloc((void **)&p->LH[fam], lh * sizeof(double)))) return rc;
         if (d == 3) zmax = std::max(zmax, (size_t)p->I[fam] * p->N[b] * p->I[c]);
     }
+    // order 6 also uses it as one grid-shaped scratch array (adjoint stencil)
+    if (d == 3 && p->order == 6) zmax = std::max(zmax, grid);
     if (d == 3 && (rc = p->mem.alloc((void **)&p->AZ, zmax * sizeof(double)))) return rc;
     p->adj_ready = true;
     return IPS_OK;
@@ -1228,7 +1230,8 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
     if ((rc = vol_inv(p, p->AY, out + off, gst, st))) return rc;
     if ((rc = vol_inv(p, p->AX, p->AX, pst, st))) return rc;
     if (six) {
-        IPS_HIP(launch_adj_r6(aa, p->AX, p->AF, p->AU, st));
+        // AZ (the slice stack of the boundary expansion, used later) is scratch here
+        IPS_HIP(launch_adj_r6(aa, p->AX, p->AF, p->AU, p->AZ, st));
         if ((rc = vol_fwd(p, p->AU + off, gst, p->AX2, st))) return rc;
         IPS_HIP(launch_adj_spec(aa, p->AX2, nullptr, st));
         if ((rc = vol_inv(p, p->AX2, p->AX2, pst, st))) return rc;
