@@ -134,7 +134,8 @@ struct R6Args {
     AxisTabs tab[3];
     const double *P[3]; // packed shell spectra (ShellSpec::P)
     const double *P1T;  // 3D: family 1 transposed (ShellSpec::P1T)
-    double *T[3];       // [10][other axes] per axis: layers 1..5, then M-1..M-5
+    void *T[3];         // [10][other axes] per axis: layers 1..5, then M-1..M-5
+    int t_f32;          // T holds FP32 (mixed modes), else FP64
     int nblk[3];        // filled by the launcher
 };
 
@@ -142,7 +143,8 @@ struct DcorrArgs {
     Geo geo;
     int64_t n[3];
     const double *phi;     // grid with boundary values already written
-    const double *RS[3];   // R_spec on the depth-5 shell layers [10][..][..]
+    const void *RS[3];     // R_spec on the depth-5 shell layers [10][..][..]
+    int rs_f32;            // RS holds FP32, else FP64
     double *C[3];          // R on the core layers 2..5, M-5..M-2: [8][..][..]
     double *D[3];          // outputs [4][..][..]
 };

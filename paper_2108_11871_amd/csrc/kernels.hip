@@ -412,7 +412,8 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
     __syncthreads();
     // group g finishes positions g*64/...: every thread of the block writes
     // its share of the PB positions
-    double *T = a.T[ax];
+    double *Td = static_cast<double *>(a.T[ax]);
+    float *Tf = static_cast<float *>(a.T[ax]);
     for (int i = threadIdx.x; i < PB; i += NT) {
         const int p = blk * PB + i;
         if (p >= npos) continue;
@@ -422,8 +423,14 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
         for (int j = 0; j < 5; ++j) {
             const double od = red[0][j][i] + red[2][j][i];
             const double ev = red[1][j][i] + red[3][j][i];
-            T[j * (int64_t)npos + pout] = g.pref * (od + ev);
-            T[(5 + j) * (int64_t)npos + pout] = g.pref * (od - ev);
+            const double v1 = g.pref * (od + ev), v2 = g.pref * (od - ev);
+            if (a.t_f32) {
+                Tf[j * (int64_t)npos + pout] = (float)v1;
+                Tf[(5 + j) * (int64_t)npos + pout] = (float)v2;
+            } else {
+                Td[j * (int64_t)npos + pout] = v1;
+                Td[(5 + j) * (int64_t)npos + pout] = v2;
+            }
         }
     }
 }
@@ -473,6 +480,12 @@ __device__ __forceinline__ void other_axes(int a, int *ob)
         if (b != a) ob[q++] = b;
 }
 
+// R_spec value (FP32 or FP64 storage)
+__device__ __forceinline__ double rs_at(const DcorrArgs &a, int fam, int64_t o)
+{
+    return a.rs_f32 ? (double)static_cast<const float *>(a.RS[fam])[o] : static_cast<const double *>(a.RS[fam])[o];
+}
+
 template <int D>
 __global__ __launch_bounds__(NT) void k_rcore(DcorrArgs a)
 {
@@ -497,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_rcore(DcorrArgs a)
     for (int b = 0; b < D; ++b) core = core && i[b] >= 2 && i[b] <= g.M[b] - 2;
     double v = 0.0;
     if (core) {
-        v = a.RS[fam][(int64_t)layer5(i[fam], Mf) * ss + e];
+        v = rs_at(a, fam, (int64_t)layer5(i[fam], Mf) * ss + e);
 #pragma unroll
         for (int x = 0; x < D; ++x) {
             if (i[x] != 2 && i[x] != g.M[x] - 2) continue;
@@ -598,7 +611,7 @@ __global__ __launch_bounds__(NT) void k_dcorr(DcorrArgs a)
                 R += w0 * w1 * v;
             }
         }
-        out = R - a.RS[fam][(int64_t)layer5(i[fam], Mf) * ss + e];
+        out = R - rs_at(a, fam, (int64_t)layer5(i[fam], Mf) * ss + e);
     }
     a.D[fam][(int64_t)jj * ss + e] = out;
 }

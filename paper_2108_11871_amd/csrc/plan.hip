@@ -182,6 +182,7 @@ struct ips_plan_s {
     double *F[3] = {nullptr, nullptr, nullptr};
     double *G[3] = {nullptr, nullptr, nullptr};
     double *T[3] = {nullptr, nullptr, nullptr};
+    float *Tf[3] = {nullptr, nullptr, nullptr}; // the same buffer as FP32 (mixed modes)
     double *D[3] = {nullptr, nullptr, nullptr};
     double *P[3] = {nullptr, nullptr, nullptr}; // parity-packed shell spectra
     double *P1T = nullptr;                      // 3D: transposed family-1 copy
@@ -304,7 +305,7 @@ int run_pass(ips_plan p, PassArgs a, const FftDesc &fd, const cx<double> *tw, bo
 
 // Forward raw DST (IN_ZPAD -> S rows) or inverse (IN_SPECS -> real rows) of
 // the last two (or one) axes of a stack of shell layers [nl][I_b][I_c].
-int shell_dst(ips_plan p, double *buf, int nl, int fam, bool inverse, hipStream_t st)
+int shell_dst(ips_plan p, void *buf, int nl, int fam, bool inverse, hipStream_t st, bool f32 = false)
 {
     int ax[2], na = 0;
     for (int b = 0; b < p->d; ++b)
@@ -326,7 +327,7 @@ int shell_dst(ips_plan p, double *buf, int nl, int fam, bool inverse, hipStream_
         a.out_r0 = inverse ? 1 : p->M[axis] + 1;
         a.out_nrows = p->I[axis];
         a.scale = inverse ? 0.5 : 1.0;
-        return run_pass(p, a, p->fd[axis], p->tw[axis], false, false, st);
+        return run_pass(p, a, p->fd[axis], p->tw[axis], f32, f32, st);
     };
     int rc;
     if (na == 2) {
@@ -342,11 +343,13 @@ int shell_dst(ips_plan p, double *buf, int nl, int fam, bool inverse, hipStream_
 
 // Shell layer transforms of all families: one launch per direction when the
 // families are uniform (contiguous buffers of identical shape).
-int shell_dst_all(ips_plan p, double *const *arr, int nl, bool inverse, hipStream_t st)
+template <typename TS>
+int shell_dst_all(ips_plan p, TS *const *arr, int nl, bool inverse, hipStream_t st)
 {
-    if (p->cube) return shell_dst(p, arr[0], nl * p->d, 0, inverse, st);
+    constexpr bool f32 = sizeof(TS) == 4;
+    if (p->cube) return shell_dst(p, arr[0], nl * p->d, 0, inverse, st, f32);
     for (int fam = 0; fam < p->d; ++fam) {
-        int rc = shell_dst(p, arr[fam], nl, fam, inverse, st);
+        int rc = shell_dst(p, arr[fam], nl, fam, inverse, st, f32);
         if (rc) return rc;
     }
     return IPS_OK;
@@ -470,7 +473,10 @@ int plan_build(ips_plan p, hipStream_t st)
             p->F[fam] = bf + of;
             p->G[fam] = bg + 2 * os;
             p->P[fam] = bpk + 6 * os;
-            if (bt) p->T[fam] = bt + 10 * os;
+            if (bt) {
+                p->T[fam] = bt + 10 * os;
+                p->Tf[fam] = reinterpret_cast<float *>(bt) + 10 * os;
+            }
             if (bd) p->D[fam] = bd + 4 * os;
             if (bc) p->C[fam] = bc + 8 * os;
             op += fsz[fam] * p->nch[fam];
@@ -896,18 +902,21 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             for (int q = 0; q < d; ++q) {
                 a.tab[q] = p->tab[q];
                 a.P[q] = p->P[q];
-                a.T[q] = p->T[q];
+                a.T[q] = f32 ? (void *)p->Tf[q] : (void *)p->T[q];
             }
+            a.t_f32 = f32;
             a.P1T = p->P1T;
             IPS_HIP(launch_r6t(a, st));
         }
-        if ((rc = shell_dst_all(p, p->T, 10, true, st))) return rc;
+        // mixed modes: the R_spec layers and their inverse transforms in FP32
+        if ((rc = f32 ? shell_dst_all(p, p->Tf, 10, true, st) : shell_dst_all(p, p->T, 10, true, st))) return rc;
         DcorrArgs a{};
         a.geo = p->geo;
         for (int q = 0; q < 3; ++q) a.n[q] = q < d ? n[q] : 1;
         a.phi = phi;
+        a.rs_f32 = f32;
         for (int fam = 0; fam < d; ++fam) {
-            a.RS[fam] = p->T[fam];
+            a.RS[fam] = f32 ? (const void *)p->Tf[fam] : (const void *)p->T[fam];
             a.C[fam] = p->C[fam];
             a.D[fam] = p->D[fam];
         }
