@@ -22,6 +22,7 @@
 //                     + K_hat(M - 1 - s) . FFT2(lambda_faceM) ].
 #include <hip/hip_runtime.h>
 
+#include "common.h"
 #include "kernels.h"
 
 namespace ips {
@@ -477,6 +478,7 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t st)
     const unsigned nblk = (unsigned)ncb * (unsigned)a.nbatch;
     const int work = (a.W / 2) * a.fd.N;
     if (nblk == 0) return hipSuccess;
+    if (!tile_strides_ok(a.fd.M, a.ors, a.ncols, a.ocs)) return hipErrorInvalidValue;
     if (a.fd.N > 2048) {
         // long transforms: one complex sequence per tile, global twiddles
         const size_t lds = (size_t)a.fd.N * a.W * sizeof(double);

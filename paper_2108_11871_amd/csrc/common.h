@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <stdint.h>
 
 #include "fft_tile.h"
 
@@ -11,6 +12,15 @@ namespace ips {
 constexpr int NT = 256;
 
 inline bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// The tile helpers address a tile with 32-bit offsets r * rsd + c * csd built
+// from 24-bit multiplies (toff): strides below 2^23, extent below 2^31.
+inline bool tile_strides_ok(int64_t nrows, int64_t rsd, int64_t ncols, int64_t csd)
+{
+    const int64_t lim24 = (int64_t)1 << 23, lim31 = ((int64_t)1 << 31) - 1;
+    const int64_t ar = rsd < 0 ? -rsd : rsd, ac = csd < 0 ? -csd : csd;
+    return ar < lim24 && ac < lim24 && nrows < lim24 && ncols < lim24 && nrows * ar + ncols * ac < lim31;
+}
 
 // Raise a kernel's dynamic LDS limit above 64 KiB when a launch needs it.
 void set_lds(const void *fn, size_t bytes);

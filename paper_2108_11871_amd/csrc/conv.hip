@@ -279,6 +279,7 @@ hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStre
     const int work = (a.W / 2) * a.fd.N;
     if (!big_fft(a.fd.N) && (work > 16 * NT || a.fd.N > 8 * NT)) return hipErrorInvalidValue;
     if (a.W < 2 || a.cols_per_chunk < 1) return hipErrorInvalidValue;
+    if (!tile_strides_ok(a.nrows_in, a.irs, a.ncols, a.ics)) return hipErrorInvalidValue;
     const bool wb = a.Bout != nullptr;
     if (!f32) {
         if (in_f32) return hipErrorInvalidValue;

@@ -433,6 +433,14 @@ __device__ __forceinline__ void pre_even(T *buf, int rs, int lgW, int M, int tid
     __syncthreads();
 }
 
+// Element offset r * rsd + c * csd of a tile in 32-bit arithmetic with
+// 24-bit multiplies: the launchers check that strides stay below 2^23 and a
+// tile spans less than 2^31 elements (true for every supported grid).
+__device__ __forceinline__ int toff(int r, int64_t rsd, int c, int64_t csd)
+{
+    return __mul24(r, (int)rsd) + __mul24(c, (int)csd);
+}
+
 template <typename T, int NT>
 __device__ __forceinline__ void zero_rows(T *buf, int rs, int lgW, int r0, int r1, int tid = -1)
 {
@@ -476,7 +484,7 @@ __device__ __forceinline__ void tile_load(T *buf, int rs, int row0, const TI *sr
         for (int e = tid; e < tot; e += NT) {
             const int c = e & cm, r = e >> lgW;
             T v = (T)0;
-            if (c < ncols) v = (T)src[r * rsd + c * csd];
+            if (c < ncols) v = (T)src[toff(r, rsd, c, csd)];
             buf[(row0 + r) * rs + c] = v;
         }
     }
@@ -522,7 +530,7 @@ __device__ void tile_load_pair(T *buf, int rs, int row0, const TI *src, int nrow
         const int c = e & cm, r = e >> lgW;
         const int sc = src_col(c);
         T v = (T)0;
-        if (sc >= 0) v = (T)src[r * rsd + sc * csd];
+        if (sc >= 0) v = (T)src[toff(r, rsd, sc, csd)];
         buf[(row0 + r) * rs + c] = v;
     }
 }
@@ -585,7 +593,7 @@ __device__ __forceinline__ void fetch_pair(TI (&v)[EPT], const TI *src, int nrow
         const int e = tid + k * NT;
         const int c = e & (WC - 1), r = e / WC;
         const int sc = src_col(c);
-        v[k] = (sc >= 0 && r < nrows) ? src[r * rsd + (int64_t)sc * csd] : (TI)0;
+        v[k] = (sc >= 0 && r < nrows) ? src[toff(r, rsd, sc, csd)] : (TI)0;
     }
 }
 
@@ -658,7 +666,7 @@ __device__ __forceinline__ void tile_load_sum(T *buf, int rs, int row0, const TI
     for (int e = tid; e < tot; e += NT) {
         const int c = e & cm, r = e >> lgW;
         T v = (T)0;
-        if (c < ncols) v = sum_strided<T>(src + r * rsd + c * csd, nsum, sstride);
+        if (c < ncols) v = sum_strided<T>(src + toff(r, rsd, c, csd), nsum, sstride);
         buf[(row0 + r) * rs + c] = v;
     }
 }
@@ -681,7 +689,7 @@ __device__ __forceinline__ void tile_store(const T *buf, int rs, int row0, TO *d
         const int tot = nrows << lgW;
         for (int e = tid; e < tot; e += NT) {
             const int c = e & cm, r = e >> lgW;
-            if (c < ncols) dst[r * rsd + c * csd] = (TO)(scale * buf[(row0 + r) * rs + c]);
+            if (c < ncols) dst[toff(r, rsd, c, csd)] = (TO)(scale * buf[(row0 + r) * rs + c]);
         }
     }
 }
@@ -703,7 +711,7 @@ __device__ __forceinline__ void tile_store_acc(const T *buf, int rs, int row0, T
         const int tot = nrows << lgW;
         for (int e = tid; e < tot; e += NT) {
             const int c = e & cm, r = e >> lgW;
-            if (c < ncols) dst[r * rsd + c * csd] += (TO)(scale * buf[(row0 + r) * rs + c]);
+            if (c < ncols) dst[toff(r, rsd, c, csd)] += (TO)(scale * buf[(row0 + r) * rs + c]);
         }
     }
 }

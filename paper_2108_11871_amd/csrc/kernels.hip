@@ -1069,6 +1069,7 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st)
     if (big_fft(a.fd.N) && (a.geo.d != 2 || !a.rowtab || a.W != 2 || work > 8 * NTB))
         return hipErrorInvalidValue;
     if (!big_fft(a.fd.N) && work > 32 * NT) return hipErrorInvalidValue;
+    if (!tile_strides_ok(a.nrows_in, a.irs, a.ncols, a.ics)) return hipErrorInvalidValue;
     if (a.mixed)
         launch_final_t<float>(a, nblk, work, st);
     else

@@ -251,10 +251,21 @@ static hipError_t launch_pass_t(const PassArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_pass_in32(const PassArgs &a, hipStream_t st) { return launch_pass_t<double, float, double>(a, st); }
+static bool pass_strides_ok(const PassArgs &a)
+{
+    // loads address rows [0, nrows_in) of the input, stores rows [0, out_nrows) of the output
+    return tile_strides_ok(a.nrows_in, a.irs, a.ncols, a.ics) && tile_strides_ok(a.out_nrows, a.ors, a.ncols, a.ocs);
+}
+
+hipError_t launch_pass_in32(const PassArgs &a, hipStream_t st)
+{
+    if (!pass_strides_ok(a)) return hipErrorInvalidValue;
+    return launch_pass_t<double, float, double>(a, st);
+}
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st)
 {
+    if (!pass_strides_ok(a)) return hipErrorInvalidValue;
     if (!in_f32 && !out_f32) return launch_pass_t<double, double, double>(a, st);
     if (in_f32 && out_f32) return launch_pass_t<float, float, float>(a, st);
     if (!in_f32 && out_f32) return launch_pass_t<float, double, float>(a, st);
