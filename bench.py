@@ -17,7 +17,9 @@ Prints ONE JSON line.  Besides the contract fields it carries
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample;
   modes         per-precision throughput, error vs FP64 and stage times;
   adjoint       time of one FP64 adjoint solve on the same grid;
-  batched       64 uneven boxes per batch, graph replay against eager launches.
+  batched       64 uneven boxes per batch, graph replay against eager launches;
+  extended      the same solve through an extended plan (8 nodes added on every
+                side, then 5-smooth panel counts), caller nodes per second.
 
 Profiling helpers (same file, so that every profile is taken on committed code):
   --copy-calibration MIB   after the timed work, one plain device copy of MIB MiB
@@ -327,6 +329,29 @@ def time_adjoint(api, torch, rho_d, h, steps, warmup):
     return {"ms_per_step": ms, "mpoints_per_s": rho_d.numel() / (ms * 1e-3) / 1e6, "precision": "fp64"}
 
 
+def time_extended(api, torch, rho_d, h, mode, margin, steps, warmup):
+    """The same workload through an extended plan (margin nodes on every side,
+    then 5-smooth panel counts): caller nodes per second."""
+    plan = api.Plan(tuple(rho_d.shape), h, order=6, precision=mode, margin=margin)
+    ne, _ = api.extension(tuple(rho_d.shape), margin)
+    out = torch.empty_like(rho_d)
+    for _ in range(max(warmup, 1)):
+        plan(rho_d, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan(rho_d, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.close()
+    return {"margin": margin, "grid_ext": list(ne), "precision": mode, "ms_per_step": ms,
+            "mpoints_per_s": rho_d.numel() / (ms * 1e-3) / 1e6}
+
+
 def load_traffic(kernel_stage: str, n: int, mode: str):
     """HBM bytes per launch measured by rocprofv3 counters, if taken on these sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -473,6 +498,8 @@ def main():
     if not args.no_extras:
         out["adjoint"] = time_adjoint(api, torch, rho_d, h, max(args.steps // 2, 1), args.warmup)
         out["batched"] = time_batched(api, torch, max(args.steps // 2, 1), args.warmup)
+        out["extended"] = time_extended(api, torch, rho_d, h, out["config"]["precision"], 8,
+                                        max(args.steps // 2, 1), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.seed)
     print(json.dumps(out), flush=True)

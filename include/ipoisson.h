@@ -64,16 +64,19 @@ typedef enum {
     IPS_E_WORKSPACE = -5    /* caller-supplied workspace too small */
 } ips_status;
 
-/* Arithmetic used by the transforms.  Input and output stay FP64; the kernel
- * spectra, the accumulation of the boundary sums over slices, the inverse
- * transforms of the face sums, and every step of the harmonic correction
- * (g~, deferred-correction differences, extrapolation, spectral combination)
- * stay FP64 in every mode. */
+/* Arithmetic used by the transforms.  Input and output stay FP64.  In every
+ * mode the kernel spectra, the accumulation of the boundary sums over chunks
+ * of slices, the inverse transforms of the face sums, g~, the core stencils
+ * and the extrapolation of the sixth-order step and the spectral symbols are
+ * FP64.  The mixed modes store the sine-space volume in FP32 and combine the
+ * spectrum in FP32 from those FP64 parts, and keep the sixth-order sine-series
+ * values on the shell layers in FP32. */
 typedef enum {
     IPS_FP64 = 0,              /* everything in FP64 */
     IPS_MIXED_FP32 = 1,        /* sine-transform passes of phi_star + phi_H in FP32 */
     IPS_MIXED_FP32_SLICES = 2  /* as 1, and the slice transforms of rho that feed the
-                                  boundary sums in FP32 (accumulated in FP64) */
+                                  boundary sums in FP32 (products summed per tile in
+                                  FP32, accumulated in FP64, chunk sums stored in FP32) */
 } ips_precision;
 
 /*
@@ -106,6 +109,37 @@ int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int
 
 /* Bytes of device memory held by the plan (workspace plus tables). */
 int ips_plan_workspace_size(ips_plan p, size_t *bytes);
+
+/*
+ * ips_extension -- the enlarged grid of an automatically extended solve (host
+ * only, no device work).  The method assumes that the support of rho lies at
+ * least a distance sigma inside the box and that each panel count suits the
+ * FFT; both are met by enlarging the box (Section 2, the assumptions on the
+ * computational domain).  For each axis a, with the caller's mesh width kept:
+ *   n_ext[a]  = the smallest n' >= n[a] + 2 margin[a] whose panel count n' - 1
+ *               has no prime factor above 5;
+ *   offset[a] = index of the caller's node 0 in the extended grid
+ *               (margin[a] plus half the rounding, rounded down).
+ * margin[a] = ceil(sigma / h[a]) nodes gives the distance sigma.
+ * Errors: IPS_E_INVALID_ARG for d outside 1..3, n[a] < 3, margin[a] < 0 or any
+ * NULL pointer.
+ */
+int ips_extension(int d, const int64_t *n, const int64_t *margin, int64_t *n_ext, int64_t *offset);
+
+/*
+ * ips_plan_create_extended -- a plan for the caller's grid n that solves on
+ * the extended grid of ips_extension.  ips_execute on it places rho (all of
+ * its nodes, boundary nodes included: they are interior nodes of the extended
+ * box) into a zero extended array, solves there, and returns phi at the
+ * caller's nodes; ips_execute_adjoint applies the transpose of that map
+ * (embed, adjoint solve, restrict).  Arguments as ips_plan_create plus the d
+ * margins (nodes added on each side before the rounding).  The two extended
+ * arrays are part of the plan's workspace.  Batches do not take extended
+ * plans.  Errors as ips_plan_create (the extended grid must meet its size
+ * limits) and as ips_extension.
+ */
+int ips_plan_create_extended(ips_plan *out, int d, const int64_t *n, const double *h, int order,
+                             int precision, unsigned flags, const int64_t *margin);
 
 /*
  * ips_execute -- enqueue one solve on `stream` (a hipStream_t, NULL = null

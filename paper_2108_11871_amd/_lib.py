@@ -42,6 +42,11 @@ SIGNATURES = {
         [ctypes.POINTER(_vp), ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_uint],
     ),
     "ips_plan_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ips_extension": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, _i64p, _i64p]),
+    "ips_plan_create_extended": (
+        ctypes.c_int,
+        [ctypes.POINTER(_vp), ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _i64p],
+    ),
     "ips_execute": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ips_execute_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ips_plan_destroy": (ctypes.c_int, [_vp]),

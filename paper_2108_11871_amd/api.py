@@ -38,11 +38,30 @@ def _check_grid(t: torch.Tensor):
         raise ValueError("rho must have 1, 2 or 3 dimensions")
 
 
+def extension(shape: Sequence[int], margin):
+    """(extended shape, offset of the caller's node 0) of an extended solve
+    (ips_extension): each axis grows by 2 margin nodes, then to the next panel
+    count with no prime factor above 5."""
+    shape = tuple(int(v) for v in shape)
+    d = len(shape)
+    mm = list(margin) if hasattr(margin, "__len__") else [int(margin)] * d
+    if len(mm) != d:
+        raise ValueError("margin needs one entry per axis")
+    ne = (ctypes.c_int64 * d)()
+    off = (ctypes.c_int64 * d)()
+    check(lib().ips_extension(d, i64_array(shape), i64_array(mm), ne, off))
+    return tuple(ne), tuple(off)
+
+
 class Plan:
     """A reusable solve of one grid geometry (ips_plan_create / ips_execute)."""
 
     def __init__(self, shape: Sequence[int], h, order: int = 6, precision: str = "fp64",
-                 device=None, timing: bool = False, adjoint: bool = False, autotune: bool = False):
+                 device=None, timing: bool = False, adjoint: bool = False, autotune: bool = False,
+                 margin=None):
+        """margin: None, or nodes added on each side of every axis (an int or one
+        per axis); the solve then runs on the enlarged grid of `extension` and
+        returns phi at the caller's nodes (ips_plan_create_extended)."""
         self.shape = tuple(int(v) for v in shape)
         d = len(self.shape)
         hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
@@ -53,12 +72,21 @@ class Plan:
         self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         handle = ctypes.c_void_p()
+        flags = ((IPS_FLAG_STAGE_TIMING if timing else 0) | (IPS_FLAG_ADJOINT if adjoint else 0)
+                 | (IPS_FLAG_AUTOTUNE if autotune else 0))
+        self.margin = None
         with torch.cuda.device(self.device):
-            check(lib().ips_plan_create(ctypes.byref(handle), d, i64_array(self.shape),
-                                        f64_array(self.h), self.order, PRECISIONS[precision],
-                                        (IPS_FLAG_STAGE_TIMING if timing else 0)
-                                        | (IPS_FLAG_ADJOINT if adjoint else 0)
-                                        | (IPS_FLAG_AUTOTUNE if autotune else 0)))
+            if margin is None:
+                check(lib().ips_plan_create(ctypes.byref(handle), d, i64_array(self.shape),
+                                            f64_array(self.h), self.order, PRECISIONS[precision], flags))
+            else:
+                mm = list(margin) if hasattr(margin, "__len__") else [int(margin)] * d
+                if len(mm) != d:
+                    raise ValueError("margin needs one entry per axis")
+                self.margin = tuple(int(v) for v in mm)
+                check(lib().ips_plan_create_extended(ctypes.byref(handle), d, i64_array(self.shape),
+                                                     f64_array(self.h), self.order, PRECISIONS[precision],
+                                                     flags, i64_array(self.margin)))
         self._h = handle
 
     @property

@@ -216,6 +216,10 @@ hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);
 hipError_t launch_pack(const PackArgs &a, hipStream_t st);
 hipError_t launch_r6t(R6Args a, hipStream_t st);
 hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st);
+// Caller's block n at offset off inside the extended grid ne: embed (extract =
+// false: dst is extended) or restrict (extract = true: src is extended).
+hipError_t launch_embed(const double *src, double *dst, int d, const int64_t *n, const int64_t *ne,
+                        const int64_t *off, bool extract, hipStream_t st);
 // Row table of the final pass (if a.rowtab): once per solve, before launch_final.
 hipError_t launch_final_rows(const FinalArgs &a, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);

@@ -70,6 +70,46 @@ int resident_blocks(const void *fn, int nthreads, size_t lds)
 }
 
 // ---------------------------------------------------------------------------
+// Domain extension: the caller's block of n nodes at offset off inside the
+// extended grid ne (one block row of threads per grid line of the last axis).
+//   extract = false: ext[off + i] = a[i]    (embed)
+//   extract = true : a[i] = ext[off + i]    (restrict; a is the output)
+// ---------------------------------------------------------------------------
+__global__ void k_embed(const double *src, double *dst, int64_t line0, int64_t n1, int64_t n2, int64_t e1,
+                        int64_t e2, int64_t o0, int64_t o1, int64_t o2, int extract)
+{
+    const int64_t line = line0 + blockIdx.y; // i0 * n1 + i1
+    const int64_t i0 = line / n1, i1 = line % n1;
+    const int64_t ebase = ((i0 + o0) * e1 + (i1 + o1)) * e2 + o2, cbase = line * n2;
+    for (int64_t i2 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i2 < n2; i2 += (int64_t)gridDim.x * blockDim.x) {
+        if (extract)
+            dst[cbase + i2] = src[ebase + i2];
+        else
+            dst[ebase + i2] = src[cbase + i2];
+    }
+}
+
+hipError_t launch_embed(const double *src, double *dst, int d, const int64_t *n, const int64_t *ne,
+                        const int64_t *off, bool extract, hipStream_t st)
+{
+    int64_t c[3] = {1, 1, 1}, e[3] = {1, 1, 1}, o[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) {
+        c[3 - d + a] = n[a];
+        e[3 - d + a] = ne[a];
+        o[3 - d + a] = off[a];
+    }
+    const int64_t lines = c[0] * c[1];
+    const unsigned gx = (unsigned)std::min<int64_t>((c[2] + NT - 1) / NT, 64);
+    // grid.y covers at most 65535 lines per launch
+    for (int64_t l0 = 0; l0 < lines; l0 += 65535) {
+        const unsigned nl = (unsigned)std::min<int64_t>(65535, lines - l0);
+        hipLaunchKernelGGL(k_embed, dim3(gx, nl), dim3(NT), 0, st, src, dst, l0, c[1], c[2], e[1], e[2], o[0], o[1],
+                           o[2], extract ? 1 : 0);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Small element-wise kernels
 // ---------------------------------------------------------------------------
 __global__ void k_reduce(const double *part, double *out, int64_t len, int nchunk)

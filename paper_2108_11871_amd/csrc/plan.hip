@@ -160,6 +160,11 @@ void kaxes(int d, int fam, int &b, int &c)
 struct ips_plan_s {
     int d = 0;
     int64_t n[3] = {1, 1, 1};
+    // automatic domain extension: the solve runs on `inner` (the extended
+    // grid), the caller's grid sits at ext_off inside it
+    ips_plan inner = nullptr;
+    int64_t ext_off[3] = {0, 0, 0};
+    double *ext_in = nullptr, *ext_out = nullptr; // extended arrays (ext_in zero outside the caller's block)
     double h[3] = {1, 1, 1};
     int order = 6, precision = 0;
     int device = 0;
@@ -1508,6 +1513,34 @@ int autotune_work(int d, const int64_t *n, const double *h, int order, int preci
     return IPS_OK;
 }
 
+// panel counts whose prime factors are 2, 3 and 5 (the fast FFT radices)
+bool smooth235(int64_t m)
+{
+    if (m < 1) return false;
+    for (int64_t q : {2, 3, 5})
+        while (m % q == 0) m /= q;
+    return m == 1;
+}
+
+// Extended plan: embed the caller's array in the zero extended array, solve
+// (or apply the adjoint) there, restrict the result to the caller's nodes.
+int execute_extended(ips_plan p, const double *in, double *out, hipStream_t st, bool adjoint)
+{
+    ips_plan q = p->inner;
+    IPS_HIP(launch_embed(in, p->ext_in, p->d, p->n, q->n, p->ext_off, false, st));
+    int rc;
+    if (adjoint) {
+        if ((rc = adj_alloc(q))) return rc;
+        STAGE(IPS_STAGE_ADJOINT);
+        rc = execute_adjoint(q, p->ext_in, p->ext_out, st);
+    } else {
+        rc = execute(q, p->ext_in, p->ext_out, st);
+    }
+    if (rc) return rc;
+    IPS_HIP(launch_embed(p->ext_out, out, p->d, p->n, q->n, p->ext_off, true, st));
+    return IPS_OK;
+}
+
 extern "C" {
 
 const char *ips_status_string(int status)
@@ -1549,7 +1582,68 @@ int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int
 int ips_plan_workspace_size(ips_plan p, size_t *bytes)
 {
     if (!p || !bytes) return fail(IPS_E_INVALID_ARG, "NULL argument");
-    *bytes = p->mem.bytes;
+    *bytes = p->mem.bytes + (p->inner ? p->inner->mem.bytes : 0);
+    return IPS_OK;
+}
+
+int ips_extension(int d, const int64_t *n, const int64_t *margin, int64_t *n_ext, int64_t *offset)
+{
+    if (!n || !margin || !n_ext || !offset) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
+    for (int a = 0; a < d; ++a)
+        if (n[a] < 3 || margin[a] < 0 || margin[a] > (int64_t)1 << 24 || n[a] > (int64_t)1 << 24)
+            return fail(IPS_E_INVALID_ARG, "n[a] must be >= 3 and margin[a] >= 0");
+    for (int a = 0; a < d; ++a) {
+        const int64_t need = n[a] + 2 * margin[a];
+        int64_t ne = need;
+        while (!smooth235(ne - 1)) ++ne;
+        n_ext[a] = ne;
+        offset[a] = margin[a] + (ne - need) / 2;
+    }
+    return IPS_OK;
+}
+
+int ips_plan_create_extended(ips_plan *out, int d, const int64_t *n, const double *h, int order,
+                             int precision, unsigned flags, const int64_t *margin)
+{
+    if (!out) return fail(IPS_E_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    int64_t ne[3] = {1, 1, 1}, off[3] = {0, 0, 0};
+    int rc = ips_extension(d, n, margin, ne, off);
+    if (rc) return rc;
+    // the caller's grid: h and the flags are checked with it, the order
+    // constraint applies to the extended grid
+    if (!h) return fail(IPS_E_INVALID_ARG, "h must not be NULL");
+    ips_plan inner = nullptr;
+    rc = ips_plan_create(&inner, d, ne, h, order, precision, flags);
+    if (rc) return rc;
+    ips_plan p = new (std::nothrow) ips_plan_s();
+    if (!p) {
+        ips_plan_destroy(inner);
+        return fail(IPS_E_NO_MEMORY, "host allocation failed");
+    }
+    p->d = d;
+    p->order = order;
+    p->precision = precision;
+    p->device = inner->device;
+    p->inner = inner;
+    size_t cnt = 1;
+    for (int a = 0; a < d; ++a) {
+        p->n[a] = n[a];
+        p->h[a] = h[a];
+        p->ext_off[a] = off[a];
+        cnt *= (size_t)ne[a];
+    }
+    if ((rc = p->mem.alloc((void **)&p->ext_in, cnt * sizeof(double))) ||
+        (rc = p->mem.alloc((void **)&p->ext_out, cnt * sizeof(double)))) {
+        ips_plan_destroy(p); // also destroys the inner plan
+        return rc;
+    }
+    if (hipMemset(p->ext_in, 0, cnt * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        ips_plan_destroy(p);
+        return fail(IPS_E_DEVICE, "clearing the extended input failed");
+    }
+    *out = p;
     return IPS_OK;
 }
 
@@ -1565,6 +1659,7 @@ int ips_execute(ips_plan p, const double *rho, double *phi, void *stream)
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
         return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
+    if (p->inner) return execute_extended(p, rho, phi, static_cast<hipStream_t>(stream), false);
     return execute(p, rho, phi, static_cast<hipStream_t>(stream));
 }
 
@@ -1580,6 +1675,7 @@ int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
         return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
+    if (p->inner) return execute_extended(p, phi_bar, rho_bar, static_cast<hipStream_t>(stream), true);
     int rc = adj_alloc(p);
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1600,6 +1696,7 @@ int ips_plan_stage_time(ips_plan p, int stage, double *ms_total, int64_t *calls)
 {
     if (!p || !ms_total || !calls) return fail(IPS_E_INVALID_ARG, "NULL argument");
     if (stage < 0 || stage >= IPS_STAGE_COUNT) return fail(IPS_E_INVALID_ARG, "bad stage");
+    if (p->inner) return ips_plan_stage_time(p->inner, stage, ms_total, calls);
     int rc = flush_timing(p);
     if (rc) return rc;
     *ms_total = p->stage_ms[stage];
@@ -1610,6 +1707,7 @@ int ips_plan_stage_time(ips_plan p, int stage, double *ms_total, int64_t *calls)
 int ips_plan_reset_stage_times(ips_plan p)
 {
     if (!p) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    if (p->inner) return ips_plan_reset_stage_times(p->inner);
     int rc = flush_timing(p);
     if (rc) return rc;
     for (int i = 0; i < IPS_STAGE_COUNT; ++i) {
@@ -1622,6 +1720,10 @@ int ips_plan_reset_stage_times(ips_plan p)
 int ips_plan_destroy(ips_plan p)
 {
     if (!p) return IPS_OK;
+    if (p->inner) {
+        ips_plan_destroy(p->inner);
+        p->inner = nullptr;
+    }
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         for (auto it = g_cache.begin(); it != g_cache.end(); ++it)

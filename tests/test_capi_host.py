@@ -99,3 +99,40 @@ def test_last_error_detail_truncates():
     buf = ctypes.create_string_buffer(5)
     assert L.ips_last_error_detail(buf, 5) == 0
     assert len(buf.value) == 4
+
+
+def _smooth235(m):
+    for q in (2, 3, 5):
+        while m % q == 0:
+            m //= q
+    return m == 1
+
+
+@pytest.mark.parametrize("n,margin", [((3,), (0,)), ((257, 257, 257), (8, 8, 8)), ((65, 80), (3, 0)),
+                                      ((97, 33, 41), (5, 1, 12)), ((1025,), (7,)), ((11, 12, 13), (0, 0, 0))])
+def test_extension_grid(n, margin):
+    """ips_extension: every axis gets at least 2 margin nodes more, then the
+    smallest count whose panel count has no prime factor above 5; the caller's
+    block sits margin nodes plus half the rounding from the low end."""
+    L = _lib.lib()
+    d = len(n)
+    ne = (ctypes.c_int64 * d)()
+    off = (ctypes.c_int64 * d)()
+    assert L.ips_extension(d, _lib.i64_array(n), _lib.i64_array(margin), ne, off) == 0
+    for a in range(d):
+        need = n[a] + 2 * margin[a]
+        assert ne[a] >= need and _smooth235(ne[a] - 1)
+        assert all(not _smooth235(m - 1) for m in range(need, ne[a]))
+        assert off[a] == margin[a] + (ne[a] - need) // 2
+        assert off[a] >= margin[a] and ne[a] - off[a] - n[a] >= margin[a]
+
+
+def test_extension_rejects_invalid_arguments():
+    """-1 is IPS_E_INVALID_ARG."""
+    L = _lib.lib()
+    ne = (ctypes.c_int64 * 3)()
+    off = (ctypes.c_int64 * 3)()
+    assert L.ips_extension(0, _lib.i64_array((5,)), _lib.i64_array((1,)), ne, off) == -1
+    assert L.ips_extension(1, _lib.i64_array((2,)), _lib.i64_array((1,)), ne, off) == -1
+    assert L.ips_extension(1, _lib.i64_array((9,)), _lib.i64_array((-1,)), ne, off) == -1
+    assert L.ips_extension(1, _lib.i64_array((9,)), None, ne, off) == -1
