@@ -210,8 +210,9 @@ static void launch_cc_k(const CcArgs &a, int nchunk, hipStream_t st)
                        st, a, nchunk);
 }
 
-// The default widths (W = 16, 8, 4 for 2M = 256, 512, 1024) get a fully
-// unrolled contraction and the register prefetch of the next tile.
+// Compile-time widths (W = 16, 8 for 2M <= 512, W = 4 up to 1024: the
+// default widths of the power-of-two lengths and of the lengths near them)
+// get a fully unrolled contraction and the register prefetch of the next tile.
 template <int WHC, int MAXE, int NTT = NT>
 static bool prefetch_fits(const CcArgs &a)
 {
@@ -223,21 +224,27 @@ static void launch_cc_m(const CcArgs &a, int nchunk, hipStream_t st)
 {
     const bool p2 = is_pow2(a.fd.N);
     if (a.fd.N <= 2 * NT) {
-        if (!p2)
-            launch_cc_k<T, TI, MAXE, WB, false, 2>(a, nchunk, st);
-        else if (prefetch_fits<8, MAXE>(a))
+        if (p2 && prefetch_fits<8, MAXE>(a))
             launch_cc_k<T, TI, MAXE, WB, true, 2, NT, 8>(a, nchunk, st);
-        else if (prefetch_fits<4, MAXE>(a))
+        else if (p2 && prefetch_fits<4, MAXE>(a))
             launch_cc_k<T, TI, MAXE, WB, true, 2, NT, 4>(a, nchunk, st);
-        else
+        else if (p2)
             launch_cc_k<T, TI, MAXE, WB, true, 2>(a, nchunk, st);
-    } else if (a.fd.N <= 4 * NT) {
-        if (!p2)
-            launch_cc_k<T, TI, MAXE, WB, false, 4>(a, nchunk, st);
-        else if (prefetch_fits<2, MAXE>(a))
-            launch_cc_k<T, TI, MAXE, WB, true, 4, NT, 2>(a, nchunk, st);
+        else if (prefetch_fits<8, MAXE>(a))
+            launch_cc_k<T, TI, MAXE, WB, false, 2, NT, 8>(a, nchunk, st);
+        else if (prefetch_fits<4, MAXE>(a))
+            launch_cc_k<T, TI, MAXE, WB, false, 2, NT, 4>(a, nchunk, st);
         else
+            launch_cc_k<T, TI, MAXE, WB, false, 2>(a, nchunk, st);
+    } else if (a.fd.N <= 4 * NT) {
+        if (p2 && prefetch_fits<2, MAXE>(a))
+            launch_cc_k<T, TI, MAXE, WB, true, 4, NT, 2>(a, nchunk, st);
+        else if (p2)
             launch_cc_k<T, TI, MAXE, WB, true, 4>(a, nchunk, st);
+        else if (prefetch_fits<2, MAXE>(a))
+            launch_cc_k<T, TI, MAXE, WB, false, 4, NT, 2>(a, nchunk, st);
+        else
+            launch_cc_k<T, TI, MAXE, WB, false, 4>(a, nchunk, st);
     } else {
         if (p2)
             launch_cc_k<T, TI, MAXE, WB, true, 8>(a, nchunk, st);

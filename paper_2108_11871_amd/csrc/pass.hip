@@ -172,8 +172,9 @@ static void launch_pass_k(const PassArgs &a, int ntiles, size_t lds, hipStream_t
                        ntiles);
 }
 
-// Default tile widths (W = 8, 16, 4 for 2M = 512, 256, 1024 at 2048 complex
-// points per tile) with plain loads get the register prefetch when EPT
+// Compile-time tile widths W = 4, 8, 16 (the default widths of 2M = 1024,
+// 512, 256 and of the lengths near them) with plain loads get the register
+// prefetch when EPT
 // registers per thread cover the loaded rows.  FP32 tiles: only the forward
 // zero-padded transforms (EPT = MAXE); for the inverse passes the
 // prefetching loop measured slower than one tile per block.
@@ -186,18 +187,18 @@ static bool pass_fits(const PassArgs &a)
 template <typename T, typename TI, typename TO, int MAXE, bool P2>
 static void launch_pass_m(const PassArgs &a, int ntiles, size_t lds, hipStream_t st)
 {
-    if constexpr (P2 && MAXE == 8) {
+    if constexpr (MAXE == 8) {
         if (!(a.in_mode == IN_HERM && a.nsum > 1)) {
             constexpr bool wide = sizeof(T) == 8; // FP64 tiles: every mode, EPT up to 2 MAXE
             if (!wide && a.in_mode != IN_ZPAD && a.in_mode != IN_ZPAD0)
                 return launch_pass_k<T, TI, TO, MAXE, P2>(a, ntiles, lds, st);
-            if (pass_fits<8, 8>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 8, 8>(a, ntiles, lds, st);
-            if (pass_fits<16, 8>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 16, 8>(a, ntiles, lds, st);
-            if (pass_fits<4, 8>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 4, 8>(a, ntiles, lds, st);
+            if (pass_fits<8, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 8, 8>(a, ntiles, lds, st);
+            if (pass_fits<16, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 16, 8>(a, ntiles, lds, st);
+            if (pass_fits<4, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 4, 8>(a, ntiles, lds, st);
             if constexpr (wide) {
-                if (pass_fits<8, 16>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 8, 16>(a, ntiles, lds, st);
-                if (pass_fits<16, 16>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 16, 16>(a, ntiles, lds, st);
-                if (pass_fits<4, 16>(a)) return launch_pass_k<T, TI, TO, 8, true, NT, 4, 16>(a, ntiles, lds, st);
+                if (pass_fits<8, 16>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 8, 16>(a, ntiles, lds, st);
+                if (pass_fits<16, 16>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 16, 16>(a, ntiles, lds, st);
+                if (pass_fits<4, 16>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 4, 16>(a, ntiles, lds, st);
             }
         }
     }
