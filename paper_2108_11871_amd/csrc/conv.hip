@@ -210,9 +210,10 @@ static void launch_cc_k(const CcArgs &a, int nchunk, hipStream_t st)
                        st, a, nchunk);
 }
 
-// Compile-time widths (W = 16, 8 for 2M <= 512, W = 4 up to 1024: the
-// default widths of the power-of-two lengths and of the lengths near them)
-// get a fully unrolled contraction and the register prefetch of the next tile.
+// Compile-time widths (W = 16, 8 for 2M = 256, 512; W = 4 for lengths in
+// (512, 1024]) get a fully unrolled contraction and the register prefetch of
+// the next tile (shorter lengths other than powers of two measured faster
+// without, in batches of small uneven boxes).
 template <int WHC, int MAXE, int NTT = NT>
 static bool prefetch_fits(const CcArgs &a)
 {
@@ -230,10 +231,6 @@ static void launch_cc_m(const CcArgs &a, int nchunk, hipStream_t st)
             launch_cc_k<T, TI, MAXE, WB, true, 2, NT, 4>(a, nchunk, st);
         else if (p2)
             launch_cc_k<T, TI, MAXE, WB, true, 2>(a, nchunk, st);
-        else if (prefetch_fits<8, MAXE>(a))
-            launch_cc_k<T, TI, MAXE, WB, false, 2, NT, 8>(a, nchunk, st);
-        else if (prefetch_fits<4, MAXE>(a))
-            launch_cc_k<T, TI, MAXE, WB, false, 2, NT, 4>(a, nchunk, st);
         else
             launch_cc_k<T, TI, MAXE, WB, false, 2>(a, nchunk, st);
     } else if (a.fd.N <= 4 * NT) {

@@ -187,8 +187,10 @@ static bool pass_fits(const PassArgs &a)
 template <typename T, typename TI, typename TO, int MAXE, bool P2>
 static void launch_pass_m(const PassArgs &a, int ntiles, size_t lds, hipStream_t st)
 {
+    // other lengths from 2M = 512 up (the small uneven boxes of a batch measured
+    // faster with one tile per block)
     if constexpr (MAXE == 8) {
-        if (!(a.in_mode == IN_HERM && a.nsum > 1)) {
+        if (!(a.in_mode == IN_HERM && a.nsum > 1) && (P2 || a.fd.N >= 512)) {
             constexpr bool wide = sizeof(T) == 8; // FP64 tiles: every mode, EPT up to 2 MAXE
             if (!wide && a.in_mode != IN_ZPAD && a.in_mode != IN_ZPAD0)
                 return launch_pass_k<T, TI, TO, MAXE, P2>(a, ntiles, lds, st);
