@@ -107,7 +107,8 @@ int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int o
 int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int order,
                     int precision, unsigned flags);
 
-/* Bytes of device memory held by the plan (workspace plus tables). */
+/* Bytes of device memory held by the plan (workspace plus tables; for an
+ * extended plan, its inner plan and the two extended arrays included). */
 int ips_plan_workspace_size(ips_plan p, size_t *bytes);
 
 /*
