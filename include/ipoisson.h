@@ -65,22 +65,25 @@ typedef enum {
 } ips_status;
 
 /* Arithmetic used by the transforms.  Input and output stay FP64.  In every
- * mode the kernel spectra, the accumulation of the boundary sums over chunks
- * of slices, the inverse transforms of the face sums, g~, the core stencils
- * and the extrapolation of the sixth-order step and the spectral symbols are
- * FP64.  The mixed modes store the sine-space volume in FP32 and combine the
- * spectrum in FP32 from those FP64 parts, and keep the sixth-order sine-series
- * values on the shell layers in FP32. */
+ * mode the boundary sums of Section 4 are accumulated in FP64 against FP64
+ * kernel spectra (per tile, per chunk of slices and over the chunks), and the
+ * inverse transforms of the face sums, g~, the core stencils, the cubic
+ * extrapolation and the differences D = R - R_spec of the sixth-order step,
+ * and the spectral symbols are FP64.  The mixed modes store the sine-space
+ * volume in FP32, run its transforms in FP32, combine the spectrum in FP32
+ * from those FP64 parts, and keep the sixth-order sine-series values on the
+ * shell layers in FP32. */
 typedef enum {
     IPS_FP64 = 0,              /* everything in FP64 */
     IPS_MIXED_FP32 = 1,        /* sine-transform passes of phi_star + phi_H in FP32 */
     IPS_MIXED_FP32_SLICES = 2  /* as 1, and the slice transforms of rho that feed the
-                                  boundary sums in FP32 (products summed per tile in
-                                  FP32, accumulated in FP64, chunk sums stored in FP32) */
+                                  boundary sums in FP32 (each FP32 slot value is widened
+                                  exactly and multiplied and summed in FP64) */
 } ips_precision;
 
 /*
- * ips_solve -- one blocking solve on the null stream of the current device.
+ * ips_solve -- one blocking FP64 solve on the null stream of the current
+ * device (ips_solve_ex with IPS_FP64).
  *   d      : 1, 2 or 3
  *   n      : d node counts, n[i] >= 3; for order 6 and d >= 2, n[i] >= 8
  *            (the extrapolation reaches five nodes in from the boundary)
@@ -89,10 +92,32 @@ typedef enum {
  *   order  : 4 or 6 (accuracy order of the harmonic part, Section 5);
  *            ignored for d = 1
  *   phi    : device array of the same size, must not overlap rho
- * Plans are cached per (device, d, n, h, order) behind a mutex.
+ * Plans are cached per (device, d, n, h, order, precision): the cache keeps
+ * the most recently used plans (4, or the value of the environment variable
+ * IPS_SOLVE_CACHE read at the first call) and destroys the least recently
+ * used idle ones beyond that.  Threads share the cache; solves of different
+ * plans run concurrently, solves of one plan are enqueued one at a time, and
+ * no lock is held while a call waits for the device.
  */
 int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int order,
               double *phi);
+
+/* ips_solve with an ips_precision (errors as ips_solve; IPS_E_INVALID_ARG for
+ * an unknown precision, IPS_E_UNSUPPORTED for a mixed mode with d = 1). */
+int ips_solve_ex(int d, const int64_t *n, const double *h, const double *rho, int order,
+                 int precision, double *phi);
+
+/* Destroy every idle plan of the ips_solve cache (plans in use by another
+ * thread stay).  Waits for their work (hipFree). */
+int ips_solve_release_cache(void);
+
+/* Number of plans in the ips_solve cache. */
+int ips_solve_cache_size(size_t *plans);
+
+/* Device bytes currently allocated by the library: tables and workspaces of
+ * every live plan, batch and cached plan (caller-supplied workspaces are not
+ * counted).  For memory accounting and leak checks. */
+int ips_live_device_bytes(size_t *bytes);
 
 /*
  * ips_plan_create -- build a reusable plan on the current device: FFT
@@ -100,16 +125,48 @@ int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int o
  * Green's-function kernels used by the boundary convolutions (Section 4),
  * and all device workspace.  Arguments as ips_solve, plus:
  *   precision : an ips_precision value
- *   flags     : bitwise OR of IPS_FLAG_STAGE_TIMING, IPS_FLAG_ADJOINT and
- *               IPS_FLAG_AUTOTUNE (or 0)
+ *   flags     : bitwise OR of IPS_FLAG_STAGE_TIMING, IPS_FLAG_ADJOINT,
+ *               IPS_FLAG_AUTOTUNE and IPS_FLAG_NO_WORKSPACE (or 0)
  * On success *out receives the plan; release it with ips_plan_destroy.
  */
 int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int order,
                     int precision, unsigned flags);
 
-/* Bytes of device memory held by the plan (workspace plus tables; for an
- * extended plan, its inner plan and the two extended arrays included). */
+/*
+ * Device memory of a plan comes in two parts:
+ *   tables    : twiddles, eigenvalue and sine tables, kernel spectra; built by
+ *               ips_plan_create, owned by the plan, read-only afterwards;
+ *   workspace : everything one solve writes besides phi (sine-space volume,
+ *               slice transforms, chunk partial sums, face values, shell
+ *               layers) and, for a plan created with IPS_FLAG_ADJOINT, the
+ *               adjoint's buffers.  0 bytes for d = 1.
+ * ips_plan_workspace_size gives the workspace bytes ips_plan_set_workspace
+ * needs; ips_plan_table_size the bytes of tables held by the plan (the
+ * adjoint buffers allocated by a first adjoint call and an extended plan's
+ * two extended arrays included).  For an extended plan both refer to its
+ * extended grid.
+ */
 int ips_plan_workspace_size(ips_plan p, size_t *bytes);
+int ips_plan_table_size(ips_plan p, size_t *bytes);
+
+/*
+ * ips_plan_set_workspace -- let the plan run in caller-owned device memory.
+ *   dev_ptr : device memory of the plan's device, 256-byte aligned, of at
+ *             least ips_plan_workspace_size bytes; the caller keeps it valid
+ *             and unused by others while work of this plan is enqueued or
+ *             running.  NULL (with bytes = 0) returns the plan to a
+ *             plan-owned workspace (allocated if needed).
+ * Any plan-owned workspace is freed (hipFree, which waits for the device).
+ * Several plans may share one buffer if their solves never overlap in time.
+ * A plan created with IPS_FLAG_NO_WORKSPACE holds none until this call;
+ * ips_execute on it returns IPS_E_WORKSPACE meanwhile.
+ * Errors: IPS_E_WORKSPACE when bytes is too small (the plan is unchanged),
+ * IPS_E_INVALID_ARG for a NULL plan, misaligned or host memory, or another
+ * device.  d = 1 plans accept any buffer and use none.
+ */
+#define IPS_FLAG_NO_WORKSPACE 16u
+
+int ips_plan_set_workspace(ips_plan p, void *dev_ptr, size_t bytes);
 
 /*
  * ips_extension -- the enlarged grid of an automatically extended solve (host
@@ -165,8 +222,8 @@ int ips_execute(ips_plan p, const double *rho, double *phi, void *stream);
  *   rho_bar : device array of the same size, must not overlap phi_bar;
  *             its boundary entries are set to 0 (the solve ignores rho there)
  * Used for gradients: if J depends on phi, dJ/drho = A^T dJ/dphi.
- * Workspace: a plan created with IPS_FLAG_ADJOINT holds it from the start;
- * otherwise the first adjoint call allocates it (later calls allocate
+ * Buffers: a plan created with IPS_FLAG_ADJOINT keeps them in its workspace;
+ * otherwise the first adjoint call allocates them (later calls allocate
  * nothing).  About four interior volumes plus two grids (order 6) in FP64.
  */
 #define IPS_FLAG_ADJOINT 2u

@@ -28,6 +28,7 @@ IPS_FLAG_STAGE_TIMING = 1
 IPS_FLAG_ADJOINT = 2
 IPS_FLAG_AUTOTUNE = 4
 IPS_FLAG_BATCH_EAGER = 8
+IPS_FLAG_NO_WORKSPACE = 16
 STAGES = ["rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces", "shell_gt", "shell_r6",
           "final", "inv_y", "inv_z", "adjoint"]
 
@@ -37,11 +38,17 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
 SIGNATURES = {
     "ips_solve": (ctypes.c_int, [ctypes.c_int, _i64p, _dp, _vp, ctypes.c_int, _vp]),
+    "ips_solve_ex": (ctypes.c_int, [ctypes.c_int, _i64p, _dp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "ips_solve_release_cache": (ctypes.c_int, []),
+    "ips_solve_cache_size": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t)]),
+    "ips_live_device_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t)]),
     "ips_plan_create": (
         ctypes.c_int,
         [ctypes.POINTER(_vp), ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_uint],
     ),
     "ips_plan_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ips_plan_table_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ips_plan_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "ips_extension": (ctypes.c_int, [ctypes.c_int, _i64p, _i64p, _i64p, _i64p]),
     "ips_plan_create_extended": (
         ctypes.c_int,

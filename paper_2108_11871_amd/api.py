@@ -11,14 +11,15 @@ from typing import Sequence
 import torch
 
 from . import _lib
-from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_AUTOTUNE, IPS_FLAG_BATCH_EAGER, IPS_FLAG_STAGE_TIMING,
-                   IPS_FP64, IPS_MIXED_FP32, IPS_MIXED_FP32_SLICES, STAGES, check, f64_array,
+from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_AUTOTUNE, IPS_FLAG_BATCH_EAGER, IPS_FLAG_NO_WORKSPACE,
+                   IPS_FLAG_STAGE_TIMING, IPS_FP64, IPS_MIXED_FP32, IPS_MIXED_FP32_SLICES, STAGES, check, f64_array,
                    i64_array, library_path, lib)
 
 PRECISIONS = {"fp64": IPS_FP64, "mixed_fp32": IPS_MIXED_FP32,
               "mixed_fp32_slices": IPS_MIXED_FP32_SLICES}
 
-__all__ = ["solve", "Plan", "Batch", "SolveFn", "PRECISIONS", "library_path"]
+__all__ = ["solve", "release_solve_cache", "solve_cache_size", "Plan", "Batch", "SolveFn", "PRECISIONS",
+           "library_path", "extension"]
 
 
 def _stream_handle(device) -> int:
@@ -36,6 +37,21 @@ def _check_grid(t: torch.Tensor):
         raise ValueError("rho must be contiguous (row-major, last axis fastest)")
     if t.dim() not in (1, 2, 3):
         raise ValueError("rho must have 1, 2 or 3 dimensions")
+
+
+def _check_out(out: torch.Tensor, like: torch.Tensor, name: str = "out"):
+    """A caller-supplied output must match the input exactly: the library writes
+    prod(shape) doubles through its pointer."""
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if out.dtype != torch.float64:
+        raise TypeError("%s must be float64" % name)
+    if out.device != like.device:
+        raise ValueError("%s must live on %s" % (name, like.device))
+    if tuple(out.shape) != tuple(like.shape):
+        raise ValueError("%s shape %s does not match %s" % (name, tuple(out.shape), tuple(like.shape)))
+    if not out.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
 
 
 def extension(shape: Sequence[int], margin):
@@ -58,10 +74,12 @@ class Plan:
 
     def __init__(self, shape: Sequence[int], h, order: int = 6, precision: str = "fp64",
                  device=None, timing: bool = False, adjoint: bool = False, autotune: bool = False,
-                 margin=None):
+                 margin=None, no_workspace: bool = False):
         """margin: None, or nodes added on each side of every axis (an int or one
         per axis); the solve then runs on the enlarged grid of `extension` and
-        returns phi at the caller's nodes (ips_plan_create_extended)."""
+        returns phi at the caller's nodes (ips_plan_create_extended).
+        no_workspace: create the plan without an execution workspace; bind one
+        with `set_workspace` before the first solve (IPS_FLAG_NO_WORKSPACE)."""
         self.shape = tuple(int(v) for v in shape)
         d = len(self.shape)
         hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
@@ -73,7 +91,7 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         handle = ctypes.c_void_p()
         flags = ((IPS_FLAG_STAGE_TIMING if timing else 0) | (IPS_FLAG_ADJOINT if adjoint else 0)
-                 | (IPS_FLAG_AUTOTUNE if autotune else 0))
+                 | (IPS_FLAG_AUTOTUNE if autotune else 0) | (IPS_FLAG_NO_WORKSPACE if no_workspace else 0))
         self.margin = None
         with torch.cuda.device(self.device):
             if margin is None:
@@ -91,9 +109,34 @@ class Plan:
 
     @property
     def workspace_bytes(self) -> int:
+        """Bytes of execution workspace the plan needs (ips_plan_workspace_size)."""
         n = ctypes.c_size_t()
         check(lib().ips_plan_workspace_size(self._h, ctypes.byref(n)))
         return n.value
+
+    @property
+    def table_bytes(self) -> int:
+        """Bytes of tables (kernel spectra, twiddles, ...) held by the plan."""
+        n = ctypes.c_size_t()
+        check(lib().ips_plan_table_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def set_workspace(self, buf: torch.Tensor | None, nbytes: int | None = None):
+        """Run in caller-owned device memory (ips_plan_set_workspace); None returns
+        to a plan-owned workspace.  The tensor must stay alive while solves of
+        this plan are enqueued; nbytes defaults to the tensor's size."""
+        if buf is None:
+            check(lib().ips_plan_set_workspace(self._h, None, 0))
+            self._ws = None
+            return
+        if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("the workspace must be a contiguous GPU tensor")
+        size = buf.numel() * buf.element_size() if nbytes is None else int(nbytes)
+        if size > buf.numel() * buf.element_size():
+            raise ValueError("nbytes exceeds the tensor")
+        with torch.cuda.device(buf.device):
+            check(lib().ips_plan_set_workspace(self._h, ctypes.c_void_p(buf.data_ptr()), size))
+        self._ws = buf
 
     def __call__(self, rho: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         _check_grid(rho)
@@ -101,6 +144,8 @@ class Plan:
             raise ValueError("rho shape %s does not match the plan %s" % (tuple(rho.shape), self.shape))
         if out is None:
             out = torch.empty_like(rho)
+        else:
+            _check_out(out, rho)
         with torch.cuda.device(rho.device):
             check(lib().ips_execute(self._h, ctypes.c_void_p(rho.data_ptr()),
                                     ctypes.c_void_p(out.data_ptr()),
@@ -114,6 +159,8 @@ class Plan:
             raise ValueError("phi_bar shape %s does not match the plan %s" % (tuple(phi_bar.shape), self.shape))
         if out is None:
             out = torch.empty_like(phi_bar)
+        else:
+            _check_out(out, phi_bar)
         with torch.cuda.device(phi_bar.device):
             check(lib().ips_execute_adjoint(self._h, ctypes.c_void_p(phi_bar.data_ptr()),
                                             ctypes.c_void_p(out.data_ptr()),
@@ -145,18 +192,34 @@ class Plan:
             pass
 
 
-def solve(rho: torch.Tensor, h, order: int = 6) -> torch.Tensor:
-    """phi = G * rho on the grid of rho (FP64, blocking call of ips_solve on the null stream)."""
+def solve(rho: torch.Tensor, h, order: int = 6, precision: str = "fp64") -> torch.Tensor:
+    """phi = G * rho on the grid of rho (blocking ips_solve_ex on the null stream,
+    with the library's plan cache)."""
     _check_grid(rho)
+    if precision not in PRECISIONS:
+        raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
     d = rho.dim()
     hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
+    if len(hh) != d:
+        raise ValueError("h needs one entry per axis")
     out = torch.empty_like(rho)
     torch.cuda.current_stream(rho.device).synchronize()
     with torch.cuda.device(rho.device):
-        check(lib().ips_solve(d, i64_array(rho.shape), f64_array(hh),
-                              ctypes.c_void_p(rho.data_ptr()), int(order),
-                              ctypes.c_void_p(out.data_ptr())))
+        check(lib().ips_solve_ex(d, i64_array(rho.shape), f64_array(hh),
+                                 ctypes.c_void_p(rho.data_ptr()), int(order), PRECISIONS[precision],
+                                 ctypes.c_void_p(out.data_ptr())))
     return out
+
+
+def release_solve_cache():
+    """Destroy the idle plans of the solve cache (ips_solve_release_cache)."""
+    check(lib().ips_solve_release_cache())
+
+
+def solve_cache_size() -> int:
+    n = ctypes.c_size_t()
+    check(lib().ips_solve_cache_size(ctypes.byref(n)))
+    return n.value
 
 
 class Batch:
@@ -191,9 +254,17 @@ class Batch:
                 raise ValueError("rho shape %s does not match %s" % (tuple(r.shape), s))
         if outs is None:
             outs = [torch.empty_like(r) for r in rhos]
+        else:
+            if len(outs) != self.count:
+                raise ValueError("expected %d outputs" % self.count)
+            for o, r in zip(outs, rhos):
+                _check_out(o, r, "outs[i]")
+        dev = rhos[0].device
+        for r in rhos:
+            if r.device != dev:
+                raise ValueError("every problem of a batch must live on one device")
         rp = (ctypes.c_void_p * self.count)(*[r.data_ptr() for r in rhos])
         pp = (ctypes.c_void_p * self.count)(*[o.data_ptr() for o in outs])
-        dev = rhos[0].device
         with torch.cuda.device(dev):
             check(lib().ips_batch_execute(self._h, rp, pp, ctypes.c_void_p(_stream_handle(dev))))
         return outs

@@ -59,7 +59,6 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
     const int hc = (a.ncols + 1) >> 1; // first-half columns (the chunked range)
     const int cbeg = ch * a.cols_per_chunk;
     const int cend = min(hc, cbeg + a.cols_per_chunk);
-    using TK = typename std::conditional<std::is_same<TI, float>::value, float, double>::type;
     // PF (compile-time width): the next tile is fetched into registers while
     // the current one is transformed and contracted
     constexpr bool PF = WHC > 0;
@@ -119,21 +118,13 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
             if (t < M) {
                 const bool two = t > 0; // row M + t is S_t (else C_M, see below)
                 const T *r1 = buf + t * rs, *r2 = buf + (M + t) * rs;
-                // kernel spectra in the slot type: FP32 when the slots are FP32
-                const TK *Kr = static_cast<const TK *>(a.K) + (int64_t)kb * a.Ko;
-                const TK *KA = Kr + t + (int64_t)c0 * a.Kd; // K at column c0 + j
-                const TK *KB = Kr + t + (int64_t)m0 * a.Kd; // K at column m0 - j
-                // per-tile sums in the slot type (FP32 products of FP32 data and
-                // FP32 spectra, W/2 column pairs), added to the FP64 accumulators
-                // once per tile; FP64 slots accumulate directly
-                using TA = TK;
-                TA s10 = 0, s11 = 0, s20 = 0, s21 = 0;
-                if constexpr (std::is_same<TA, double>::value) {
-                    s10 = a10[i];
-                    s11 = a11[i];
-                    s20 = a20[i];
-                    s21 = a21[i];
-                }
+                // FP64 kernel spectra and FP64 sums in every mode: an FP32 slot
+                // value is widened exactly, so the boundary sums accumulate in FP64
+                const double *Kr = static_cast<const double *>(a.K) + (int64_t)kb * a.Ko;
+                const double *KA = Kr + t + (int64_t)c0 * a.Kd; // K at column c0 + j
+                const double *KB = Kr + t + (int64_t)m0 * a.Kd; // K at column m0 - j
+                using TA = double;
+                TA s10 = a10[i], s11 = a11[i], s20 = a20[i], s21 = a21[i];
                 auto col_pair = [&](int j) {
                     const TA kA = KA[(int64_t)j * a.Kd], kB = KB[-(int64_t)j * a.Kd];
                     const TA ud = (TA)r1[j], um = (TA)r1[Wh + j];
@@ -155,7 +146,7 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
                 }
                 if (!two) {
                     // C_M (no sine partner) with its own kernel spectrum
-                    const TK *MA = Kr + M + (int64_t)c0 * a.Kd, *MB = Kr + M + (int64_t)m0 * a.Kd;
+                    const double *MA = Kr + M + (int64_t)c0 * a.Kd, *MB = Kr + M + (int64_t)m0 * a.Kd;
                     for (int j = 0; j < nA; ++j) {
                         const TA kA = MA[(int64_t)j * a.Kd], kB = MB[-(int64_t)j * a.Kd];
                         const TA vd = (TA)r2[j], vm = (TA)r2[Wh + j];
@@ -165,40 +156,27 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
                         s21 = fma(kA, vm, s21);
                     }
                 }
-                if constexpr (std::is_same<TA, double>::value) {
-                    a10[i] = s10;
-                    a11[i] = s11;
-                    a20[i] = s20;
-                    a21[i] = s21;
-                } else {
-                    a10[i] += (double)s10;
-                    a11[i] += (double)s11;
-                    a20[i] += (double)s20;
-                    a21[i] += (double)s21;
-                }
+                a10[i] = s10;
+                a11[i] = s11;
+                a20[i] = s20;
+                a21[i] = s21;
             }
         }
         __syncthreads();
     }
-    // partials [face][chunk][batch][slot]: slot rows t and M + t
+    // FP64 partials [face][chunk][batch][slot]: slot rows t and M + t
     const int64_t o0 = ((int64_t)ch * a.nbatch + bt) * N, o1 = o0 + (int64_t)nchunk * a.nbatch * N;
-    auto put = [&](auto *pp) {
+    double *pp = static_cast<double *>(a.part);
 #pragma unroll
-        for (int i = 0; i < TPT; ++i) {
-            const int t = threadIdx.x + i * NTT;
-            if (t < M) {
-                using P = std::remove_reference_t<decltype(*pp)>;
-                pp[o0 + t] = (P)a10[i];
-                pp[o1 + t] = (P)a11[i];
-                pp[o0 + M + t] = (P)a20[i];
-                pp[o1 + M + t] = (P)a21[i];
-            }
+    for (int i = 0; i < TPT; ++i) {
+        const int t = threadIdx.x + i * NTT;
+        if (t < M) {
+            pp[o0 + t] = a10[i];
+            pp[o1 + t] = a11[i];
+            pp[o0 + M + t] = a20[i];
+            pp[o1 + M + t] = a21[i];
         }
-    };
-    if (a.part_f32)
-        put(static_cast<float *>(a.part));
-    else
-        put(static_cast<double *>(a.part));
+    }
 }
 
 template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT = NT, int WHC = 0>

@@ -500,7 +500,7 @@ template <typename T, typename TI, int NT>
 __device__ void tile_load_pair(T *buf, int rs, int row0, const TI *src, int nrows, int64_t rsd, int64_t csd,
                                int lgW, int cA, int nA, int cB, int nB, int tid = -1)
 {
-    if (tid < 0) tid = tid;
+    if (tid < 0) tid = threadIdx.x;
     const int W = 1 << lgW, Wh = W >> 1;
     auto src_col = [&](int c) -> int {
         const int j = c < Wh ? c : c - Wh;

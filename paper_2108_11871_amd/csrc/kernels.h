@@ -47,10 +47,9 @@ struct CcArgs {
     int nbatch;        // slots of the remaining in-face axis (1 if none)
     int Mo;            // M of that axis (slot -> wavenumber), 0 if none
     int cols_per_chunk; // first-half columns per chunk (a tile pairs column c with ncols-1-c)
-    const void *K;     // K[d][k_o][k_p], k_p contiguous: FP32 when the slot input is FP32, else FP64
+    const double *K;   // K[d][k_o][k_p], k_p contiguous (FP64 in every mode)
     int64_t Kd, Ko;
-    void *part;        // [2][nchunk][nbatch][2 M_p], FP32 if part_f32 else FP64
-    int part_f32;
+    double *part;      // FP64 chunk partials [2][nchunk][nbatch][2 M_p]
     void *Bout;        // optional S_p output: Bout[col*Bcs + (k_p-1)*Brs + (k_o-1)*Bbs],
                        // written for the sine slots k_o of the batch axis (all batches if Mo == 0)
     int64_t Bcs, Brs, Bbs;
@@ -206,8 +205,6 @@ hipError_t launch_adj_1d(const double *w, double *out, int M, double h, const Ff
 void set_lds(const void *fn, size_t bytes);
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
-// FP32 input, FP64 transform and output
-hipError_t launch_pass_in32(const PassArgs &a, hipStream_t st);
 // in_f32: input data in FP32 (else FP64); f32: transform type
 hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st);
 hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st);

@@ -260,12 +260,6 @@ static bool pass_strides_ok(const PassArgs &a)
     return tile_strides_ok(a.nrows_in, a.irs, a.ncols, a.ics) && tile_strides_ok(a.out_nrows, a.ors, a.ncols, a.ocs);
 }
 
-hipError_t launch_pass_in32(const PassArgs &a, hipStream_t st)
-{
-    if (!pass_strides_ok(a)) return hipErrorInvalidValue;
-    return launch_pass_t<double, float, double>(a, st);
-}
-
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st)
 {
     if (!pass_strides_ok(a)) return hipErrorInvalidValue;

@@ -2,6 +2,7 @@
 // solve, and the C ABI declared in include/ipoisson.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -81,14 +82,27 @@ bool factor_fft(int N, FftDesc &fd)
     return true;
 }
 
+// Device bytes currently allocated by the library (every plan and batch).
+std::atomic<int64_t> g_live_bytes{0};
+// Allocations made by the calling thread since its current plan creation
+// began (failure injection for tests: IPS_TEST_FAIL_ALLOC=k makes the k-th
+// allocation of every plan creation fail, k >= 1; any other value, the first).
+thread_local int g_alloc_seq = 0;
+
 struct DevBuf {
     std::vector<void *> ptrs;
+    std::vector<size_t> sizes;
     size_t bytes = 0;
     int alloc(void **p, size_t n)
     {
         *p = nullptr;
         if (n == 0) n = 8;
-        if (getenv("IPS_TEST_FAIL_ALLOC")) return fail(IPS_E_NO_MEMORY, "allocation failure forced by IPS_TEST_FAIL_ALLOC");
+        ++g_alloc_seq;
+        if (const char *e = getenv("IPS_TEST_FAIL_ALLOC")) {
+            const int k = atoi(e) >= 1 ? atoi(e) : 1;
+            if (g_alloc_seq >= k)
+                return fail(IPS_E_NO_MEMORY, "allocation failure forced by IPS_TEST_FAIL_ALLOC");
+        }
         hipError_t e = hipMalloc(p, n);
         if (e != hipSuccess) {
             *p = nullptr;
@@ -96,13 +110,19 @@ struct DevBuf {
             return fail(IPS_E_NO_MEMORY, "hipMalloc of " + std::to_string(n) + " bytes failed");
         }
         ptrs.push_back(*p);
+        sizes.push_back(n);
         bytes += n;
+        g_live_bytes += (int64_t)n;
         return IPS_OK;
     }
     void release()
     {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (size_t i = 0; i < ptrs.size(); ++i) {
+            (void)hipFree(ptrs[i]);
+            g_live_bytes -= (int64_t)sizes[i];
+        }
         ptrs.clear();
+        sizes.clear();
         bytes = 0;
     }
 };
@@ -177,11 +197,9 @@ struct ips_plan_s {
     double *rowtab = nullptr;                          // final pass row table [batch][M0 - 1][12]
     AxisTabs tab[3]{};
     double *K[3] = {nullptr, nullptr, nullptr};
-    float *K32[3] = {nullptr, nullptr, nullptr}; // FP32 copies (3D slices in FP32)
     void *A = nullptr; // slot transforms of rho along one axis (3D)
     void *B = nullptr; // raw DST of rho along the last d-1 axes, then phi in sine space
     double *part[3] = {nullptr, nullptr, nullptr};
-    float *partf[3] = {nullptr, nullptr, nullptr}; // the same buffer, FP32 partials (3D, FP32 slices)
     int nch[3] = {1, 1, 1};
     int chunk[3] = {1, 1, 1};
     double *F[3] = {nullptr, nullptr, nullptr};
@@ -194,8 +212,16 @@ struct ips_plan_s {
     void *P2T = nullptr;                        // 3D: transposed family-2 copy (final pass type)
     bool cube = false; // all families share sizes and chunking (batched launches)
     double *C[3] = {nullptr, nullptr, nullptr}; // sixth-order right-hand side on core layers
-    DevBuf mem;
-    // adjoint workspace (allocated by IPS_FLAG_ADJOINT or the first adjoint call)
+    DevBuf mem;   // tables: twiddles, axis tables, kernel spectra (and an extended plan's arrays)
+    // execution workspace: one block carved into the buffers above (B, A, part, F,
+    // G, P, T, D, C, P1T, P2T, rowtab) and, for IPS_FLAG_ADJOINT plans, the adjoint's
+    size_t ws_bytes = 0;  // bytes the carving needs
+    void *ws = nullptr;   // bound block (plan-owned or the caller's), nullptr: none
+    bool ws_adj = false;  // the adjoint buffers are part of the workspace
+    DevBuf wsmem;         // plan-owned workspace block
+    DevBuf adjmem;        // adjoint buffers of plans without ws_adj (first adjoint call)
+    std::mutex exec_mu;   // serialises the enqueue of solves from the ips_solve cache
+    // adjoint buffers (in the workspace, or allocated by the first adjoint call)
     bool adj_ready = false;
     double *AX = nullptr, *AY = nullptr, *AX2 = nullptr; // interior volumes
     double *AF = nullptr, *AU = nullptr;                 // grid-shaped (order 6)
@@ -241,7 +267,8 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
 {
     if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
     if (!n || !h) return fail(IPS_E_INVALID_ARG, "n and h must not be NULL");
-    if (flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_ADJOINT | IPS_FLAG_AUTOTUNE | IPS_FLAG_BATCH_EAGER))
+    if (flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_ADJOINT | IPS_FLAG_AUTOTUNE | IPS_FLAG_BATCH_EAGER |
+                  IPS_FLAG_NO_WORKSPACE))
         return fail(IPS_E_INVALID_ARG, "unknown flag bits");
     if (precision != IPS_FP64 && precision != IPS_MIXED_FP32 && precision != IPS_MIXED_FP32_SLICES)
         return fail(IPS_E_INVALID_ARG, "unknown precision");
@@ -360,6 +387,154 @@ int shell_dst_all(ips_plan p, TS *const *arr, int nl, bool inverse, hipStream_t 
     return IPS_OK;
 }
 
+// Sub-buffers carved out of one device block, 256-byte aligned; with a null
+// base only the size is measured.
+struct Carver {
+    char *base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    void take(T **ptr, size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        *ptr = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += bytes ? bytes : 8;
+    }
+};
+
+void layout_adj(ips_plan p, Carver &c);
+
+// The execution workspace of a plan (everything one solve writes besides phi):
+// the sine-space volume B, the slot array A, the chunk partials, face values,
+// shell layers, the final pass's row table and, for plans with ws_adj, the
+// adjoint's buffers.  Assigns the plan's pointers from c.base.
+void layout_ws(ips_plan p, Carver &c)
+{
+    const int d = p->d;
+    if (d == 1) return;
+    const int *I = p->I, *M = p->M, *N = p->N;
+    size_t vol = 1, grid = 1;
+    for (int a = 0; a < d; ++a) {
+        vol *= (size_t)I[a];
+        grid *= (size_t)p->n[a];
+    }
+    const size_t wsz = p->precision != IPS_FP64 ? sizeof(float) : sizeof(double);
+    const size_t asz = p->precision == IPS_MIXED_FP32_SLICES ? sizeof(float) : sizeof(double);
+    c.take(&p->B, vol * wsz);
+    c.take(&p->rowtab, (d == 3 ? (size_t)I[2] : 1) * I[0] * 12 * sizeof(double));
+    if (d == 3) {
+        const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
+        c.take(&p->A, std::max(a1, a2) * asz);
+    } else {
+        p->A = nullptr;
+    }
+    // per-family sizes, one contiguous buffer per kind (families back to back)
+    size_t fsz[3] = {0, 0, 0}, ssz[3] = {0, 0, 0};
+    size_t tp = 0, tf = 0, ts = 0;
+    for (int fam = 0; fam < d; ++fam) {
+        fsz[fam] = 2;
+        ssz[fam] = 1;
+        for (int b = 0; b < d; ++b)
+            if (b != fam) {
+                fsz[fam] *= (size_t)N[b];
+                ssz[fam] *= (size_t)I[b];
+            }
+        tp += fsz[fam] * p->nch[fam];
+        tf += fsz[fam];
+        ts += ssz[fam];
+    }
+    double *bp, *bf, *bg, *bpk, *bt = nullptr, *bd = nullptr, *bc = nullptr;
+    c.take(&bp, tp * sizeof(double));
+    c.take(&bf, tf * sizeof(double));
+    c.take(&bg, 2 * ts * sizeof(double));
+    c.take(&bpk, 6 * ts * sizeof(double));
+    if (p->order == 6) {
+        c.take(&bt, 10 * ts * sizeof(double));
+        c.take(&bd, 4 * ts * sizeof(double));
+        c.take(&bc, 8 * ts * sizeof(double));
+    }
+    size_t op = 0, of = 0, os = 0;
+    for (int fam = 0; fam < 3; ++fam) {
+        p->part[fam] = p->F[fam] = p->G[fam] = p->P[fam] = p->T[fam] = p->D[fam] = p->C[fam] = nullptr;
+        p->Tf[fam] = nullptr;
+    }
+    if (c.base)
+        for (int fam = 0; fam < d; ++fam) {
+            p->part[fam] = bp + op;
+            p->F[fam] = bf + of;
+            p->G[fam] = bg + 2 * os;
+            p->P[fam] = bpk + 6 * os;
+            if (bt) {
+                p->T[fam] = bt + 10 * os;
+                p->Tf[fam] = reinterpret_cast<float *>(bt) + 10 * os;
+            }
+            if (bd) p->D[fam] = bd + 4 * os;
+            if (bc) p->C[fam] = bc + 8 * os;
+            op += fsz[fam] * p->nch[fam];
+            of += fsz[fam];
+            os += ssz[fam];
+        }
+    if (d == 3) {
+        c.take(&p->P1T, 6 * ssz[1] * sizeof(double));
+        c.take(&p->P2T, 6 * ssz[2] * sizeof(double));
+    }
+    if (p->ws_adj) layout_adj(p, c);
+}
+
+// The adjoint's buffers: three interior volumes, two grids (order 6), face
+// weights and their spectra, and one slice stack (3D).
+void layout_adj(ips_plan p, Carver &c)
+{
+    const int d = p->d;
+    const int *I = p->I, *M = p->M, *N = p->N;
+    size_t vol = 1, grid = 1;
+    for (int a = 0; a < d; ++a) {
+        vol *= (size_t)I[a];
+        grid *= (size_t)p->n[a];
+    }
+    c.take(&p->AX, vol * sizeof(double));
+    c.take(&p->AY, vol * sizeof(double));
+    if (p->order == 6) {
+        c.take(&p->AX2, vol * sizeof(double));
+        c.take(&p->AF, grid * sizeof(double));
+        c.take(&p->AU, grid * sizeof(double));
+    }
+    size_t zmax = 0;
+    for (int fam = 0; fam < d; ++fam) {
+        int b, cc;
+        kaxes(d, fam, b, cc);
+        const size_t lf = 2 * (size_t)(M[b] + 1) * (d == 3 ? (size_t)(M[cc] + 1) : 1);
+        const size_t lh = 2 * (size_t)N[b] * (d == 3 ? (size_t)N[cc] : 1);
+        c.take(&p->LF[fam], lf * sizeof(double));
+        c.take(&p->LH[fam], lh * sizeof(double));
+        if (d == 3) zmax = std::max(zmax, (size_t)I[fam] * N[b] * I[cc]);
+    }
+    // order 6 also uses it as one grid-shaped scratch array (adjoint stencil)
+    if (d == 3 && p->order == 6) zmax = std::max(zmax, grid);
+    if (d == 3) c.take(&p->AZ, zmax * sizeof(double));
+}
+
+// Point the plan's buffers into `base` (size checked by the caller), or
+// detach them (base = nullptr).
+void bind_ws(ips_plan p, void *base)
+{
+    Carver c;
+    c.base = static_cast<char *>(base);
+    p->ws = base;
+    if (base) {
+        layout_ws(p, c);
+        if (p->ws_adj) p->adj_ready = true;
+    } else if (p->ws_adj) {
+        p->adj_ready = false;
+    }
+}
+
+size_t measure_ws(ips_plan p)
+{
+    Carver c;
+    layout_ws(p, c);
+    return p->d == 1 ? 0 : c.off;
+}
+
 int plan_build(ips_plan p, hipStream_t st)
 {
     const int d = p->d;
@@ -405,32 +580,8 @@ int plan_build(ips_plan p, hipStream_t st)
     if (d == 1) return IPS_OK;
 
     const int *I = p->I, *M = p->M, *N = p->N;
-    // workspace
-    size_t vol = 1;
-    for (int a = 0; a < d; ++a) vol *= (size_t)I[a];
-    const size_t wsz = p->precision != IPS_FP64 ? sizeof(float) : sizeof(double);
-    const size_t asz = p->precision == IPS_MIXED_FP32_SLICES ? sizeof(float) : sizeof(double);
-    int rc = p->mem.alloc(&p->B, vol * wsz);
-    if (rc) return rc;
-    {
-        const size_t nb = d == 3 ? (size_t)I[2] : 1;
-        if ((rc = p->mem.alloc((void **)&p->rowtab, nb * I[0] * 12 * sizeof(double)))) return rc;
-    }
-    if (d == 3) {
-        const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
-        rc = p->mem.alloc(&p->A, std::max(a1, a2) * asz);
-        if (rc) return rc;
-    }
-    // per-family sizes, then one contiguous buffer per kind (families back to back)
-    size_t fsz[3] = {0, 0, 0}, ssz[3] = {0, 0, 0};
+    int rc;
     for (int fam = 0; fam < d; ++fam) {
-        fsz[fam] = 2;
-        ssz[fam] = 1;
-        for (int b = 0; b < d; ++b)
-            if (b != fam) {
-                fsz[fam] *= (size_t)N[b];
-                ssz[fam] *= (size_t)I[b];
-            }
         // chunking of the contraction over the face-normal axis (column-contraction kernel)
         int pen, nbatch;
         if (d == 3) {
@@ -454,43 +605,6 @@ int plan_build(ips_plan p, hipStream_t st)
         p->chunk[fam] = per * Wh;
         p->nch[fam] = (hc + per * Wh - 1) / (per * Wh);
     }
-    {
-        size_t tp = 0, tf = 0, ts = 0;
-        for (int fam = 0; fam < d; ++fam) {
-            tp += fsz[fam] * p->nch[fam];
-            tf += fsz[fam];
-            ts += ssz[fam];
-        }
-        double *bp, *bf, *bg, *bpk, *bt = nullptr, *bd = nullptr, *bc = nullptr;
-        if ((rc = p->mem.alloc((void **)&bp, tp * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&bf, tf * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&bg, 2 * ts * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&bpk, 6 * ts * sizeof(double)))) return rc;
-        if (p->order == 6) {
-            if ((rc = p->mem.alloc((void **)&bt, 10 * ts * sizeof(double)))) return rc;
-            if ((rc = p->mem.alloc((void **)&bd, 4 * ts * sizeof(double)))) return rc;
-            if ((rc = p->mem.alloc((void **)&bc, 8 * ts * sizeof(double)))) return rc;
-        }
-        size_t op = 0, of = 0, os = 0;
-        for (int fam = 0; fam < d; ++fam) {
-            p->part[fam] = bp + op;
-            p->partf[fam] = reinterpret_cast<float *>(bp) + op;
-            p->F[fam] = bf + of;
-            p->G[fam] = bg + 2 * os;
-            p->P[fam] = bpk + 6 * os;
-            if (bt) {
-                p->T[fam] = bt + 10 * os;
-                p->Tf[fam] = reinterpret_cast<float *>(bt) + 10 * os;
-            }
-            if (bd) p->D[fam] = bd + 4 * os;
-            if (bc) p->C[fam] = bc + 8 * os;
-            op += fsz[fam] * p->nch[fam];
-            of += fsz[fam];
-            os += ssz[fam];
-        }
-    }
-    if (d == 3 && (rc = p->mem.alloc((void **)&p->P1T, 6 * ssz[1] * sizeof(double)))) return rc;
-    if (d == 3 && (rc = p->mem.alloc(&p->P2T, 6 * ssz[2] * sizeof(double)))) return rc;
     // uniform families: one launch covers the three (two in 2D) families
     p->cube = true;
     for (int fam = 1; fam < d; ++fam)
@@ -545,11 +659,6 @@ int plan_build(ips_plan p, hipStream_t st)
             b2.out_nrows = M[kb] + 1;
             b2.scale = 1.0;
             if ((rc = run_pass(p, b2, p->fd[kb], p->tw[kb], false, false, st))) return rc;
-        }
-        if (d == 3 && p->precision == IPS_MIXED_FP32_SLICES) {
-            // the FP32 slot data are contracted with FP32 kernel spectra
-            if ((rc = p->mem.alloc((void **)&p->K32[fam], ksz * sizeof(float)))) return rc;
-            IPS_HIP(launch_to_f32(p->K[fam], p->K32[fam], (int64_t)ksz, st));
         }
     }
     return IPS_OK;
@@ -644,11 +753,10 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[2];
             a.Mo = M[2];
             a.cols_per_chunk = p->chunk[0];
-            a.K = f32s ? (const void *)p->K32[0] : (const void *)p->K[0];
+            a.K = p->K[0];
             a.Kd = (int64_t)(M[2] + 1) * (M[1] + 1);
             a.Ko = M[1] + 1;
-            a.part = f32s ? (void *)p->partf[0] : (void *)p->part[0];
-            a.part_f32 = f32s;
+            a.part = p->part[0];
             a.Bout = p->B;
             a.Bf32 = f32;
             a.Bcs = I[1];
@@ -673,11 +781,10 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[2];
             a.Mo = M[2];
             a.cols_per_chunk = p->chunk[1];
-            a.K = f32s ? (const void *)p->K32[1] : (const void *)p->K[1];
+            a.K = p->K[1];
             a.Kd = (int64_t)(M[2] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
-            a.part = f32s ? (void *)p->partf[1] : (void *)p->part[1];
-            a.part_f32 = f32s;
+            a.part = p->part[1];
             a.Bout = nullptr;
             a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
@@ -719,11 +826,10 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[1];
             a.Mo = M[1];
             a.cols_per_chunk = p->chunk[2];
-            a.K = f32s ? (const void *)p->K32[2] : (const void *)p->K[2];
+            a.K = p->K[2];
             a.Kd = (int64_t)(M[1] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
-            a.part = f32s ? (void *)p->partf[2] : (void *)p->part[2];
-            a.part_f32 = f32s;
+            a.part = p->part[2];
             a.Bout = nullptr;
             a.W = tile_width(N[0], p->work, a.ncols);
             a.fd = p->fd[0];
@@ -741,7 +847,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             const int r = fr[fam], c = fc[fam];
             const int64_t plane = (int64_t)N[r] * N[c];
             PassArgs a{};
-            a.in = f32s ? (const void *)p->partf[fam] : (const void *)p->part[fam];
+            a.in = p->part[fam];
             a.out = p->F[fam];
             a.irs = a.ors = 1;
             a.ics = a.ocs = N[c];
@@ -758,15 +864,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.scale = 1.0 / N[c];
             // few faces: narrow tiles give enough blocks to fill the device
             a.W = tile_width(N[c], std::min(p->work, 512), a.ncols);
-            if (f32s) {
-                // FP32 chunk partials, summed and transformed in FP64
-                a.fd = p->fd[c];
-                a.tw = p->tw[c];
-                a.twf = p->twf[c];
-                IPS_HIP(launch_pass_in32(a, st));
-            } else if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) {
-                return rc;
-            }
+            if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) return rc;
             PassArgs b{};
             b.in = b.out = p->F[fam];
             b.irs = b.ors = N[c];
@@ -1029,39 +1127,23 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
 
 // ---- adjoint ---------------------------------------------------------------------------
 
+// Adjoint buffers of a plan whose workspace does not hold them: one block,
+// allocated by the first adjoint call.
 int adj_alloc(ips_plan p)
 {
     if (p->adj_ready || p->d == 1) {
         p->adj_ready = true;
         return IPS_OK;
     }
-    const int d = p->d;
-    size_t vol = 1, grid = 1;
-    for (int a = 0; a < d; ++a) {
-        vol *= (size_t)p->I[a];
-        grid *= (size_t)p->n[a];
-    }
-    int rc;
-    if ((rc = p->mem.alloc((void **)&p->AX, vol * sizeof(double)))) return rc;
-    if ((rc = p->mem.alloc((void **)&p->AY, vol * sizeof(double)))) return rc;
-    if (p->order == 6) {
-        if ((rc = p->mem.alloc((void **)&p->AX2, vol * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&p->AF, grid * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&p->AU, grid * sizeof(double)))) return rc;
-    }
-    size_t zmax = 0;
-    for (int fam = 0; fam < d; ++fam) {
-        int b, c;
-        kaxes(d, fam, b, c);
-        const size_t lf = 2 * (size_t)(p->M[b] + 1) * (d == 3 ? (size_t)(p->M[c] + 1) : 1);
-        const size_t lh = 2 * (size_t)p->N[b] * (d == 3 ? (size_t)p->N[c] : 1);
-        if ((rc = p->mem.alloc((void **)&p->LF[fam], lf * sizeof(double)))) return rc;
-        if ((rc = p->mem.alloc((void **)&p->LH[fam], lh * sizeof(double)))) return rc;
-        if (d == 3) zmax = std::max(zmax, (size_t)p->I[fam] * p->N[b] * p->I[c]);
-    }
-    // order 6 also uses it as one grid-shaped scratch array (adjoint stencil)
-    if (d == 3 && p->order == 6) zmax = std::max(zmax, grid);
-    if (d == 3 && (rc = p->mem.alloc((void **)&p->AZ, zmax * sizeof(double)))) return rc;
+    if (p->ws_adj) return fail(IPS_E_WORKSPACE, "the plan has no workspace bound");
+    Carver c;
+    layout_adj(p, c);
+    void *blk = nullptr;
+    int rc = p->adjmem.alloc(&blk, c.off);
+    if (rc) return rc;
+    c.base = static_cast<char *>(blk);
+    c.off = 0;
+    layout_adj(p, c);
     p->adj_ready = true;
     return IPS_OK;
 }
@@ -1392,12 +1474,49 @@ void plan_free(ips_plan p)
     if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     p->mem.release();
+    p->wsmem.release();
+    p->adjmem.release();
     if (cur != p->device) (void)hipSetDevice(cur);
     delete p;
 }
 
+// Plan cache of ips_solve / ips_solve_ex: least recently used plans beyond
+// the capacity (IPS_SOLVE_CACHE plans, default 4) are destroyed, except those
+// another thread is using.
+using CacheKey = std::tuple<int, int, int64_t, int64_t, int64_t, double, double, double, int, int>;
+struct CacheEnt {
+    ips_plan p = nullptr;
+    uint64_t last = 0; // use tick
+    int users = 0;     // threads inside a solve with this plan
+};
 std::mutex g_cache_mu;
-std::map<std::tuple<int, int, int64_t, int64_t, int64_t, double, double, double, int>, ips_plan> g_cache;
+std::map<CacheKey, CacheEnt> g_cache;
+uint64_t g_cache_tick = 0;
+
+size_t cache_capacity()
+{
+    static const size_t cap = [] {
+        const char *e = getenv("IPS_SOLVE_CACHE");
+        const long v = e ? atol(e) : 4;
+        return (size_t)(v < 1 ? 1 : v);
+    }();
+    return cap;
+}
+
+// Destroy idle entries, least recently used first, until at most `keep`
+// remain (entries in use are skipped).  Call with g_cache_mu held.
+void cache_trim(size_t keep)
+{
+    while (g_cache.size() > keep) {
+        auto victim = g_cache.end();
+        for (auto it = g_cache.begin(); it != g_cache.end(); ++it)
+            if (it->second.users == 0 && (victim == g_cache.end() || it->second.last < victim->second.last))
+                victim = it;
+        if (victim == g_cache.end()) return;
+        plan_free(victim->second.p);
+        g_cache.erase(victim);
+    }
+}
 
 } // namespace
 
@@ -1405,6 +1524,7 @@ std::map<std::tuple<int, int, int64_t, int64_t, int64_t, double, double, double,
 int plan_create_work(ips_plan *out, int d, const int64_t *n, const double *h, int order,
                      int precision, unsigned flags, int work)
 {
+    g_alloc_seq = 0;
     ips_plan p = new (std::nothrow) ips_plan_s();
     if (!p) return fail(IPS_E_NO_MEMORY, "host allocation failed");
     p->d = d;
@@ -1425,7 +1545,19 @@ int plan_create_work(ips_plan *out, int d, const int64_t *n, const double *h, in
         return fail(IPS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
     int rc = plan_build(p, nullptr);
-    if (rc == IPS_OK && (flags & IPS_FLAG_ADJOINT)) rc = adj_alloc(p);
+    if (rc == IPS_OK) {
+        // execution workspace: measured, then owned by the plan unless the
+        // caller brings it (IPS_FLAG_NO_WORKSPACE, ips_plan_set_workspace)
+        p->ws_adj = (flags & IPS_FLAG_ADJOINT) != 0 && d > 1;
+        p->ws_bytes = measure_ws(p);
+        if (d == 1) {
+            p->adj_ready = true;
+        } else if (!(flags & IPS_FLAG_NO_WORKSPACE)) {
+            void *blk = nullptr;
+            rc = p->wsmem.alloc(&blk, p->ws_bytes);
+            if (rc == IPS_OK) bind_ws(p, blk);
+        }
+    }
     if (rc == IPS_OK) {
         e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("plan build: ") + hipGetErrorString(e));
@@ -1582,7 +1714,51 @@ int ips_plan_create(ips_plan *out, int d, const int64_t *n, const double *h, int
 int ips_plan_workspace_size(ips_plan p, size_t *bytes)
 {
     if (!p || !bytes) return fail(IPS_E_INVALID_ARG, "NULL argument");
-    *bytes = p->mem.bytes + (p->inner ? p->inner->mem.bytes : 0);
+    *bytes = p->inner ? p->inner->ws_bytes : p->ws_bytes;
+    return IPS_OK;
+}
+
+int ips_plan_table_size(ips_plan p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    *bytes = p->mem.bytes + p->adjmem.bytes + (p->inner ? p->inner->mem.bytes + p->inner->adjmem.bytes : 0);
+    return IPS_OK;
+}
+
+int ips_plan_set_workspace(ips_plan p, void *dev_ptr, size_t bytes)
+{
+    if (!p) return fail(IPS_E_INVALID_ARG, "plan must not be NULL");
+    if (p->inner) return ips_plan_set_workspace(p->inner, dev_ptr, bytes);
+    if (p->d == 1) return IPS_OK; // the 1D solve needs no workspace
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
+    if (!dev_ptr) {
+        if (bytes != 0) return fail(IPS_E_INVALID_ARG, "a NULL workspace must come with 0 bytes");
+        // back to a plan-owned block
+        if (p->wsmem.ptrs.empty()) {
+            void *blk = nullptr;
+            int rc = p->wsmem.alloc(&blk, p->ws_bytes);
+            if (rc) return rc;
+        }
+        bind_ws(p, p->wsmem.ptrs[0]);
+        return IPS_OK;
+    }
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0)
+        return fail(IPS_E_INVALID_ARG, "the workspace must be 256-byte aligned");
+    if (bytes < p->ws_bytes)
+        return fail(IPS_E_WORKSPACE, "workspace of " + std::to_string(bytes) + " bytes, the plan needs " +
+                                         std::to_string(p->ws_bytes));
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type == hipMemoryTypeHost ||
+        attr.device != p->device) {
+        (void)hipGetLastError();
+        return fail(IPS_E_INVALID_ARG, "the workspace must be device memory of the plan's device");
+    }
+    // the plan's own block is released: the previous solves on it must have
+    // completed (hipFree waits for the device)
+    p->wsmem.release();
+    bind_ws(p, dev_ptr);
     return IPS_OK;
 }
 
@@ -1659,7 +1835,11 @@ int ips_execute(ips_plan p, const double *rho, double *phi, void *stream)
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
         return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
-    if (p->inner) return execute_extended(p, rho, phi, static_cast<hipStream_t>(stream), false);
+    if (p->inner) {
+        if (!p->inner->ws && p->d > 1) return fail(IPS_E_WORKSPACE, "the plan has no workspace bound");
+        return execute_extended(p, rho, phi, static_cast<hipStream_t>(stream), false);
+    }
+    if (!p->ws && p->d > 1) return fail(IPS_E_WORKSPACE, "the plan has no workspace bound");
     return execute(p, rho, phi, static_cast<hipStream_t>(stream));
 }
 
@@ -1727,7 +1907,7 @@ int ips_plan_destroy(ips_plan p)
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         for (auto it = g_cache.begin(); it != g_cache.end(); ++it)
-            if (it->second == p) {
+            if (it->second.p == p) {
                 g_cache.erase(it);
                 break;
             }
@@ -1736,30 +1916,77 @@ int ips_plan_destroy(ips_plan p)
     return IPS_OK;
 }
 
-int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int order, double *phi)
+int ips_solve_ex(int d, const int64_t *n, const double *h, const double *rho, int order, int precision,
+                 double *phi)
 {
-    int rc = validate(d, n, h, order, IPS_FP64, 0);
+    int rc = validate(d, n, h, order, precision, 0);
     if (rc) return rc;
     if (!rho || !phi) return fail(IPS_E_INVALID_ARG, "rho and phi must not be NULL");
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(IPS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
-    auto key = std::make_tuple(dev, d, n[0], d > 1 ? n[1] : 0, d > 2 ? n[2] : 0, h[0],
-                               d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0, d == 1 ? 4 : order);
+    const CacheKey key = std::make_tuple(dev, d, n[0], d > 1 ? n[1] : 0, d > 2 ? n[2] : 0, h[0],
+                                         d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0, d == 1 ? 4 : order, precision);
     ips_plan p = nullptr;
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto it = g_cache.find(key);
-    if (it != g_cache.end()) {
-        p = it->second;
-    } else {
-        rc = ips_plan_create(&p, d, n, h, order, IPS_FP64, 0);
-        if (rc) return rc;
-        g_cache[key] = p;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            p = it->second.p;
+        } else {
+            rc = ips_plan_create(&p, d, n, h, order, precision, 0);
+            if (rc) return rc;
+            it = g_cache.emplace(key, CacheEnt{p, 0, 0}).first;
+        }
+        it->second.users += 1;
+        it->second.last = ++g_cache_tick;
+        cache_trim(cache_capacity());
     }
-    rc = ips_execute(p, rho, phi, nullptr);
-    if (rc) return rc;
-    e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess) return fail(IPS_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    {
+        // the enqueue of one solve must not interleave with another thread's
+        // solve on the same plan (they share its workspace); the wait for the
+        // device happens outside every lock
+        std::lock_guard<std::mutex> plk(p->exec_mu);
+        rc = ips_execute(p, rho, phi, nullptr);
+    }
+    if (rc == IPS_OK) {
+        e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) it->second.users -= 1;
+        cache_trim(cache_capacity());
+    }
+    return rc;
+}
+
+int ips_solve(int d, const int64_t *n, const double *h, const double *rho, int order, double *phi)
+{
+    return ips_solve_ex(d, n, h, rho, order, IPS_FP64, phi);
+}
+
+int ips_solve_release_cache(void)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    cache_trim(0);
+    return IPS_OK;
+}
+
+int ips_live_device_bytes(size_t *bytes)
+{
+    if (!bytes) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    const int64_t v = g_live_bytes.load();
+    *bytes = (size_t)(v < 0 ? 0 : v);
+    return IPS_OK;
+}
+
+int ips_solve_cache_size(size_t *plans)
+{
+    if (!plans) return fail(IPS_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    *plans = g_cache.size();
     return IPS_OK;
 }
 
@@ -1857,7 +2084,7 @@ int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)
     b->eager = (flags & IPS_FLAG_BATCH_EAGER) != 0;
     (void)hipGetDevice(&b->device);
     // per-problem plans: no stage timing inside a batch
-    const unsigned pflags = flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_BATCH_EAGER);
+    const unsigned pflags = flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_BATCH_EAGER | IPS_FLAG_NO_WORKSPACE);
     std::vector<std::pair<int64_t, int>> sz;
     for (int i = 0; i < count; ++i) {
         ips_plan p = nullptr;

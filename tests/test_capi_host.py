@@ -67,7 +67,7 @@ def test_plan_create_rejects_bad_geometry(args, code):
 def test_plan_create_rejects_bad_order_precision_flags():
     assert _create(2, [9, 9], [0.1, 0.1], order=5)[0] == -1
     assert _create(2, [9, 9], [0.1, 0.1], precision=7)[0] == -1
-    assert _create(2, [9, 9], [0.1, 0.1], flags=16)[0] == -1
+    assert _create(2, [9, 9], [0.1, 0.1], flags=32)[0] == -1
     assert _create(1, [9], [0.1], precision=1)[0] == -2
 
 
@@ -78,6 +78,24 @@ def test_null_arguments_are_rejected():
     assert L.ips_plan_create(ctypes.byref(h), 2, None, _lib.f64_array([0.1, 0.1]), 6, 0, 0) == -1
     assert L.ips_execute(None, None, None, None) == -1
     assert L.ips_execute_adjoint(None, None, None, None) == -1
+    n = ctypes.c_size_t()
+    assert L.ips_plan_workspace_size(None, ctypes.byref(n)) == -1
+    assert L.ips_plan_table_size(None, ctypes.byref(n)) == -1
+    assert L.ips_plan_set_workspace(None, None, 0) == -1
+    assert L.ips_live_device_bytes(None) == -1
+    assert L.ips_solve_cache_size(None) == -1
+    assert L.ips_solve_cache_size(ctypes.byref(n)) == 0 and n.value == 0
+    assert L.ips_live_device_bytes(ctypes.byref(n)) == 0 and n.value == 0
+    assert L.ips_solve_release_cache() == 0
+
+
+def test_solve_ex_rejects_bad_precision_before_the_device():
+    L = _lib.lib()
+    n = _lib.i64_array([9, 9, 9])
+    h = _lib.f64_array([0.1] * 3)
+    assert L.ips_solve_ex(3, n, h, None, 6, 9, None) == -1
+    assert L.ips_solve_ex(1, _lib.i64_array([9]), _lib.f64_array([0.1]), None, 6, 1, None) == -2
+    assert L.ips_solve_ex(3, n, h, None, 6, 0, None) == -1  # NULL arrays
     assert L.ips_solve(2, _lib.i64_array([9, 9]), _lib.f64_array([0.1, 0.1]), None, 6, None) == -1
     n = ctypes.c_size_t()
     assert L.ips_plan_workspace_size(None, ctypes.byref(n)) == -1

@@ -75,11 +75,16 @@ def test_table1_convergence_rates(order):
         rates.append(rate)
         banner("order %d  p %d  errors %s  rate %.2f  (paper %.1f)"
                % (order, p, " ".join("%.2e" % e for e in errs), rate, ref))
-    # The paper gives the h window of each regression but not the mesh widths
-    # inside it; before the asymptotic regime the local slopes vary by about
-    # +-1 inside the window (for p = 7, order 6: 7.5 to 9.6 between
-    # neighbouring widths here), hence the tolerance of 1.25.
+    # Per-entry tolerances around the printed rates.  Measured here (p = 1, 3,
+    # 5, 7, 9): order 4: 2.42 4.49 4.93 4.00 4.00; order 6: 2.43 4.43 6.62
+    # 8.65 10.11.  Most entries agree within 0.25.  The paper gives the h
+    # window of each regression but not the mesh widths inside it, and for the
+    # smoothest densities at order 6 the local slopes still vary inside the
+    # window (p = 7: 7.5 to 9.6 between neighbouring widths here), so those
+    # two entries carry the measured gap plus 0.15.
+    tol = {4: {1: 0.25, 3: 0.25, 7: 0.25, 9: 0.25}, 6: {1: 0.25, 3: 0.25, 5: 0.25, 7: 1.3, 9: 0.85}}[order]
     for p, rate, ref in zip(gold["p"], rates, paper):
+        banner("order %d p %d: rate %.2f, paper %.1f, deviation %+.2f" % (order, p, rate, ref, rate - ref))
         if order == 4 and p == 5:
             # At h in [0.01, 0.02] this case sits where the spectral error of
             # phi_star (rate 6.6, the 6th-order row) and the 4th-order error of
@@ -88,7 +93,7 @@ def test_table1_convergence_rates(order):
             # constants; the paper's run landed on the phi_star side.
             assert 4.0 - 0.25 <= rate <= ref + 0.25, (rates, paper)
         else:
-            assert abs(rate - ref) <= 1.25, (rates, paper)
+            assert abs(rate - ref) <= tol[p], (p, rates, paper)
     if order == 6:
         # spectral accuracy: the rate grows with the smoothness of rho
         assert all(b > a + 1.0 for a, b in zip(rates, rates[1:])), rates
@@ -113,4 +118,8 @@ def test_figure2_domain_invariance():
             diff = float(np.abs(sub - base).max() / np.abs(base).max())
             banner("order %d D %.1f: variation %.2e (error of the [-1,1] solve %.2e)" % (order, D, diff, err))
             # the paper: variation at most the size of the discretisation error
+            # (order 4), and essentially machine precision at order 6 except at
+            # the largest mesh width (measured 7.8e-12 at h = 0.02)
             assert diff <= err
+            if order == 6:
+                assert diff <= 1e-10
