@@ -209,6 +209,29 @@ int ips_plan_create_extended(ips_plan *out, int d, const int64_t *n, const doubl
 int ips_execute(ips_plan p, const double *rho, double *phi, void *stream);
 
 /*
+ * ips_execute_static -- ips_execute without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The solve runs in a scratch array
+ * that the library holds in device memory, one per GPU, of
+ * IPS_STATIC_SCRATCH_BYTES bytes, instead of the plan's workspace; the
+ * plan's own workspace binding is left as it was (a plan created with
+ * IPS_FLAG_NO_WORKSPACE holds tables only).  The call itself allocates
+ * nothing and performs no host synchronisation.
+ *   p, rho, phi, stream : as ips_execute
+ * Every call on one GPU shares that GPU's array and leaves its last contents
+ * there; the solve writes every scratch value it reads, so nothing needs
+ * clearing.  Calls whose work overlaps in time on one GPU (other streams,
+ * other threads, other plans) race on the array: serialise them.
+ * Errors: as ips_execute; IPS_E_WORKSPACE when the plan's workspace
+ * (ips_plan_workspace_size) exceeds IPS_STATIC_SCRATCH_BYTES (3D grids up to
+ * about 97^3 in FP64 fit); IPS_E_DEVICE if the array's address cannot be
+ * obtained.
+ */
+#define IPS_STATIC_SCRATCH_BYTES (64u << 20)
+
+int ips_execute_static(ips_plan p, const double *rho, double *phi, void *stream);
+
+/*
  * ips_execute_adjoint -- enqueue rho_bar = A^T phi_bar, where A is the
  * linear map rho -> phi of the method (Sections 2-5) at the plan's grid and
  * order, i.e. the transpose of the FP64 solve.  Every step runs in FP64

@@ -29,6 +29,7 @@ IPS_FLAG_ADJOINT = 2
 IPS_FLAG_AUTOTUNE = 4
 IPS_FLAG_BATCH_EAGER = 8
 IPS_FLAG_NO_WORKSPACE = 16
+IPS_STATIC_SCRATCH_BYTES = 64 << 20
 STAGES = ["rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces", "shell_gt", "shell_r6",
           "final", "inv_y", "inv_z", "adjoint"]
 
@@ -55,6 +56,7 @@ SIGNATURES = {
         [ctypes.POINTER(_vp), ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _i64p],
     ),
     "ips_execute": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "ips_execute_static": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ips_execute_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ips_plan_destroy": (ctypes.c_int, [_vp]),
     "ips_batch_create": (

@@ -1673,6 +1673,35 @@ int execute_extended(ips_plan p, const double *in, double *out, hipStream_t st, 
     return IPS_OK;
 }
 
+// Library-held scratch for ips_execute_static: one fixed device array per
+// GPU (every device that loads the library holds it until the process ends).
+// Host code never uses the array's name as an address: the device address
+// of each GPU's copy comes from hipGetSymbolAddress with that GPU current.
+constexpr size_t kStaticScratchBytes = (size_t)IPS_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array (looked up once per device).
+int static_scratch(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(IPS_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q) {
+            (void)hipGetLastError();
+            return fail(IPS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = q;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return IPS_OK;
+}
+
 extern "C" {
 
 const char *ips_status_string(int status)
@@ -1841,6 +1870,42 @@ int ips_execute(ips_plan p, const double *rho, double *phi, void *stream)
     }
     if (!p->ws && p->d > 1) return fail(IPS_E_WORKSPACE, "the plan has no workspace bound");
     return execute(p, rho, phi, static_cast<hipStream_t>(stream));
+}
+
+int ips_execute_static(ips_plan p, const double *rho, double *phi, void *stream)
+{
+    if (!p) return fail(IPS_E_INVALID_ARG, "plan must not be NULL");
+    if (!rho || !phi) return fail(IPS_E_INVALID_ARG, "rho and phi must not be NULL");
+    size_t cnt = 1;
+    for (int a = 0; a < p->d; ++a) cnt *= (size_t)p->n[a];
+    const char *r0 = reinterpret_cast<const char *>(rho), *p0 = reinterpret_cast<const char *>(phi);
+    if (r0 < p0 + cnt * sizeof(double) && p0 < r0 + cnt * sizeof(double))
+        return fail(IPS_E_INVALID_ARG, "rho and phi must not overlap");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
+    ips_plan q = p->inner ? p->inner : p; // the plan whose workspace the solve uses
+    if (q->ws_bytes > kStaticScratchBytes)
+        return fail(IPS_E_WORKSPACE, "the plan needs " + std::to_string(q->ws_bytes) +
+                                         " bytes of workspace, the static scratch holds " +
+                                         std::to_string(kStaticScratchBytes));
+    void *sp = nullptr;
+    int rc = static_scratch(cur, &sp);
+    if (rc) return rc;
+    // run on the scratch, then give the plan its own binding back (kernel
+    // arguments are fixed when a launch is enqueued)
+    void *saved = q->ws;
+    const bool saved_adj = q->adj_ready;
+    if (q->d > 1) bind_ws(q, sp);
+    if (p->inner)
+        rc = execute_extended(p, rho, phi, static_cast<hipStream_t>(stream), false);
+    else
+        rc = execute(p, rho, phi, static_cast<hipStream_t>(stream));
+    if (q->d > 1) {
+        bind_ws(q, saved);
+        q->adj_ready = saved_adj;
+    }
+    return rc;
 }
 
 int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void *stream)
