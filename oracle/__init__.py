@@ -10,6 +10,8 @@ Modules
 poisson       the method, step by step, in plain numpy FP64 (dense sine
               matrices, direct stencils, direct boundary quadrature)
 closed_forms  exact potentials of the compact radial test densities
+screening     boundary values from the screening charge d phi*/dn and a
+              corrected surface trapezoidal rule (James-type methods)
 quad.c        direct boundary quadrature in plain C (OpenMP over targets)
 """
-from . import poisson, closed_forms  # noqa: F401
+from . import poisson, closed_forms, screening  # noqa: F401
