@@ -275,12 +275,30 @@ typedef enum {
     IPS_STAGE_INV_Y = 9,  /* inverse sine transform along axis 1 (3D) */
     IPS_STAGE_INV_Z = 10, /* inverse sine transform along the last axis into phi */
     IPS_STAGE_ADJOINT = 11, /* one whole ips_execute_adjoint */
-    IPS_STAGE_COUNT = 12
+    IPS_STAGE_SCREEN = 12,  /* screening charge and surface sums (IPS_FLAG_SCREENING;
+                               its sine transforms of rho count as rho_z) */
+    IPS_STAGE_COUNT = 13
 } ips_stage;
 
 const char *ips_stage_name(int stage);
 int ips_plan_stage_time(ips_plan p, int stage, double *ms_total, int64_t *calls);
 int ips_plan_reset_stage_times(ips_plan p);
+
+/*
+ * Boundary values from the screening charge (the James-type methods the
+ * paper builds on, Sections 1 and 2) instead of the volume sums of Section 4.
+ * A plan created with IPS_FLAG_SCREENING computes
+ *   g(x) = surface integral of G(|x - s|) sigma(s) dS(s),  sigma = d phi_star / dn,
+ * with sigma from the sine coefficients of phi_star (Section 3) and the surface
+ * integral by the trapezoidal rule on each face (fourth-order Gregory weights
+ * at the face edges, the target node left out, a third-order correction of
+ * the 1/r or log r singularity at the target), then the harmonic part of
+ * Section 5 as usual.  1D: the exact two-point sum.  FP64 only, no adjoint;
+ * for d >= 2 every n[i] >= 7.  Its accuracy is that of the surface rule
+ * (about second order), not the spectral accuracy of the volume sums; the
+ * surface sums are evaluated directly (O(boundary nodes^2) work).
+ */
+#define IPS_FLAG_SCREENING 32u
 
 /* Release a plan and its device memory (waits for nothing: the caller must
  * make sure no enqueued work still uses it). NULL is accepted. */

@@ -29,9 +29,10 @@ IPS_FLAG_ADJOINT = 2
 IPS_FLAG_AUTOTUNE = 4
 IPS_FLAG_BATCH_EAGER = 8
 IPS_FLAG_NO_WORKSPACE = 16
+IPS_FLAG_SCREENING = 32
 IPS_STATIC_SCRATCH_BYTES = 64 << 20
 STAGES = ["rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces", "shell_gt", "shell_r6",
-          "final", "inv_y", "inv_z", "adjoint"]
+          "final", "inv_y", "inv_z", "adjoint", "screen"]
 
 # Every exported symbol with (restype, argtypes).
 _i64p = ctypes.POINTER(ctypes.c_int64)

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kernels.hip", "pass.hip", "conv.hip", "adjoint.hip", "plan.hip"]
+SOURCES = ["kernels.hip", "pass.hip", "conv.hip", "adjoint.hip", "screen.hip", "plan.hip"]
 LIB = os.path.join(HERE, "libipoisson.so")
 ARCH = os.environ.get("IPS_OFFLOAD_ARCH", "gfx950")
 

@@ -123,9 +123,32 @@ struct FinalArgs {
     FftDesc fd;
     const cx<double> *tw;
     const cx<float> *twf;
+    int group;      // neighbouring column blocks taken together (their rows share 128-byte lines)
+    int pre;        // buf already holds the raw sine spectrum along axis 0 (no forward transform)
     void *rowtab;   // if set: row table [nbatch][M0 - 1][12] (transform type) in global memory, written by
                     // launch_final_rows before the pass (required for transforms longer than 2048)
 };
+
+// Boundary values from the screening charge (screen.hip).
+struct ScreenArgs {
+    int d;
+    int M[3];
+    double h[3];
+    double piL[3];       // pi / L_a
+    double pref;         // prod 2/M_a
+    double tau[3];       // singular correction of a target inside a face of axis a
+    AxisTabs tab[3];
+    const double *Y;     // raw sine spectrum of rho_I, final-pass layout
+    double *S[3];        // face coefficients, then (after the inverse transforms) sigma: [2][I_b][I_c]
+    const double *sig[3];
+    double *src;         // [4][nsrc]: x, y, z, W sigma
+    int64_t nsrc, ntgt;  // surface nodes with sigma, boundary nodes
+};
+
+// face coefficients of sigma from Y
+hipError_t launch_screen(const ScreenArgs &a, double *phi, hipStream_t st);
+// surface nodes and g at every boundary node of phi
+hipError_t launch_screen_g(const ScreenArgs &a, double *phi, hipStream_t st);
 
 // Sixth-order right-hand side on the depth-5 shell layers (see k_r6t).
 struct R6Args {
@@ -224,8 +247,9 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st);
 // the in-face axes in storage order (c contiguous).
 hipError_t launch_ksample(double *out, int d, int a, int b, int c, const int *M, const double *h,
                           hipStream_t st);
+// screen: end values from the screening charge instead of the direct sums
 hipError_t launch_1d(const double *rho, double *phi, int M, double h, const FftDesc &fd,
-                     const cx<double> *tw, const AxisTabs &tab, double *scratch, hipStream_t st);
+                     const cx<double> *tw, const AxisTabs &tab, int screen, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 

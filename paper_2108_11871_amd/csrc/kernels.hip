@@ -805,19 +805,23 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     T *buf = reinterpret_cast<T *>(smem + twb);
     const int ncb = (a.ncols + W - 1) / W;
     const int grid = gridDim.x;
-    // logical order: pairs of neighbouring column blocks, then the batch, then
-    // the pair index -- each XCD sweeps all batches over a narrow band of
-    // columns, so the per-element shell data of that band stays in its L2
+    // logical order: groups of a.group neighbouring column blocks (together one
+    // 128-byte line of every row), then the batch, then the group index -- the
+    // blocks that share a line run side by side on one XCD, and each XCD sweeps
+    // all batches over a narrow band of columns, so the per-element shell data
+    // of that band stays in its L2
     auto decode = [&](int lb, int &cb, int &bt) {
-        const int pairs = ncb / 2;
-        if (lb < 2 * pairs * a.nbatch) {
-            const int pr = lb / (2 * a.nbatch), rem = lb % (2 * a.nbatch);
-            bt = rem >> 1;
-            cb = 2 * pr + (rem & 1);
+        const int G = a.group;
+        const int full = ncb / G;
+        if (lb < G * full * a.nbatch) {
+            const int pr = lb / (G * a.nbatch), rem = lb % (G * a.nbatch);
+            bt = rem / G;
+            cb = G * pr + rem % G;
         } else {
-            const int rem = lb - 2 * pairs * a.nbatch; // odd ncb: last column block
-            bt = rem;
-            cb = ncb - 1;
+            const int left = ncb - G * full; // the last, partial group
+            const int rem = lb - G * full * a.nbatch;
+            bt = rem / left;
+            cb = G * full + rem % left;
         }
     };
     const int lb0 = xcd_remap(blockIdx.x, grid);
@@ -919,7 +923,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
             for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = (T)a.sh.P[0][(par * 3 + t) * ss0 + o];
     }
     __syncthreads();
-    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
+    if (!a.pre) fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
     // One sweep over the row pairs (k, N-k) of every complex sequence s
     // (real columns 2s and 2s+1):
     //   sine coefficients  S_a = (z(N-k).y - z(k).y)/2,  S_b = (z(k).x - z(N-k).x)/2
@@ -950,7 +954,8 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
         for (int sq = 0; sq < nseq; ++sq) {
             const cx<T> z1 = lds_c(buf, rs, k, sq), z2 = lds_c(buf, rs, N - k, sq);
             T cab[2];
-            const T beta2[2] = {(T)0.5 * (z2.y - z1.y), (T)0.5 * (z1.x - z2.x)};
+            // the spectrum as loaded (pre), or from the forward transform
+            const T beta2[2] = {a.pre ? z1.x : (T)0.5 * (z2.y - z1.y), a.pre ? z1.y : (T)0.5 * (z1.x - z2.x)};
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
                 const int c = 2 * sq + h2;
@@ -1157,9 +1162,14 @@ hipError_t launch_ksample(double *out, int d, int a, int b, int c, const int *M,
 // 1D: phi* by one sine-transform pencil, end values by direct sums of
 // G(r) = r/2, phi_H linear between them.
 // ---------------------------------------------------------------------------
+// screen != 0: the end values come from the screening charge instead: with the
+// sine coefficients alpha_k of phi*, sigma_lo = -sum (pi k/L) alpha_k and
+// sigma_hi = sum (pi k/L)(-1)^k alpha_k are the outward derivatives at the two
+// ends and g(x) = sum over both ends of G(|x - end|) sigma, i.e.
+// g_0 = (L/2) sigma_hi and g_M = (L/2) sigma_lo (G = r/2 vanishes at r = 0).
 template <int MAXE, int NTT>
 __global__ __launch_bounds__(NTT) void k_1d(const double *rho, double *phi, int M, double h,
-                                            FftDesc fd, const cx<double> *twg, AxisTabs tab)
+                                            FftDesc fd, const cx<double> *twg, AxisTabs tab, int screen)
 {
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1187,11 +1197,33 @@ __global__ __launch_bounds__(NTT) void k_1d(const double *rho, double *phi, int 
         }
         __syncthreads();
     }
-    const double g0 = h * red[0][0], g1 = h * red[1][0];
+    double g0 = h * red[0][0], g1 = h * red[1][0];
     fft_tile<double, MAXE, NTT>(buf, rs, 0, fd, tw, false);
     post_cs<double, MAXE, NTT>(buf, rs, 0, M);
-    for (int k = 1 + threadIdx.x; k < M; k += NTT)
-        buf[(M + k) * rs] = -(2.0 / M) * buf[(M + k) * rs] / tab.q[k - 1];
+    __syncthreads();
+    double slo = 0.0, shi = 0.0;
+    const double L = M * h, piL = 3.14159265358979323846264338327950288 / L;
+    for (int k = 1 + threadIdx.x; k < M; k += NTT) {
+        const double al = -(2.0 / M) * buf[(M + k) * rs] / tab.q[k - 1];
+        buf[(M + k) * rs] = al;
+        const double t = (k * piL) * al;
+        slo -= t;
+        shi += (k & 1) ? -t : t;
+    }
+    if (screen) {
+        red[0][threadIdx.x] = slo;
+        red[1][threadIdx.x] = shi;
+        __syncthreads();
+        for (int w = NTT / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + w];
+                red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        g0 = 0.5 * L * red[1][0];
+        g1 = 0.5 * L * red[0][0];
+    }
     __syncthreads();
     pre_herm<double, MAXE, NTT>(buf, rs, 0, M, true);
     fft_tile<double, MAXE, NTT>(buf, rs, 0, fd, tw, true);
@@ -1208,25 +1240,24 @@ __global__ __launch_bounds__(NTT) void k_1d(const double *rho, double *phi, int 
 }
 
 hipError_t launch_1d(const double *rho, double *phi, int M, double h, const FftDesc &fd,
-                     const cx<double> *tw, const AxisTabs &tab, double * /*scratch*/,
-                     hipStream_t st)
+                     const cx<double> *tw, const AxisTabs &tab, int screen, hipStream_t st)
 {
     const size_t lds = tile_lds<double>(fd.N, 2);
     if (big_fft(fd.N)) {
         if (fd.N > 8 * NTB) return hipErrorInvalidValue;
         if (fd.N <= 4 * NTB) {
             set_lds((const void *)&k_1d<4, NTB>, lds);
-            hipLaunchKernelGGL((k_1d<4, NTB>), dim3(1), dim3(NTB), lds, st, rho, phi, M, h, fd, tw, tab);
+            hipLaunchKernelGGL((k_1d<4, NTB>), dim3(1), dim3(NTB), lds, st, rho, phi, M, h, fd, tw, tab, screen);
         } else {
             set_lds((const void *)&k_1d<8, NTB>, lds);
-            hipLaunchKernelGGL((k_1d<8, NTB>), dim3(1), dim3(NTB), lds, st, rho, phi, M, h, fd, tw, tab);
+            hipLaunchKernelGGL((k_1d<8, NTB>), dim3(1), dim3(NTB), lds, st, rho, phi, M, h, fd, tw, tab, screen);
         }
     } else if (fd.N <= 4 * NT) {
         set_lds((const void *)&k_1d<4, NT>, lds);
-        hipLaunchKernelGGL((k_1d<4, NT>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
+        hipLaunchKernelGGL((k_1d<4, NT>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab, screen);
     } else if (fd.N <= 8 * NT) {
         set_lds((const void *)&k_1d<8, NT>, lds);
-        hipLaunchKernelGGL((k_1d<8, NT>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab);
+        hipLaunchKernelGGL((k_1d<8, NT>), dim3(1), dim3(NT), lds, st, rho, phi, M, h, fd, tw, tab, screen);
     } else {
         return hipErrorInvalidValue;
     }

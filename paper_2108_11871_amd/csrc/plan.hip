@@ -153,6 +153,18 @@ int tile_width(int N, int maxwork, int ncols)
     return std::min(W, need);
 }
 
+// Blocks of a column-contraction launch the chunking aims at (IPS_CC_BLOCKS
+// overrides the default, for measurements).
+int cc_block_target()
+{
+    static const int v = [] {
+        const char *e = getenv("IPS_CC_BLOCKS");
+        const int x = e ? atoi(e) : 0;
+        return x >= 256 && x <= 65536 ? x : 6144;
+    }();
+    return v;
+}
+
 // In-face axes (b, c) of the kernel-spectrum table of face family `fam`, in
 // storage order K[dd][k_b][k_c] (c contiguous).  The column-contraction
 // kernels read K[dd][k_o][k_p] with k_p the transform (pencil) axis.
@@ -212,6 +224,12 @@ struct ips_plan_s {
     void *P2T = nullptr;                        // 3D: transposed family-2 copy (final pass type)
     bool cube = false; // all families share sizes and chunking (batched launches)
     double *C[3] = {nullptr, nullptr, nullptr}; // sixth-order right-hand side on core layers
+    // boundary values from the screening charge (IPS_FLAG_SCREENING)
+    bool screen = false;
+    double tau[3] = {0, 0, 0};                   // singular corrections of the surface sums
+    double *S[3] = {nullptr, nullptr, nullptr};  // face coefficients / sigma [2][I_b][I_c]
+    double *src = nullptr;                       // surface nodes [4][nsrc]
+    int64_t nsrc = 0, ntgt = 0;
     DevBuf mem;   // tables: twiddles, axis tables, kernel spectra (and an extended plan's arrays)
     // execution workspace: one block carved into the buffers above (B, A, part, F,
     // G, P, T, D, C, P1T, P2T, rowtab) and, for IPS_FLAG_ADJOINT plans, the adjoint's
@@ -249,6 +267,19 @@ int final_work(int precision)
     return 2048;
 }
 
+// Column blocks of the final pass that cover one 128-byte line of each row
+// (IPS_FINAL_GROUP overrides it, for measurements).
+int final_group(int W, int tsz)
+{
+    static const int env = [] {
+        const char *e = getenv("IPS_FINAL_GROUP");
+        return e ? atoi(e) : 0;
+    }();
+    if (env >= 1 && env <= 16) return env;
+    const int g = 128 / (W * tsz);
+    return g < 1 ? 1 : g;
+}
+
 // LDS bytes of the final pass along axis 0 (tile, twiddles, staged column
 // table).
 size_t final_pass_lds(int d, const int64_t *n, int precision, int work)
@@ -268,8 +299,16 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
     if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
     if (!n || !h) return fail(IPS_E_INVALID_ARG, "n and h must not be NULL");
     if (flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_ADJOINT | IPS_FLAG_AUTOTUNE | IPS_FLAG_BATCH_EAGER |
-                  IPS_FLAG_NO_WORKSPACE))
+                  IPS_FLAG_NO_WORKSPACE | IPS_FLAG_SCREENING))
         return fail(IPS_E_INVALID_ARG, "unknown flag bits");
+    if (flags & IPS_FLAG_SCREENING) {
+        if (precision != IPS_FP64) return fail(IPS_E_UNSUPPORTED, "the screening variant runs in FP64 only");
+        if (flags & IPS_FLAG_ADJOINT) return fail(IPS_E_UNSUPPORTED, "the screening variant has no adjoint");
+        if (d >= 2 && n)
+            for (int a = 0; a < d; ++a)
+                if (n[a] < 7)
+                    return fail(IPS_E_INVALID_ARG, "the screening variant needs n[i] >= 7 (surface end weights)");
+    }
     if (precision != IPS_FP64 && precision != IPS_MIXED_FP32 && precision != IPS_MIXED_FP32_SLICES)
         return fail(IPS_E_INVALID_ARG, "unknown precision");
     if (d >= 2 && order != 4 && order != 6) return fail(IPS_E_INVALID_ARG, "order must be 4 or 6");
@@ -387,6 +426,38 @@ int shell_dst_all(ips_plan p, TS *const *arr, int nl, bool inverse, hipStream_t 
     return IPS_OK;
 }
 
+// Regularised value of  integral over R^2 of 1/|x|  -  a b sum over x_j != 0
+// of 1/|x_j|  for the lattice x_j = (m a, n b): the constant that makes the
+// punctured trapezoidal rule third-order accurate at a 1/r singularity.
+// Ewald split 1/r = erfc(s r)/r + erf(s r)/r: the first part is summed over
+// the lattice directly, the second through Poisson summation over the
+// reciprocal lattice (2 pi m/a, 2 pi n/b), where its transform is
+// (2 pi/k) erfc(k/(2 s)); the removed k = 0 and r = 0 terms give
+// 2 sqrt(pi)/s and 2 s a b / sqrt(pi).
+double lattice_constant(double a, double b)
+{
+    const double pi = 3.141592653589793238462643383279502884;
+    const double area = a * b, s = 1.5 / std::sqrt(area), reach = 12.0;
+    const int mr = (int)std::ceil(reach / (s * a)), nr = (int)std::ceil(reach / (s * b));
+    long double real = 0.0L;
+    for (int m = -mr; m <= mr; ++m)
+        for (int n = -nr; n <= nr; ++n) {
+            if (m == 0 && n == 0) continue;
+            const double r = std::hypot(m * a, n * b);
+            real += (long double)(std::erfc(s * r) / r);
+        }
+    const int km = (int)std::ceil(s * reach * a / pi), kn = (int)std::ceil(s * reach * b / pi);
+    long double rec = 0.0L;
+    for (int m = -km; m <= km; ++m)
+        for (int n = -kn; n <= kn; ++n) {
+            if (m == 0 && n == 0) continue;
+            const double k = std::hypot(2.0 * pi * m / a, 2.0 * pi * n / b);
+            rec += (long double)(2.0 * pi / k * std::erfc(k / (2.0 * s)));
+        }
+    return (double)(2.0L * std::sqrt((long double)pi) / s - (long double)area * real - rec +
+                    2.0L * s * area / std::sqrt((long double)pi));
+}
+
 // Sub-buffers carved out of one device block, 256-byte aligned; with a null
 // base only the size is measured.
 struct Carver {
@@ -421,7 +492,31 @@ void layout_ws(ips_plan p, Carver &c)
     const size_t asz = p->precision == IPS_MIXED_FP32_SLICES ? sizeof(float) : sizeof(double);
     c.take(&p->B, vol * wsz);
     c.take(&p->rowtab, (d == 3 ? (size_t)I[2] : 1) * I[0] * 12 * sizeof(double));
-    if (d == 3) {
+    if (p->screen) {
+        // no slice transforms or chunk partials: the face coefficients of the
+        // screening charge and the surface node list instead
+        size_t ts = 0;
+        for (int fam = 0; fam < d; ++fam) {
+            size_t f = 1;
+            for (int b = 0; b < d; ++b)
+                if (b != fam) f *= (size_t)I[b];
+            ts += f;
+        }
+        double *bs;
+        c.take(&bs, 2 * ts * sizeof(double));
+        c.take(&p->src, 4 * 2 * ts * sizeof(double));
+        size_t os = 0;
+        for (int fam = 0; fam < 3; ++fam) {
+            p->S[fam] = nullptr;
+            if (fam >= d || !c.base) continue;
+            size_t f = 1;
+            for (int b = 0; b < d; ++b)
+                if (b != fam) f *= (size_t)I[b];
+            p->S[fam] = bs + os;
+            os += 2 * f;
+        }
+    }
+    if (d == 3 && !p->screen) {
         const size_t a1 = (size_t)I[0] * I[1] * N[2], a2 = (size_t)I[0] * N[1] * I[2];
         c.take(&p->A, std::max(a1, a2) * asz);
     } else {
@@ -442,9 +537,11 @@ void layout_ws(ips_plan p, Carver &c)
         tf += fsz[fam];
         ts += ssz[fam];
     }
-    double *bp, *bf, *bg, *bpk, *bt = nullptr, *bd = nullptr, *bc = nullptr;
-    c.take(&bp, tp * sizeof(double));
-    c.take(&bf, tf * sizeof(double));
+    double *bp = nullptr, *bf = nullptr, *bg, *bpk, *bt = nullptr, *bd = nullptr, *bc = nullptr;
+    if (!p->screen) {
+        c.take(&bp, tp * sizeof(double));
+        c.take(&bf, tf * sizeof(double));
+    }
     c.take(&bg, 2 * ts * sizeof(double));
     c.take(&bpk, 6 * ts * sizeof(double));
     if (p->order == 6) {
@@ -459,8 +556,8 @@ void layout_ws(ips_plan p, Carver &c)
     }
     if (c.base)
         for (int fam = 0; fam < d; ++fam) {
-            p->part[fam] = bp + op;
-            p->F[fam] = bf + of;
+            p->part[fam] = bp ? bp + op : nullptr;
+            p->F[fam] = bf ? bf + of : nullptr;
             p->G[fam] = bg + 2 * os;
             p->P[fam] = bpk + 6 * os;
             if (bt) {
@@ -599,7 +696,7 @@ int plan_build(ips_plan p, hipStream_t st)
         // about 6144 blocks of 256 threads (a few tiles each: measured faster
         // than fewer, longer blocks, although the face pass then sums more
         // chunk partials); 256 blocks of 1024 for long transforms
-        const int target = N[pen] > kLdsMaxN ? 256 : 6144;
+        const int target = N[pen] > kLdsMaxN ? 256 : cc_block_target();
         int nch = std::max(1, std::min(ncb, (target + nbatch - 1) / nbatch));
         const int per = (ncb + nch - 1) / nch;
         p->chunk[fam] = per * Wh;
@@ -609,6 +706,30 @@ int plan_build(ips_plan p, hipStream_t st)
     p->cube = true;
     for (int fam = 1; fam < d; ++fam)
         if (M[fam] != M[0] || p->nch[fam] != p->nch[0]) p->cube = false;
+    if (p->screen) {
+        // singular corrections of the surface sums (targets inside a face)
+        const double pi = 3.141592653589793238462643383279502884;
+        for (int fam = 0; fam < d; ++fam) {
+            if (d == 3) {
+                const int b = fam == 0 ? 1 : 0, c = fam == 2 ? 1 : 2;
+                p->tau[fam] = -lattice_constant(p->h[b], p->h[c]) / (4.0 * pi);
+            } else {
+                const double hb = p->h[1 - fam];
+                p->tau[fam] = hb * std::log(hb / (2.0 * pi)) / (2.0 * pi);
+            }
+        }
+        size_t ts = 0;
+        for (int fam = 0; fam < d; ++fam) {
+            size_t f = 1;
+            for (int b = 0; b < d; ++b)
+                if (b != fam) f *= (size_t)I[b];
+            ts += f;
+        }
+        p->nsrc = (int64_t)(2 * ts);
+        const int64_t n0 = p->n[0], n1 = p->n[1], n2 = d == 3 ? p->n[2] : 1;
+        p->ntgt = 2 * n1 * n2 + 2 * (n0 - 2) * n2 + (d == 3 ? 2 * (n0 - 2) * (n1 - 2) : 0);
+        return IPS_OK; // no kernel spectra: the volume sums are not used
+    }
     for (int fam = 0; fam < d; ++fam) {
         // kernel spectra: samples then even transforms along the in-face axes
         size_t ksz = (size_t)I[fam];
@@ -701,6 +822,113 @@ struct StageScope {
 #define IPS_CAT(a, b) IPS_CAT2(a, b)
 #define STAGE(id) StageScope IPS_CAT(stage_scope_, __LINE__)(p, (id), st)
 
+// Boundary values from the screening charge (d = 2, 3): the raw sine spectrum
+// of rho_I over all axes into B, in the final pass's layout ([k2][k0][k1],
+// 2D [k0][k1]); the face coefficients of sigma = d phi*/dn; sigma on the
+// faces by inverse sine transforms over the in-face axes; the corrected
+// surface sums at every boundary node of phi.
+int screen_boundary(ips_plan p, const double *rho, double *phi, hipStream_t st)
+{
+    const int d = p->d;
+    const int *I = p->I, *M = p->M;
+    const int64_t *n = p->n;
+    int rc;
+    {
+        STAGE(IPS_STAGE_RHO_Z);
+        PassArgs a{};
+        a.in_mode = IN_ZPAD;
+        a.scale = 1.0;
+        if (d == 3) {
+            // along z: rho[x][y][z] -> B[kz][x][y]
+            a.in = rho + n[1] * n[2] + n[2] + 1;
+            a.out = p->B;
+            a.irs = 1;
+            a.ics = n[2];
+            a.ibs = n[1] * n[2];
+            a.ors = (int64_t)I[0] * I[1];
+            a.ocs = 1;
+            a.obs = I[1];
+            a.nrows_in = I[2];
+            a.ncols = I[1];
+            a.nbatch = I[0];
+            a.out_r0 = M[2] + 1;
+            a.out_nrows = I[2];
+            if ((rc = run_pass(p, a, p->fd[2], p->tw[2], false, false, st))) return rc;
+            // along y, in place: B[kz][x][y] -> B[kz][x][ky]
+            PassArgs b = a;
+            b.in = p->B;
+            b.irs = b.ors = 1;
+            b.ics = b.ocs = I[1];
+            b.ibs = b.obs = (int64_t)I[0] * I[1];
+            b.nrows_in = I[1];
+            b.ncols = I[0];
+            b.nbatch = I[2];
+            b.out_r0 = M[1] + 1;
+            b.out_nrows = I[1];
+            b.W = 0;
+            if ((rc = run_pass(p, b, p->fd[1], p->tw[1], false, false, st))) return rc;
+            // along x, in place: B[kz][x][ky] -> B[kz][kx][ky]
+            PassArgs c = b;
+            c.irs = c.ors = I[1];
+            c.ics = c.ocs = 1;
+            c.nrows_in = I[0];
+            c.ncols = I[1];
+            c.nbatch = I[2];
+            c.out_r0 = M[0] + 1;
+            c.out_nrows = I[0];
+            c.W = 0;
+            if ((rc = run_pass(p, c, p->fd[0], p->tw[0], false, false, st))) return rc;
+        } else {
+            // along y: rho[x][y] -> B[x][ky]; then along x in place
+            a.in = rho + n[1] + 1;
+            a.out = p->B;
+            a.irs = 1;
+            a.ics = n[1];
+            a.ors = 1;
+            a.ocs = I[1];
+            a.nrows_in = I[1];
+            a.ncols = I[0];
+            a.nbatch = 1;
+            a.out_r0 = M[1] + 1;
+            a.out_nrows = I[1];
+            if ((rc = run_pass(p, a, p->fd[1], p->tw[1], false, false, st))) return rc;
+            PassArgs b = a;
+            b.in = p->B;
+            b.irs = b.ors = I[1];
+            b.ics = b.ocs = 1;
+            b.nrows_in = I[0];
+            b.ncols = I[1];
+            b.out_r0 = M[0] + 1;
+            b.out_nrows = I[0];
+            b.W = 0;
+            if ((rc = run_pass(p, b, p->fd[0], p->tw[0], false, false, st))) return rc;
+        }
+    }
+    STAGE(IPS_STAGE_SCREEN);
+    ScreenArgs s{};
+    s.d = d;
+    s.pref = p->geo.pref;
+    for (int a = 0; a < 3; ++a) {
+        s.M[a] = a < d ? M[a] : 1;
+        s.h[a] = a < d ? p->h[a] : 1.0;
+        s.piL[a] = a < d ? 3.141592653589793238462643383279502884 / ((double)M[a] * p->h[a]) : 0.0;
+        s.tau[a] = p->tau[a];
+        if (a < d) s.tab[a] = p->tab[a];
+        s.S[a] = p->S[a];
+        s.sig[a] = p->S[a];
+    }
+    s.Y = static_cast<const double *>(p->B);
+    s.src = p->src;
+    s.nsrc = p->nsrc;
+    s.ntgt = p->ntgt;
+    IPS_HIP(launch_screen(s, phi, st));
+    // sigma on the faces: inverse sine transforms over the in-face axes
+    for (int fam = 0; fam < d; ++fam)
+        if ((rc = shell_dst(p, p->S[fam], 2, fam, true, st))) return rc;
+    IPS_HIP(launch_screen_g(s, phi, st));
+    return IPS_OK;
+}
+
 int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
 {
     const int d = p->d;
@@ -711,10 +939,12 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
     int rc;
     if (d == 1) {
         STAGE(IPS_STAGE_FINAL);
-        IPS_HIP(launch_1d(rho, phi, M[0], p->h[0], p->fd[0], p->tw[0], p->tab[0], nullptr, st));
+        IPS_HIP(launch_1d(rho, phi, M[0], p->h[0], p->fd[0], p->tw[0], p->tab[0], p->screen ? 1 : 0, st));
         return IPS_OK;
     }
-    if (d == 3) {
+    if (p->screen) {
+        if ((rc = screen_boundary(p, rho, phi, st))) return rc;
+    } else if (d == 3) {
         const int64_t s1 = n[2], s0 = n[1] * n[2];
         const double *rin = rho + s0 + s1 + 1;
         const int64_t vxy = (int64_t)I[0] * I[1];
@@ -1061,6 +1291,8 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         a.tw = p->tw[0];
         a.twf = p->twf[0];
         a.rowtab = p->rowtab;
+        a.group = final_group(a.W, f32 ? 4 : 8);
+        a.pre = p->screen ? 1 : 0; // B already holds the spectrum along axis 0
         IPS_HIP(launch_final_rows(a, st));
         STAGE(IPS_STAGE_FINAL);
         IPS_HIP(launch_final(a, st));
@@ -1532,6 +1764,7 @@ int plan_create_work(ips_plan *out, int d, const int64_t *n, const double *h, in
     p->precision = precision;
     p->work = work;
     p->timing = (flags & IPS_FLAG_STAGE_TIMING) != 0;
+    p->screen = (flags & IPS_FLAG_SCREENING) != 0;
     for (int a = 0; a < d; ++a) {
         p->n[a] = n[a];
         p->h[a] = h[a];
@@ -1920,6 +2153,8 @@ int ips_execute_adjoint(ips_plan p, const double *phi_bar, double *rho_bar, void
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
         return fail(IPS_E_INVALID_ARG, "plan belongs to another device than the current one");
+    if ((p->inner ? p->inner : p)->screen)
+        return fail(IPS_E_UNSUPPORTED, "the screening variant has no adjoint");
     if (p->inner) return execute_extended(p, phi_bar, rho_bar, static_cast<hipStream_t>(stream), true);
     int rc = adj_alloc(p);
     if (rc) return rc;
@@ -1932,7 +2167,7 @@ const char *ips_stage_name(int stage)
 {
     static const char *names[IPS_STAGE_COUNT] = {
         "rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces",
-        "shell_gt", "shell_r6", "final", "inv_y", "inv_z", "adjoint"};
+        "shell_gt", "shell_r6", "final", "inv_y", "inv_z", "adjoint", "screen"};
     if (stage < 0 || stage >= IPS_STAGE_COUNT) return "unknown";
     return names[stage];
 }
