@@ -125,7 +125,9 @@ def nchunks(n: int, mode: str) -> dict:
         W = tw(N, I)
         hc, Wh = (I + 1) // 2, W // 2
         ncb = (hc + Wh - 1) // Wh
-        nch = max(1, min(ncb, (6144 + N - 1) // N))
+        target = int(os.environ.get("IPS_CC_BLOCKS", "6144"))
+        target = target if 256 <= target <= 65536 else 6144
+        nch = max(1, min(ncb, (target + N - 1) // N))
         per = (ncb + nch - 1) // nch
         out[key] = (hc + per * Wh - 1) // (per * Wh)
     return out
