@@ -338,8 +338,11 @@ def ingest_stats(stats_csv, bench_json, title, cmd, out_name, top=20):
 
 
 def time_batched(api, torch, steps, warmup, modes=("fp64", "mixed_fp32_slices")):
-    """64 independent boxes of uneven size (seed 3), order 6: graph replays
-    and eager launches, whole-batch nodes per second."""
+    """64 independent boxes of uneven size (seed 3), order 6, whole-batch
+    nodes per second: graph replays of the plain batch (every box at its own
+    size) and of the smooth batch (every box solved on its 5-smooth
+    extension, caller nodes counted), eager launches of the plain FP64 batch
+    for comparison."""
     from paper_2108_11871_amd import inputs
 
     probs = inputs.batched_problems(seed=3, count=64)
@@ -347,29 +350,35 @@ def time_batched(api, torch, steps, warmup, modes=("fp64", "mixed_fp32_slices"))
     shapes = [tuple(r.shape) for r in rhos]
     hs = [p[1] for p in probs]
     nodes = sum(r.numel() for r in rhos)
+    ext_nodes = 0
+    for s_ in shapes:
+        ne, _ = api.extension(s_, 0)
+        c = 1
+        for v in ne:
+            c *= v
+        ext_nodes += c
     stream = torch.cuda.current_stream()
     out = {"workload": "64 boxes, n per axis log-uniform in [33, 193], box [-s, s] with s ~ U(0.5, 2) "
                        "per axis, 5-bump sums, order 6, seed 3",
-           "nodes": nodes, "modes": {}}
-    for mode in modes:
-        res = {}
-        for kind in ("graph", "eager"):
-            b = api.Batch(shapes, hs, order=6, precision=mode, eager=(kind == "eager"))
-            outs = [torch.empty_like(r) for r in rhos]
-            for _ in range(max(warmup, 1) + 1):
-                b(rhos, outs)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(steps):
-                b(rhos, outs)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / steps
-            res[kind] = {"ms_per_batch": ms, "mpoints_per_s": nodes / (ms * 1e-3) / 1e6}
-            b.close()
-        out["modes"][mode] = res
+           "nodes": nodes, "smooth_extension_nodes": ext_nodes, "modes": {}}
+    runs = [(m, kind) for m in modes for kind in ("graph", "smooth_graph")] + [("fp64", "eager")]
+    for mode, kind in runs:
+        b = api.Batch(shapes, hs, order=6, precision=mode, eager=(kind == "eager"),
+                      smooth=(kind == "smooth_graph"))
+        outs = [torch.empty_like(r) for r in rhos]
+        for _ in range(max(warmup, 1) + 1):
+            b(rhos, outs)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            b(rhos, outs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out["modes"].setdefault(mode, {})[kind] = {"ms_per_batch": ms, "mpoints_per_s": nodes / (ms * 1e-3) / 1e6}
+        b.close()
     return out
 
 
@@ -444,6 +453,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint timings")
+    ap.add_argument("--batched-only", action="store_true", help="only the batched leg (profiling)")
     ap.add_argument("--ingest", nargs="+", metavar="ARG")
     args = ap.parse_args()
 
@@ -467,6 +477,10 @@ def main():
     import torch
 
     from paper_2108_11871_amd import api, inputs
+
+    if args.batched_only:
+        print(json.dumps(time_batched(api, torch, args.steps, args.warmup)), flush=True)
+        return
 
     n = args.n
     rho, h, _ = inputs.workload_bumps_3d(n, seed=args.seed)

@@ -320,12 +320,20 @@ int ips_plan_destroy(ips_plan p);
  * solve of Sections 2-5; nothing is shared between problems).
  *   d[b], n[b][0..d[b]-1], h[b][0..d[b]-1] describe problem b
  *   order, precision : as ips_plan_create, for every problem
- *   flags : IPS_FLAG_ADJOINT and IPS_FLAG_AUTOTUNE apply to every problem's
- *           plan (IPS_FLAG_STAGE_TIMING is ignored); IPS_FLAG_BATCH_EAGER
- *           makes ips_batch_execute launch the problems one after another
- *           on the caller's stream instead of through a graph.
+ *   flags : IPS_FLAG_ADJOINT, IPS_FLAG_AUTOTUNE and IPS_FLAG_SCREENING
+ *           apply to every problem's plan (IPS_FLAG_STAGE_TIMING and
+ *           IPS_FLAG_NO_WORKSPACE are ignored); IPS_FLAG_BATCH_EAGER makes
+ *           ips_batch_execute launch the problems one after another on the
+ *           caller's stream instead of through a graph; IPS_FLAG_BATCH_SMOOTH
+ *           solves every problem on its extended grid with zero margin
+ *           (ips_extension: each panel count rounded up to one with no prime
+ *           factor above 5, as Section 2 prescribes for FFT-friendly panel
+ *           counts) and returns phi at the caller's nodes -- the result is
+ *           that of the enlarged box, not bit-identical to the plain solve;
+ *           not combined with IPS_FLAG_SCREENING.
  */
 #define IPS_FLAG_BATCH_EAGER 8u
+#define IPS_FLAG_BATCH_SMOOTH 64u
 
 int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)[3],
                      const double (*h)[3], int order, int precision, unsigned flags);

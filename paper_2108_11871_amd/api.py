@@ -11,7 +11,8 @@ from typing import Sequence
 import torch
 
 from . import _lib
-from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_AUTOTUNE, IPS_FLAG_BATCH_EAGER, IPS_FLAG_NO_WORKSPACE,
+from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_AUTOTUNE, IPS_FLAG_BATCH_EAGER, IPS_FLAG_BATCH_SMOOTH,
+                   IPS_FLAG_NO_WORKSPACE,
                    IPS_FLAG_SCREENING, IPS_FLAG_STAGE_TIMING, IPS_FP64, IPS_MIXED_FP32, IPS_MIXED_FP32_SLICES, STAGES, check, f64_array,
                    i64_array, library_path, lib)
 
@@ -230,7 +231,9 @@ class Batch:
     """Many independent problems of uneven size (ips_batch_create / ips_batch_execute)."""
 
     def __init__(self, shapes, hs, order: int = 6, precision: str = "fp64", eager: bool = False,
-                 autotune: bool = False, device=None):
+                 autotune: bool = False, device=None, smooth: bool = False, screening: bool = False):
+        """smooth: solve every problem on its 5-smooth extension (IPS_FLAG_BATCH_SMOOTH);
+        screening: boundary values from the screening charge (IPS_FLAG_SCREENING)."""
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         count = len(self.shapes)
@@ -242,7 +245,8 @@ class Batch:
                 nn[3 * b + a] = s[a]
                 hh[3 * b + a] = float(h[a])
         handle = ctypes.c_void_p()
-        flags = (IPS_FLAG_BATCH_EAGER if eager else 0) | (IPS_FLAG_AUTOTUNE if autotune else 0)
+        flags = ((IPS_FLAG_BATCH_EAGER if eager else 0) | (IPS_FLAG_AUTOTUNE if autotune else 0)
+                 | (IPS_FLAG_BATCH_SMOOTH if smooth else 0) | (IPS_FLAG_SCREENING if screening else 0))
         with torch.cuda.device(self.device):
             check(lib().ips_batch_create(ctypes.byref(handle), count, dims, nn, hh, int(order),
                                          PRECISIONS[precision], flags))

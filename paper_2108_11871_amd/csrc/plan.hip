@@ -1935,6 +1935,12 @@ int static_scratch(int dev, void **ptr)
     return IPS_OK;
 }
 
+// A solve on a plain or an extended plan.
+int execute_any(ips_plan p, const double *rho, double *phi, hipStream_t st)
+{
+    return p->inner ? execute_extended(p, rho, phi, st, false) : execute(p, rho, phi, st);
+}
+
 extern "C" {
 
 const char *ips_status_string(int status)
@@ -2342,7 +2348,7 @@ int batch_capture(ips_batch b, const double *const *rho, double *const *phi)
     if (e != hipSuccess) rc = fail(IPS_E_DEVICE, std::string("batch capture fork: ") + hipGetErrorString(e));
     for (size_t j = 0; j < b->order.size() && !rc; ++j) {
         const int i = b->order[j];
-        rc = execute(b->plans[i], rho[i], phi[i], b->streams[j % kBatchStreams]);
+        rc = execute_any(b->plans[i], rho[i], phi[i], b->streams[j % kBatchStreams]);
     }
     for (int k = 1; k < kBatchStreams && !rc; ++k) {
         e = hipEventRecord(b->events[k], b->streams[k]);
@@ -2379,18 +2385,24 @@ int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)
     if (!out) return fail(IPS_E_INVALID_ARG, "out must not be NULL");
     *out = nullptr;
     if (count <= 0 || !d || !n || !h) return fail(IPS_E_INVALID_ARG, "bad batch description");
+    if ((flags & IPS_FLAG_BATCH_SMOOTH) && (flags & IPS_FLAG_SCREENING))
+        return fail(IPS_E_UNSUPPORTED, "smooth batches take the volume sums only");
     ips_batch b = new (std::nothrow) ips_batch_s();
     if (!b) return fail(IPS_E_NO_MEMORY, "host allocation failed");
     b->eager = (flags & IPS_FLAG_BATCH_EAGER) != 0;
     (void)hipGetDevice(&b->device);
     // per-problem plans: no stage timing inside a batch
-    const unsigned pflags = flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_BATCH_EAGER | IPS_FLAG_NO_WORKSPACE);
+    const unsigned pflags =
+        flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_BATCH_EAGER | IPS_FLAG_NO_WORKSPACE | IPS_FLAG_BATCH_SMOOTH);
+    const int64_t zero[3] = {0, 0, 0};
     std::vector<std::pair<int64_t, int>> sz;
     for (int i = 0; i < count; ++i) {
         ips_plan p = nullptr;
-        int rc = ips_plan_create(&p, d[i], n[i], h[i], order, precision, pflags);
+        int rc = (flags & IPS_FLAG_BATCH_SMOOTH)
+                     ? ips_plan_create_extended(&p, d[i], n[i], h[i], order, precision, pflags, zero)
+                     : ips_plan_create(&p, d[i], n[i], h[i], order, precision, pflags);
         if (rc) {
-            for (ips_plan q : b->plans) plan_free(q);
+            for (ips_plan q : b->plans) ips_plan_destroy(q);
             delete b;
             return rc;
         }
@@ -2423,7 +2435,7 @@ int ips_batch_execute(ips_batch b, const double *const *rho, double *const *phi,
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (b->eager) {
         for (int i : b->order) {
-            int rc = execute(b->plans[i], rho[i], phi[i], st);
+            int rc = execute_any(b->plans[i], rho[i], phi[i], st);
             if (rc) return rc;
         }
         return IPS_OK;
@@ -2439,7 +2451,7 @@ int ips_batch_execute(ips_batch b, const double *const *rho, double *const *phi,
     // calls with these buffers replay
     batch_release_graph(b);
     for (int i : b->order) {
-        int rc = execute(b->plans[i], rho[i], phi[i], st);
+        int rc = execute_any(b->plans[i], rho[i], phi[i], st);
         if (rc) return rc;
     }
     return batch_capture(b, rho, phi);
@@ -2451,7 +2463,7 @@ int ips_batch_destroy(ips_batch b)
     batch_release_graph(b);
     for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
-    for (ips_plan p : b->plans) plan_free(p);
+    for (ips_plan p : b->plans) ips_plan_destroy(p);
     delete b;
     return IPS_OK;
 }

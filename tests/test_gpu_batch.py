@@ -142,3 +142,73 @@ def test_autotuned_plan_matches_default(shape, precision):
     err = float((got - ref).abs().max() / ref.abs().max())
     print("  autotuned vs default rel diff %.2e" % err, flush=True)
     assert err < (1e-12 if precision == "fp64" else 1e-6)
+
+
+def _max_prime(m):
+    best, p = 1, 2
+    while m > 1:
+        while m % p == 0:
+            best, m = max(best, p), m // p
+        p += 1
+    return best
+
+
+def _prime_heavy(count=3, max_nodes=1.6e6):
+    """The boxes whose transform lengths 2M carry the largest prime factors
+    (the slow generic stages), among those the oracle solves in seconds."""
+    probs = [p for p in _workload() if p[0].size <= max_nodes]
+    probs.sort(key=lambda p: -max(_max_prime(2 * (v - 1)) for v in p[0].shape))
+    return probs[:count]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed_fp32_slices", 1e-6)])
+def test_batch_prime_length_boxes_match_oracle(precision, tol):
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner, rel_err, to_dev
+
+    probs = _prime_heavy()
+    rhos = [to_dev(p[0]) for p in probs]
+    batch = api.Batch([r.shape for r in rhos], [p[1] for p in probs], order=6, precision=precision)
+    outs = batch(rhos)
+    torch.cuda.synchronize()
+    for (rho, h, _), o in zip(probs, outs):
+        ref = P.solve(rho, h, 6, boundary="fft")
+        err = rel_err(o.cpu().numpy(), ref)
+        banner("batch %s box %s (largest prime of 2M: %d): rel err vs oracle %.3e"
+               % (precision, rho.shape, max(_max_prime(2 * (v - 1)) for v in rho.shape), err))
+        assert err < tol
+    batch.close()
+
+
+def _oracle_on_extension(rho, h, order):
+    from paper_2108_11871_amd import api
+
+    ne, off = api.extension(rho.shape, 0)
+    big = np.zeros(ne)
+    sl = tuple(slice(o, o + s) for o, s in zip(off, rho.shape))
+    big[sl] = rho
+    return P.solve(big, h, order, boundary="fft")[sl]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed_fp32_slices", 1e-6)])
+def test_smooth_batch_matches_oracle_on_the_extended_grids(precision, tol):
+    """IPS_FLAG_BATCH_SMOOTH: every box is solved on its 5-smooth extension."""
+    import torch
+    from paper_2108_11871_amd import api
+    from gpu_util import banner, rel_err, to_dev
+
+    probs = _prime_heavy(count=4)
+    rhos = [to_dev(p[0]) for p in probs]
+    batch = api.Batch([r.shape for r in rhos], [p[1] for p in probs], order=6, precision=precision,
+                      smooth=True)
+    for rep in range(2):  # eager first call, then the graph replay
+        outs = batch(rhos)
+        torch.cuda.synchronize()
+        for (rho, h, _), o in zip(probs, outs):
+            ref = _oracle_on_extension(rho, h, 6)
+            err = rel_err(o.cpu().numpy(), ref)
+            banner("smooth batch %s box %s -> %s: rel err vs oracle %.3e"
+                   % (precision, rho.shape, api.extension(rho.shape, 0)[0], err))
+            assert err < tol
+    batch.close()
