@@ -47,11 +47,15 @@ __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y
 template <typename T>
 __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
 
-// multiply by -i (forward) or +i (inverse)
-template <typename T>
-__device__ __forceinline__ cx<T> rot90(cx<T> a, bool inv)
+// multiply by -i (forward) or +i (inverse); the direction is a template
+// argument throughout the engine, so no per-element selects are emitted
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot90(cx<T> a)
 {
-    return inv ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+    if constexpr (INV)
+        return cx<T>{-a.y, a.x};
+    else
+        return cx<T>{a.y, -a.x};
 }
 
 constexpr int kMaxStages = 16;
@@ -89,17 +93,17 @@ __device__ __forceinline__ void lds_cs(T *buf, int rs, int n, int s, cx<T> v)
     p[1] = v.y;
 }
 
-template <typename T>
-__device__ __forceinline__ cx<T> twid(const cx<T> *tw, int t, bool inv)
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> twid(const cx<T> *tw, int t)
 {
     cx<T> w = tw[t];
-    if (inv) w.y = -w.y;
+    if constexpr (INV) w.y = -w.y;
     return w;
 }
 
 // In-register DFT of length R (forward: exp(-2 pi i/R); inverse: conjugate).
-template <typename T, int R>
-__device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool inv)
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N)
 {
     if constexpr (R == 2) {
         cx<T> t = a[1];
@@ -107,7 +111,7 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool
         a[0] = cadd(a[0], t);
     } else if constexpr (R == 4) {
         cx<T> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
-        cx<T> s13 = cadd(a[1], a[3]), d13 = rot90(csub(a[1], a[3]), inv);
+        cx<T> s13 = cadd(a[1], a[3]), d13 = rot90<T, INV>(csub(a[1], a[3]));
         a[0] = cadd(s02, s13);
         a[2] = csub(s02, s13);
         a[1] = cadd(d02, d13);
@@ -115,15 +119,19 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool
     } else if constexpr (R == 8) {
         cx<T> e[4] = {a[0], a[2], a[4], a[6]};
         cx<T> o[4] = {a[1], a[3], a[5], a[7]};
-        dft_small<T, 4>(e, tw, N, inv);
-        dft_small<T, 4>(o, tw, N, inv);
+        dft_small<T, 4, INV>(e, tw, N);
+        dft_small<T, 4, INV>(o, tw, N);
         const T r = (T)0.70710678118654752440084436210484903928;
         // o[k] *= w8^k
-        cx<T> o1 = inv ? cx<T>{r * (o[1].x - o[1].y), r * (o[1].x + o[1].y)}
-                       : cx<T>{r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)};
-        cx<T> o2 = rot90(o[2], inv);
-        cx<T> o3 = inv ? cx<T>{-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y)}
-                       : cx<T>{r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)};
+        cx<T> o1, o3;
+        if constexpr (INV) {
+            o1 = cx<T>{r * (o[1].x - o[1].y), r * (o[1].x + o[1].y)};
+            o3 = cx<T>{-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y)};
+        } else {
+            o1 = cx<T>{r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)};
+            o3 = cx<T>{r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)};
+        }
+        cx<T> o2 = rot90<T, INV>(o[2]);
         a[0] = cadd(e[0], o[0]);
         a[4] = csub(e[0], o[0]);
         a[1] = cadd(e[1], o1);
@@ -140,7 +148,7 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool
         for (int q = 0; q < R; ++q) {
             cx<T> acc = a[0];
 #pragma unroll
-            for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(a[r], twid(tw, ((r * q) % R) * step, inv)));
+            for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(a[r], twid<T, INV>(tw, ((r * q) % R) * step)));
             out[q] = acc;
         }
 #pragma unroll
@@ -151,9 +159,9 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N, bool
 // One Stockham stage of radix R (R <= 8) over nseq = 2^lgs sequences of
 // length N.  MAXE bounds the complex elements a thread holds
 // (nseq * N <= MAXE * NT).
-template <typename T, int R, int MAXE, int NT>
+template <typename T, int R, int MAXE, int NT, bool INV>
 __device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDesc &fd, int st,
-                                           const cx<T> *tw, bool inv, int tid)
+                                           const cx<T> *tw, int tid)
 {
     constexpr int BPT = (MAXE + R - 1) / R;
     const int N = fd.N, Ns = fd.ns[st];
@@ -175,9 +183,9 @@ __device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDes
             if (jm != 0) {
                 const int e = jm * tstep;
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid(tw, e * r, inv));
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid<T, INV>(tw, e * r));
             }
-            dft_small<T, R>(v[i], tw, N, inv);
+            dft_small<T, R, INV>(v[i], tw, N);
         }
     }
     __syncthreads();
@@ -194,9 +202,9 @@ __device__ __forceinline__ void stage_bfly(T *buf, int rs, int lgs, const FftDes
 }
 
 // Stockham stage of arbitrary radix R computed output by output.
-template <typename T, int MAXE, int NT>
+template <typename T, int MAXE, int NT, bool INV>
 __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftDesc &fd, int st,
-                                             const cx<T> *tw, bool inv, int tid)
+                                             const cx<T> *tw, int tid)
 {
     const int N = fd.N, Ns = fd.ns[st], R = fd.rad[st];
     const int NR = N / R;
@@ -218,7 +226,7 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftD
             for (int r = 1; r < R; ++r) {
                 ex += E;
                 if (ex >= N) ex -= N;
-                acc = cadd(acc, cmul(lds_c(buf, rs, j + r * NR, s), twid(tw, ex, inv)));
+                acc = cadd(acc, cmul(lds_c(buf, rs, j + r * NR, s), twid<T, INV>(tw, ex)));
             }
             out[i] = acc;
         }
@@ -236,8 +244,8 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftD
 // N, radix R, product of the earlier radices NS (a power of two), row pitch
 // RS and 2^LGS sequences.  Same data movement as stage_bfly; the index and
 // twiddle arithmetic folds to shifts and constants.
-template <typename T, int R, int NT, int N, int NS, int RS, int LGS>
-__device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv, int tid)
+template <typename T, int R, int NT, int N, int NS, int RS, int LGS, bool INV>
+__device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, int tid)
 {
     constexpr int NR = N / R, NBF = NR << LGS, TSTEP = N / (NS * R), SMASK = (1 << LGS) - 1;
     constexpr int BPT = (NBF + NT - 1) / NT;
@@ -255,9 +263,9 @@ __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv, int 
             if (NS > 1 && jm != 0) {
                 const int e = jm * TSTEP;
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid(tw, e * r, inv));
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid<T, INV>(tw, e * r));
             }
-            dft_small<T, R>(v[i], tw, N, inv);
+            dft_small<T, R, INV>(v[i], tw, N);
         }
     }
     __syncthreads();
@@ -279,63 +287,75 @@ __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, bool inv, int 
 // may pass one the compiler cannot see through, so that the per-thread index
 // and twiddle values are recomputed for each transform instead of being held
 // in registers across the loop).
-template <typename T, int NT, int N, int RS, int LGS>
-__device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, bool inv, int tid)
+template <typename T, int NT, int N, int RS, int LGS, bool INV>
+__device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, int tid)
 {
     if constexpr (N == 256) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv, tid);
-        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv, tid);
-        stage_ct<T, 4, NT, N, 64, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 1, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 4, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
     } else if constexpr (N == 512) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv, tid);
-        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv, tid);
-        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 1, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
     } else if constexpr (N == 1024) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS>(buf, tw, inv, tid);
-        stage_ct<T, 8, NT, N, 8, RS, LGS>(buf, tw, inv, tid);
-        stage_ct<T, 8, NT, N, 64, RS, LGS>(buf, tw, inv, tid);
-        stage_ct<T, 2, NT, N, 512, RS, LGS>(buf, tw, inv, tid);
+        stage_ct<T, 8, NT, N, 1, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 2, NT, N, 512, RS, LGS, INV>(buf, tw, tid);
     }
 }
 
-// Full length-N complex FFT of 2^lgs sequences held in LDS (in place).
+// Full length-N complex FFT of 2^lgs sequences held in LDS (in place), in the
+// direction INV (false: exp(-2 pi i t/N), true: the conjugate).
 // P2: N is a power of two (only radix-2/4/8 stages are compiled in).
-// CT = false keeps the generic stages only.  tid: see fft_ct (-1: threadIdx.x).
-template <typename T, int MAXE, int NT, bool P2 = false, bool CT = true>
-__device__ __forceinline__ void fft_tile(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, bool inv,
-                                         int tid = -1)
+// CT = false keeps the generic stages only.  tid: see fft_ct.
+template <typename T, int MAXE, int NT, bool P2, bool CT, bool INV>
+__device__ __forceinline__ void fft_tile_dir(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, int tid)
 {
-    if (tid < 0) tid = threadIdx.x;
     if constexpr (P2 && CT && NT == 256) {
         // (N, tile width) pairs of the default tile budget: N * W / 2 = MAXE * NT
         if constexpr (MAXE == 8) {
-            if (fd.N == 512 && rs == 9) return fft_ct<T, NT, 512, 9, 2>(buf, tw, inv, tid);
-            if (fd.N == 256 && rs == 17) return fft_ct<T, NT, 256, 17, 3>(buf, tw, inv, tid);
-            if (fd.N == 1024 && rs == 5) return fft_ct<T, NT, 1024, 5, 1>(buf, tw, inv, tid);
+            if (fd.N == 512 && rs == 9) return fft_ct<T, NT, 512, 9, 2, INV>(buf, tw, tid);
+            if (fd.N == 256 && rs == 17) return fft_ct<T, NT, 256, 17, 3, INV>(buf, tw, tid);
+            if (fd.N == 1024 && rs == 5) return fft_ct<T, NT, 1024, 5, 1, INV>(buf, tw, tid);
         }
     }
     if constexpr (P2) {
         for (int st = 0; st < fd.nst; ++st) {
             const int R = fd.rad[st];
             if (R == 8)
-                stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid);
+                stage_bfly<T, 8, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid);
             else if (R == 4)
-                stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid);
+                stage_bfly<T, 4, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid);
             else
-                stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid);
+                stage_bfly<T, 2, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid);
         }
         return;
     }
     for (int st = 0; st < fd.nst; ++st) {
         switch (fd.rad[st]) {
-        case 2: stage_bfly<T, 2, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
-        case 3: stage_bfly<T, 3, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
-        case 4: stage_bfly<T, 4, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
-        case 5: stage_bfly<T, 5, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
-        case 8: stage_bfly<T, 8, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
-        default: stage_direct<T, MAXE, NT>(buf, rs, lgs, fd, st, tw, inv, tid); break;
+        case 2: stage_bfly<T, 2, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid); break;
+        case 3: stage_bfly<T, 3, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid); break;
+        case 4: stage_bfly<T, 4, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid); break;
+        case 5: stage_bfly<T, 5, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid); break;
+        case 8: stage_bfly<T, 8, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid); break;
+        default: stage_direct<T, MAXE, NT, INV>(buf, rs, lgs, fd, st, tw, tid); break;
         }
     }
+}
+
+// fft_tile_dir with the direction as an argument (a constant argument folds
+// to one instantiation).  tid: see fft_ct (-1: threadIdx.x).
+template <typename T, int MAXE, int NT, bool P2 = false, bool CT = true>
+__device__ __forceinline__ void fft_tile(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, bool inv,
+                                         int tid = -1)
+{
+    if (tid < 0) tid = threadIdx.x;
+    if (inv)
+        fft_tile_dir<T, MAXE, NT, P2, CT, true>(buf, rs, lgs, fd, tw, tid);
+    else
+        fft_tile_dir<T, MAXE, NT, P2, CT, false>(buf, rs, lgs, fd, tw, tid);
 }
 
 // After a forward zero-padded FFT: write C and S in slot layout (in place).
