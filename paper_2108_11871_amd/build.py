@@ -68,5 +68,34 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_check(verbose: bool = False) -> str:
+    """The sanitizer build of the host code: plan.hip compiled with
+    AddressSanitizer and UndefinedBehaviorSanitizer on its host side only (the
+    device code is built as usual), linked with the other objects of the
+    library and the host-only driver tests/host_check.cpp into one program.
+    Returns the program's path."""
+    objdir = os.path.join(HERE, "_build")
+    if not all(os.path.exists(os.path.join(objdir, s.replace(".hip", ".o"))) for s in SOURCES):
+        build(verbose)
+    sdir = os.path.join(objdir, "sanitize")
+    os.makedirs(sdir, exist_ok=True)
+    san = []
+    for f in ("-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined",
+              "-fno-omit-frame-pointer"):
+        san += ["-Xarch_host", f]
+    plan_o = os.path.join(sdir, "plan.o")
+    cmd = [hipcc()] + compile_flags() + ["-g"] + san + ["-c", os.path.join(CSRC, "plan.hip"), "-o", plan_o]
+    subprocess.check_call(cmd, stdout=subprocess.DEVNULL if not verbose else None,
+                          stderr=subprocess.DEVNULL if not verbose else None)
+    drv_o = os.path.join(sdir, "host_check.o")
+    subprocess.check_call(["g++", "-std=c++17", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                           "-I" + os.path.join(ROOT, "include"), "-c",
+                           os.path.join(ROOT, "tests", "host_check.cpp"), "-o", drv_o])
+    exe = os.path.join(sdir, "ips_host_check")
+    objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES if s != "plan.hip"]
+    subprocess.check_call([hipcc(), "--offload-arch=" + ARCH] + san + ["-o", exe, drv_o, plan_o] + objs)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
