@@ -23,9 +23,12 @@ Prints ONE JSON line.  Besides the contract fields it carries
                 median of per-step HIP events), error vs the oracle and vs
                 FP64, and stage times;
   adjoint       time of one FP64 adjoint solve on the same grid;
-  batched       64 uneven boxes per batch, graph replay against eager launches;
+  batched       64 uneven boxes per batch: graph replays of the plain batch and of
+                the batch on 5-smooth extensions, eager launches for comparison;
   extended      the same solve through an extended plan (8 nodes added on every
-                side, then 5-smooth panel counts), caller nodes per second.
+                side, then 5-smooth panel counts), caller nodes per second;
+  screening     the screening-charge boundary values against the volume sums
+                (FP64, 65^3 to 257^3): time and error against the closed form.
 
 Profiling helpers (same file, so that every profile is taken on committed code):
   --copy-calibration MIB   after the timed work, one plain device copy of MIB MiB
@@ -87,9 +90,9 @@ def stage_bytes(n: int, mode: str, nch: dict) -> dict:
     vol = I ** 3
     wa = 4 if mode == "mixed_fp32_slices" else 8  # slot data of rho
     wb = 4 if mode != "fp64" else 8  # sine-space volume
-    kt = I * (M + 1) ** 2 * wa  # kernel spectra of one face family (FP32 with FP32 slots)
+    kt = I * (M + 1) ** 2 * 8  # FP64 kernel spectra of one face family (every mode)
     A = I * I * N * wa
-    part = 2 * N * N * wa  # chunk partials of both faces (FP32 with FP32 slots)
+    part = 2 * N * N * 8  # FP64 chunk partials of both faces (every mode)
     return {
         "rho_z": vol * 8 + A,
         "conv_x": A + kt + vol * wb + nch.get("x", 1) * part,
@@ -308,6 +311,57 @@ def ingest_traffic(fetch_csv, write_csv, n, mode, mib, cmd):
     print(json.dumps(out, indent=1))
 
 
+def ingest_counters(csv_a, csv_b, title, cmd, out_name, cu=256, xcd=8):
+    """Per-kernel SQ counter summary of the last solve in two rocprofv3 --pmc
+    passes (same program, same dispatch order).  GRBM_GUI_ACTIVE is reported
+    once per XCD and summed here, so the per-XCD cycle count is the sum / xcd.
+      occupancy  = SQ_WAVE_CYCLES * 4 / cycles / CUs / 32   (fraction of the 32 wave slots of a CU)
+      VALU busy  = SQ_ACTIVE_INST_VALU / cycles / CUs
+      LDS bank   = SQ_LDS_BANK_CONFLICT / cycles / CUs       (cycles stalled by bank conflicts)
+      LDS wait   = SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES         (wave time waiting for LDS results)
+      any wait   = SQ_WAIT_ANY / SQ_WAVE_CYCLES              (wave time in s_waitcnt)
+    and instructions per wave of VALU, LDS and vector-memory reads."""
+    import csv
+
+    def load(path):
+        disp = {}
+        for r in csv.DictReader(open(path)):
+            e = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                                                        "wg": int(r["Workgroup_Size"]), "c": {}})
+            e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        return [disp[k] for k in sorted(disp)]
+
+    a, b = load(csv_a), load(csv_b)
+    # the last solve: from the last rho_z-style forward pass of k_pass before the final k_final
+    last_final = max(i for i, e in enumerate(a) if "k_final<" in e["name"])
+    first = last_final
+    while first > 0 and "k_cc" not in a[first]["name"]:
+        first -= 1
+    while first > 0 and ("k_cc" in a[first - 1]["name"] or "k_pass" in a[first - 1]["name"]):
+        first -= 1
+    lines = ["# %s" % title, "", "Command (run from the repository root, one pass per counter set):", "",
+             "```", cmd, "```", "", ingest_counters.__doc__.strip().replace("\n    ", "\n"), "",
+             "| kernel | waves | occupancy | VALU busy | LDS bank | LDS wait | any wait | VALU/wave | LDS/wave | VMEM rd/wave |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for ea, eb in zip(a[first:last_final + 3], b[first:last_final + 3]):
+        c, c2 = ea["c"], eb["c"]
+        cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / xcd
+        if cyc <= 0:
+            continue
+        waves = c.get("SQ_WAVES", 0.0)
+        wc = max(c.get("SQ_WAVE_CYCLES", 1.0), 1.0)
+        nm = ea["name"].replace("void ", "").replace("ips::", "")
+        nm = nm.split("(")[0]
+        lines.append("| `%s` | %d | %.0f%% | %.0f%% | %.0f%% | %.2f | %.2f | %.0f | %.0f | %.0f |" % (
+            nm, waves, 100 * 4 * wc / cyc / cu / 32, 100 * c.get("SQ_ACTIVE_INST_VALU", 0) / cyc / cu,
+            100 * c.get("SQ_LDS_BANK_CONFLICT", 0) / cyc / cu, c.get("SQ_WAIT_INST_LDS", 0) / wc,
+            c2.get("SQ_WAIT_ANY", 0) / wc, c.get("SQ_INSTS_VALU", 0) / max(waves, 1),
+            c.get("SQ_INSTS_LDS", 0) / max(waves, 1), c2.get("SQ_INSTS_VMEM_RD", 0) / max(waves, 1)))
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def ingest_stats(stats_csv, bench_json, title, cmd, out_name, top=20):
     """Kernel table (rocprofv3 --stats) plus the bench line's stage means."""
     import csv
@@ -425,6 +479,55 @@ def time_extended(api, torch, rho_d, h, mode, margin, steps, warmup):
             "mpoints_per_s": rho_d.numel() / (ms * 1e-3) / 1e6}
 
 
+def time_screening(api, torch, sizes=(65, 129, 257), steps=3):
+    """Boundary values by the screening charge (IPS_FLAG_SCREENING; surface sums
+    by transforms, and by direct summation) against the volume sums, FP64, on
+    the bump-sum workload (seed 2): time per solve, plan table bytes and the
+    error against the closed-form potential on every boundary node and on
+    sampled interior nodes (max error / max |phi|)."""
+    import numpy as np
+
+    from oracle import closed_forms as CF
+    from oracle import poisson as P
+    from paper_2108_11871_amd import inputs
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    for n in sizes:
+        rho, h, meta = inputs.workload_bumps_3d(n, seed=2)
+        rho_d = torch.from_numpy(rho).to("cuda:0")
+        mask = P.boundary_mask(rho.shape)
+        bidx = np.argwhere(mask)
+        rng = np.random.default_rng(n)
+        iidx = rng.integers(1, n - 1, (20000, 3))
+        idx = np.concatenate([bidx, iidx])
+        ex = CF.bump_sum_potential(-1.0 + idx * h[0], meta["centers"], meta["widths"], meta["amps"], meta["p"])
+        rec = {}
+        for name, screening, direct in (("volume", False, False), ("screening", True, False),
+                                        ("screening_direct", True, True)):
+            plan = api.Plan(rho.shape, h, order=6, screening=screening, screen_direct=direct)
+            phi = plan(rho_d)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                plan(rho_d, phi)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            got = phi.cpu().numpy()[idx[:, 0], idx[:, 1], idx[:, 2]]
+            nb = len(bidx)
+            sc = np.abs(ex).max()
+            rec[name] = {"ms_per_step": ms, "table_bytes": plan.table_bytes,
+                         "rel_err_boundary": float(np.abs(got[:nb] - ex[:nb]).max() / sc),
+                         "rel_err_sampled": float(np.abs(got - ex).max() / sc)}
+            plan.close()
+        out["%d^3" % n] = rec
+        log("screening %d^3: %s" % (n, rec))
+    return out
+
+
 def load_traffic(kernel_stage: str, n: int, mode: str):
     """HBM bytes per launch measured by rocprofv3 counters, if taken on these sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -463,6 +566,8 @@ def main():
             ingest_traffic(rest[0], rest[1], args.n, rest[2], int(rest[3]), rest[4])
         elif kind == "stats":  # STATS_CSV BENCH_JSON OUT_NAME TITLE COMMAND
             ingest_stats(rest[0], rest[1], rest[3], rest[4], rest[2])
+        elif kind == "counters":  # CSV_A CSV_B OUT_NAME TITLE COMMAND
+            ingest_counters(rest[0], rest[1], rest[3], rest[4], rest[2])
         else:
             raise SystemExit("unknown --ingest kind %r" % kind)
         return
@@ -541,6 +646,8 @@ def main():
     if not ok:
         ok, checked = list(modes), None
     best = min(ok, key=lambda m: res[m]["ms"])
+    if not args.no_extras:
+        extras["screening"] = time_screening(api, torch)
     if "extended" not in extras and not args.no_extras:
         extras["extended"] = time_extended(api, torch, rho_d, h, best, 8, max(args.steps // 2, 1), args.warmup)
     r = res[best]

@@ -295,10 +295,19 @@ int ips_plan_reset_stage_times(ips_plan p);
  * the 1/r or log r singularity at the target), then the harmonic part of
  * Section 5 as usual.  1D: the exact two-point sum.  FP64 only, no adjoint;
  * for d >= 2 every n[i] >= 7.  Its accuracy is that of the surface rule
- * (about second order), not the spectral accuracy of the volume sums; the
- * surface sums are evaluated directly (O(boundary nodes^2) work).
+ * (about second order), not the spectral accuracy of the volume sums.
+ *
+ * Evaluation of the 3D surface sums: by default, when every n[i] <= 768, as
+ * convolutions -- the two faces of an axis by zero-padded 2D transforms over
+ * the face axes, each pair of perpendicular face families by a transform along
+ * their shared axis and, per wavenumber, a dense product over the other two
+ * coordinates -- in O(n^3) work, with tables of about 3 n^3 doubles held by
+ * the plan.  With IPS_FLAG_SCREEN_DIRECT too (and always in 2D or beyond that
+ * size) by the direct sums over all surface nodes: O(boundary nodes^2) work,
+ * no tables.  Both give the same sums up to rounding.
  */
 #define IPS_FLAG_SCREENING 32u
+#define IPS_FLAG_SCREEN_DIRECT 128u
 
 /* Release a plan and its device memory (waits for nothing: the caller must
  * make sure no enqueued work still uses it). NULL is accepted. */

@@ -31,6 +31,7 @@ IPS_FLAG_BATCH_EAGER = 8
 IPS_FLAG_NO_WORKSPACE = 16
 IPS_FLAG_SCREENING = 32
 IPS_FLAG_BATCH_SMOOTH = 64
+IPS_FLAG_SCREEN_DIRECT = 128
 IPS_STATIC_SCRATCH_BYTES = 64 << 20
 STAGES = ["rho_z", "conv_x", "conv_y", "rho_y", "conv_z", "faces", "shell_gt", "shell_r6",
           "final", "inv_y", "inv_z", "adjoint", "screen"]

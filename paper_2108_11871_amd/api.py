@@ -12,7 +12,7 @@ import torch
 
 from . import _lib
 from ._lib import (IPS_FLAG_ADJOINT, IPS_FLAG_AUTOTUNE, IPS_FLAG_BATCH_EAGER, IPS_FLAG_BATCH_SMOOTH,
-                   IPS_FLAG_NO_WORKSPACE,
+                   IPS_FLAG_NO_WORKSPACE, IPS_FLAG_SCREEN_DIRECT,
                    IPS_FLAG_SCREENING, IPS_FLAG_STAGE_TIMING, IPS_FP64, IPS_MIXED_FP32, IPS_MIXED_FP32_SLICES, STAGES, check, f64_array,
                    i64_array, library_path, lib)
 
@@ -75,7 +75,8 @@ class Plan:
 
     def __init__(self, shape: Sequence[int], h, order: int = 6, precision: str = "fp64",
                  device=None, timing: bool = False, adjoint: bool = False, autotune: bool = False,
-                 margin=None, no_workspace: bool = False, screening: bool = False):
+                 margin=None, no_workspace: bool = False, screening: bool = False,
+                 screen_direct: bool = False):
         """margin: None, or nodes added on each side of every axis (an int or one
         per axis); the solve then runs on the enlarged grid of `extension` and
         returns phi at the caller's nodes (ips_plan_create_extended).
@@ -83,7 +84,9 @@ class Plan:
         with `set_workspace` before the first solve (IPS_FLAG_NO_WORKSPACE).
         screening: boundary values from the screening charge d phi*/dn and a
         corrected surface quadrature instead of the volume sums
-        (IPS_FLAG_SCREENING; FP64, no adjoint)."""
+        (IPS_FLAG_SCREENING; FP64, no adjoint).
+        screen_direct: with screening, the 3D surface sums by direct summation
+        instead of by transforms (IPS_FLAG_SCREEN_DIRECT: no tables, O(n^4))."""
         self.shape = tuple(int(v) for v in shape)
         d = len(self.shape)
         hh = list(h) if hasattr(h, "__len__") else [float(h)] * d
@@ -96,7 +99,7 @@ class Plan:
         handle = ctypes.c_void_p()
         flags = ((IPS_FLAG_STAGE_TIMING if timing else 0) | (IPS_FLAG_ADJOINT if adjoint else 0)
                  | (IPS_FLAG_AUTOTUNE if autotune else 0) | (IPS_FLAG_NO_WORKSPACE if no_workspace else 0)
-                 | (IPS_FLAG_SCREENING if screening else 0))
+                 | (IPS_FLAG_SCREENING if screening else 0) | (IPS_FLAG_SCREEN_DIRECT if screen_direct else 0))
         self.margin = None
         with torch.cuda.device(self.device):
             if margin is None:

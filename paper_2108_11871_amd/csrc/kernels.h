@@ -145,6 +145,39 @@ struct ScreenArgs {
     int64_t nsrc, ntgt;  // surface nodes with sigma, boundary nodes
 };
 
+// Fast evaluation of the 3D surface sums (screen.hip).  Faces (axis f, side s),
+// in-face axes (b, c) in increasing order; pairs pr = (0,1), (0,2), (1,2) of
+// face axes (a, b) with the third axis c.
+struct SurfArgs {
+    int M[3];
+    double h[3];
+    double tau[3];
+    const double *sig[3]; // sigma on the face interiors [2][I_b][I_c]
+    double *FA[3];        // face charges W sigma on all face nodes [2][M_b + 1][M_c + 1]
+    double *XH[3];        // their slot spectra over both in-face axes [2][2 M_b][2 M_c]
+    const double *KP[3];  // kernel spectra of the same face and the opposite face [2][M_b + 1][M_c + 1]
+    double *PP[3];        // parallel-face sums at the face nodes [2][M_b + 1][M_c + 1]
+    // per pair: slot spectra along c of the charges of faces a and b, the
+    // transfer to the other family, and the sums back on the face nodes
+    double *XA[3], *XB[3]; // [2][M_b + 1][2 M_c], [2][M_a + 1][2 M_c]
+    double *YA[3], *YB[3]; // same shapes: targets on a (from b), targets on b (from a)
+    double *QA[3], *QB[3]; // [2][M_b + 1][M_c + 1], [2][M_a + 1][M_c + 1]
+    const double *KT[3];   // kernel spectra along c: KT[k][i][j] = FFT_c G(i h_a, j h_b, .)
+    int rows;              // table rows per LDS tile in k_perp
+};
+
+// G samples of the tables: same face / opposite face of axis f ([2][M_b + 1][M_c + 1])
+hipError_t launch_par_sample(double *out, int f, const int *M, const double *h, hipStream_t st);
+// perpendicular pair (a, b), third axis c: out[dc][i][j] (zero at the origin)
+hipError_t launch_perp_sample(double *out, int a, int b, int c, const int *M, const double *h, hipStream_t st);
+hipError_t launch_face_charge(const SurfArgs &s, hipStream_t st);
+hipError_t launch_par_mul(const SurfArgs &s, hipStream_t st);
+// table rows per LDS tile of the perpendicular-pair kernel for these sizes
+// (0: a face side too long for it)
+int perp_rows(const int *M);
+hipError_t launch_perp(const SurfArgs &s, hipStream_t st);
+hipError_t launch_surf_assemble(const SurfArgs &s, double *phi, hipStream_t st);
+
 // face coefficients of sigma from Y
 hipError_t launch_screen(const ScreenArgs &a, double *phi, hipStream_t st);
 // surface nodes and g at every boundary node of phi

@@ -187,6 +187,22 @@ void kaxes(int d, int fam, int &b, int &c)
     }
 }
 
+// In-face axes (b, c) of face family f in increasing order (the storage order
+// of the surface arrays, c contiguous).
+void face_axes(int f, int &b, int &c)
+{
+    b = f == 0 ? 1 : 0;
+    c = f == 2 ? 1 : 2;
+}
+
+// Pairs of perpendicular face families (a, b), a < b, with their shared axis c.
+void pair_axes(int pr, int &a, int &b, int &c)
+{
+    a = pr == 2 ? 1 : 0;
+    b = pr == 0 ? 1 : 2;
+    c = 3 - a - b;
+}
+
 } // namespace
 
 struct ips_plan_s {
@@ -228,8 +244,19 @@ struct ips_plan_s {
     bool screen = false;
     double tau[3] = {0, 0, 0};                   // singular corrections of the surface sums
     double *S[3] = {nullptr, nullptr, nullptr};  // face coefficients / sigma [2][I_b][I_c]
-    double *src = nullptr;                       // surface nodes [4][nsrc]
+    double *src = nullptr;                       // surface nodes [4][nsrc] (direct sums)
     int64_t nsrc = 0, ntgt = 0;
+    // 3D surface sums by transforms (surf_rows > 0) instead of the direct sums:
+    // tables KP (parallel faces, per family) and KT (perpendicular pairs), and
+    // workspace per family (charges, their slot spectra, the parallel sums) and
+    // per pair (spectra along the shared axis, overwritten by the transfers,
+    // and the sums back on the face nodes)
+    int surf_rows = 0;
+    double *KP[3] = {nullptr, nullptr, nullptr}, *KT[3] = {nullptr, nullptr, nullptr};
+    double *FA[3] = {nullptr, nullptr, nullptr}, *XH[3] = {nullptr, nullptr, nullptr};
+    double *PP[3] = {nullptr, nullptr, nullptr};
+    double *XA[3] = {nullptr, nullptr, nullptr}, *XB[3] = {nullptr, nullptr, nullptr};
+    double *QA[3] = {nullptr, nullptr, nullptr}, *QB[3] = {nullptr, nullptr, nullptr};
     DevBuf mem;   // tables: twiddles, axis tables, kernel spectra (and an extended plan's arrays)
     // execution workspace: one block carved into the buffers above (B, A, part, F,
     // G, P, T, D, C, P1T, P2T, rowtab) and, for IPS_FLAG_ADJOINT plans, the adjoint's
@@ -299,8 +326,10 @@ int validate(int d, const int64_t *n, const double *h, int order, int precision,
     if (d < 1 || d > 3) return fail(IPS_E_INVALID_ARG, "d must be 1, 2 or 3");
     if (!n || !h) return fail(IPS_E_INVALID_ARG, "n and h must not be NULL");
     if (flags & ~(IPS_FLAG_STAGE_TIMING | IPS_FLAG_ADJOINT | IPS_FLAG_AUTOTUNE | IPS_FLAG_BATCH_EAGER |
-                  IPS_FLAG_NO_WORKSPACE | IPS_FLAG_SCREENING))
+                  IPS_FLAG_NO_WORKSPACE | IPS_FLAG_SCREENING | IPS_FLAG_SCREEN_DIRECT))
         return fail(IPS_E_INVALID_ARG, "unknown flag bits");
+    if ((flags & IPS_FLAG_SCREEN_DIRECT) && !(flags & IPS_FLAG_SCREENING))
+        return fail(IPS_E_INVALID_ARG, "IPS_FLAG_SCREEN_DIRECT applies to IPS_FLAG_SCREENING plans only");
     if (flags & IPS_FLAG_SCREENING) {
         if (precision != IPS_FP64) return fail(IPS_E_UNSUPPORTED, "the screening variant runs in FP64 only");
         if (flags & IPS_FLAG_ADJOINT) return fail(IPS_E_UNSUPPORTED, "the screening variant has no adjoint");
@@ -504,7 +533,26 @@ void layout_ws(ips_plan p, Carver &c)
         }
         double *bs;
         c.take(&bs, 2 * ts * sizeof(double));
-        c.take(&p->src, 4 * 2 * ts * sizeof(double));
+        if (p->surf_rows) {
+            for (int f = 0; f < 3; ++f) {
+                int b, cc;
+                face_axes(f, b, cc);
+                const size_t face = (size_t)(M[b] + 1) * (M[cc] + 1);
+                c.take(&p->FA[f], 2 * face * sizeof(double));
+                c.take(&p->XH[f], 2 * (size_t)N[b] * N[cc] * sizeof(double));
+                c.take(&p->PP[f], 2 * face * sizeof(double));
+            }
+            for (int pr = 0; pr < 3; ++pr) {
+                int a, b, cc;
+                pair_axes(pr, a, b, cc);
+                c.take(&p->XA[pr], 2 * (size_t)(M[b] + 1) * N[cc] * sizeof(double));
+                c.take(&p->XB[pr], 2 * (size_t)(M[a] + 1) * N[cc] * sizeof(double));
+                c.take(&p->QA[pr], 2 * (size_t)(M[b] + 1) * (M[cc] + 1) * sizeof(double));
+                c.take(&p->QB[pr], 2 * (size_t)(M[a] + 1) * (M[cc] + 1) * sizeof(double));
+            }
+        } else {
+            c.take(&p->src, 4 * 2 * ts * sizeof(double));
+        }
         size_t os = 0;
         for (int fam = 0; fam < 3; ++fam) {
             p->S[fam] = nullptr;
@@ -728,7 +776,59 @@ int plan_build(ips_plan p, hipStream_t st)
         p->nsrc = (int64_t)(2 * ts);
         const int64_t n0 = p->n[0], n1 = p->n[1], n2 = d == 3 ? p->n[2] : 1;
         p->ntgt = 2 * n1 * n2 + 2 * (n0 - 2) * n2 + (d == 3 ? 2 * (n0 - 2) * (n1 - 2) : 0);
-        return IPS_OK; // no kernel spectra: the volume sums are not used
+        if (!p->surf_rows) return IPS_OK; // no tables: direct surface sums
+        // parallel faces of family f: G at in-plane offsets on the same face and
+        // on the opposite one, even transforms along c then b
+        for (int f = 0; f < 3; ++f) {
+            int b, c;
+            face_axes(f, b, c);
+            const int64_t plane = (int64_t)(M[b] + 1) * (M[c] + 1);
+            if ((rc = p->mem.alloc((void **)&p->KP[f], 2 * plane * sizeof(double)))) return rc;
+            IPS_HIP(launch_par_sample(p->KP[f], f, M, p->h, st));
+            PassArgs a{};
+            a.in = a.out = p->KP[f];
+            a.irs = a.ors = 1;
+            a.ics = a.ocs = M[c] + 1;
+            a.ibs = a.obs = plane;
+            a.nrows_in = M[c] + 1;
+            a.ncols = M[b] + 1;
+            a.nbatch = 2;
+            a.in_mode = IN_EVEN;
+            a.out_r0 = 0;
+            a.out_nrows = M[c] + 1;
+            a.scale = 1.0;
+            if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) return rc;
+            PassArgs b2 = a;
+            b2.irs = b2.ors = M[c] + 1;
+            b2.ics = b2.ocs = 1;
+            b2.nrows_in = M[b] + 1;
+            b2.ncols = M[c] + 1;
+            b2.out_nrows = M[b] + 1;
+            b2.W = 0;
+            if ((rc = run_pass(p, b2, p->fd[b], p->tw[b], false, false, st))) return rc;
+        }
+        // perpendicular pairs (a, b): G at (i h_a, j h_b, dc h_c), even
+        // transform along dc
+        for (int pr = 0; pr < 3; ++pr) {
+            int a, b, c;
+            pair_axes(pr, a, b, c);
+            const int64_t slab = (int64_t)(M[a] + 1) * (M[b] + 1);
+            if ((rc = p->mem.alloc((void **)&p->KT[pr], (size_t)(M[c] + 1) * slab * sizeof(double)))) return rc;
+            IPS_HIP(launch_perp_sample(p->KT[pr], a, b, c, M, p->h, st));
+            PassArgs t{};
+            t.in = t.out = p->KT[pr];
+            t.irs = t.ors = slab;
+            t.ics = t.ocs = 1;
+            t.nrows_in = M[c] + 1;
+            t.ncols = (int)slab;
+            t.nbatch = 1;
+            t.in_mode = IN_EVEN;
+            t.out_r0 = 0;
+            t.out_nrows = M[c] + 1;
+            t.scale = 1.0;
+            if ((rc = run_pass(p, t, p->fd[c], p->tw[c], false, false, st))) return rc;
+        }
+        return IPS_OK;
     }
     for (int fam = 0; fam < d; ++fam) {
         // kernel spectra: samples then even transforms along the in-face axes
@@ -821,6 +921,148 @@ struct StageScope {
 #define IPS_CAT2(a, b) a##b
 #define IPS_CAT(a, b) IPS_CAT2(a, b)
 #define STAGE(id) StageScope IPS_CAT(stage_scope_, __LINE__)(p, (id), st)
+
+// 3D surface sums by transforms (sigma already on the faces): face charges
+// W sigma; slot spectra of every face over both face axes and of every face
+// along each of its axes; the parallel-face products and the perpendicular
+// transfers; the inverse transforms; g at every boundary node.
+int surface_sums(ips_plan p, double *phi, hipStream_t st)
+{
+    const int *M = p->M, *N = p->N;
+    int rc;
+    SurfArgs s{};
+    for (int a = 0; a < 3; ++a) {
+        s.M[a] = M[a];
+        s.h[a] = p->h[a];
+        s.tau[a] = p->tau[a];
+        s.sig[a] = p->S[a];
+        s.FA[a] = p->FA[a];
+        s.XH[a] = p->XH[a];
+        s.KP[a] = p->KP[a];
+        s.PP[a] = p->PP[a];
+        s.XA[a] = s.YA[a] = p->XA[a]; // the transfer of slot k overwrites slot k
+        s.XB[a] = s.YB[a] = p->XB[a];
+        s.QA[a] = p->QA[a];
+        s.QB[a] = p->QB[a];
+        s.KT[a] = p->KT[a];
+    }
+    s.rows = p->surf_rows;
+    IPS_HIP(launch_face_charge(s, st));
+    // face f along its axis x (o the other face axis): FA[f] -> out[2][M_o + 1][N_x]
+    // (sides obs apart, default (M_o + 1) N_x)
+    auto along = [&](int f, int x, double *out, int64_t obs) -> int {
+        int b, c;
+        face_axes(f, b, c);
+        const int o = x == c ? b : c;
+        PassArgs a{};
+        a.in = p->FA[f];
+        a.out = out;
+        a.irs = x == c ? 1 : M[c] + 1;
+        a.ics = x == c ? M[c] + 1 : 1;
+        a.ibs = (int64_t)(M[b] + 1) * (M[c] + 1);
+        a.ors = 1;
+        a.ocs = N[x];
+        a.obs = obs ? obs : (int64_t)(M[o] + 1) * N[x];
+        a.nrows_in = M[x] + 1;
+        a.ncols = M[o] + 1;
+        a.nbatch = 2;
+        a.in_mode = IN_ZPAD0;
+        a.out_r0 = 0;
+        a.out_nrows = N[x];
+        a.scale = 1.0;
+        return run_pass(p, a, p->fd[x], p->tw[x], false, false, st);
+    };
+    // back on the nodes along the shared axis x: in[2][M_o + 1][N_x] -> out[2][M_o + 1][M_x + 1]
+    auto back = [&](const double *in, double *out, int x, int o) -> int {
+        PassArgs a{};
+        a.in = in;
+        a.out = out;
+        a.irs = 1;
+        a.ics = N[x];
+        a.ibs = (int64_t)(M[o] + 1) * N[x];
+        a.ors = 1;
+        a.ocs = M[x] + 1;
+        a.obs = (int64_t)(M[o] + 1) * (M[x] + 1);
+        a.nrows_in = N[x];
+        a.ncols = M[o] + 1;
+        a.nbatch = 2;
+        a.in_mode = IN_HERM;
+        a.out_r0 = 0;
+        a.out_nrows = M[x] + 1;
+        a.scale = 1.0 / N[x];
+        return run_pass(p, a, p->fd[x], p->tw[x], false, false, st);
+    };
+    for (int f = 0; f < 3; ++f) {
+        int b, c;
+        face_axes(f, b, c);
+        // along c into [2][N_b][N_c] (rows 0..M_b), then along b in place
+        if ((rc = along(f, c, p->XH[f], (int64_t)N[b] * N[c]))) return rc;
+        PassArgs a{};
+        a.in = a.out = p->XH[f];
+        a.irs = a.ors = N[c];
+        a.ics = a.ocs = 1;
+        a.ibs = a.obs = (int64_t)N[b] * N[c];
+        a.nrows_in = M[b] + 1;
+        a.ncols = N[c];
+        a.nbatch = 2;
+        a.in_mode = IN_ZPAD0;
+        a.out_r0 = 0;
+        a.out_nrows = N[b];
+        a.scale = 1.0;
+        if ((rc = run_pass(p, a, p->fd[b], p->tw[b], false, false, st))) return rc;
+    }
+    for (int pr = 0; pr < 3; ++pr) {
+        int a, b, c;
+        pair_axes(pr, a, b, c);
+        if ((rc = along(a, c, p->XA[pr], 0))) return rc;
+        if ((rc = along(b, c, p->XB[pr], 0))) return rc;
+    }
+    IPS_HIP(launch_par_mul(s, st));
+    for (int f = 0; f < 3; ++f) {
+        int b, c;
+        face_axes(f, b, c);
+        // synthesis along b in place (rows 0..M_b), then along c into PP
+        PassArgs a{};
+        a.in = a.out = p->XH[f];
+        a.irs = a.ors = N[c];
+        a.ics = a.ocs = 1;
+        a.ibs = a.obs = (int64_t)N[b] * N[c];
+        a.nrows_in = N[b];
+        a.ncols = N[c];
+        a.nbatch = 2;
+        a.in_mode = IN_HERM;
+        a.out_r0 = 0;
+        a.out_nrows = M[b] + 1;
+        a.scale = 1.0 / N[b];
+        if ((rc = run_pass(p, a, p->fd[b], p->tw[b], false, false, st))) return rc;
+        PassArgs z{};
+        z.in = p->XH[f];
+        z.out = p->PP[f];
+        z.irs = 1;
+        z.ics = N[c];
+        z.ibs = (int64_t)N[b] * N[c];
+        z.ors = 1;
+        z.ocs = M[c] + 1;
+        z.obs = (int64_t)(M[b] + 1) * (M[c] + 1);
+        z.nrows_in = N[c];
+        z.ncols = M[b] + 1;
+        z.nbatch = 2;
+        z.in_mode = IN_HERM;
+        z.out_r0 = 0;
+        z.out_nrows = M[c] + 1;
+        z.scale = 1.0 / N[c];
+        if ((rc = run_pass(p, z, p->fd[c], p->tw[c], false, false, st))) return rc;
+    }
+    IPS_HIP(launch_perp(s, st));
+    for (int pr = 0; pr < 3; ++pr) {
+        int a, b, c;
+        pair_axes(pr, a, b, c);
+        if ((rc = back(p->XA[pr], p->QA[pr], c, b))) return rc;
+        if ((rc = back(p->XB[pr], p->QB[pr], c, a))) return rc;
+    }
+    IPS_HIP(launch_surf_assemble(s, phi, st));
+    return IPS_OK;
+}
 
 // Boundary values from the screening charge (d = 2, 3): the raw sine spectrum
 // of rho_I over all axes into B, in the final pass's layout ([k2][k0][k1],
@@ -925,8 +1167,11 @@ int screen_boundary(ips_plan p, const double *rho, double *phi, hipStream_t st)
     // sigma on the faces: inverse sine transforms over the in-face axes
     for (int fam = 0; fam < d; ++fam)
         if ((rc = shell_dst(p, p->S[fam], 2, fam, true, st))) return rc;
-    IPS_HIP(launch_screen_g(s, phi, st));
-    return IPS_OK;
+    if (!p->surf_rows) {
+        IPS_HIP(launch_screen_g(s, phi, st));
+        return IPS_OK;
+    }
+    return surface_sums(p, phi, st);
 }
 
 int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
@@ -1772,6 +2017,7 @@ int plan_create_work(ips_plan *out, int d, const int64_t *n, const double *h, in
         p->I[a] = p->M[a] - 1;
         p->N[a] = 2 * p->M[a];
     }
+    if (p->screen && d == 3 && !(flags & IPS_FLAG_SCREEN_DIRECT)) p->surf_rows = perp_rows(p->M);
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
         delete p;

@@ -39,6 +39,8 @@ int main()
     expect(ips_plan_create(&p, 3, n3, h3, 6, 1, IPS_FLAG_SCREENING) == IPS_E_UNSUPPORTED, "screening mixed");
     expect(ips_plan_create(&p, 3, n3, h3, 6, 0, IPS_FLAG_SCREENING | IPS_FLAG_ADJOINT) == IPS_E_UNSUPPORTED,
            "screening adjoint");
+    expect(ips_plan_create(&p, 3, n3, h3, 6, 0, IPS_FLAG_SCREEN_DIRECT) == IPS_E_INVALID_ARG,
+           "direct surface sums without screening");
     const int64_t small[3] = {9, 6, 9};
     expect(ips_plan_create(&p, 3, small, h3, 4, 0, IPS_FLAG_SCREENING) == IPS_E_INVALID_ARG, "screening n < 7");
     const int64_t seven[3] = {9, 7, 9};

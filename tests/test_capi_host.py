@@ -68,6 +68,8 @@ def test_plan_create_rejects_bad_order_precision_flags():
     assert _create(2, [9, 9], [0.1, 0.1], order=5)[0] == -1
     assert _create(2, [9, 9], [0.1, 0.1], precision=7)[0] == -1
     assert _create(2, [9, 9], [0.1, 0.1], flags=64)[0] == -1
+    assert _create(2, [9, 9], [0.1, 0.1], flags=128)[0] == -1  # direct surface sums need screening
+    assert _create(2, [9, 9], [0.1, 0.1], flags=256)[0] == -1
     assert _create(2, [9, 9], [0.1, 0.1], precision=1, flags=32)[0] == -2
     assert _create(2, [9, 9], [0.1, 0.1], flags=32 | 2)[0] == -2
     assert _create(3, [9, 6, 9], [0.1, 0.1, 0.1], order=4, flags=32)[0] == -1

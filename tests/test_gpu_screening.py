@@ -45,6 +45,26 @@ def test_screening_3d(shape, order):
     _run(shape, order, 5, [1.0, 0.9, 1.15])
 
 
+@pytest.mark.parametrize("shape", [(41, 37, 45), (65, 65, 65), (9, 30, 12)])
+def test_screening_transforms_match_the_direct_sums(shape):
+    """The 3D surface sums by transforms (the default) against the direct sums
+    of IPS_FLAG_SCREEN_DIRECT, on the same input."""
+    from gpu_util import banner, rel_err, to_dev
+
+    banner("screening transforms vs direct %s" % (shape,))
+    rho, h, _ = I.workload_bumps(shape, seed=21, scale=[1.0, 1.1, 0.95])
+    x = to_dev(rho)
+    pf = api.Plan(shape, h, order=6, screening=True)
+    pd = api.Plan(shape, h, order=6, screening=True, screen_direct=True)
+    fast = pf(x).cpu().numpy()
+    direct = pd(x).cpu().numpy()
+    pf.close()
+    pd.close()
+    err = rel_err(fast, direct)
+    banner("  rel err %.3e" % err)
+    assert err <= TOL
+
+
 def test_screening_boundary_values_are_the_surface_sums():
     """The boundary nodes of the GPU result are the oracle's surface sums g."""
     from gpu_util import to_dev
@@ -70,6 +90,7 @@ def test_screening_rejections():
     h = _lib.f64_array([0.1] * 3)
     assert L.ips_plan_create(ctypes.byref(hnd), 3, n, h, 6, 1, 32) == -2  # mixed precision
     assert L.ips_plan_create(ctypes.byref(hnd), 3, n, h, 6, 0, 32 | 2) == -2  # adjoint flag
+    assert L.ips_plan_create(ctypes.byref(hnd), 3, n, h, 6, 0, 128) == -1  # direct sums without screening
     p = api.Plan((20, 20, 20), [0.1] * 3, screening=True)
     x = torch.zeros((20, 20, 20), dtype=torch.float64, device="cuda:0")
     with pytest.raises(_lib.IpsError) as ei:
