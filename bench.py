@@ -339,6 +339,10 @@ def ingest_counters(csv_a, csv_b, title, cmd, out_name, cu=256, xcd=8):
         first -= 1
     while first > 0 and ("k_cc" in a[first - 1]["name"] or "k_pass" in a[first - 1]["name"]):
         first -= 1
+    # the run of passes reaches back into the previous solve's inverse passes:
+    # the solve starts at the forward pass of rho that the first contraction follows
+    while first < last_final and not ("k_pass" in a[first]["name"] and "k_cc" in a[first + 1]["name"]):
+        first += 1
     lines = ["# %s" % title, "", "Command (run from the repository root, one pass per counter set):", "",
              "```", cmd, "```", "", ingest_counters.__doc__.strip().replace("\n    ", "\n"), "",
              "| kernel | waves | occupancy | VALU busy | LDS bank | LDS wait | any wait | VALU/wave | LDS/wave | VMEM rd/wave |",
@@ -557,6 +561,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint timings")
     ap.add_argument("--batched-only", action="store_true", help="only the batched leg (profiling)")
+    ap.add_argument("--screening-only", action="store_true", help="only the screening leg (profiling)")
     ap.add_argument("--ingest", nargs="+", metavar="ARG")
     args = ap.parse_args()
 
@@ -585,6 +590,9 @@ def main():
 
     if args.batched_only:
         print(json.dumps(time_batched(api, torch, args.steps, args.warmup)), flush=True)
+        return
+    if args.screening_only:
+        print(json.dumps(time_screening(api, torch, sizes=(args.n,), steps=args.steps)), flush=True)
         return
 
     n = args.n

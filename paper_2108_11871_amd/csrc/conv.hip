@@ -57,8 +57,13 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
     for (int i = 0; i < TPT; ++i) a10[i] = a11[i] = a20[i] = a21[i] = 0.0;
     if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
     const int hc = (a.ncols + 1) >> 1; // first-half columns (the chunked range)
-    const int cbeg = ch * a.cols_per_chunk;
-    const int cend = min(hc, cbeg + a.cols_per_chunk);
+    // tiles of this chunk: a contiguous run of columns, or (interleaved) every
+    // nchunk-th tile, so that the blocks of one batch entry, which run side by
+    // side, read neighbouring columns at the same time (strided pencils share
+    // their cache lines across those blocks instead of re-fetching them)
+    const int cbeg = a.interleave ? ch * Wh : ch * a.cols_per_chunk;
+    const int cend = a.interleave ? hc : min(hc, cbeg + a.cols_per_chunk);
+    const int cstep = a.interleave ? nchunk * Wh : Wh;
     // PF (compile-time width): the next tile is fetched into registers while
     // the current one is transformed and contracted
     constexpr bool PF = WHC > 0;
@@ -71,7 +76,7 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
         if (cbeg < cend)
             fetch_pair<TI, NTT, WCF, MAXE>(pf, in, a.nrows_in, a.irs, a.ics, cbeg, n_a(cbeg), a.ncols - 1 - cbeg,
                                           n_b(cbeg), threadIdx.x);
-    for (int c0 = cbeg; c0 < cend; c0 += Wh) {
+    for (int c0 = cbeg; c0 < cend; c0 += cstep) {
         const int nA = n_a(c0);
         const int m0 = a.ncols - 1 - c0; // mirror of c0
         const int nB = n_b(c0);          // mirrors distinct from their column
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
         zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N, tid);
         if constexpr (PF) {
             put_pair<T, TI, NTT, WCF, MAXE>(buf, rs, 1, pf, a.nrows_in, rcont, tid);
-            const int c1 = c0 + Wh;
+            const int c1 = c0 + cstep;
             if (c1 < cend)
                 fetch_pair<TI, NTT, WCF, MAXE>(pf, in, a.nrows_in, a.irs, a.ics, c1, n_a(c1), a.ncols - 1 - c1,
                                               n_b(c1), tid);

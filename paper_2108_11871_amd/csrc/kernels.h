@@ -47,6 +47,7 @@ struct CcArgs {
     int nbatch;        // slots of the remaining in-face axis (1 if none)
     int Mo;            // M of that axis (slot -> wavenumber), 0 if none
     int cols_per_chunk; // first-half columns per chunk (a tile pairs column c with ncols-1-c)
+    int interleave;     // chunk ch takes tiles ch, ch + nchunk, ... instead of a contiguous run
     const double *K;   // K[d][k_o][k_p], k_p contiguous (FP64 in every mode)
     int64_t Kd, Ko;
     double *part;      // FP64 chunk partials [2][nchunk][nbatch][2 M_p]
@@ -157,13 +158,15 @@ struct SurfArgs {
     double *XH[3];        // their slot spectra over both in-face axes [2][2 M_b][2 M_c]
     const double *KP[3];  // kernel spectra of the same face and the opposite face [2][M_b + 1][M_c + 1]
     double *PP[3];        // parallel-face sums at the face nodes [2][M_b + 1][M_c + 1]
-    // per pair: slot spectra along c of the charges of faces a and b, the
-    // transfer to the other family, and the sums back on the face nodes
-    double *XA[3], *XB[3]; // [2][M_b + 1][2 M_c], [2][M_a + 1][2 M_c]
-    double *YA[3], *YB[3]; // same shapes: targets on a (from b), targets on b (from a)
-    double *QA[3], *QB[3]; // [2][M_b + 1][M_c + 1], [2][M_a + 1][M_c + 1]
-    const double *KT[3];   // kernel spectra along c: KT[k][i][j] = FFT_c G(i h_a, j h_b, .)
-    int rows;              // table rows per LDS tile in k_perp
+    // per pair: slot spectra along c of the charges of faces a and b (slot
+    // major), the partial transfers to the other family, and the sums back on
+    // the face nodes
+    const double *XA[3], *XB[3]; // [2 M_c][2][M_b + 1], [2 M_c][2][M_a + 1]
+    double *PA[3];               // targets on a: [2 M_c][2 groups][2][M_b + 1]
+    double *PB[3];               // targets on b: [2 M_c][2][2][M_a + 1]
+    double *QA[3], *QB[3];       // [2][M_b + 1][M_c + 1], [2][M_a + 1][M_c + 1]
+    const double *KT[3];         // kernel spectra along c: KT[k][i][j] = FFT_c G(i h_a, j h_b, .)
+    int groups[3];               // row groups per wavenumber (perp_groups)
 };
 
 // G samples of the tables: same face / opposite face of axis f ([2][M_b + 1][M_c + 1])
@@ -172,9 +175,10 @@ hipError_t launch_par_sample(double *out, int f, const int *M, const double *h, 
 hipError_t launch_perp_sample(double *out, int a, int b, int c, const int *M, const double *h, hipStream_t st);
 hipError_t launch_face_charge(const SurfArgs &s, hipStream_t st);
 hipError_t launch_par_mul(const SurfArgs &s, hipStream_t st);
-// table rows per LDS tile of the perpendicular-pair kernel for these sizes
-// (0: a face side too long for it)
-int perp_rows(const int *M);
+// the perpendicular-pair kernel takes these sizes (face sides up to 3 NT nodes)
+bool perp_fits(const int *M);
+// row groups per wavenumber of pair pr (a launch runs (M_c + 1) x groups blocks)
+int perp_groups(const int *M, int pr);
 hipError_t launch_perp(const SurfArgs &s, hipStream_t st);
 hipError_t launch_surf_assemble(const SurfArgs &s, double *phi, hipStream_t st);
 

@@ -246,16 +246,17 @@ struct ips_plan_s {
     double *S[3] = {nullptr, nullptr, nullptr};  // face coefficients / sigma [2][I_b][I_c]
     double *src = nullptr;                       // surface nodes [4][nsrc] (direct sums)
     int64_t nsrc = 0, ntgt = 0;
-    // 3D surface sums by transforms (surf_rows > 0) instead of the direct sums:
+    // 3D surface sums by transforms (surf_fast) instead of the direct sums:
     // tables KP (parallel faces, per family) and KT (perpendicular pairs), and
     // workspace per family (charges, their slot spectra, the parallel sums) and
     // per pair (spectra along the shared axis, overwritten by the transfers,
     // and the sums back on the face nodes)
-    int surf_rows = 0;
+    bool surf_fast = false;
     double *KP[3] = {nullptr, nullptr, nullptr}, *KT[3] = {nullptr, nullptr, nullptr};
     double *FA[3] = {nullptr, nullptr, nullptr}, *XH[3] = {nullptr, nullptr, nullptr};
     double *PP[3] = {nullptr, nullptr, nullptr};
     double *XA[3] = {nullptr, nullptr, nullptr}, *XB[3] = {nullptr, nullptr, nullptr};
+    double *PA[3] = {nullptr, nullptr, nullptr}, *PB[3] = {nullptr, nullptr, nullptr};
     double *QA[3] = {nullptr, nullptr, nullptr}, *QB[3] = {nullptr, nullptr, nullptr};
     DevBuf mem;   // tables: twiddles, axis tables, kernel spectra (and an extended plan's arrays)
     // execution workspace: one block carved into the buffers above (B, A, part, F,
@@ -533,7 +534,7 @@ void layout_ws(ips_plan p, Carver &c)
         }
         double *bs;
         c.take(&bs, 2 * ts * sizeof(double));
-        if (p->surf_rows) {
+        if (p->surf_fast) {
             for (int f = 0; f < 3; ++f) {
                 int b, cc;
                 face_axes(f, b, cc);
@@ -547,6 +548,9 @@ void layout_ws(ips_plan p, Carver &c)
                 pair_axes(pr, a, b, cc);
                 c.take(&p->XA[pr], 2 * (size_t)(M[b] + 1) * N[cc] * sizeof(double));
                 c.take(&p->XB[pr], 2 * (size_t)(M[a] + 1) * N[cc] * sizeof(double));
+                const size_t G = (size_t)perp_groups(M, pr);
+                c.take(&p->PA[pr], 4 * G * (M[b] + 1) * N[cc] * sizeof(double));
+                c.take(&p->PB[pr], 4 * (size_t)(M[a] + 1) * N[cc] * sizeof(double));
                 c.take(&p->QA[pr], 2 * (size_t)(M[b] + 1) * (M[cc] + 1) * sizeof(double));
                 c.take(&p->QB[pr], 2 * (size_t)(M[a] + 1) * (M[cc] + 1) * sizeof(double));
             }
@@ -776,7 +780,7 @@ int plan_build(ips_plan p, hipStream_t st)
         p->nsrc = (int64_t)(2 * ts);
         const int64_t n0 = p->n[0], n1 = p->n[1], n2 = d == 3 ? p->n[2] : 1;
         p->ntgt = 2 * n1 * n2 + 2 * (n0 - 2) * n2 + (d == 3 ? 2 * (n0 - 2) * (n1 - 2) : 0);
-        if (!p->surf_rows) return IPS_OK; // no tables: direct surface sums
+        if (!p->surf_fast) return IPS_OK; // no tables: direct surface sums
         // parallel faces of family f: G at in-plane offsets on the same face and
         // on the opposite one, even transforms along c then b
         for (int f = 0; f < 3; ++f) {
@@ -940,17 +944,19 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         s.XH[a] = p->XH[a];
         s.KP[a] = p->KP[a];
         s.PP[a] = p->PP[a];
-        s.XA[a] = s.YA[a] = p->XA[a]; // the transfer of slot k overwrites slot k
-        s.XB[a] = s.YB[a] = p->XB[a];
+        s.XA[a] = p->XA[a];
+        s.XB[a] = p->XB[a];
+        s.PA[a] = p->PA[a];
+        s.PB[a] = p->PB[a];
         s.QA[a] = p->QA[a];
         s.QB[a] = p->QB[a];
         s.KT[a] = p->KT[a];
+        s.groups[a] = perp_groups(M, a);
     }
-    s.rows = p->surf_rows;
     IPS_HIP(launch_face_charge(s, st));
-    // face f along its axis x (o the other face axis): FA[f] -> out[2][M_o + 1][N_x]
-    // (sides obs apart, default (M_o + 1) N_x)
-    auto along = [&](int f, int x, double *out, int64_t obs) -> int {
+    // face f along its axis x (o the other face axis), slot q of side s and
+    // node m of axis o to out[q ors + s obs + m ocs]
+    auto along = [&](int f, int x, double *out, int64_t ors, int64_t ocs, int64_t obs) -> int {
         int b, c;
         face_axes(f, b, c);
         const int o = x == c ? b : c;
@@ -960,9 +966,9 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         a.irs = x == c ? 1 : M[c] + 1;
         a.ics = x == c ? M[c] + 1 : 1;
         a.ibs = (int64_t)(M[b] + 1) * (M[c] + 1);
-        a.ors = 1;
-        a.ocs = N[x];
-        a.obs = obs ? obs : (int64_t)(M[o] + 1) * N[x];
+        a.ors = ors;
+        a.ocs = ocs;
+        a.obs = obs;
         a.nrows_in = M[x] + 1;
         a.ncols = M[o] + 1;
         a.nbatch = 2;
@@ -972,14 +978,17 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         a.scale = 1.0;
         return run_pass(p, a, p->fd[x], p->tw[x], false, false, st);
     };
-    // back on the nodes along the shared axis x: in[2][M_o + 1][N_x] -> out[2][M_o + 1][M_x + 1]
-    auto back = [&](const double *in, double *out, int x, int o) -> int {
+    // back on the nodes along the shared axis x, the sum of ncopy partials:
+    // in[N_x][ncopy][2][M_o + 1] -> out[2][M_o + 1][M_x + 1]
+    auto back = [&](const double *in, double *out, int x, int o, int ncopy) -> int {
         PassArgs a{};
         a.in = in;
         a.out = out;
-        a.irs = 1;
-        a.ics = N[x];
-        a.ibs = (int64_t)(M[o] + 1) * N[x];
+        a.irs = (int64_t)ncopy * 2 * (M[o] + 1);
+        a.ics = 1;
+        a.ibs = M[o] + 1;
+        a.nsum = ncopy;
+        a.sstride = 2 * (int64_t)(M[o] + 1);
         a.ors = 1;
         a.ocs = M[x] + 1;
         a.obs = (int64_t)(M[o] + 1) * (M[x] + 1);
@@ -996,7 +1005,7 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         int b, c;
         face_axes(f, b, c);
         // along c into [2][N_b][N_c] (rows 0..M_b), then along b in place
-        if ((rc = along(f, c, p->XH[f], (int64_t)N[b] * N[c]))) return rc;
+        if ((rc = along(f, c, p->XH[f], 1, N[c], (int64_t)N[b] * N[c]))) return rc;
         PassArgs a{};
         a.in = a.out = p->XH[f];
         a.irs = a.ors = N[c];
@@ -1014,8 +1023,8 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
     for (int pr = 0; pr < 3; ++pr) {
         int a, b, c;
         pair_axes(pr, a, b, c);
-        if ((rc = along(a, c, p->XA[pr], 0))) return rc;
-        if ((rc = along(b, c, p->XB[pr], 0))) return rc;
+        if ((rc = along(a, c, p->XA[pr], 2 * (int64_t)(M[b] + 1), 1, M[b] + 1))) return rc;
+        if ((rc = along(b, c, p->XB[pr], 2 * (int64_t)(M[a] + 1), 1, M[a] + 1))) return rc;
     }
     IPS_HIP(launch_par_mul(s, st));
     for (int f = 0; f < 3; ++f) {
@@ -1057,8 +1066,8 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
     for (int pr = 0; pr < 3; ++pr) {
         int a, b, c;
         pair_axes(pr, a, b, c);
-        if ((rc = back(p->XA[pr], p->QA[pr], c, b))) return rc;
-        if ((rc = back(p->XB[pr], p->QB[pr], c, a))) return rc;
+        if ((rc = back(p->PA[pr], p->QA[pr], c, b, 2 * s.groups[pr]))) return rc;
+        if ((rc = back(p->PB[pr], p->QB[pr], c, a, 2))) return rc;
     }
     IPS_HIP(launch_surf_assemble(s, phi, st));
     return IPS_OK;
@@ -1167,7 +1176,7 @@ int screen_boundary(ips_plan p, const double *rho, double *phi, hipStream_t st)
     // sigma on the faces: inverse sine transforms over the in-face axes
     for (int fam = 0; fam < d; ++fam)
         if ((rc = shell_dst(p, p->S[fam], 2, fam, true, st))) return rc;
-    if (!p->surf_rows) {
+    if (!p->surf_fast) {
         IPS_HIP(launch_screen_g(s, phi, st));
         return IPS_OK;
     }
@@ -1256,6 +1265,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[2];
             a.Mo = M[2];
             a.cols_per_chunk = p->chunk[1];
+            a.interleave = 1; // pencils along x: strided rows
             a.K = p->K[1];
             a.Kd = (int64_t)(M[2] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
@@ -1301,6 +1311,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = N[1];
             a.Mo = M[1];
             a.cols_per_chunk = p->chunk[2];
+            a.interleave = 1;
             a.K = p->K[2];
             a.Kd = (int64_t)(M[1] + 1) * (M[0] + 1);
             a.Ko = M[0] + 1;
@@ -1389,6 +1400,7 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.nbatch = 1;
             a.Mo = 0;
             a.cols_per_chunk = p->chunk[fam];
+            a.interleave = fam == 1;
             a.K = p->K[fam];
             a.Kd = M[pen] + 1;
             a.Ko = 0;
@@ -2017,7 +2029,7 @@ int plan_create_work(ips_plan *out, int d, const int64_t *n, const double *h, in
         p->I[a] = p->M[a] - 1;
         p->N[a] = 2 * p->M[a];
     }
-    if (p->screen && d == 3 && !(flags & IPS_FLAG_SCREEN_DIRECT)) p->surf_rows = perp_rows(p->M);
+    if (p->screen && d == 3 && !(flags & IPS_FLAG_SCREEN_DIRECT)) p->surf_fast = perp_fits(p->M);
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
         delete p;

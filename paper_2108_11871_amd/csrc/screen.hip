@@ -2,9 +2,13 @@
 // and 2), the alternative to the volume sums of Section 4:
 //   g(x) = surface integral of G(|x - s|) sigma(s) dS(s),  sigma = d phi*/dn,
 // sigma from the sine coefficients alpha of phi* (Section 3).
-//   k_sigma_sums : face sine coefficients of sigma, sums over the normal wavenumber
+//   k_sigma_rows, k_sigma_cols : face sine coefficients of sigma, sums over
+//                  the normal wavenumber
 //   k_screen_src : the weighted surface nodes (position, W sigma) of every face
 //   k_screen_g   : the corrected surface trapezoidal sums at every boundary node
+//                  (direct sums)
+//   k_face_charge, k_par_mul, k_perp, k_surf_assemble : the same sums in 3D by
+//                  transforms (with the slot passes of the plan)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,55 +58,57 @@ __device__ __forceinline__ int64_t face_elems(const ScreenArgs &a, int fam)
 //   S[a][0][k_other] = -sum_{k_a} (pi k_a/L_a) alpha_k          (face x_a = lo)
 //   S[a][1][k_other] =  sum_{k_a} (pi k_a/L_a) (-1)^{k_a} alpha_k (face x_a = hi)
 // stored as [side][k_b - 1][k_c - 1], the other axes in increasing order.
-// One wave per output pair: its lanes stride over k_a and reduce by shuffles.
+// k_sigma_rows takes the family whose sum runs over the contiguous axis
+// (a = 1): one wave per output pair, its lanes stride over k_1 and reduce by
+// shuffles; k_sigma_cols takes the others.  Both issue kSigU loads per lane
+// before using them.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_sigma_sums(ScreenArgs a, int64_t nfam0, int64_t nfam1)
+constexpr int kSigU = 8;
+
+__global__ __launch_bounds__(NT) void k_sigma_rows(ScreenArgs a, int64_t nout)
 {
     const int lane = threadIdx.x & 63;
-    int64_t w = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-    int fam = 0;
-    if (w >= nfam0) {
-        w -= nfam0;
-        fam = 1;
-        if (w >= nfam1) {
-            w -= nfam1;
-            fam = 2;
-        }
-    }
-    if (fam >= a.d || w >= face_elems(a, fam)) return;
-    const int I0 = a.M[0] - 1, I1 = a.M[1] - 1, I2 = a.d == 3 ? a.M[2] - 1 : 1;
-    // the two fixed wavenumbers of this output (face layout order)
-    int k[3] = {0, 0, 0};
+    const int64_t w = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    if (w >= nout) return;
+    const int I0 = a.M[0] - 1, I1 = a.M[1] - 1;
+    // face layout of family 1: [side][k0][k2] (3D) or [side][k0]
+    int k0, k2 = 1;
     if (a.d == 3) {
-        const int b = fam == 0 ? 1 : 0, c = fam == 2 ? 1 : 2;
-        const int Ic = a.M[c] - 1;
-        k[b] = 1 + (int)(w / Ic);
-        k[c] = 1 + (int)(w % Ic);
+        const int I2 = a.M[2] - 1;
+        k0 = 1 + (int)(w / I2);
+        k2 = 1 + (int)(w % I2);
     } else {
-        k[1 - fam] = 1 + (int)w;
+        k0 = 1 + (int)w;
     }
-    const int Ia = a.M[fam] - 1;
+    const double *row = a.Y + (a.d == 3 ? ((int64_t)(k2 - 1) * I0 + (k0 - 1)) * I1 : (int64_t)(k0 - 1) * I1);
+    double qo = a.tab[0].q[k0 - 1];
+    if (a.d == 3) qo += a.tab[2].q[k2 - 1];
     double lo = 0.0, hi = 0.0;
-    for (int ka = 1 + lane; ka <= Ia; ka += 64) {
-        k[fam] = ka;
-        const int64_t idx = a.d == 3 ? ((int64_t)(k[2] - 1) * I0 + (k[0] - 1)) * I1 + (k[1] - 1)
-                                     : (int64_t)(k[0] - 1) * I1 + (k[1] - 1);
-        double q = 0.0;
-        for (int b = 0; b < a.d; ++b) q += a.tab[b].q[k[b] - 1];
-        const double alpha = -a.pref * a.Y[idx] / q;
-        const double t = (ka * a.piL[fam]) * alpha;
-        lo -= t;
-        hi += (ka & 1) ? -t : t;
+    for (int base = 1 + lane; base <= I1; base += 64 * kSigU) {
+        double y[kSigU];
+#pragma unroll
+        for (int u = 0; u < kSigU; ++u) {
+            const int k1 = base + 64 * u;
+            y[u] = k1 <= I1 ? row[k1 - 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSigU; ++u) {
+            const int k1 = base + 64 * u;
+            if (k1 <= I1) {
+                const double alpha = -a.pref * y[u] / (qo + a.tab[1].q[k1 - 1]);
+                const double t = (k1 * a.piL[1]) * alpha;
+                lo -= t;
+                hi += (k1 & 1) ? -t : t;
+            }
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         lo += __shfl_xor(lo, off);
         hi += __shfl_xor(hi, off);
     }
-    (void)I2;
     if (lane == 0) {
-        const int64_t fe = face_elems(a, fam);
-        a.S[fam][w] = lo;
-        a.S[fam][fe + w] = hi;
+        a.S[1][w] = lo;
+        a.S[1][nout + w] = hi;
     }
 }
 
@@ -385,32 +391,46 @@ hipError_t launch_par_mul(const SurfArgs &s, hipStream_t st)
     return hipGetLastError();
 }
 
-// One block per wavenumber k of the shared axis c of pair (a, b): both slots
-// (cosine k, sine k) of
-//   YA[s][t][.] = sum_(s', u) KT[k][|s M_a - u|][|t - s' M_b|] XB[s'][u][.]   (targets on face (a, s))
-//   YB[s'][u][.] = sum_(s, t) KT[k][|s M_a - u|][|t - s' M_b|] XA[s][t][.]   (targets on face (b, s'))
-// The table slab KT[k] streams through LDS in tiles of rows i; the targets on
-// a are owned by the threads (columns j, accumulated over the rows), the
-// targets on b by the rows (each wave reduces its rows over the columns).
-// With i = |s M_a - u| and j = |t - s' M_b|: u = i or M_a - i by side s, and
-// t = j or M_b - j by side s'.
+// Perpendicular pairs.  Block (k, g): wavenumber k of the shared axis c of
+// pair (a, b), both slots (cosine k, sine k), and the table rows i of row
+// group g.  With i = |s M_a - u| and j = |t - s' M_b| (u = i or M_a - i by the
+// side s of face a, t = j or M_b - j by the side s' of face b):
+//   targets on face (a, s), node t:   sum over (s', u) of KT[k][i][j] XB[s'][u]
+//   targets on face (b, s'), node u:  sum over (s, t) of KT[k][i][j] XA[s][t]
+// The first sum runs over the rows of every group: each block writes its
+// partial for every target, one copy per (group, s') -- the inverse transform
+// adds the copies.  The second is complete within a row; the row of side
+// s = 0 and that of s = 1 land in two copies.  Rows of KT[k] stream through
+// LDS in tiles, the next tile held in registers while the current one is
+// used (two tiles in flight); threads own columns j for the first sum, waves
+// own rows for the second.
+// Slot-major layouts: X*[q][side][node], partials PA[q][2 G][2][M_b + 1]
+// (copy g * 2 + s', then s) and PB[q][2][2][M_a + 1] (copy s, then s').
 constexpr int kPerpJpt = 3; // columns per thread: M_b + 1 <= 3 * NT
+constexpr int kPerpPf = 8; // table elements per thread in each of the two prefetch buffers:
+                            // tile rows * (M_b + 1) <= 8 * NT
 
-static size_t perp_lds_bytes(const int *M, int rows)
+bool perp_fits(const int *M)
 {
-    int mx = 0;
-    for (int a = 0; a < 3; ++a) mx = std::max(mx, M[a] + 1);
-    // xa, xb, two halves of YB, the second halves of YA, the tile
-    return (size_t)(4 * mx + 4 * mx + 8 * mx + 4 * mx + rows * mx) * sizeof(double);
+    for (int a = 0; a < 3; ++a)
+        if (M[a] + 1 > kPerpJpt * NT) return false;
+    return true;
 }
 
-int perp_rows(const int *M)
+int perp_groups(const int *M, int pr)
 {
-    int mx = 0;
-    for (int a = 0; a < 3; ++a) mx = std::max(mx, M[a] + 1);
-    if (mx > kPerpJpt * NT) return 0;
-    const int r = (int)((size_t)(160 * 1024) / (sizeof(double) * (size_t)mx)) - 20;
-    return std::max(0, std::min(16, r));
+    const int a = pr == 2 ? 1 : 0, b = pr == 0 ? 1 : 2, c = 3 - a - b;
+    (void)b;
+    // about 1024 blocks per launch, at least 8 rows per group
+    const int want = (1024 + M[c]) / (M[c] + 1);
+    return std::max(1, std::min(want, (M[a] + 1) / 8));
+}
+
+static size_t perp_lds_bytes(const int *M, int pr)
+{
+    const int a = pr == 2 ? 1 : 0, b = pr == 0 ? 1 : 2;
+    // xa, xb, the tile
+    return (size_t)(4 * (M[b] + 1) + 4 * (M[a] + 1) + kPerpPf * NT) * sizeof(double);
 }
 
 __global__ __launch_bounds__(NT) void k_perp(SurfArgs s, int pr)
@@ -419,41 +439,55 @@ __global__ __launch_bounds__(NT) void k_perp(SurfArgs s, int pr)
     int a, b, c;
     pair_axes(pr, a, b, c);
     const int Ma = s.M[a], Mb = s.M[b], Mc = s.M[c];
-    const int na = Ma + 1, nb = Mb + 1, Nc = 2 * Mc;
-    const int k = blockIdx.x;
-    const int nq = (k == 0 || k == Mc) ? 1 : 2;
+    const int na = Ma + 1, nb = Mb + 1;
+    const int k = blockIdx.x, g = blockIdx.y, G = gridDim.y;
+    const bool two = k > 0 && k < Mc; // the sine slot exists
     const int q0 = k, q1 = Mc + k;
-    double *xa = reinterpret_cast<double *>(smem); // [2][nb][2]
-    double *xb = xa + 4 * nb;                      // [2][na][2]
-    double *yb0 = xb + 4 * na;                     // [2][na][2] from the rows u = i (source side 0)
-    double *yb1 = yb0 + 4 * na;                    // [2][na][2] from the rows u = M_a - i (source side 1)
-    double *ls = yb1 + 4 * na;                     // [2][nb][2] targets on a, parts of source side 1
-    double *tile = ls + 4 * nb;                    // [rows][nb]
+    const int ibeg = (int)((int64_t)g * na / G), iend = (int)((int64_t)(g + 1) * na / G);
+    const int rows = kPerpPf * NT / nb;
+    double *xa = reinterpret_cast<double *>(smem); // [2][nb][2 slots]
+    double *xb = xa + 4 * nb;                      // [2][na][2 slots]
+    double *tile = xb + 4 * na;                    // [rows][nb]
     const double *XA = s.XA[pr], *XB = s.XB[pr];
+    const double *slab = s.KT[pr] + (int64_t)k * na * nb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double pfa[kPerpPf], pfb[kPerpPf];
+    auto fetch = [&](double(&pf)[kPerpPf], int i0) {
+        const int cnt = min(rows, iend - i0) * nb;
+        const double *src = slab + (int64_t)i0 * nb;
+#pragma unroll
+        for (int m = 0; m < kPerpPf; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (e < cnt) pf[m] = src[e];
+        }
+    };
+    auto put = [&](const double(&pf)[kPerpPf], int nr) {
+#pragma unroll
+        for (int m = 0; m < kPerpPf; ++m) {
+            const int e = threadIdx.x + m * NT;
+            if (e < nr * nb) tile[e] = pf[m];
+        }
+    };
+    // the first two tiles are requested before anything else
+    if (ibeg < iend) fetch(pfa, ibeg);
+    if (ibeg + rows < iend) fetch(pfb, ibeg + rows);
     for (int e = threadIdx.x; e < 2 * nb; e += NT) {
-        const int64_t o = (int64_t)e * Nc;
-        xa[2 * e] = XA[o + q0];
-        xa[2 * e + 1] = nq > 1 ? XA[o + q1] : 0.0;
+        xa[2 * e] = XA[(int64_t)q0 * 2 * nb + e];
+        xa[2 * e + 1] = two ? XA[(int64_t)q1 * 2 * nb + e] : 0.0;
     }
     for (int e = threadIdx.x; e < 2 * na; e += NT) {
-        const int64_t o = (int64_t)e * Nc;
-        xb[2 * e] = XB[o + q0];
-        xb[2 * e + 1] = nq > 1 ? XB[o + q1] : 0.0;
+        xb[2 * e] = XB[(int64_t)q0 * 2 * na + e];
+        xb[2 * e + 1] = two ? XB[(int64_t)q1 * 2 * na + e] : 0.0;
     }
-    for (int e = threadIdx.x; e < 8 * na; e += NT) yb0[e] = 0.0;
     double acc[kPerpJpt][2][2][2]; // [column][target side s][source side s'][slot]
 #pragma unroll
     for (int jj = 0; jj < kPerpJpt; ++jj)
 #pragma unroll
         for (int v = 0; v < 8; ++v) (&acc[jj][0][0][0])[v] = 0.0;
-    const double *slab = s.KT[pr] + (int64_t)k * na * nb;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int i0 = 0; i0 < na; i0 += s.rows) {
-        const int nr = min(s.rows, na - i0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < nr * nb; e += NT) tile[e] = slab[(int64_t)i0 * nb + e];
-        __syncthreads();
-        // targets on face a (threads own the columns)
+    double *PB = s.PB[pr];
+    const int64_t pbq = 4 * (int64_t)na;
+    auto work = [&](int i0, int nr) {
+        // targets on face a: threads own the columns
         for (int r = 0; r < nr; ++r) {
             const int i = i0 + r;
             double x[2][2][2]; // [s][s'][slot] = XB[s'][u_s(i)][slot]
@@ -481,82 +515,101 @@ __global__ __launch_bounds__(NT) void k_perp(SurfArgs s, int pr)
                 }
             }
         }
-        // targets on face b (each wave reduces whole rows)
-        for (int r = wave; r < nr; r += NT / 64) {
-            const int i = i0 + r;
-            double ps[2][2][2]; // [source side s][target side s'][slot]
+        // targets on face b: each wave reduces whole rows over the columns, two
+        // rows (r, r + 4) at a time so that they share the loads of xa
+        for (int r = wave; r < nr; r += 2 * (NT / 64)) {
+            const int r2 = r + NT / 64;
+            const bool has2 = r2 < nr;
+            double v[16]; // [row][s][s'][slot]
 #pragma unroll
-            for (int v = 0; v < 8; ++v) (&ps[0][0][0])[v] = 0.0;
+            for (int t = 0; t < 16; ++t) v[t] = 0.0;
             for (int j = lane; j < nb; j += 64) {
-                const double K = tile[r * nb + j];
+                const double K1 = tile[r * nb + j];
+                const double K2 = has2 ? tile[r2 * nb + j] : 0.0;
 #pragma unroll
                 for (int sp = 0; sp < 2; ++sp) {
                     const int t = sp ? Mb - j : j;
 #pragma unroll
                     for (int sd = 0; sd < 2; ++sd) {
-                        ps[sd][sp][0] = fma(K, xa[(sd * nb + t) * 2], ps[sd][sp][0]);
-                        ps[sd][sp][1] = fma(K, xa[(sd * nb + t) * 2 + 1], ps[sd][sp][1]);
+                        const double x0 = xa[(sd * nb + t) * 2], x1 = xa[(sd * nb + t) * 2 + 1];
+                        const int o = sd * 4 + sp * 2;
+                        v[o] = fma(K1, x0, v[o]);
+                        v[o + 1] = fma(K1, x1, v[o + 1]);
+                        v[8 + o] = fma(K2, x0, v[8 + o]);
+                        v[8 + o + 1] = fma(K2, x1, v[8 + o + 1]);
                     }
                 }
             }
+            // halving reduction: after the exchanges over lane bits 5, 4, 3, 2
+            // a lane holds one of the 16 values, index lane >> 2
+            double w8[8], w4[4], w2[2];
+            const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                double w = (&ps[0][0][0])[v];
-                for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
-                (&ps[0][0][0])[v] = w;
-            }
-            if (lane == 0) {
+            for (int m = 0; m < 8; ++m)
+                w8[m] = (h5 ? v[m + 8] : v[m]) + __shfl_xor(h5 ? v[m] : v[m + 8], 32);
 #pragma unroll
-                for (int sp = 0; sp < 2; ++sp) {
-                    // source side 0: u = i; source side 1: u = M_a - i
-                    yb0[(sp * na + i) * 2] = ps[0][sp][0];
-                    yb0[(sp * na + i) * 2 + 1] = ps[0][sp][1];
-                    yb1[(sp * na + (Ma - i)) * 2] = ps[1][sp][0];
-                    yb1[(sp * na + (Ma - i)) * 2 + 1] = ps[1][sp][1];
-                }
+            for (int m = 0; m < 4; ++m)
+                w4[m] = (h4 ? w8[m + 4] : w8[m]) + __shfl_xor(h4 ? w8[m] : w8[m + 4], 16);
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                w2[m] = (h3 ? w4[m + 2] : w4[m]) + __shfl_xor(h3 ? w4[m] : w4[m + 2], 8);
+            double w = (h2 ? w2[1] : w2[0]) + __shfl_xor(h2 ? w2[0] : w2[1], 4);
+            w += __shfl_xor(w, 2);
+            w += __shfl_xor(w, 1);
+            const int vi = lane >> 2; // row (vi >> 3), s = (vi >> 2) & 1, s' = (vi >> 1) & 1, slot = vi & 1
+            if ((lane & 3) == 0 && (vi < 8 || has2)) {
+                const int i = i0 + (vi < 8 ? r : r2);
+                const int sd = (vi >> 2) & 1, sp = (vi >> 1) & 1, sl = vi & 1;
+                const int u = sd ? Ma - i : i;
+                if (!sl || two)
+                    PB[(int64_t)(sl ? q1 : q0) * pbq + (sd * 2 + sp) * na + u] = w;
             }
         }
+    };
+    for (int i0 = ibeg; i0 < iend; i0 += 2 * rows) {
+        int nr = min(rows, iend - i0);
+        __syncthreads(); // the previous tile is consumed (and xa, xb are stored)
+        put(pfa, nr);
+        __syncthreads();
+        if (i0 + 2 * rows < iend) fetch(pfa, i0 + 2 * rows);
+        work(i0, nr);
+        const int i1 = i0 + rows;
+        if (i1 >= iend) break;
+        nr = min(rows, iend - i1);
+        __syncthreads();
+        put(pfb, nr);
+        __syncthreads();
+        if (i1 + 2 * rows < iend) fetch(pfb, i1 + 2 * rows);
+        work(i1, nr);
     }
-    __syncthreads();
-    // targets on a: t = j from source side 0, t = M_b - j from side 1
+    // partials of the targets on face a: copy (g, s'), t = j (s' = 0) or M_b - j (s' = 1)
+    double *PA = s.PA[pr];
+    const int64_t paq = (int64_t)G * 4 * nb;
 #pragma unroll
     for (int jj = 0; jj < kPerpJpt; ++jj) {
         const int j = threadIdx.x + jj * NT;
         if (j < nb)
 #pragma unroll
-            for (int sd = 0; sd < 2; ++sd) {
-                ls[(sd * nb + (Mb - j)) * 2] = acc[jj][sd][1][0];
-                ls[(sd * nb + (Mb - j)) * 2 + 1] = acc[jj][sd][1][1];
-            }
-    }
-    __syncthreads();
-    double *YA = s.YA[pr], *YB = s.YB[pr];
+            for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int jj = 0; jj < kPerpJpt; ++jj) {
-        const int j = threadIdx.x + jj * NT;
-        if (j < nb)
-#pragma unroll
-            for (int sd = 0; sd < 2; ++sd) {
-                const int64_t o = ((int64_t)sd * nb + j) * Nc;
-                YA[o + q0] = acc[jj][sd][0][0] + ls[(sd * nb + j) * 2];
-                if (nq > 1) YA[o + q1] = acc[jj][sd][0][1] + ls[(sd * nb + j) * 2 + 1];
-            }
-    }
-    for (int e = threadIdx.x; e < 2 * na; e += NT) {
-        const int64_t o = (int64_t)e * Nc;
-        YB[o + q0] = yb0[2 * e] + yb1[2 * e];
-        if (nq > 1) YB[o + q1] = yb0[2 * e + 1] + yb1[2 * e + 1];
+                for (int sd = 0; sd < 2; ++sd) {
+                    const int t = sp ? Mb - j : j;
+                    const int64_t o = ((int64_t)(g * 2 + sp) * 2 + sd) * nb + t;
+                    PA[q0 * paq + o] = acc[jj][sd][sp][0];
+                    if (two) PA[q1 * paq + o] = acc[jj][sd][sp][1];
+                }
     }
 }
 
 hipError_t launch_perp(const SurfArgs &s, hipStream_t st)
 {
-    if (s.rows < 1 || perp_rows(s.M) < s.rows) return hipErrorInvalidValue;
-    const size_t lds = perp_lds_bytes(s.M, s.rows);
-    set_lds((const void *)&k_perp, lds);
+    if (!perp_fits(s.M)) return hipErrorInvalidValue;
     for (int pr = 0; pr < 3; ++pr) {
         const int c = pr == 0 ? 2 : (pr == 1 ? 1 : 0);
-        hipLaunchKernelGGL(k_perp, dim3(s.M[c] + 1), dim3(NT), lds, st, s, pr);
+        if (s.groups[pr] != perp_groups(s.M, pr)) return hipErrorInvalidValue;
+        const size_t lds = perp_lds_bytes(s.M, pr);
+        set_lds((const void *)&k_perp, lds);
+        hipLaunchKernelGGL(k_perp, dim3(s.M[c] + 1, s.groups[pr]), dim3(NT), lds, st, s, pr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -627,20 +680,93 @@ hipError_t launch_surf_assemble(const SurfArgs &s, double *phi, hipStream_t st)
     return hipGetLastError();
 }
 
+// Face coefficients of the families whose sum runs over a strided axis of Y
+// (axis 0, and axis 2 in 3D): the lanes take 64 consecutive k_1 (contiguous in
+// Y), the waves every fourth term of the sum, combined in LDS in a fixed order.
+// blockIdx.y: the remaining wavenumber (k_2 for fam 0, k_0 for fam 2; 3D).
+__global__ __launch_bounds__(NT) void k_sigma_cols(ScreenArgs a, int fam)
+{
+    __shared__ double red[NT / 64][2][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int I0 = a.M[0] - 1, I1 = a.M[1] - 1;
+    const int k1 = blockIdx.x * 64 + lane + 1;
+    const int ko = blockIdx.y + 1;
+    const int Ia = a.M[fam] - 1;
+    double lo = 0.0, hi = 0.0;
+    if (k1 <= I1) {
+        // Y at (k0, k1, k2) = col[(ka - 1) step] with ka the summed wavenumber
+        int64_t step;
+        const double *col;
+        double qo = a.tab[1].q[k1 - 1];
+        if (fam == 0) {
+            step = I1;
+            col = a.Y + (a.d == 3 ? (int64_t)(ko - 1) * I0 * I1 : 0) + (k1 - 1);
+            if (a.d == 3) qo += a.tab[2].q[ko - 1];
+        } else {
+            step = (int64_t)I0 * I1;
+            col = a.Y + (int64_t)(ko - 1) * I1 + (k1 - 1);
+            qo += a.tab[0].q[ko - 1];
+        }
+        const double *qa = a.tab[fam].q;
+        for (int base = 1 + wave; base <= Ia; base += (NT / 64) * kSigU) {
+            double y[kSigU];
+#pragma unroll
+            for (int u = 0; u < kSigU; ++u) {
+                const int ka = base + (NT / 64) * u;
+                y[u] = ka <= Ia ? col[(ka - 1) * step] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSigU; ++u) {
+                const int ka = base + (NT / 64) * u;
+                if (ka <= Ia) {
+                    const double alpha = -a.pref * y[u] / (qo + qa[ka - 1]);
+                    const double t = (ka * a.piL[fam]) * alpha;
+                    lo -= t;
+                    hi += (ka & 1) ? -t : t;
+                }
+            }
+        }
+    }
+    red[wave][0][lane] = lo;
+    red[wave][1][lane] = hi;
+    __syncthreads();
+    if (wave == 0 && k1 <= I1) {
+        for (int w = 1; w < NT / 64; ++w) {
+            lo += red[w][0][lane];
+            hi += red[w][1][lane];
+        }
+        // face layouts: fam 0 [side][k1][k2] (3D) or [side][k1]; fam 2 [side][k0][k1]
+        int64_t o;
+        if (fam == 0)
+            o = a.d == 3 ? (int64_t)(k1 - 1) * (a.M[2] - 1) + (ko - 1) : (int64_t)(k1 - 1);
+        else
+            o = (int64_t)(ko - 1) * I1 + (k1 - 1);
+        const int64_t fe = face_elems(a, fam);
+        a.S[fam][o] = lo;
+        a.S[fam][fe + o] = hi;
+    }
+}
+
 hipError_t launch_screen(const ScreenArgs &a, double *phi, hipStream_t st)
 {
-    int64_t nf[3] = {0, 0, 0};
-    for (int f = 0; f < a.d; ++f) {
-        int64_t s = 1;
-        for (int b = 0; b < a.d; ++b)
-            if (b != f) s *= a.M[b] - 1;
-        nf[f] = s;
-    }
-    const int64_t waves = nf[0] + nf[1] + nf[2];
-    const int64_t nb = (waves + NT / 64 - 1) / (NT / 64);
+    (void)phi;
+    // family 1 (sum over the contiguous axis): one wave per output
+    int64_t nf1 = 1;
+    for (int b = 0; b < a.d; ++b)
+        if (b != 1) nf1 *= a.M[b] - 1;
+    const int64_t nb = (nf1 + NT / 64 - 1) / (NT / 64);
     if (nb > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sigma_sums, dim3((unsigned)nb), dim3(NT), 0, st, a, nf[0], nf[1]);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_sigma_rows, dim3((unsigned)nb), dim3(NT), 0, st, a, nf1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned nx = (unsigned)((a.M[1] - 1 + 63) / 64);
+    hipLaunchKernelGGL(k_sigma_cols, dim3(nx, a.d == 3 ? a.M[2] - 1 : 1), dim3(NT), 0, st, a, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.d == 3) {
+        hipLaunchKernelGGL(k_sigma_cols, dim3(nx, a.M[0] - 1), dim3(NT), 0, st, a, 2);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_screen_g(const ScreenArgs &a, double *phi, hipStream_t st)
