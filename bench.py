@@ -12,6 +12,8 @@ and every mode's error against the oracle, max |phi - phi_oracle| / max
 1e-6 of the oracle (without the oracle run: within 1e-6 of the FP64 GPU path).
 
 Prints ONE JSON line.  Besides the contract fields it carries
+  stage_roofline  every volume stage against the HBM roof, the sixth-order
+                shell stage against the FP64 roof;
   roofline      HBM roofline of the dominant kernel (per-launch algorithmic
                 bytes / its average duration from HIP events on the library's
                 stream) and, when counters for the current sources exist
@@ -51,6 +53,7 @@ if ROOT not in sys.path:
 
 METRIC = "3D 6th-order solve Mpoints/s: mixed-prec vs FP64 at rel err<=1e-6; % HBM BW"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 MODES = ["fp64", "mixed_fp32", "mixed_fp32_slices"]
 # kernel (function) that implements each timed stage, as rocprofv3 names it
 STAGE_KERNEL = {
@@ -99,6 +102,8 @@ def stage_bytes(n: int, mode: str, nch: dict) -> dict:
         "conv_y": A + kt + nch.get("y", 1) * part,
         "rho_y": vol * 8 + A,
         "conv_z": A + kt + nch.get("z", 1) * part,
+        # chunk partials of the three families read, face spectra written
+        "faces": (nch.get("x", 1) + nch.get("y", 1) + nch.get("z", 1)) * part + 3 * part,
         "final": 2 * vol * wb,
         "inv_y": 2 * vol * wb,
         "inv_z": vol * wb + vol * 8,
@@ -294,6 +299,17 @@ def ingest_traffic(fetch_csv, write_csv, n, mode, mib, cmd):
             hits = [e for e in d if sub in e["name"]]
             if len(hits) > occ:
                 per.setdefault(stage, {})[cname] = hits[occ]["v"] * 1024.0 * factor
+        # the whole last solve: from the forward pass of rho before its first
+        # contraction to the two inverse passes after its final pass
+        last = max(i for i, e in enumerate(d) if "k_final<" in e["name"])
+        first = last
+        while first > 0 and "k_cc" not in d[first]["name"]:
+            first -= 1
+        while first > 0 and ("k_cc" in d[first - 1]["name"] or "k_pass" in d[first - 1]["name"]):
+            first -= 1
+        while first < last and not ("k_pass" in d[first]["name"] and "k_cc" in d[first + 1]["name"]):
+            first += 1
+        per.setdefault("whole_solve", {})[cname] = sum(e["v"] for e in d[first:last + 3]) * 1024.0 * factor
     for stage, v in per.items():
         if "FETCH_SIZE" in v and "WRITE_SIZE" in v:
             out["per_launch_bytes"]["%s/%d/%s" % (stage, n, mode)] = {
@@ -666,6 +682,22 @@ def main():
     achieved = byts[dom] / (stage_ms[dom] * 1e-3) / 1e9
     traffic = load_traffic(dom, n, best)
     vol_bytes = sum(byts.values())
+    b_node = (16 + 6 * (8 if best == "fp64" else 4)) + 16 + 24
+    whole = load_traffic("whole_solve", n, best)
+    solve_traffic = None if whole is None else whole.get("total")
+    # every volume stage against the HBM roof, and the sixth-order shell
+    # contraction (k_r6t) against the FP64 roof: 3 families x I^2 positions x
+    # I wavenumbers, about 32 FP64 flops per step (rebuild V(k), one
+    # reciprocal, five layer sums); its stage also holds the layer passes
+    I = n - 2
+    stage_roof = {k: {"bytes": byts[k], "ms": stage_ms[k], "GBs": byts[k] / (stage_ms[k] * 1e-3) / 1e9,
+                      "frac": byts[k] / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                  for k in byts if k in stage_ms}
+    if "shell_r6" in stage_ms:
+        fl = 3.0 * I * I * I * 32
+        stage_roof["shell_r6"] = {"flops": fl, "ms": stage_ms["shell_r6"],
+                                  "TFLOPs": fl / (stage_ms["shell_r6"] * 1e-3) / 1e12,
+                                  "frac": fl / (stage_ms["shell_r6"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
     out = {
         "metric": METRIC,
         "value": npts / (r["ms"] * 1e-3) / 1e6,
@@ -697,15 +729,27 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": None if traffic is None else traffic["total"],
+            "traffic_fetch_write": None if traffic is None else [traffic["fetch"], traffic["write"]],
             "avg_launch_ms": stage_ms[dom],
             "bytes_per_launch": byts[dom],
         },
         "whole_solve_hbm": {
-            "volume_bytes_per_step": vol_bytes,
-            "achieved_GBs": vol_bytes / (r["ms"] * 1e-3) / 1e9,
-            "frac": vol_bytes / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            # per-node compulsory streams: 16 + 6w B (rho in, phi out, three
+            # intermediates written and read), 16 B for the second and third
+            # reads of rho, 24 B for the kernel spectra read every solve
+            "bytes_per_node": b_node,
+            "algorithmic_GBs": b_node * npts / (r["ms"] * 1e-3) / 1e9,
+            "frac": b_node * npts / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            # the sum of the stage bytes of the table above
+            "stage_bytes_per_step": vol_bytes,
+            "stage_GBs": vol_bytes / (r["ms"] * 1e-3) / 1e9,
+            # FETCH_SIZE + WRITE_SIZE over every kernel of one solve, when the
+            # counters were taken on the current sources
+            "counted_bytes_per_step": solve_traffic,
+            "counted_GBs": None if solve_traffic is None else solve_traffic / (r["ms"] * 1e-3) / 1e9,
         },
+        "stage_roofline": stage_roof,
         "modes": {
             m: {
                 "mpoints_per_s": npts / (res[m]["ms"] * 1e-3) / 1e6,
