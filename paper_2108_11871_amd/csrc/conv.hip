@@ -98,7 +98,11 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
             tile_load_pair<T, TI, NTT>(buf, rs, 1, in, a.nrows_in, a.irs, a.ics, lgW, c0, nA, m0, nB, tid);
         }
         __syncthreads();
-        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
+        // rows 1..nrows_in <= M-1 hold data, rows from M on are zero
+        if (a.nrows_in <= M - 1)
+            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, tid);
+        else
+            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
         post_cs<T, MAXE, NTT>(buf, rs, lgs, M, tid);
         if (WB && (a.Mo == 0 || bt > a.Mo)) {
             const int64_t bb = a.Mo == 0 ? 0 : (int64_t)(bt - a.Mo - 1) * a.Bbs;

@@ -101,6 +101,42 @@ __device__ __forceinline__ cx<T> twid(const cx<T> *tw, int t)
     return w;
 }
 
+// Last step of a length-8 DFT from the length-4 DFTs e of the even and o of
+// the odd inputs: a[k] = e[k] + w8^k o[k], a[k+4] = e[k] - w8^k o[k].
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8_combine(cx<T> *a, const cx<T> *e, const cx<T> *o)
+{
+    const T r = (T)0.70710678118654752440084436210484903928;
+    cx<T> o1, o3;
+    if constexpr (INV) {
+        o1 = cx<T>{r * (o[1].x - o[1].y), r * (o[1].x + o[1].y)};
+        o3 = cx<T>{-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y)};
+    } else {
+        o1 = cx<T>{r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)};
+        o3 = cx<T>{r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)};
+    }
+    const cx<T> o2 = rot90<T, INV>(o[2]);
+    a[0] = cadd(e[0], o[0]);
+    a[4] = csub(e[0], o[0]);
+    a[1] = cadd(e[1], o1);
+    a[5] = csub(e[1], o1);
+    a[2] = cadd(e[2], o2);
+    a[6] = csub(e[2], o2);
+    a[3] = cadd(e[3], o3);
+    a[7] = csub(e[3], o3);
+}
+
+// Length-8 DFT of a[0..3] followed by four zeros: the first stage of a
+// transform whose upper half of inputs is zero (zero-padded sequences).
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8_lower(cx<T> *a)
+{
+    const cx<T> r2 = rot90<T, INV>(a[2]), r3 = rot90<T, INV>(a[3]);
+    const cx<T> e[4] = {cadd(a[0], a[2]), cadd(a[0], r2), csub(a[0], a[2]), csub(a[0], r2)};
+    const cx<T> o[4] = {cadd(a[1], a[3]), cadd(a[1], r3), csub(a[1], a[3]), csub(a[1], r3)};
+    dft8_combine<T, INV>(a, e, o);
+}
+
 // In-register DFT of length R (forward: exp(-2 pi i/R); inverse: conjugate).
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N)
@@ -121,25 +157,7 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N)
         cx<T> o[4] = {a[1], a[3], a[5], a[7]};
         dft_small<T, 4, INV>(e, tw, N);
         dft_small<T, 4, INV>(o, tw, N);
-        const T r = (T)0.70710678118654752440084436210484903928;
-        // o[k] *= w8^k
-        cx<T> o1, o3;
-        if constexpr (INV) {
-            o1 = cx<T>{r * (o[1].x - o[1].y), r * (o[1].x + o[1].y)};
-            o3 = cx<T>{-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y)};
-        } else {
-            o1 = cx<T>{r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)};
-            o3 = cx<T>{r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)};
-        }
-        cx<T> o2 = rot90<T, INV>(o[2]);
-        a[0] = cadd(e[0], o[0]);
-        a[4] = csub(e[0], o[0]);
-        a[1] = cadd(e[1], o1);
-        a[5] = csub(e[1], o1);
-        a[2] = cadd(e[2], o2);
-        a[6] = csub(e[2], o2);
-        a[3] = cadd(e[3], o3);
-        a[7] = csub(e[3], o3);
+        dft8_combine<T, INV>(a, e, o);
     } else {
         // R = 3, 5, 7: direct sum with table roots of unity w_R^m = w_N^(m N/R)
         cx<T> out[R];
@@ -244,9 +262,12 @@ __device__ __forceinline__ void stage_direct(T *buf, int rs, int lgs, const FftD
 // N, radix R, product of the earlier radices NS (a power of two), row pitch
 // RS and 2^LGS sequences.  Same data movement as stage_bfly; the index and
 // twiddle arithmetic folds to shifts and constants.
-template <typename T, int R, int NT, int N, int NS, int RS, int LGS, bool INV>
+// Z: the inputs of rows N/2..N-1 are zero (first stage, radix 8, of a
+// zero-padded sequence): they are not loaded, and the butterfly skips them.
+template <typename T, int R, int NT, int N, int NS, int RS, int LGS, bool INV, bool Z = false>
 __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, int tid)
 {
+    static_assert(!Z || (R == 8 && NS == 1), "the zero upper half applies to a first radix-8 stage");
     constexpr int NR = N / R, NBF = NR << LGS, TSTEP = N / (NS * R), SMASK = (1 << LGS) - 1;
     constexpr int BPT = (NBF + NT - 1) / NT;
     cx<T> v[BPT][R];
@@ -258,14 +279,20 @@ __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, int tid)
             const int sq = b & SMASK, j = b >> LGS;
             const int jm = j & (NS - 1);
             base[i] = (j - jm) * R + jm;
+            if constexpr (Z) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = lds_c(buf, RS, j + r * NR, sq);
-            if (NS > 1 && jm != 0) {
-                const int e = jm * TSTEP;
+                for (int r = 0; r < R / 2; ++r) v[i][r] = lds_c(buf, RS, j + r * NR, sq);
+                dft8_lower<T, INV>(v[i]);
+            } else {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid<T, INV>(tw, e * r));
+                for (int r = 0; r < R; ++r) v[i][r] = lds_c(buf, RS, j + r * NR, sq);
+                if (NS > 1 && jm != 0) {
+                    const int e = jm * TSTEP;
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], twid<T, INV>(tw, e * r));
+                }
+                dft_small<T, R, INV>(v[i], tw, N);
             }
-            dft_small<T, R, INV>(v[i], tw, N);
         }
     }
     __syncthreads();
@@ -287,19 +314,20 @@ __device__ __forceinline__ void stage_ct(T *buf, const cx<T> *tw, int tid)
 // may pass one the compiler cannot see through, so that the per-thread index
 // and twiddle values are recomputed for each transform instead of being held
 // in registers across the loop).
-template <typename T, int NT, int N, int RS, int LGS, bool INV>
+// Z: the upper half of the inputs is zero (see stage_ct).
+template <typename T, int NT, int N, int RS, int LGS, bool INV, bool Z = false>
 __device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, int tid)
 {
     if constexpr (N == 256) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 1, RS, LGS, INV, Z>(buf, tw, tid);
         stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
         stage_ct<T, 4, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
     } else if constexpr (N == 512) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 1, RS, LGS, INV, Z>(buf, tw, tid);
         stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
         stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
     } else if constexpr (N == 1024) {
-        stage_ct<T, 8, NT, N, 1, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 1, RS, LGS, INV, Z>(buf, tw, tid);
         stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
         stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
         stage_ct<T, 2, NT, N, 512, RS, LGS, INV>(buf, tw, tid);
@@ -310,15 +338,17 @@ __device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, int tid)
 // direction INV (false: exp(-2 pi i t/N), true: the conjugate).
 // P2: N is a power of two (only radix-2/4/8 stages are compiled in).
 // CT = false keeps the generic stages only.  tid: see fft_ct.
-template <typename T, int MAXE, int NT, bool P2, bool CT, bool INV>
+// Z: the upper half of the inputs is zero; the compile-time transforms skip
+// it in their first stage, the generic ones read the zeros.
+template <typename T, int MAXE, int NT, bool P2, bool CT, bool INV, bool Z = false>
 __device__ __forceinline__ void fft_tile_dir(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw, int tid)
 {
     if constexpr (P2 && CT && NT == 256) {
         // (N, tile width) pairs of the default tile budget: N * W / 2 = MAXE * NT
         if constexpr (MAXE == 8) {
-            if (fd.N == 512 && rs == 9) return fft_ct<T, NT, 512, 9, 2, INV>(buf, tw, tid);
-            if (fd.N == 256 && rs == 17) return fft_ct<T, NT, 256, 17, 3, INV>(buf, tw, tid);
-            if (fd.N == 1024 && rs == 5) return fft_ct<T, NT, 1024, 5, 1, INV>(buf, tw, tid);
+            if (fd.N == 512 && rs == 9) return fft_ct<T, NT, 512, 9, 2, INV, Z>(buf, tw, tid);
+            if (fd.N == 256 && rs == 17) return fft_ct<T, NT, 256, 17, 3, INV, Z>(buf, tw, tid);
+            if (fd.N == 1024 && rs == 5) return fft_ct<T, NT, 1024, 5, 1, INV, Z>(buf, tw, tid);
         }
     }
     if constexpr (P2) {
@@ -356,6 +386,16 @@ __device__ __forceinline__ void fft_tile(T *buf, int rs, int lgs, const FftDesc 
         fft_tile_dir<T, MAXE, NT, P2, CT, true>(buf, rs, lgs, fd, tw, tid);
     else
         fft_tile_dir<T, MAXE, NT, P2, CT, false>(buf, rs, lgs, fd, tw, tid);
+}
+
+// Forward transform of zero-padded sequences: rows N/2..N-1 of the tile must
+// hold zeros (the generic stages read them); tid: see fft_ct.
+template <typename T, int MAXE, int NT, bool P2 = false, bool CT = true>
+__device__ __forceinline__ void fft_tile_zpad(T *buf, int rs, int lgs, const FftDesc &fd, const cx<T> *tw,
+                                              int tid = -1)
+{
+    if (tid < 0) tid = threadIdx.x;
+    fft_tile_dir<T, MAXE, NT, P2, CT, false, true>(buf, rs, lgs, fd, tw, tid);
 }
 
 // After a forward zero-padded FFT: write C and S in slot layout (in place).

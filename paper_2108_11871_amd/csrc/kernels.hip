@@ -923,7 +923,13 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
             for (int t = 0; t < nt; ++t) r[4 + par * 3 + t] = (T)a.sh.P[0][(par * 3 + t) * ss0 + o];
     }
     __syncthreads();
-    if (!a.pre) fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
+    // forward transform of the zero-padded rows 1..M0-1 (unless B already holds the spectrum)
+    if (!a.pre) {
+        if (a.nrows_in <= M - 1)
+            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, tid);
+        else
+            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
+    }
     // One sweep over the row pairs (k, N-k) of every complex sequence s
     // (real columns 2s and 2s+1):
     //   sine coefficients  S_a = (z(N-k).y - z(k).y)/2,  S_b = (z(k).x - z(N-k).x)/2

@@ -66,7 +66,12 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
             pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, true);
             inv = true;
         }
-        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv);
+        // zero-padded input (rows 1..nrows_in <= M-1, zeros from row M on):
+        // the first stage skips the zero half
+        if (a.in_mode == IN_ZPAD && a.nrows_in <= M - 1)
+            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw);
+        else
+            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv);
         if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
         if (a.accum)
             tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
@@ -146,7 +151,10 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
             pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, true, tid);
             inv = true;
         }
-        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv, tid);
+        if (mode == IN_ZPAD && a.nrows_in <= M - 1)
+            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, tid);
+        else
+            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv, tid);
         if (mode == IN_ZPAD || mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M, tid);
         if (a.accum)
             tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out0 + oo, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW,
