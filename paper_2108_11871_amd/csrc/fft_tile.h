@@ -158,8 +158,34 @@ __device__ __forceinline__ void dft_small(cx<T> *a, const cx<T> *tw, int N)
         dft_small<T, 4, INV>(e, tw, N);
         dft_small<T, 4, INV>(o, tw, N);
         dft8_combine<T, INV>(a, e, o);
+    } else if constexpr (R == 3) {
+        // w3 = -1/2 -/+ i sqrt(3)/2:  X1,2 = a0 - (a1 + a2)/2 +/- rot90((sqrt(3)/2)(a1 - a2))
+        const T h = (T)0.86602540378443864676372317075293618347;
+        const cx<T> t1 = cadd(a[1], a[2]);
+        const cx<T> t2 = {a[0].x - (T)0.5 * t1.x, a[0].y - (T)0.5 * t1.y};
+        const cx<T> t3 = rot90<T, INV>(cx<T>{h * (a[1].x - a[2].x), h * (a[1].y - a[2].y)});
+        a[0] = cadd(a[0], t1);
+        a[1] = cadd(t2, t3);
+        a[2] = csub(t2, t3);
+    } else if constexpr (R == 5) {
+        // with b1 = a1 + a4, b2 = a2 + a3, d1 = a1 - a4, d2 = a2 - a3 and
+        // c_m = cos(2 pi m/5), s_m = sin(2 pi m/5):
+        //   X1,4 = a0 + c1 b1 + c2 b2 +/- rot90(s1 d1 + s2 d2)
+        //   X2,3 = a0 + c2 b1 + c1 b2 +/- rot90(s2 d1 - s1 d2)
+        const T c1 = (T)0.30901699437494742410229341718281905886, c2 = (T)-0.80901699437494742410229341718281905886;
+        const T s1 = (T)0.95105651629515357211643933337938214340, s2 = (T)0.58778525229247312916870595463907276860;
+        const cx<T> b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]), d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+        const cx<T> t1 = {a[0].x + c1 * b1.x + c2 * b2.x, a[0].y + c1 * b1.y + c2 * b2.y};
+        const cx<T> t2 = {a[0].x + c2 * b1.x + c1 * b2.x, a[0].y + c2 * b1.y + c1 * b2.y};
+        const cx<T> u1 = rot90<T, INV>(cx<T>{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y});
+        const cx<T> u2 = rot90<T, INV>(cx<T>{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y});
+        a[0] = cadd(a[0], cadd(b1, b2));
+        a[1] = cadd(t1, u1);
+        a[4] = csub(t1, u1);
+        a[2] = cadd(t2, u2);
+        a[3] = csub(t2, u2);
     } else {
-        // R = 3, 5, 7: direct sum with table roots of unity w_R^m = w_N^(m N/R)
+        // R = 7: direct sum with table roots of unity w_R^m = w_N^(m N/R)
         cx<T> out[R];
         const int step = N / R;
 #pragma unroll
