@@ -578,6 +578,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint timings")
     ap.add_argument("--batched-only", action="store_true", help="only the batched leg (profiling)")
     ap.add_argument("--screening-only", action="store_true", help="only the screening leg (profiling)")
+    ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint leg (profiling)")
     ap.add_argument("--ingest", nargs="+", metavar="ARG")
     args = ap.parse_args()
 
@@ -609,6 +610,11 @@ def main():
         return
     if args.screening_only:
         print(json.dumps(time_screening(api, torch, sizes=(args.n,), steps=args.steps)), flush=True)
+        return
+    if args.adjoint_only:
+        rho, h, _ = inputs.workload_bumps_3d(args.n, seed=args.seed)
+        rho_d = torch.from_numpy(rho).to("cuda:0")
+        print(json.dumps(time_adjoint(api, torch, rho_d, h, args.steps, args.warmup)), flush=True)
         return
 
     n = args.n
