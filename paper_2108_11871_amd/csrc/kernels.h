@@ -267,7 +267,8 @@ void set_lds(const void *fn, size_t bytes);
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
 // in_f32: input data in FP32 (else FP64); f32: transform type
 hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st);
-hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st);
+// out[s][i] = sum over the chunks c of part[s][c][i]  (nset sets of nchunk rows of len)
+hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, int nset, hipStream_t st);
 hipError_t launch_bwrite(const BwriteArgs &a, hipStream_t st);
 hipError_t launch_gtilde(const GtArgs &a, hipStream_t st);
 hipError_t launch_pack(const PackArgs &a, hipStream_t st);

@@ -112,20 +112,45 @@ hipError_t launch_embed(const double *src, double *dst, int d, const int64_t *n,
 // ---------------------------------------------------------------------------
 // Small element-wise kernels
 // ---------------------------------------------------------------------------
-__global__ void k_reduce(const double *part, double *out, int64_t len, int nchunk)
+// out[s][i] = sum over c of part[s][c][i] (i < len, s < nset, c < nchunk): the
+// lanes take 64 consecutive i, the 16 waves of a block every 16th chunk with
+// eight loads in flight, combined in LDS in a fixed order.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduce(const double *part, double *out, int64_t len,
+                                                           int nchunk)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < nchunk; ++c) s += part[c * len + i];
-        out[i] = s;
+    __shared__ double red[kRedWaves][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = blockIdx.x * (int64_t)64 + lane;
+    const double *src = part + (int64_t)blockIdx.y * nchunk * len + i;
+    double s = 0.0;
+    if (i < len) {
+        for (int c0 = wave; c0 < nchunk; c0 += 8 * kRedWaves) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = c0 + u * kRedWaves;
+                v[u] = c < nchunk ? src[(int64_t)c * len] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+    }
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && i < len) {
+        for (int w = 1; w < kRedWaves; ++w) s += red[w][lane];
+        out[(int64_t)blockIdx.y * len + i] = s;
     }
 }
 
-hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, hipStream_t st)
+hipError_t launch_reduce(const double *part, double *out, int64_t len, int nchunk, int nset, hipStream_t st)
 {
-    const int nb = (int)std::min<int64_t>((len + NT - 1) / NT, 4096);
-    hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(NT), 0, st, part, out, len, nchunk);
+    const int64_t nb = (len + 63) / 64;
+    if (nb > INT32_MAX || nset < 1 || nset > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)nb, (unsigned)nset), dim3(64 * kRedWaves), 0, st, part, out, len,
+                       nchunk);
     return hipGetLastError();
 }
 

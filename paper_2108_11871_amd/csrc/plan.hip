@@ -1423,15 +1423,17 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             if (p->cube && fam > 0) break;
             const int nfam = p->cube ? 2 : 1;
             const int pen = 1 - fam;
+            // the chunk partials of every face summed in parallel (a face line has
+            // few columns, so a summing load inside the pass would leave most of
+            // the GPU idle), then the inverse transform in place
+            IPS_HIP(launch_reduce(p->part[fam], p->F[fam], N[pen], p->nch[fam], 2 * nfam, st));
             PassArgs a{};
-            a.in = p->part[fam];
+            a.in = p->F[fam];
             a.out = p->F[fam];
             a.irs = a.ors = 1;
-            a.ics = (int64_t)p->nch[fam] * N[pen];
+            a.ics = N[pen];
             a.ocs = N[pen];
             a.ibs = a.obs = 0;
-            a.nsum = p->nch[fam];
-            a.sstride = N[pen];
             a.nrows_in = N[pen];
             a.ncols = 2 * nfam;
             a.nbatch = 1;
