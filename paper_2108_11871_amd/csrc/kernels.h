@@ -196,7 +196,15 @@ struct R6Args {
     void *T[3];         // [10][other axes] per axis: layers 1..5, then M-1..M-5
     int t_f32;          // T holds FP32 (mixed modes), else FP64
     int nblk[3];        // filled by the launcher
+    // more than one split of the k_a sums (r6t_splits > 1, shells with few
+    // positions): FP64 partials [axis][split][10][positions], axis ax at part_off[ax]
+    double *part;
+    int64_t part_off[3];
 };
+
+// splits of the k_a sums of k_r6t (1: none); the partial buffer holds
+// splits * 10 * (sum of the shell sizes) doubles
+int r6t_splits(const Geo &g);
 
 struct DcorrArgs {
     Geo geo;

@@ -454,7 +454,10 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
     for (int q = 0; q < PPT; ++q)
 #pragma unroll
         for (int j = 0; j < 5; ++j) acc[q][j] = 0.0;
-    for (int ka = 1 + grp; ka <= Ia; ka += NG) {
+    // split s of gridDim.y: every gridDim.y-th wavenumber of this group's
+    // residue (the parity of k_a stays that of the group)
+    const int ks = gridDim.y, sp = blockIdx.y;
+    for (int ka = 1 + grp + NG * sp; ka <= Ia; ka += NG * ks) {
         const double lk = tl[ka - 1], sk = ts[ka - 1];
         double sj[5];
 #pragma unroll
@@ -477,7 +480,9 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
     __syncthreads();
     // group g finishes positions g*64/...: every thread of the block writes
     // its share of the PB positions
-    double *Td = static_cast<double *>(a.T[ax]);
+    // several splits: FP64 partials [split][10][positions] of this axis,
+    // summed into T by k_r6t_sum
+    double *Td = ks > 1 ? a.part + a.part_off[ax] + (int64_t)sp * 10 * npos : static_cast<double *>(a.T[ax]);
     float *Tf = static_cast<float *>(a.T[ax]);
     for (int i = threadIdx.x; i < PB; i += NT) {
         const int p = blk * PB + i;
@@ -489,7 +494,7 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
             const double od = red[0][j][i] + red[2][j][i];
             const double ev = red[1][j][i] + red[3][j][i];
             const double v1 = g.pref * (od + ev), v2 = g.pref * (od - ev);
-            if (a.t_f32) {
+            if (a.t_f32 && ks == 1) {
                 Tf[j * (int64_t)npos + pout] = (float)v1;
                 Tf[(5 + j) * (int64_t)npos + pout] = (float)v2;
             } else {
@@ -497,6 +502,21 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
                 Td[(5 + j) * (int64_t)npos + pout] = v2;
             }
         }
+    }
+}
+
+// T[ax][l][p] = sum over the splits of part[ax][s][l][p] (10 layers of npos)
+__global__ void k_r6t_sum(R6Args a, int ax, int ks)
+{
+    const int64_t len = 10 * shell_size(a.geo, ax);
+    const double *src = a.part + a.part_off[ax];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int sp = 0; sp < ks; ++sp) v += src[(int64_t)sp * len + i];
+        if (a.t_f32)
+            static_cast<float *>(a.T[ax])[i] = (float)v;
+        else
+            static_cast<double *>(a.T[ax])[i] = v;
     }
 }
 
@@ -510,14 +530,35 @@ static hipError_t launch_r6t_p(R6Args a, hipStream_t st)
         a.nblk[ax] = (np + 64 * PPT - 1) / (64 * PPT);
         tot += a.nblk[ax];
     }
+    const int ks = r6t_splits(a.geo);
+    if (ks > 1 && !a.part) return hipErrorInvalidValue;
     if (d == 3)
-        hipLaunchKernelGGL((k_r6t<3, PPT>), dim3(tot), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((k_r6t<3, PPT>), dim3(tot, ks), dim3(NT), 0, st, a);
     else
-        hipLaunchKernelGGL((k_r6t<2, PPT>), dim3(tot), dim3(NT), 0, st, a);
-    return hipGetLastError();
+        hipLaunchKernelGGL((k_r6t<2, PPT>), dim3(tot, ks), dim3(NT), 0, st, a);
+    hipError_t e = hipGetLastError();
+    for (int ax = 0; ax < d && ks > 1 && e == hipSuccess; ++ax) {
+        const int64_t len = 10 * shell_size(a.geo, ax);
+        const unsigned nb = (unsigned)std::min<int64_t>((len + NT - 1) / NT, 4096);
+        hipLaunchKernelGGL(k_r6t_sum, dim3(nb), dim3(NT), 0, st, a, ax, ks);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_r6t(R6Args a, hipStream_t st) { return launch_r6t_p<2>(a, st); }
+
+int r6t_splits(const Geo &g)
+{
+    int tot = 0, mina = 1 << 30;
+    for (int ax = 0; ax < g.d; ++ax) {
+        tot += (int)((shell_size(g, ax) + 127) / 128);
+        mina = std::min(mina, g.M[ax] - 1);
+    }
+    const int want = (1024 + tot - 1) / tot;
+    const int cap = std::max(1, mina / 128);
+    return std::max(1, std::min(want, cap));
+}
 
 // ---------------------------------------------------------------------------
 // D = R - R_spec on the nodes with an index in {1, 2, M-2, M-1}, in two steps.

@@ -187,6 +187,15 @@ void kaxes(int d, int fam, int &b, int &c)
     }
 }
 
+// Interior nodes of a face of family a (product of I over the other axes).
+int64_t shell_size_host(const Geo &g, int a)
+{
+    int64_t s = 1;
+    for (int b = 0; b < g.d; ++b)
+        if (b != a) s *= g.M[b] - 1;
+    return s;
+}
+
 // In-face axes (b, c) of face family f in increasing order (the storage order
 // of the surface arrays, c contiguous).
 void face_axes(int f, int &b, int &c)
@@ -240,6 +249,7 @@ struct ips_plan_s {
     void *P2T = nullptr;                        // 3D: transposed family-2 copy (final pass type)
     bool cube = false; // all families share sizes and chunking (batched launches)
     double *C[3] = {nullptr, nullptr, nullptr}; // sixth-order right-hand side on core layers
+    double *r6part = nullptr;                    // split partials of the R_spec contraction (small shells)
     // boundary values from the screening charge (IPS_FLAG_SCREENING)
     bool screen = false;
     double tau[3] = {0, 0, 0};                   // singular corrections of the surface sums
@@ -596,10 +606,13 @@ void layout_ws(ips_plan p, Carver &c)
     }
     c.take(&bg, 2 * ts * sizeof(double));
     c.take(&bpk, 6 * ts * sizeof(double));
+    p->r6part = nullptr;
     if (p->order == 6) {
         c.take(&bt, 10 * ts * sizeof(double));
         c.take(&bd, 4 * ts * sizeof(double));
         c.take(&bc, 8 * ts * sizeof(double));
+        const int ks = r6t_splits(p->geo);
+        if (ks > 1) c.take(&p->r6part, (size_t)ks * 10 * ts * sizeof(double));
     }
     size_t op = 0, of = 0, os = 0;
     for (int fam = 0; fam < 3; ++fam) {
@@ -1498,6 +1511,12 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             }
             a.t_f32 = f32;
             a.P1T = p->P1T;
+            a.part = p->r6part;
+            int64_t off = 0;
+            for (int q = 0; q < d; ++q) {
+                a.part_off[q] = off;
+                off += (int64_t)r6t_splits(p->geo) * 10 * shell_size_host(p->geo, q);
+            }
             IPS_HIP(launch_r6t(a, st));
         }
         // mixed modes: the R_spec layers and their inverse transforms in FP32
