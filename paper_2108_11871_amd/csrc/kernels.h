@@ -273,6 +273,16 @@ hipError_t launch_adj_1d(const double *w, double *out, int M, double h, const Ff
 void set_lds(const void *fn, size_t bytes);
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
+
+// Up to kMultiPass independent passes (generic widths, transforms up to 2048)
+// in one launch; first[] is filled by the launcher.
+constexpr int kMultiPass = 3;
+struct MultiPassArgs {
+    PassArgs p[kMultiPass];
+    int first[kMultiPass + 1];
+    int n;
+};
+hipError_t launch_pass_multi(const PassArgs *p, int n, bool in_f32, bool out_f32, hipStream_t st);
 // in_f32: input data in FP32 (else FP64); f32: transform type
 hipError_t launch_cc(const CcArgs &a, int nchunk, bool f32, bool in_f32, hipStream_t st);
 // out[s][i] = sum over the chunks c of part[s][c][i]  (nset sets of nchunk rows of len)

@@ -3,10 +3,73 @@
 // along one axis of a strided 2D/3D array (Sections 3, 4, 5).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace ips {
+
+// One tile of a pass: tile lb (column block lb % ncb of batch entry lb / ncb),
+// loaded into LDS (rows placed as the input mode needs), transformed along its
+// rows and stored.
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT>
+__device__ __forceinline__ void pass_tile(const PassArgs &a, int lb)
+{
+    constexpr bool BIG = NTT != NT;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
+    const int lgW = 31 - __clz(W), lgs = lgW - 1;
+    const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
+    T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
+    const int ncb = (a.ncols + W - 1) / W;
+    const int cb = lb % ncb, bt = lb / ncb;
+    const int c0 = cb * W;
+    const int nc = min(W, a.ncols - c0);
+    const TI *in = static_cast<const TI *>(a.in) + bt * a.ibs + c0 * a.ics;
+    TO *out = static_cast<TO *>(a.out) + bt * a.obs + c0 * a.ocs;
+    if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
+    bool inv = false;
+    if (a.in_mode == IN_ZPAD) {
+        zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
+        zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
+        tile_load<T, TI, NTT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        __syncthreads();
+    } else if (a.in_mode == IN_ZPAD0) {
+        zero_rows<T, NTT>(buf, rs, lgW, a.nrows_in, N);
+        tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        __syncthreads();
+    } else if (a.in_mode == IN_EVEN) {
+        tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        __syncthreads();
+        pre_even<T, NTT>(buf, rs, lgW, M);
+    } else if (a.in_mode == IN_HERM) {
+        if (a.nsum > 1)
+            tile_load_sum<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW, a.nsum,
+                                      a.sstride);
+        else
+            tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        __syncthreads();
+        pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, false);
+        inv = true;
+    } else {
+        tile_load<T, TI, NTT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
+        __syncthreads();
+        pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, true);
+        inv = true;
+    }
+    // zero-padded input (rows 1..nrows_in <= M-1, zeros from row M on):
+    // the first stage skips the zero half
+    if (a.in_mode == IN_ZPAD && a.nrows_in <= M - 1)
+        fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw);
+    else
+        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv);
+    if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
+    if (a.accum)
+        tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+    else
+        tile_store<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+}
 
 // One pencil pass.  A tile is W consecutive columns of one batch entry; it is
 // loaded into LDS (rows placed as the input mode needs), transformed along
@@ -23,60 +86,7 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
     constexpr bool PF = WC > 0;
     if constexpr (!PF) {
         // one tile per block
-        constexpr bool BIG = NTT != NT;
-        extern __shared__ __align__(16) unsigned char smem[];
-        const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
-        const int lgW = 31 - __clz(W), lgs = lgW - 1;
-        const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
-        T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
-        const int ncb = (a.ncols + W - 1) / W;
-        const int lb = xcd_remap(blockIdx.x, ntiles);
-        const int cb = lb % ncb, bt = lb / ncb;
-        const int c0 = cb * W;
-        const int nc = min(W, a.ncols - c0);
-        const TI *in = static_cast<const TI *>(a.in) + bt * a.ibs + c0 * a.ics;
-        TO *out = static_cast<TO *>(a.out) + bt * a.obs + c0 * a.ocs;
-        if (!BIG) load_twiddles<T, NTT>(reinterpret_cast<cx<T> *>(smem), a.tw, N);
-        bool inv = false;
-        if (a.in_mode == IN_ZPAD) {
-            zero_rows<T, NTT>(buf, rs, lgW, 0, 1);
-            zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N);
-            tile_load<T, TI, NTT>(buf, rs, 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-            __syncthreads();
-        } else if (a.in_mode == IN_ZPAD0) {
-            zero_rows<T, NTT>(buf, rs, lgW, a.nrows_in, N);
-            tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-            __syncthreads();
-        } else if (a.in_mode == IN_EVEN) {
-            tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-            __syncthreads();
-            pre_even<T, NTT>(buf, rs, lgW, M);
-        } else if (a.in_mode == IN_HERM) {
-            if (a.nsum > 1)
-                tile_load_sum<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW, a.nsum,
-                                          a.sstride);
-            else
-                tile_load<T, TI, NTT>(buf, rs, 0, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-            __syncthreads();
-            pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, false);
-            inv = true;
-        } else {
-            tile_load<T, TI, NTT>(buf, rs, M + 1, in, a.nrows_in, nc, a.irs, a.ics, lgW);
-            __syncthreads();
-            pre_herm<T, MAXE, NTT>(buf, rs, lgs, M, true);
-            inv = true;
-        }
-        // zero-padded input (rows 1..nrows_in <= M-1, zeros from row M on):
-        // the first stage skips the zero half
-        if (a.in_mode == IN_ZPAD && a.nrows_in <= M - 1)
-            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw);
-        else
-            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv);
-        if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
-        if (a.accum)
-            tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
-        else
-            tile_store<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
+        pass_tile<T, TI, TO, MAXE, P2, NTT>(a, xcd_remap(blockIdx.x, ntiles));
         return;
     }
     constexpr bool BIG = NTT != NT;
@@ -266,6 +276,69 @@ static bool pass_strides_ok(const PassArgs &a)
 {
     // loads address rows [0, nrows_in) of the input, stores rows [0, out_nrows) of the output
     return tile_strides_ok(a.nrows_in, a.irs, a.ncols, a.ics) && tile_strides_ok(a.out_nrows, a.ors, a.ncols, a.ocs);
+}
+
+// Several independent passes in one launch, one tile per block: block b runs
+// tile b - first[i] of pass i (first[i] <= b < first[i + 1]).  The passes
+// share the element types; the tile budget and the LDS are those of the
+// largest tile.  Used where the passes are small (the per-family transforms
+// of uneven boxes), so that they fill the device together.
+template <typename T, typename TI, typename TO, int MAXE, bool P2>
+__global__ __launch_bounds__(NT) void k_pass_multi(MultiPassArgs m)
+{
+    const int b = xcd_remap(blockIdx.x, m.first[m.n]);
+    int i = 0;
+    while (i + 1 < m.n && b >= m.first[i + 1]) ++i;
+    pass_tile<T, TI, TO, MAXE, P2, NT>(m.p[i], b - m.first[i]);
+}
+
+template <typename T, typename TI, typename TO>
+static hipError_t launch_multi_t(MultiPassArgs &m, hipStream_t st)
+{
+    size_t lds = 0;
+    int work = 0, tot = 0;
+    bool p2 = true;
+    for (int i = 0; i < m.n; ++i) {
+        const PassArgs &a = m.p[i];
+        if (big_fft(a.fd.N) || a.W < 2 || !pass_strides_ok(a)) return hipErrorInvalidValue;
+        const int64_t ntl = (int64_t)((a.ncols + a.W - 1) / a.W) * a.nbatch;
+        if (ntl < 0 || tot + ntl > INT32_MAX) return hipErrorInvalidValue;
+        m.first[i] = tot;
+        tot += (int)ntl;
+        lds = std::max(lds, tile_lds<T>(a.fd.N, a.W));
+        work = std::max(work, (a.W / 2) * a.fd.N);
+        p2 = p2 && is_pow2(a.fd.N);
+    }
+    m.first[m.n] = tot;
+    if (tot == 0) return hipSuccess;
+    auto go = [&](const void *fn, auto kern) {
+        set_lds(fn, lds);
+        hipLaunchKernelGGL(kern, dim3((unsigned)tot), dim3(NT), lds, st, m);
+    };
+#define IPS_MULTI(MX, PP) go((const void *)&k_pass_multi<T, TI, TO, MX, PP>, k_pass_multi<T, TI, TO, MX, PP>)
+    if (work <= 4 * NT) {
+        if (p2) IPS_MULTI(4, true); else IPS_MULTI(4, false);
+    } else if (work <= 8 * NT) {
+        if (p2) IPS_MULTI(8, true); else IPS_MULTI(8, false);
+    } else if (work <= 16 * NT) {
+        if (p2) IPS_MULTI(16, true); else IPS_MULTI(16, false);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef IPS_MULTI
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_multi(const PassArgs *p, int n, bool in_f32, bool out_f32, hipStream_t st)
+{
+    if (n < 1 || n > kMultiPass) return hipErrorInvalidValue;
+    MultiPassArgs m{};
+    m.n = n;
+    for (int i = 0; i < n; ++i) m.p[i] = p[i];
+    if (!in_f32 && !out_f32) return launch_multi_t<double, double, double>(m, st);
+    if (in_f32 && out_f32) return launch_multi_t<float, float, float>(m, st);
+    if (!in_f32 && out_f32) return launch_multi_t<float, double, float>(m, st);
+    return launch_multi_t<float, float, double>(m, st);
 }
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st)

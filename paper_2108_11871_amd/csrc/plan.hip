@@ -401,8 +401,8 @@ std::vector<cx<double>> twiddles(int N)
     return w;
 }
 
-int run_pass(ips_plan p, PassArgs a, const FftDesc &fd, const cx<double> *tw, bool in_f32,
-             bool out_f32, hipStream_t st)
+// Transform description and tile width of a pass along an axis (fd, tw).
+void prep_pass(ips_plan p, PassArgs &a, const FftDesc &fd, const cx<double> *tw)
 {
     a.fd = fd;
     a.tw = tw;
@@ -410,58 +410,93 @@ int run_pass(ips_plan p, PassArgs a, const FftDesc &fd, const cx<double> *tw, bo
     for (int ax = 0; ax < p->d; ++ax)
         if (p->tw[ax] == tw) a.twf = p->twf[ax];
     if (a.W == 0) a.W = tile_width(fd.N, p->work, a.ncols);
+}
+
+int run_pass(ips_plan p, PassArgs a, const FftDesc &fd, const cx<double> *tw, bool in_f32,
+             bool out_f32, hipStream_t st)
+{
+    prep_pass(p, a, fd, tw);
     IPS_HIP(launch_pass(a, in_f32, out_f32, st));
     return IPS_OK;
 }
 
+// Independent passes (prepared) in one launch when their transforms fit the
+// multi-pass kernel, else one launch each.
+int run_passes(PassArgs *a, int n, bool in_f32, bool out_f32, hipStream_t st)
+{
+    bool fit = n > 1 && n <= kMultiPass;
+    for (int i = 0; i < n; ++i) fit = fit && a[i].fd.N <= kLdsMaxN;
+    if (fit) {
+        IPS_HIP(launch_pass_multi(a, n, in_f32, out_f32, st));
+        return IPS_OK;
+    }
+    for (int i = 0; i < n; ++i) IPS_HIP(launch_pass(a[i], in_f32, out_f32, st));
+    return IPS_OK;
+}
+
 // Forward raw DST (IN_ZPAD -> S rows) or inverse (IN_SPECS -> real rows) of
-// the last two (or one) axes of a stack of shell layers [nl][I_b][I_c].
-int shell_dst(ips_plan p, void *buf, int nl, int fam, bool inverse, hipStream_t st, bool f32 = false)
+// the last two (or one) axes of a stack of shell layers [nl][I_b][I_c]:
+// the prepared pass of step 0 (along the contiguous axis) or step 1 (3D:
+// along the lower axis).  Returns the number of steps.
+int shell_dst_pass(ips_plan p, void *buf, int nl, int fam, bool inverse, int step, PassArgs &a)
 {
     int ax[2], na = 0;
     for (int b = 0; b < p->d; ++b)
         if (b != fam) ax[na++] = b;
     const int last = ax[na - 1];
     const int64_t plane = na == 2 ? (int64_t)p->I[ax[0]] * p->I[ax[1]] : p->I[ax[0]];
-    auto one = [&](int axis, int64_t rstride, int64_t cstride, int ncols, int nbatch,
-                   int64_t bstride) -> int {
-        PassArgs a{};
-        a.in = buf;
-        a.out = buf;
-        a.irs = a.ors = rstride;
-        a.ics = a.ocs = cstride;
-        a.ibs = a.obs = bstride;
-        a.nrows_in = p->I[axis];
-        a.ncols = ncols;
-        a.nbatch = nbatch;
-        a.in_mode = inverse ? IN_SPECS : IN_ZPAD;
-        a.out_r0 = inverse ? 1 : p->M[axis] + 1;
-        a.out_nrows = p->I[axis];
-        a.scale = inverse ? 0.5 : 1.0;
-        return run_pass(p, a, p->fd[axis], p->tw[axis], f32, f32, st);
-    };
-    int rc;
-    if (na == 2) {
+    int axis, ncols, nbatch;
+    int64_t rstride, cstride, bstride;
+    if (na == 2 && step == 0) {
         // along the contiguous axis: rows stride 1, columns = lower axis
-        rc = one(last, 1, p->I[last], p->I[ax[0]], nl, plane);
-        if (rc) return rc;
-        rc = one(ax[0], p->I[last], 1, p->I[last], nl, plane);
+        axis = last, rstride = 1, cstride = p->I[last], ncols = p->I[ax[0]], nbatch = nl, bstride = plane;
+    } else if (na == 2) {
+        axis = ax[0], rstride = p->I[last], cstride = 1, ncols = p->I[last], nbatch = nl, bstride = plane;
     } else {
-        rc = one(last, 1, plane, nl, 1, 0);
+        axis = last, rstride = 1, cstride = plane, ncols = nl, nbatch = 1, bstride = 0;
     }
-    return rc;
+    a = PassArgs{};
+    a.in = buf;
+    a.out = buf;
+    a.irs = a.ors = rstride;
+    a.ics = a.ocs = cstride;
+    a.ibs = a.obs = bstride;
+    a.nrows_in = p->I[axis];
+    a.ncols = ncols;
+    a.nbatch = nbatch;
+    a.in_mode = inverse ? IN_SPECS : IN_ZPAD;
+    a.out_r0 = inverse ? 1 : p->M[axis] + 1;
+    a.out_nrows = p->I[axis];
+    a.scale = inverse ? 0.5 : 1.0;
+    prep_pass(p, a, p->fd[axis], p->tw[axis]);
+    return na;
+}
+
+int shell_dst(ips_plan p, void *buf, int nl, int fam, bool inverse, hipStream_t st, bool f32 = false)
+{
+    PassArgs a;
+    const int nstep = shell_dst_pass(p, buf, nl, fam, inverse, 0, a);
+    IPS_HIP(launch_pass(a, f32, f32, st));
+    if (nstep == 2) {
+        shell_dst_pass(p, buf, nl, fam, inverse, 1, a);
+        IPS_HIP(launch_pass(a, f32, f32, st));
+    }
+    return IPS_OK;
 }
 
 // Shell layer transforms of all families: one launch per direction when the
-// families are uniform (contiguous buffers of identical shape).
+// families are uniform (contiguous buffers of identical shape), else the
+// families' passes of each step together in one multi-pass launch.
 template <typename TS>
 int shell_dst_all(ips_plan p, TS *const *arr, int nl, bool inverse, hipStream_t st)
 {
     constexpr bool f32 = sizeof(TS) == 4;
     if (p->cube) return shell_dst(p, arr[0], nl * p->d, 0, inverse, st, f32);
-    for (int fam = 0; fam < p->d; ++fam) {
-        int rc = shell_dst(p, arr[fam], nl, fam, inverse, st, f32);
-        if (rc) return rc;
+    PassArgs a[3];
+    int nstep = 1, rc;
+    for (int step = 0; step < nstep; ++step) {
+        for (int fam = 0; fam < p->d; ++fam) nstep = shell_dst_pass(p, arr[fam], nl, fam, inverse, step, a[fam]);
+        if ((rc = run_passes(a, p->d, f32, f32, st))) return rc;
     }
     return IPS_OK;
 }
@@ -1340,12 +1375,14 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
         // (6) face spectra: sum of the chunk partials, inverse transform along the
         //     contiguous slot axis c, then along r; F[fam][face][slot_r][slot_c]
         const int fr[3] = {2, 2, 1}, fc[3] = {1, 0, 0};
-        for (int fam = 0; fam < 3; ++fam) {
-            if (p->cube && fam > 0) break;
+        PassArgs fa[3], fb[3];
+        const int nf = p->cube ? 1 : 3;
+        for (int fam = 0; fam < nf; ++fam) {
             const int nfam = p->cube ? 3 : 1;
             const int r = fr[fam], c = fc[fam];
             const int64_t plane = (int64_t)N[r] * N[c];
-            PassArgs a{};
+            PassArgs &a = fa[fam];
+            a = PassArgs{};
             a.in = p->part[fam];
             a.out = p->F[fam];
             a.irs = a.ors = 1;
@@ -1363,8 +1400,9 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             a.scale = 1.0 / N[c];
             // few faces: narrow tiles give enough blocks to fill the device
             a.W = tile_width(N[c], std::min(p->work, 512), a.ncols);
-            if ((rc = run_pass(p, a, p->fd[c], p->tw[c], false, false, st))) return rc;
-            PassArgs b{};
+            prep_pass(p, a, p->fd[c], p->tw[c]);
+            PassArgs &b = fb[fam];
+            b = PassArgs{};
             b.in = b.out = p->F[fam];
             b.irs = b.ors = N[c];
             b.ics = b.ocs = 1;
@@ -1377,8 +1415,11 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             b.out_nrows = M[r] + 1;
             b.scale = 1.0 / N[r];
             b.W = tile_width(N[r], std::min(p->work, 512), b.ncols);
-            if ((rc = run_pass(p, b, p->fd[r], p->tw[r], false, false, st))) return rc;
+            prep_pass(p, b, p->fd[r], p->tw[r]);
         }
+        // the families' passes of each step together (one launch each when uniform)
+        if ((rc = run_passes(fa, nf, false, false, st))) return rc;
+        if ((rc = run_passes(fb, nf, false, false, st))) return rc;
         // (8) boundary values into phi; F[fam][face][j_r][j_c] -> strides of the in-face
         //     axes in increasing order
         BwriteArgs a{};
