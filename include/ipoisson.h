@@ -353,7 +353,7 @@ int ips_batch_create(ips_batch *out, int count, const int *d, const int64_t (*n)
  *                    rho[b] and phi[b] must not overlap
  * The first call (and any call with different array pointers) solves the
  * problems one after another on `stream` and then captures the same solves
- * into one HIP graph, spread over four internal streams so that independent
+ * into one HIP graph, spread over eight internal streams so that independent
  * problems can run side by side, largest first; later calls with the same
  * pointers replay that graph with a single launch on `stream`.  Capturing
  * creates the graph and, on first use, the internal streams; replays
