@@ -265,6 +265,9 @@ STAGE_DISPATCH = {
     "conv_x": ("k_cc", 0),
     "conv_y": ("k_cc", 1),
     "conv_z": ("k_cc", 2),
+    # the two forward slot passes of rho (FP64 in, FP32 slots: the mixed-slices mode)
+    "rho_z": ("k_pass<float, double, float", 0),
+    "rho_y": ("k_pass<float, double, float", 1),
 }
 
 
