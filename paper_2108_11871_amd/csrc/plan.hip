@@ -1004,7 +1004,7 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
     IPS_HIP(launch_face_charge(s, st));
     // face f along its axis x (o the other face axis), slot q of side s and
     // node m of axis o to out[q ors + s obs + m ocs]
-    auto along = [&](int f, int x, double *out, int64_t ors, int64_t ocs, int64_t obs) -> int {
+    auto along = [&](int f, int x, double *out, int64_t ors, int64_t ocs, int64_t obs) -> PassArgs {
         int b, c;
         face_axes(f, b, c);
         const int o = x == c ? b : c;
@@ -1024,11 +1024,12 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         a.out_r0 = 0;
         a.out_nrows = N[x];
         a.scale = 1.0;
-        return run_pass(p, a, p->fd[x], p->tw[x], false, false, st);
+        prep_pass(p, a, p->fd[x], p->tw[x]);
+        return a;
     };
     // back on the nodes along the shared axis x, the sum of ncopy partials:
     // in[N_x][ncopy][2][M_o + 1] -> out[2][M_o + 1][M_x + 1]
-    auto back = [&](const double *in, double *out, int x, int o, int ncopy) -> int {
+    auto back = [&](const double *in, double *out, int x, int o, int ncopy) -> PassArgs {
         PassArgs a{};
         a.in = in;
         a.out = out;
@@ -1047,14 +1048,19 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         a.out_r0 = 0;
         a.out_nrows = M[x] + 1;
         a.scale = 1.0 / N[x];
-        return run_pass(p, a, p->fd[x], p->tw[x], false, false, st);
+        prep_pass(p, a, p->fd[x], p->tw[x]);
+        return a;
     };
+    // The passes of the three faces (or pairs) of each step are independent:
+    // one multi-pass launch per step.
+    PassArgs g1[3], g2[3];
     for (int f = 0; f < 3; ++f) {
         int b, c;
         face_axes(f, b, c);
         // along c into [2][N_b][N_c] (rows 0..M_b), then along b in place
-        if ((rc = along(f, c, p->XH[f], 1, N[c], (int64_t)N[b] * N[c]))) return rc;
-        PassArgs a{};
+        g1[f] = along(f, c, p->XH[f], 1, N[c], (int64_t)N[b] * N[c]);
+        PassArgs &a = g2[f];
+        a = PassArgs{};
         a.in = a.out = p->XH[f];
         a.irs = a.ors = N[c];
         a.ics = a.ocs = 1;
@@ -1066,20 +1072,25 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         a.out_r0 = 0;
         a.out_nrows = N[b];
         a.scale = 1.0;
-        if ((rc = run_pass(p, a, p->fd[b], p->tw[b], false, false, st))) return rc;
+        prep_pass(p, a, p->fd[b], p->tw[b]);
     }
+    if ((rc = run_passes(g1, 3, false, false, st))) return rc;
+    if ((rc = run_passes(g2, 3, false, false, st))) return rc;
     for (int pr = 0; pr < 3; ++pr) {
         int a, b, c;
         pair_axes(pr, a, b, c);
-        if ((rc = along(a, c, p->XA[pr], 2 * (int64_t)(M[b] + 1), 1, M[b] + 1))) return rc;
-        if ((rc = along(b, c, p->XB[pr], 2 * (int64_t)(M[a] + 1), 1, M[a] + 1))) return rc;
+        g1[pr] = along(a, c, p->XA[pr], 2 * (int64_t)(M[b] + 1), 1, M[b] + 1);
+        g2[pr] = along(b, c, p->XB[pr], 2 * (int64_t)(M[a] + 1), 1, M[a] + 1);
     }
+    if ((rc = run_passes(g1, 3, false, false, st))) return rc;
+    if ((rc = run_passes(g2, 3, false, false, st))) return rc;
     IPS_HIP(launch_par_mul(s, st));
     for (int f = 0; f < 3; ++f) {
         int b, c;
         face_axes(f, b, c);
         // synthesis along b in place (rows 0..M_b), then along c into PP
-        PassArgs a{};
+        PassArgs &a = g1[f];
+        a = PassArgs{};
         a.in = a.out = p->XH[f];
         a.irs = a.ors = N[c];
         a.ics = a.ocs = 1;
@@ -1091,8 +1102,9 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         a.out_r0 = 0;
         a.out_nrows = M[b] + 1;
         a.scale = 1.0 / N[b];
-        if ((rc = run_pass(p, a, p->fd[b], p->tw[b], false, false, st))) return rc;
-        PassArgs z{};
+        prep_pass(p, a, p->fd[b], p->tw[b]);
+        PassArgs &z = g2[f];
+        z = PassArgs{};
         z.in = p->XH[f];
         z.out = p->PP[f];
         z.irs = 1;
@@ -1108,15 +1120,19 @@ int surface_sums(ips_plan p, double *phi, hipStream_t st)
         z.out_r0 = 0;
         z.out_nrows = M[c] + 1;
         z.scale = 1.0 / N[c];
-        if ((rc = run_pass(p, z, p->fd[c], p->tw[c], false, false, st))) return rc;
+        prep_pass(p, z, p->fd[c], p->tw[c]);
     }
+    if ((rc = run_passes(g1, 3, false, false, st))) return rc;
+    if ((rc = run_passes(g2, 3, false, false, st))) return rc;
     IPS_HIP(launch_perp(s, st));
     for (int pr = 0; pr < 3; ++pr) {
         int a, b, c;
         pair_axes(pr, a, b, c);
-        if ((rc = back(p->PA[pr], p->QA[pr], c, b, 2 * s.groups[pr]))) return rc;
-        if ((rc = back(p->PB[pr], p->QB[pr], c, a, 2))) return rc;
+        g1[pr] = back(p->PA[pr], p->QA[pr], c, b, 2 * s.groups[pr]);
+        g2[pr] = back(p->PB[pr], p->QB[pr], c, a, 2);
     }
+    if ((rc = run_passes(g1, 3, false, false, st))) return rc;
+    if ((rc = run_passes(g2, 3, false, false, st))) return rc;
     IPS_HIP(launch_surf_assemble(s, phi, st));
     return IPS_OK;
 }
@@ -1221,9 +1237,9 @@ int screen_boundary(ips_plan p, const double *rho, double *phi, hipStream_t st)
     s.nsrc = p->nsrc;
     s.ntgt = p->ntgt;
     IPS_HIP(launch_screen(s, phi, st));
-    // sigma on the faces: inverse sine transforms over the in-face axes
-    for (int fam = 0; fam < d; ++fam)
-        if ((rc = shell_dst(p, p->S[fam], 2, fam, true, st))) return rc;
+    // sigma on the faces: inverse sine transforms over the in-face axes (the
+    // families' face arrays are carved one after the other, as the shell layers)
+    if ((rc = shell_dst_all(p, p->S, 2, true, st))) return rc;
     if (!p->surf_fast) {
         IPS_HIP(launch_screen_g(s, phi, st));
         return IPS_OK;
