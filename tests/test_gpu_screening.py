@@ -1,7 +1,9 @@
 """Screening-charge boundary values on the GPU (IPS_FLAG_SCREENING) against the
 oracle's screening reading (oracle/screening.py), node by node at 1e-12
-relative to max |phi|: 1D, 2D and 3D, orders 4 and 6, anisotropic spacings,
-ragged sizes; plus the variant's rejections (mixed precision, adjoint)."""
+relative to max |phi|: 1D, 2D and 3D (up to 65x60x70, where the surface sums
+run by transforms with several row groups), orders 4 and 6, anisotropic
+spacings, ragged sizes; the transforms against the direct sums up to 257^3;
+plus the variant's rejections (mixed precision, adjoint)."""
 import numpy as np
 import pytest
 import torch
@@ -40,7 +42,8 @@ def test_screening_2d(shape, order):
     _run(shape, order, 4, [1.0, 1.2])
 
 
-@pytest.mark.parametrize("shape,order", [((25, 28, 23), 6), ((33, 33, 33), 4), ((17, 20, 31), 6), ((8, 9, 10), 6)])
+@pytest.mark.parametrize("shape,order", [((25, 28, 23), 6), ((33, 33, 33), 4), ((17, 20, 31), 6), ((8, 9, 10), 6),
+                                         ((65, 60, 70), 6)])
 def test_screening_3d(shape, order):
     _run(shape, order, 5, [1.0, 0.9, 1.15])
 
