@@ -24,7 +24,8 @@ Prints ONE JSON line.  Besides the contract fields it carries
   modes         per-precision throughput (mean over the timed steps and the
                 median of per-step HIP events), error vs the oracle and vs
                 FP64, and stage times;
-  adjoint       time of one FP64 adjoint solve on the same grid;
+  adjoint       time of one adjoint solve on the same grid, FP64 and the
+                headline mixed mode;
   batched       64 uneven boxes per batch: graph replays of the plain batch and of
                 the batch on 5-smooth extensions, eager launches for comparison;
   extended      the same solve through an extended plan (8 nodes added on every
@@ -460,23 +461,34 @@ def time_batched(api, torch, steps, warmup, modes=("fp64", "mixed_fp32_slices"))
 
 
 def time_adjoint(api, torch, rho_d, h, steps, warmup):
-    """One FP64 adjoint rho_bar = A^T phi_bar per step on the same grid."""
-    plan = api.Plan(tuple(rho_d.shape), h, order=6, adjoint=True)
-    out = torch.empty_like(rho_d)
-    for _ in range(max(warmup, 1)):
-        plan.adjoint(rho_d, out)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        plan.adjoint(rho_d, out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    plan.close()
-    return {"ms_per_step": ms, "mpoints_per_s": rho_d.numel() / (ms * 1e-3) / 1e6, "precision": "fp64"}
+    """One adjoint rho_bar = A^T phi_bar per step on the same grid, in FP64
+    and in the headline mixed mode (FP32 transform tiles, FP64 in memory),
+    with the mixed result's max-norm difference from the FP64 one."""
+    res = {}
+    ref = None
+    for prec in ("fp64", "mixed_fp32_slices"):
+        plan = api.Plan(tuple(rho_d.shape), h, order=6, precision=prec, adjoint=True)
+        out = torch.empty_like(rho_d)
+        for _ in range(max(warmup, 1)):
+            plan.adjoint(rho_d, out)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            plan.adjoint(rho_d, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        plan.close()
+        r = {"ms_per_step": ms, "mpoints_per_s": rho_d.numel() / (ms * 1e-3) / 1e6}
+        if ref is None:
+            ref = out
+        else:
+            r["rel_diff_vs_fp64"] = float((out - ref).abs().max() / ref.abs().max())
+        res[prec] = r
+    return res
 
 
 def time_extended(api, torch, rho_d, h, mode, margin, steps, warmup):
@@ -650,7 +662,8 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["adjoint"] = time_adjoint(api, torch, rho_d, h, max(args.steps // 2, 1), args.warmup)
-        log("adjoint: %.4f ms" % extras["adjoint"]["ms_per_step"])
+        log("adjoint: fp64 %.4f ms, mixed_fp32_slices %.4f ms" % (
+            extras["adjoint"]["fp64"]["ms_per_step"], extras["adjoint"]["mixed_fp32_slices"]["ms_per_step"]))
         extras["batched"] = time_batched(api, torch, max(args.steps // 2, 1), args.warmup)
         log("batched done")
     # the oracle on the host: CPU baseline and every mode's error against it

@@ -234,8 +234,11 @@ int ips_execute_static(ips_plan p, const double *rho, double *phi, void *stream)
 /*
  * ips_execute_adjoint -- enqueue rho_bar = A^T phi_bar, where A is the
  * linear map rho -> phi of the method (Sections 2-5) at the plan's grid and
- * order, i.e. the transpose of the FP64 solve.  Every step runs in FP64
- * whatever the plan's precision.  The steps of the solve are transposed in
+ * order, i.e. the transpose of the FP64 solve.  FP64 plans run every step
+ * in FP64.  Mixed plans run the sine transforms of the volume in FP32 tiles
+ * (data in memory stay FP64; every other step FP64): the result then agrees
+ * with the FP64 adjoint to a few FP32 roundings (about 3e-7 relative, as the
+ * mixed forward solve).  The steps of the solve are transposed in
  * reverse order: the sine-transform solves are symmetric; the transfer of
  * boundary values (eq. harmonic4thOrderNH2D), the sixth-order stencils and
  * their cubic extrapolation (eqs. 6thOrderRelation2D/3D) are applied

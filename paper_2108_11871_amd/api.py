@@ -161,7 +161,8 @@ class Plan:
         return out
 
     def adjoint(self, phi_bar: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        """rho_bar = A^T phi_bar for the map A: rho -> phi of this plan (FP64)."""
+        """rho_bar = A^T phi_bar for the map A: rho -> phi of this plan (FP64 data;
+        mixed plans run the volume sine transforms in FP32 tiles)."""
         _check_grid(phi_bar)
         if tuple(phi_bar.shape) != self.shape:
             raise ValueError("phi_bar shape %s does not match the plan %s" % (tuple(phi_bar.shape), self.shape))

@@ -273,6 +273,8 @@ hipError_t launch_adj_1d(const double *w, double *out, int M, double h, const Ff
 void set_lds(const void *fn, size_t bytes);
 
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st);
+// FP64 input and output, FP32 tiles (the adjoint's volume transforms in the mixed modes)
+hipError_t launch_pass_f32t(const PassArgs &a, hipStream_t st);
 
 // Up to kMultiPass independent passes (generic widths, transforms up to 2048)
 // in one launch; first[] is filled by the launcher.

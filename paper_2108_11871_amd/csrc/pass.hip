@@ -341,6 +341,12 @@ hipError_t launch_pass_multi(const PassArgs *p, int n, bool in_f32, bool out_f32
     return launch_multi_t<float, float, double>(m, st);
 }
 
+hipError_t launch_pass_f32t(const PassArgs &a, hipStream_t st)
+{
+    if (!pass_strides_ok(a)) return hipErrorInvalidValue;
+    return launch_pass_t<float, double, double>(a, st);
+}
+
 hipError_t launch_pass(const PassArgs &a, bool in_f32, bool out_f32, hipStream_t st)
 {
     if (!pass_strides_ok(a)) return hipErrorInvalidValue;

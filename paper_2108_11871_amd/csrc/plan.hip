@@ -412,11 +412,15 @@ void prep_pass(ips_plan p, PassArgs &a, const FftDesc &fd, const cx<double> *tw)
     if (a.W == 0) a.W = tile_width(fd.N, p->work, a.ncols);
 }
 
+// f32t: FP32 tiles between FP64 input and output
 int run_pass(ips_plan p, PassArgs a, const FftDesc &fd, const cx<double> *tw, bool in_f32,
-             bool out_f32, hipStream_t st)
+             bool out_f32, hipStream_t st, bool f32t = false)
 {
     prep_pass(p, a, fd, tw);
-    IPS_HIP(launch_pass(a, in_f32, out_f32, st));
+    if (f32t && !in_f32 && !out_f32)
+        IPS_HIP(launch_pass_f32t(a, st));
+    else
+        IPS_HIP(launch_pass(a, in_f32, out_f32, st));
     return IPS_OK;
 }
 
@@ -1730,7 +1734,7 @@ int adj_alloc(ips_plan p)
 // Raw DST-I of an interior field over all axes.  src points at node (1, 1, 1)
 // of an array with strides sst[] (a grid or a packed interior); X receives
 // the packed coefficients [k0][k1][k2].
-int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStream_t st)
+int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStream_t st, bool f32t)
 {
     const int *I = p->I, *M = p->M;
     PassArgs a{};
@@ -1750,7 +1754,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
         a.nbatch = I[0];
         a.out_r0 = M[2] + 1;
         a.out_nrows = I[2];
-        int rc = run_pass(p, a, p->fd[2], p->tw[2], false, false, st);
+        int rc = run_pass(p, a, p->fd[2], p->tw[2], false, false, st, f32t);
         if (rc) return rc;
         PassArgs b = a;
         b.in = X;
@@ -1763,7 +1767,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
         b.out_r0 = M[1] + 1;
         b.out_nrows = I[1];
         b.W = 0;
-        if ((rc = run_pass(p, b, p->fd[1], p->tw[1], false, false, st))) return rc;
+        if ((rc = run_pass(p, b, p->fd[1], p->tw[1], false, false, st, f32t))) return rc;
         PassArgs c = b;
         c.irs = c.ors = (int64_t)I[1] * I[2];
         c.ics = c.ocs = 1;
@@ -1774,7 +1778,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
         c.out_r0 = M[0] + 1;
         c.out_nrows = I[0];
         c.W = 0;
-        return run_pass(p, c, p->fd[0], p->tw[0], false, false, st);
+        return run_pass(p, c, p->fd[0], p->tw[0], false, false, st, f32t);
     }
     a.in = src;
     a.out = X;
@@ -1787,7 +1791,7 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
     a.nbatch = 1;
     a.out_r0 = M[1] + 1;
     a.out_nrows = I[1];
-    int rc = run_pass(p, a, p->fd[1], p->tw[1], false, false, st);
+    int rc = run_pass(p, a, p->fd[1], p->tw[1], false, false, st, f32t);
     if (rc) return rc;
     PassArgs b = a;
     b.in = X;
@@ -1798,13 +1802,13 @@ int vol_fwd(ips_plan p, const double *src, const int64_t *sst, double *X, hipStr
     b.out_r0 = M[0] + 1;
     b.out_nrows = I[0];
     b.W = 0;
-    return run_pass(p, b, p->fd[0], p->tw[0], false, false, st);
+    return run_pass(p, b, p->fd[0], p->tw[0], false, false, st, f32t);
 }
 
 // Inverse of vol_fwd's coefficients (raw DST-I again, scaled by 1/2 per axis
 // as the synthesis returns twice the sine sum): X is overwritten, the result
 // goes to dst (node (1, 1, 1), strides dst_st[]).
-int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream_t st)
+int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream_t st, bool f32t)
 {
     const int *I = p->I, *M = p->M;
     PassArgs a{};
@@ -1820,7 +1824,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
         a.ncols = I[2];
         a.nbatch = I[1];
         a.out_nrows = I[0];
-        int rc = run_pass(p, a, p->fd[0], p->tw[0], false, false, st);
+        int rc = run_pass(p, a, p->fd[0], p->tw[0], false, false, st, f32t);
         if (rc) return rc;
         PassArgs b = a;
         b.irs = b.ors = I[2];
@@ -1831,7 +1835,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
         b.nbatch = I[0];
         b.out_nrows = I[1];
         b.W = 0;
-        if ((rc = run_pass(p, b, p->fd[1], p->tw[1], false, false, st))) return rc;
+        if ((rc = run_pass(p, b, p->fd[1], p->tw[1], false, false, st, f32t))) return rc;
         PassArgs c = b;
         c.out = dst;
         c.irs = 1;
@@ -1846,7 +1850,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
         c.out_nrows = I[2];
         c.W = 0;
         (void)M;
-        return run_pass(p, c, p->fd[2], p->tw[2], false, false, st);
+        return run_pass(p, c, p->fd[2], p->tw[2], false, false, st, f32t);
     }
     a.in = a.out = X;
     a.irs = a.ors = I[1];
@@ -1855,7 +1859,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
     a.ncols = I[1];
     a.nbatch = 1;
     a.out_nrows = I[0];
-    int rc = run_pass(p, a, p->fd[0], p->tw[0], false, false, st);
+    int rc = run_pass(p, a, p->fd[0], p->tw[0], false, false, st, f32t);
     if (rc) return rc;
     PassArgs b = a;
     b.out = dst;
@@ -1867,7 +1871,7 @@ int vol_inv(ips_plan p, double *X, double *dst, const int64_t *dst_st, hipStream
     b.ncols = I[0];
     b.out_nrows = I[1];
     b.W = 0;
-    return run_pass(p, b, p->fd[1], p->tw[1], false, false, st);
+    return run_pass(p, b, p->fd[1], p->tw[1], false, false, st, f32t);
 }
 
 int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
@@ -1898,18 +1902,20 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
         aa.lf_size[fam] = 2 * (int64_t)(M[b] + 1) * (d == 3 ? (M[c] + 1) : 1);
     }
     const bool six = p->order == 6;
+    // the mixed modes run the volume transforms in FP32 tiles (FP64 in HBM)
+    const bool f32t = p->precision != IPS_FP64;
     int rc;
     // phi_star part and a = L0^-1 w_I from one forward transform
-    if ((rc = vol_fwd(p, w + off, gst, p->AX, st))) return rc;
+    if ((rc = vol_fwd(p, w + off, gst, p->AX, st, f32t))) return rc;
     IPS_HIP(launch_adj_spec(aa, p->AX, p->AY, st));
-    if ((rc = vol_inv(p, p->AY, out + off, gst, st))) return rc;
-    if ((rc = vol_inv(p, p->AX, p->AX, pst, st))) return rc;
+    if ((rc = vol_inv(p, p->AY, out + off, gst, st, f32t))) return rc;
+    if ((rc = vol_inv(p, p->AX, p->AX, pst, st, f32t))) return rc;
     if (six) {
         // AZ (the slice stack of the boundary expansion, used later) is scratch here
         IPS_HIP(launch_adj_r6(aa, p->AX, p->AF, p->AU, p->AZ, st));
-        if ((rc = vol_fwd(p, p->AU + off, gst, p->AX2, st))) return rc;
+        if ((rc = vol_fwd(p, p->AU + off, gst, p->AX2, st, f32t))) return rc;
         IPS_HIP(launch_adj_spec(aa, p->AX2, nullptr, st));
-        if ((rc = vol_inv(p, p->AX2, p->AX2, pst, st))) return rc;
+        if ((rc = vol_inv(p, p->AX2, p->AX2, pst, st, f32t))) return rc;
     }
     IPS_HIP(launch_zero_boundary(aa, out, st));
     IPS_HIP(launch_adj_lambda(aa, w, p->AX, six ? p->AX2 : nullptr, six ? p->AU : nullptr, st));
