@@ -26,7 +26,8 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
 {
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
+    // the prefetching variants run one tile width only (their launcher checks it)
+    const int N = a.fd.N, M = a.fd.M, W = WHC > 0 ? 2 * WHC : a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1, Wh = W >> 1;
     const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
     T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));

@@ -12,13 +12,14 @@ namespace ips {
 
 // One tile of a pass: tile lb (column block lb % ncb of batch entry lb / ncb),
 // loaded into LDS (rows placed as the input mode needs), transformed along its
-// rows and stored.
-template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT>
+// rows and stored.  WT > 0: the tile width, known at compile time (equal to
+// a.W, which the launcher checks).
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT, int WT = 0>
 __device__ __forceinline__ void pass_tile(const PassArgs &a, int lb)
 {
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = a.W, rs = BIG ? W : W + 1;
+    const int N = a.fd.N, M = a.fd.M, W = WT > 0 ? WT : a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1;
     const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
     T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
@@ -85,8 +86,8 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
 {
     constexpr bool PF = WC > 0;
     if constexpr (!PF) {
-        // one tile per block
-        pass_tile<T, TI, TO, MAXE, P2, NTT>(a, xcd_remap(blockIdx.x, ntiles));
+        // one tile per block (WC < 0: of the compile-time width -WC)
+        pass_tile<T, TI, TO, MAXE, P2, NTT, (WC < 0 ? -WC : 0)>(a, xcd_remap(blockIdx.x, ntiles));
         return;
     }
     constexpr bool BIG = NTT != NT;
@@ -210,8 +211,12 @@ static void launch_pass_m(const PassArgs &a, int ntiles, size_t lds, hipStream_t
     if constexpr (MAXE == 8) {
         if (!(a.in_mode == IN_HERM && a.nsum > 1) && (P2 || a.fd.N >= 512)) {
             constexpr bool wide = sizeof(T) == 8; // FP64 tiles: every mode, EPT up to 2 MAXE
-            if (!wide && a.in_mode != IN_ZPAD && a.in_mode != IN_ZPAD0)
+            if (!wide && a.in_mode != IN_ZPAD && a.in_mode != IN_ZPAD0) {
+                // one tile per block, the default widths at compile time
+                if (P2 && a.W == 8) return launch_pass_k<T, TI, TO, MAXE, P2, NT, -8, 0>(a, ntiles, lds, st);
+                if (P2 && a.W == 16) return launch_pass_k<T, TI, TO, MAXE, P2, NT, -16, 0>(a, ntiles, lds, st);
                 return launch_pass_k<T, TI, TO, MAXE, P2>(a, ntiles, lds, st);
+            }
             if (pass_fits<8, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 8, 8>(a, ntiles, lds, st);
             if (pass_fits<16, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 16, 8>(a, ntiles, lds, st);
             if (pass_fits<4, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 4, 8>(a, ntiles, lds, st);
