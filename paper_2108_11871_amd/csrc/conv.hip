@@ -21,13 +21,21 @@ namespace ips {
 // an odd count only once), so each kernel-spectrum value loaded serves two
 // columns, and with the C and S rows of the pencil transform four products
 // per face.
-template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT, int WHC>
+template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT, int WHC, int NC>
 __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
 {
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
+    // NC > 0: the transform length, known at compile time (only the
+    // compile-time Stockham stages of that length are built in)
+    FftDesc fdc{};
+    if constexpr (NC > 0) {
+        fdc.N = NC;
+        fdc.M = NC / 2;
+    }
+    const FftDesc &fd = NC > 0 ? fdc : a.fd;
     // the prefetching variants run one tile width only (their launcher checks it)
-    const int N = a.fd.N, M = a.fd.M, W = WHC > 0 ? 2 * WHC : a.W, rs = BIG ? W : W + 1;
+    const int N = fd.N, M = fd.M, W = WHC > 0 ? 2 * WHC : a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1, Wh = W >> 1;
     const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
     T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
@@ -101,9 +109,9 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
         __syncthreads();
         // rows 1..nrows_in <= M-1 hold data, rows from M on are zero
         if (a.nrows_in <= M - 1)
-            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, tid);
+            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, tid);
         else
-            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
+            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, false, tid);
         post_cs<T, MAXE, NTT>(buf, rs, lgs, M, tid);
         if (WB && (a.Mo == 0 || bt > a.Mo)) {
             const int64_t bb = a.Mo == 0 ? 0 : (int64_t)(bt - a.Mo - 1) * a.Bbs;
@@ -189,12 +197,12 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
     }
 }
 
-template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT = NT, int WHC = 0>
+template <typename T, typename TI, int MAXE, bool WB, bool P2, int RPT, int NTT = NT, int WHC = 0, int NC = 0>
 static void launch_cc_k(const CcArgs &a, int nchunk, hipStream_t st)
 {
     const size_t lds = tile_lds<T>(a.fd.N, a.W);
-    set_lds((const void *)&k_cc<T, TI, MAXE, WB, P2, RPT, NTT, WHC>, lds);
-    hipLaunchKernelGGL((k_cc<T, TI, MAXE, WB, P2, RPT, NTT, WHC>), dim3(nchunk * a.nbatch), dim3(NTT), lds,
+    set_lds((const void *)&k_cc<T, TI, MAXE, WB, P2, RPT, NTT, WHC, NC>, lds);
+    hipLaunchKernelGGL((k_cc<T, TI, MAXE, WB, P2, RPT, NTT, WHC, NC>), dim3(nchunk * a.nbatch), dim3(NTT), lds,
                        st, a, nchunk);
 }
 
@@ -212,6 +220,15 @@ template <typename T, typename TI, int MAXE, bool WB>
 static void launch_cc_m(const CcArgs &a, int nchunk, hipStream_t st)
 {
     const bool p2 = is_pow2(a.fd.N);
+    if constexpr (MAXE == 8) {
+        // the default (length, width) pairs with compile-time Stockham stages
+        if (a.fd.N == 512 && prefetch_fits<4, 8>(a))
+            return launch_cc_k<T, TI, 8, WB, true, 2, NT, 4, 512>(a, nchunk, st);
+        if (a.fd.N == 256 && prefetch_fits<8, 8>(a))
+            return launch_cc_k<T, TI, 8, WB, true, 2, NT, 8, 256>(a, nchunk, st);
+        if (a.fd.N == 1024 && prefetch_fits<2, 8>(a))
+            return launch_cc_k<T, TI, 8, WB, true, 4, NT, 2, 1024>(a, nchunk, st);
+    }
     if (a.fd.N <= 2 * NT) {
         if (p2 && prefetch_fits<8, MAXE>(a))
             launch_cc_k<T, TI, MAXE, WB, true, 2, NT, 8>(a, nchunk, st);
