@@ -854,7 +854,7 @@ __device__ __forceinline__ void final_row(const FinalArgs &a, int i, int kB, dou
         for (int t = nt; t < 3; ++t) r[4 + par * 3 + t] = (TR)0;
 }
 
-template <typename T, int MAXE, bool P2, int WC, int NTT>
+template <typename T, int MAXE, bool P2, int WC, int NTT, int NC>
 __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
 {
     constexpr bool BIG = NTT != NT;
@@ -864,7 +864,15 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     constexpr bool PF = WC > 0 && !BIG && sizeof(T) == 8;
     extern __shared__ __align__(16) unsigned char smem[];
     // WC > 0: tile width known at compile time (row offsets become shifts)
-    const int N = a.fd.N, M = a.fd.M, W = WC > 0 ? WC : a.W, rs = BIG ? W : W + 1;
+    // NC > 0: the transform length, known at compile time (only the
+    // compile-time Stockham stages of that length are built in)
+    FftDesc fdc{};
+    if constexpr (NC > 0) {
+        fdc.N = NC;
+        fdc.M = NC / 2;
+    }
+    const FftDesc &fd = NC > 0 ? fdc : a.fd;
+    const int N = fd.N, M = fd.M, W = WC > 0 ? WC : a.W, rs = BIG ? W : W + 1;
     const int lgW = WC > 0 ? __builtin_ctz(WC > 0 ? WC : 1) : 31 - __clz(W), lgs = lgW - 1;
     const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
     const size_t twb = BIG ? 0 : (size_t)N * sizeof(cx<T>);
@@ -992,9 +1000,9 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     // forward transform of the zero-padded rows 1..M0-1 (unless B already holds the spectrum)
     if (!a.pre) {
         if (a.nrows_in <= M - 1)
-            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, tid);
+            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, tid);
         else
-            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, false, tid);
+            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, false, tid);
     }
     // One sweep over the row pairs (k, N-k) of every complex sequence s
     // (real columns 2s and 2s+1):
@@ -1064,24 +1072,35 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
         }
     }
     __syncthreads();
-    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, true, tid);
+    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, true, tid);
     tile_store<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW, tid);
     if constexpr (!PF) break; // one tile per block: no loop for the compiler to hoist out of
     __syncthreads();          // the next tile reuses the LDS
     }
 }
 
-template <typename T, int MAXE, bool P2, int WC, int NTT = NT>
-static void launch_final_w(const FinalArgs &a, int nblk, size_t lds, hipStream_t st)
+template <typename T, int MAXE, bool P2, int WC, int NTT = NT, int NC = 0>
+static void launch_final_n(const FinalArgs &a, int nblk, size_t lds, hipStream_t st)
 {
-    const void *fn = (const void *)&k_final<T, MAXE, P2, WC, NTT>;
+    const void *fn = (const void *)&k_final<T, MAXE, P2, WC, NTT, NC>;
     set_lds(fn, lds);
     int grid = nblk;
     if (WC > 0 && NTT == NT && sizeof(T) == 8) {
         const int r = resident_blocks(fn, NTT, lds);
         if (r > 0 && r < nblk) grid = r;
     }
-    hipLaunchKernelGGL((k_final<T, MAXE, P2, WC, NTT>), dim3(grid), dim3(NTT), lds, st, a, nblk);
+    hipLaunchKernelGGL((k_final<T, MAXE, P2, WC, NTT, NC>), dim3(grid), dim3(NTT), lds, st, a, nblk);
+}
+
+// Compile-time widths 4, 8, 16 of the default tile budget (N WC / 2 = 8 NT):
+// the transform length at compile time too when it is the plan's.
+template <typename T, int MAXE, bool P2, int WC, int NTT = NT>
+static void launch_final_w(const FinalArgs &a, int nblk, size_t lds, hipStream_t st)
+{
+    constexpr int NCT = (MAXE == 8 && P2 && NTT == NT && (WC == 4 || WC == 8 || WC == 16)) ? 16 * NT / WC : 0;
+    if constexpr (NCT > 0)
+        if (a.fd.N == NCT) return launch_final_n<T, MAXE, P2, WC, NTT, NCT>(a, nblk, lds, st);
+    launch_final_n<T, MAXE, P2, WC, NTT>(a, nblk, lds, st);
 }
 
 template <typename T, int MAXE, bool P2>

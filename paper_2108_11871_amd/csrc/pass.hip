@@ -13,13 +13,20 @@ namespace ips {
 // One tile of a pass: tile lb (column block lb % ncb of batch entry lb / ncb),
 // loaded into LDS (rows placed as the input mode needs), transformed along its
 // rows and stored.  WT > 0: the tile width, known at compile time (equal to
-// a.W, which the launcher checks).
-template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT, int WT = 0>
+// a.W, which the launcher checks); NC > 0 likewise the transform length (only
+// the compile-time Stockham stages of that length are built in).
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT, int WT = 0, int NC = 0>
 __device__ __forceinline__ void pass_tile(const PassArgs &a, int lb)
 {
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = WT > 0 ? WT : a.W, rs = BIG ? W : W + 1;
+    FftDesc fdc{};
+    if constexpr (NC > 0) {
+        fdc.N = NC;
+        fdc.M = NC / 2;
+    }
+    const FftDesc &fd = NC > 0 ? fdc : a.fd;
+    const int N = fd.N, M = fd.M, W = WT > 0 ? WT : a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1;
     const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
     T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
@@ -62,9 +69,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int lb)
     // zero-padded input (rows 1..nrows_in <= M-1, zeros from row M on):
     // the first stage skips the zero half
     if (a.in_mode == IN_ZPAD && a.nrows_in <= M - 1)
-        fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw);
+        fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw);
     else
-        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv);
+        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, inv);
     if (a.in_mode == IN_ZPAD || a.in_mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M);
     if (a.accum)
         tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW);
@@ -81,18 +88,24 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int lb)
 // registers while the current one is transformed.  The thread index is made
 // opaque inside that loop so that the compiler recomputes per-thread index
 // values instead of holding them in registers for the whole loop.
-template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT, int WC, int EPT>
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT, int WC, int EPT, int NC>
 __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
 {
     constexpr bool PF = WC > 0;
     if constexpr (!PF) {
         // one tile per block (WC < 0: of the compile-time width -WC)
-        pass_tile<T, TI, TO, MAXE, P2, NTT, (WC < 0 ? -WC : 0)>(a, xcd_remap(blockIdx.x, ntiles));
+        pass_tile<T, TI, TO, MAXE, P2, NTT, (WC < 0 ? -WC : 0), NC>(a, xcd_remap(blockIdx.x, ntiles));
         return;
     }
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = a.fd.N, M = a.fd.M, W = PF ? WC : a.W, rs = BIG ? W : W + 1;
+    FftDesc fdc{};
+    if constexpr (NC > 0) {
+        fdc.N = NC;
+        fdc.M = NC / 2;
+    }
+    const FftDesc &fd = NC > 0 ? fdc : a.fd;
+    const int N = fd.N, M = fd.M, W = PF ? WC : a.W, rs = BIG ? W : W + 1;
     const int lgW = 31 - __clz(W), lgs = lgW - 1;
     const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
     T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
@@ -163,9 +176,9 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
             inv = true;
         }
         if (mode == IN_ZPAD && a.nrows_in <= M - 1)
-            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, tid);
+            fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, tid);
         else
-            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, a.fd, tw, inv, tid);
+            fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, inv, tid);
         if (mode == IN_ZPAD || mode == IN_ZPAD0) post_cs<T, MAXE, NTT>(buf, rs, lgs, M, tid);
         if (a.accum)
             tile_store_acc<T, TO, NTT>(buf, rs, a.out_r0, out0 + oo, a.out_nrows, nc, a.ors, a.ocs, (T)a.scale, lgW,
@@ -177,18 +190,31 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
     }
 }
 
-template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT = NT, int WC = 0, int EPT = 0>
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int NTT = NT, int WC = 0, int EPT = 0, int NC = 0>
 static void launch_pass_k(const PassArgs &a, int ntiles, size_t lds, hipStream_t st)
 {
-    const void *fn = (const void *)&k_pass<T, TI, TO, MAXE, P2, NTT, WC, EPT>;
+    const void *fn = (const void *)&k_pass<T, TI, TO, MAXE, P2, NTT, WC, EPT, NC>;
     set_lds(fn, lds);
     int grid = ntiles;
     if (WC > 0) {
         const int r = resident_blocks(fn, NTT, lds);
         if (r > 0 && r < ntiles) grid = r;
     }
-    hipLaunchKernelGGL((k_pass<T, TI, TO, MAXE, P2, NTT, WC, EPT>), dim3((unsigned)grid), dim3(NTT), lds, st, a,
-                       ntiles);
+    hipLaunchKernelGGL((k_pass<T, TI, TO, MAXE, P2, NTT, WC, EPT, NC>), dim3((unsigned)grid), dim3(NTT), lds, st,
+                       a, ntiles);
+}
+
+// A compile-time width |WC|: the transform length of the default tile budget
+// (N |WC| / 2 = 8 NT, lengths 256, 512, 1024) also at compile time when it is
+// the plan's.
+template <typename T, typename TI, typename TO, int MAXE, bool P2, int WC, int EPT>
+static void launch_pass_w(const PassArgs &a, int ntiles, size_t lds, hipStream_t st)
+{
+    constexpr int AW = WC < 0 ? -WC : WC;
+    constexpr int NCT = (MAXE == 8 && P2 && (AW == 4 || AW == 8 || AW == 16)) ? 16 * NT / AW : 0;
+    if constexpr (NCT > 0)
+        if (a.fd.N == NCT) return launch_pass_k<T, TI, TO, MAXE, P2, NT, WC, EPT, NCT>(a, ntiles, lds, st);
+    launch_pass_k<T, TI, TO, MAXE, P2, NT, WC, EPT>(a, ntiles, lds, st);
 }
 
 // Compile-time tile widths W = 4, 8, 16 (the default widths of 2M = 1024,
@@ -213,17 +239,17 @@ static void launch_pass_m(const PassArgs &a, int ntiles, size_t lds, hipStream_t
             constexpr bool wide = sizeof(T) == 8; // FP64 tiles: every mode, EPT up to 2 MAXE
             if (!wide && a.in_mode != IN_ZPAD && a.in_mode != IN_ZPAD0) {
                 // one tile per block, the default widths at compile time
-                if (P2 && a.W == 8) return launch_pass_k<T, TI, TO, MAXE, P2, NT, -8, 0>(a, ntiles, lds, st);
-                if (P2 && a.W == 16) return launch_pass_k<T, TI, TO, MAXE, P2, NT, -16, 0>(a, ntiles, lds, st);
+                if (P2 && a.W == 8) return launch_pass_w<T, TI, TO, MAXE, P2, -8, 0>(a, ntiles, lds, st);
+                if (P2 && a.W == 16) return launch_pass_w<T, TI, TO, MAXE, P2, -16, 0>(a, ntiles, lds, st);
                 return launch_pass_k<T, TI, TO, MAXE, P2>(a, ntiles, lds, st);
             }
-            if (pass_fits<8, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 8, 8>(a, ntiles, lds, st);
-            if (pass_fits<16, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 16, 8>(a, ntiles, lds, st);
-            if (pass_fits<4, 8>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 4, 8>(a, ntiles, lds, st);
+            if (pass_fits<8, 8>(a)) return launch_pass_w<T, TI, TO, 8, P2, 8, 8>(a, ntiles, lds, st);
+            if (pass_fits<16, 8>(a)) return launch_pass_w<T, TI, TO, 8, P2, 16, 8>(a, ntiles, lds, st);
+            if (pass_fits<4, 8>(a)) return launch_pass_w<T, TI, TO, 8, P2, 4, 8>(a, ntiles, lds, st);
             if constexpr (wide) {
-                if (pass_fits<8, 16>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 8, 16>(a, ntiles, lds, st);
-                if (pass_fits<16, 16>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 16, 16>(a, ntiles, lds, st);
-                if (pass_fits<4, 16>(a)) return launch_pass_k<T, TI, TO, 8, P2, NT, 4, 16>(a, ntiles, lds, st);
+                if (pass_fits<8, 16>(a)) return launch_pass_w<T, TI, TO, 8, P2, 8, 16>(a, ntiles, lds, st);
+                if (pass_fits<16, 16>(a)) return launch_pass_w<T, TI, TO, 8, P2, 16, 16>(a, ntiles, lds, st);
+                if (pass_fits<4, 16>(a)) return launch_pass_w<T, TI, TO, 8, P2, 4, 16>(a, ntiles, lds, st);
             }
         }
     }
