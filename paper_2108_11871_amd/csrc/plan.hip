@@ -155,14 +155,16 @@ int tile_width(int N, int maxwork, int ncols)
 
 // Blocks of a column-contraction launch the chunking aims at (IPS_CC_BLOCKS
 // overrides the default, for measurements).
-int cc_block_target()
+int cc_block_target(int N)
 {
     static const int v = [] {
         const char *e = getenv("IPS_CC_BLOCKS");
         const int x = e ? atoi(e) : 0;
-        return x >= 256 && x <= 65536 ? x : 6144;
+        return x >= 256 && x <= 65536 ? x : 0;
     }();
-    return v;
+    // fewer chunks (fewer partials for the face pass to sum) up to 2M = 512;
+    // the strided pencils of 2M = 1024 measured faster with more blocks
+    return v ? v : (N >= 1024 ? 6144 : 4112);
 }
 
 // In-face axes (b, c) of the kernel-spectrum table of face family `fam`, in
@@ -807,10 +809,10 @@ int plan_build(ips_plan p, hipStream_t st)
         const int W = tile_width(N[pen], p->work, I[fam]);
         const int hc = (I[fam] + 1) / 2, Wh = W / 2;
         const int ncb = (hc + Wh - 1) / Wh;
-        // about 6144 blocks of 256 threads (a few tiles each: measured faster
-        // than fewer, longer blocks, although the face pass then sums more
-        // chunk partials); 256 blocks of 1024 for long transforms
-        const int target = N[pen] > kLdsMaxN ? 256 : cc_block_target();
+        // about 4096 (2M <= 512) or 6144 blocks of 256 threads, a few tiles
+        // each (more chunks give more blocks but more partials for the face
+        // pass to sum); 256 blocks of 1024 for long transforms
+        const int target = N[pen] > kLdsMaxN ? 256 : cc_block_target(N[pen]);
         int nch = std::max(1, std::min(ncb, (target + nbatch - 1) / nbatch));
         const int per = (ncb + nch - 1) / nch;
         p->chunk[fam] = per * Wh;
@@ -1446,7 +1448,9 @@ int execute(ips_plan p, const double *rho, double *phi, hipStream_t st)
             b.out_r0 = 0;
             b.out_nrows = M[r] + 1;
             b.scale = 1.0 / N[r];
-            b.W = tile_width(N[r], std::min(p->work, 512), b.ncols);
+            // the second step reads no partials: the default tile budget
+            // (compile-time stages) measured faster than narrow tiles
+            b.W = tile_width(N[r], std::min(p->work, 2048), b.ncols);
             prep_pass(p, b, p->fd[r], p->tw[r]);
         }
         // the families' passes of each step together (one launch each when uniform)
