@@ -364,7 +364,7 @@ __device__ __forceinline__ float recip(float x)
 // Each thread carries PPT positions (64 apart) through the k_a loop: their
 // loads and reciprocals are independent, which hides more latency per wave.
 // ---------------------------------------------------------------------------
-template <int D, int PPT>
+template <int D, int PPT, int KU>
 __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
 {
     constexpr int PB = 64 * PPT, NG = NT / 64;
@@ -456,22 +456,48 @@ __global__ __launch_bounds__(NT) void k_r6t(R6Args a)
         for (int j = 0; j < 5; ++j) acc[q][j] = 0.0;
     // split s of gridDim.y: every gridDim.y-th wavenumber of this group's
     // residue (the parity of k_a stays that of the group)
-    const int ks = gridDim.y, sp = blockIdx.y;
-    for (int ka = 1 + grp + NG * sp; ka <= Ia; ka += NG * ks) {
+    const int ks = gridDim.y, sp = blockIdx.y, step = NG * ks;
+    // one wavenumber: pbv, pcv are the family values at (position q, ka)
+    auto term = [&](int ka, const double *pbv, const double *pcv) {
         const double lk = tl[ka - 1], sk = ts[ka - 1];
         double sj[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) sj[j] = ts[j * Ia + ka - 1];
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-            double gt = sk * gown[q] + sbl[q] * pb[q][(int64_t)(ka - 1) * bs];
-            if (D == 3) gt += scw[q] * pc[q][(int64_t)(ka - 1) * cs];
+            double gt = sk * gown[q] + sbl[q] * pbv[q];
+            if (D == 3) gt += scw[q] * pcv[q];
             const double L = fma(A1[q], lk, A0[q]);
             const double R = fma(fma(B2[q], lk, B1[q]), lk, B0[q]);
             const double v = R * gt * recip(L);
 #pragma unroll
             for (int j = 0; j < 5; ++j) acc[q][j] = fma(sj[j], v, acc[q][j]);
         }
+    };
+    // KU wavenumbers per iteration, their strided family loads issued first
+    // (more loads in flight per wave)
+    int ka = 1 + grp + NG * sp;
+    for (; ka + (KU - 1) * step <= Ia; ka += KU * step) {
+        double pbv[KU][PPT], pcv[KU][PPT];
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const int64_t k1 = ka - 1 + u * step;
+                pbv[u][q] = pb[q][k1 * bs];
+                pcv[u][q] = D == 3 ? pc[q][k1 * cs] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) term(ka + u * step, pbv[u], pcv[u]);
+    }
+    for (; ka <= Ia; ka += step) {
+        double pbv[PPT], pcv[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            pbv[q] = pb[q][(int64_t)(ka - 1) * bs];
+            pcv[q] = D == 3 ? pc[q][(int64_t)(ka - 1) * cs] : 0.0;
+        }
+        term(ka, pbv, pcv);
     }
 #pragma unroll
     for (int q = 0; q < PPT; ++q)
@@ -520,7 +546,7 @@ __global__ void k_r6t_sum(R6Args a, int ax, int ks)
     }
 }
 
-template <int PPT>
+template <int PPT, int KU>
 static hipError_t launch_r6t_p(R6Args a, hipStream_t st)
 {
     const int d = a.geo.d;
@@ -533,9 +559,9 @@ static hipError_t launch_r6t_p(R6Args a, hipStream_t st)
     const int ks = r6t_splits(a.geo);
     if (ks > 1 && !a.part) return hipErrorInvalidValue;
     if (d == 3)
-        hipLaunchKernelGGL((k_r6t<3, PPT>), dim3(tot, ks), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((k_r6t<3, PPT, KU>), dim3(tot, ks), dim3(NT), 0, st, a);
     else
-        hipLaunchKernelGGL((k_r6t<2, PPT>), dim3(tot, ks), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((k_r6t<2, PPT, KU>), dim3(tot, ks), dim3(NT), 0, st, a);
     hipError_t e = hipGetLastError();
     for (int ax = 0; ax < d && ks > 1 && e == hipSuccess; ++ax) {
         const int64_t len = 10 * shell_size(a.geo, ax);
@@ -546,7 +572,9 @@ static hipError_t launch_r6t_p(R6Args a, hipStream_t st)
     return e;
 }
 
-hipError_t launch_r6t(R6Args a, hipStream_t st) { return launch_r6t_p<2>(a, st); }
+// two positions per thread, two wavenumbers per iteration (measured against
+// one and four of each)
+hipError_t launch_r6t(R6Args a, hipStream_t st) { return launch_r6t_p<2, 2>(a, st); }
 
 int r6t_splits(const Geo &g)
 {
