@@ -78,6 +78,32 @@ def test_3d_129_order6():
     _check(rho, h, 6, boundary="fft")
 
 
+# Transform lengths 2M = 512 and 1024 along single axes (and 256 along the
+# others): the kernel instances with compile-time lengths and tile widths, in
+# 2D and in thin 3D boxes whose long axis is in turn the axis of the final
+# pass, of the convolution pencils and of the last inverse pass.
+LONG_AXIS = [((257, 257), 6), ((513, 385), 6), ((20, 513, 24), 6), ((513, 18, 22), 6), ((24, 20, 513), 4),
+             ((129, 257, 40), 6)]
+
+
+@pytest.mark.parametrize("shape,order", LONG_AXIS)
+def test_long_axis_lengths(shape, order):
+    rho, h, _ = I.workload_bumps(shape, seed=23, scale=[1.0, 1.1, 0.9][:len(shape)])
+    _check(rho, h, order, boundary="fft")
+
+
+@pytest.mark.parametrize("mode", ["mixed_fp32", "mixed_fp32_slices"])
+@pytest.mark.parametrize("shape,order", LONG_AXIS[:4])
+def test_long_axis_lengths_mixed(shape, order, mode):
+    from gpu_util import banner, rel_err
+
+    rho, h, _ = I.workload_bumps(shape, seed=23, scale=[1.0, 1.1, 0.9][:len(shape)])
+    banner("mixed %s shape=%s" % (mode, shape))
+    err = rel_err(_gpu_solve(rho, h, order, precision=mode), P.solve(rho, h, order, boundary="fft"))
+    print("  rel err %.3e" % err, flush=True)
+    assert err < 1e-6
+
+
 def test_random_rho_3d_small():
     # arbitrary data (no smoothness): parity is purely discrete
     rng = np.random.default_rng(5)
