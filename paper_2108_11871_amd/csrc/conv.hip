@@ -28,6 +28,8 @@ __global__ __launch_bounds__(NTT) void k_cc(CcArgs a, int nchunk)
     extern __shared__ __align__(16) unsigned char smem[];
     // NC > 0: the transform length, known at compile time (only the
     // compile-time Stockham stages of that length are built in)
+    // (only the pairs that have compile-time stages: fdc carries no stage list)
+    static_assert(NC == 0 || (P2 && MAXE == 8 && NTT == NT && NC * WHC == 8 * NT), "no compile-time stages");
     FftDesc fdc{};
     if constexpr (NC > 0) {
         fdc.N = NC;

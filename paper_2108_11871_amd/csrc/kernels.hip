@@ -894,6 +894,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     // WC > 0: tile width known at compile time (row offsets become shifts)
     // NC > 0: the transform length, known at compile time (only the
     // compile-time Stockham stages of that length are built in)
+    static_assert(NC == 0 || (P2 && MAXE == 8 && !BIG && NC * WC == 16 * NT), "no compile-time stages");
     FftDesc fdc{};
     if constexpr (NC > 0) {
         fdc.N = NC;

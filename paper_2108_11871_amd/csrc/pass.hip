@@ -20,6 +20,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int lb)
 {
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
+    // (only the pairs that have compile-time stages: fdc carries no stage list)
+    static_assert(NC == 0 || (P2 && MAXE == 8 && !BIG && NC * WT == 16 * NT), "no compile-time stages");
     FftDesc fdc{};
     if constexpr (NC > 0) {
         fdc.N = NC;
@@ -99,6 +101,7 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
     }
     constexpr bool BIG = NTT != NT;
     extern __shared__ __align__(16) unsigned char smem[];
+    static_assert(!PF || NC == 0 || (P2 && MAXE == 8 && !BIG && NC * WC == 16 * NT), "no compile-time stages");
     FftDesc fdc{};
     if constexpr (NC > 0) {
         fdc.N = NC;
