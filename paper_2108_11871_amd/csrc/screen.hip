@@ -7,7 +7,7 @@
 //   k_screen_src : the weighted surface nodes (position, W sigma) of every face
 //   k_screen_g   : the corrected surface trapezoidal sums at every boundary node
 //                  (direct sums)
-//   k_face_charge, k_par_mul, k_perp, k_surf_assemble : the same sums in 3D by
+//   k_face_charge, k_par_mul, k_perp_mfma / k_perp, k_surf_assemble : the same sums in 3D by
 //                  transforms (with the slot passes of the plan)
 #include <hip/hip_runtime.h>
 
@@ -601,15 +601,189 @@ __global__ __launch_bounds__(NT) void k_perp(SurfArgs s, int pr)
     }
 }
 
+// The same sums on the matrix cores (FP64 16x16x4 MFMA), for face sides up
+// to kPerpMfmaMax nodes.  Per wavenumber k both sums are products of the
+// table slab K = KT[k] (rows i, columns j) with eight vectors, the
+// combinations n = 4 s + 2 s' + slot of target side, source side and slot
+// (the N dimension of the instruction, 16 wide, half used):
+//   targets on face a:  D_A[j][n] = sum_i K[i][j] xb[s'][u_s(i)][slot]
+//   targets on face b:  D_B[i][n] = sum_j K[i][j] xa[s][t_s'(j)][slot]
+// Rows of the slab stream through LDS in tiles of 16 (the next tile held in
+// registers).  D_A: each wave owns every fourth 16-column block and keeps its
+// accumulators over all tiles (K dimension: the 16 rows of a tile, four
+// steps).  D_B: the four waves split the columns of a tile (K dimension, four
+// columns a step) and their partial 16 x 16 products are summed through LDS.
+// Operand layouts of the instruction (lane l): A[m][kk] with m = l % 16,
+// kk = l / 16; B[kk][n] with n = l % 16, kk = l / 16; result element v of
+// lane l is D[4 v + l / 16][l % 16].
+constexpr int kPerpMfmaMax = 320;                 // M_a + 1, M_b + 1 at most
+constexpr int kPerpTR = 16;                        // slab rows per tile
+constexpr int kPerpJB = (kPerpMfmaMax + 15) / 16;  // 16-column blocks of a row
+constexpr int kPerpJPW = (kPerpJB + 3) / 4;        // column blocks per wave
+constexpr int kPerpMPf = (kPerpTR * kPerpMfmaMax + NT - 1) / NT; // prefetch registers per thread
+typedef double perp_v4d __attribute__((ext_vector_type(4)));
+
+bool perp_mfma_fits(const int *M)
+{
+    for (int a = 0; a < 3; ++a)
+        if (M[a] + 1 > kPerpMfmaMax) return false;
+    return true;
+}
+
+static size_t perp_mfma_lds_bytes(const int *M, int pr)
+{
+    const int a = pr == 2 ? 1 : 0, b = pr == 0 ? 1 : 2;
+    // xa, xb, the tile (which also holds the cross-wave sums of D_B)
+    return (size_t)(4 * (M[b] + 1) + 4 * (M[a] + 1) + std::max(kPerpTR * (M[b] + 1), 4 * 256)) * sizeof(double);
+}
+
+__global__ __launch_bounds__(NT) void k_perp_mfma(SurfArgs s, int pr)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int a, b, c;
+    pair_axes(pr, a, b, c);
+    const int Ma = s.M[a], Mb = s.M[b], Mc = s.M[c];
+    const int na = Ma + 1, nb = Mb + 1;
+    const int k = blockIdx.x, g = blockIdx.y, G = gridDim.y;
+    const bool two = k > 0 && k < Mc; // the sine slot exists
+    const int q0 = k, q1 = Mc + k;
+    const int ibeg = (int)((int64_t)g * na / G), iend = (int)((int64_t)(g + 1) * na / G);
+    double *xa = reinterpret_cast<double *>(smem); // [2][nb][2 slots]
+    double *xb = xa + 4 * nb;                      // [2][na][2 slots]
+    double *tile = xb + 4 * na;                    // [kPerpTR][nb]
+    double *red = tile;                            // [4 waves][64 lanes][4], after the tile is used
+    const double *XA = s.XA[pr], *XB = s.XB[pr];
+    const double *slab = s.KT[pr] + (int64_t)k * na * nb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lm = lane & 15, lk = lane >> 4; // operand row / column, K index
+    // this lane's combination n (B operands and results): s, s', slot
+    const int nsd = (lm >> 2) & 1, nsp = (lm >> 1) & 1, nsl = lm & 1;
+    const bool nval = lm < 8;
+    double pf[kPerpMPf];
+    auto fetch = [&](int i0) {
+        const int cnt = min(kPerpTR, iend - i0) * nb;
+        const double *src = slab + (int64_t)i0 * nb;
+#pragma unroll
+        for (int m = 0; m < kPerpMPf; ++m) {
+            const int e = tid + m * NT;
+            if (e < cnt) pf[m] = src[e];
+        }
+    };
+    if (ibeg < iend) fetch(ibeg);
+    for (int e = tid; e < 2 * nb; e += NT) {
+        xa[2 * e] = XA[(int64_t)q0 * 2 * nb + e];
+        xa[2 * e + 1] = two ? XA[(int64_t)q1 * 2 * nb + e] : 0.0;
+    }
+    for (int e = tid; e < 2 * na; e += NT) {
+        xb[2 * e] = XB[(int64_t)q0 * 2 * na + e];
+        xb[2 * e + 1] = two ? XB[(int64_t)q1 * 2 * na + e] : 0.0;
+    }
+    const int njb = (nb + 15) >> 4, nj4 = (nb + 3) >> 2;
+    perp_v4d accA[kPerpJPW];
+#pragma unroll
+    for (int q = 0; q < kPerpJPW; ++q) accA[q] = perp_v4d{0.0, 0.0, 0.0, 0.0};
+    double *PB = s.PB[pr];
+    const int64_t pbq = 4 * (int64_t)na;
+    for (int i0 = ibeg; i0 < iend; i0 += kPerpTR) {
+        const int nr = min(kPerpTR, iend - i0);
+        __syncthreads(); // the previous sums are consumed (and xa, xb are stored)
+#pragma unroll
+        for (int m = 0; m < kPerpMPf; ++m) {
+            const int e = tid + m * NT;
+            if (e < nr * nb) tile[e] = pf[m];
+        }
+        __syncthreads();
+        if (i0 + kPerpTR < iend) fetch(i0 + kPerpTR);
+        // D_A: B operands of the four K steps (rows 4 st + lk of the tile)
+        double bA[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int r = 4 * st + lk, i = i0 + r;
+            const int u = nsd ? Ma - i : i;
+            bA[st] = (nval && r < nr) ? xb[(nsp * na + u) * 2 + nsl] : 0.0;
+        }
+        // (K steps outermost: the column blocks' accumulations are independent)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int r = 4 * st + lk;
+#pragma unroll
+            for (int q = 0; q < kPerpJPW; ++q) {
+                const int jb = wave + 4 * q;
+                if (jb < njb) {
+                    const int j = 16 * jb + lm;
+                    const double av = (r < nr && j < nb) ? tile[r * nb + j] : 0.0;
+                    accA[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bA[st], accA[q], 0, 0, 0);
+                }
+            }
+        }
+        // D_B: this wave's columns (steps wave, wave + 4, ...), rows lm of the
+        // tile, in four independent accumulations
+        perp_v4d dB[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) dB[x] = perp_v4d{0.0, 0.0, 0.0, 0.0};
+        for (int st0 = wave; st0 < nj4; st0 += 16) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const int st = st0 + 4 * x;
+                const int j = 4 * st + lk;
+                const double av = (lm < nr && j < nb) ? tile[lm * nb + j] : 0.0;
+                const int t = nsp ? Mb - j : j;
+                const double bv = (nval && j < nb) ? xa[(nsd * nb + t) * 2 + nsl] : 0.0;
+                dB[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, dB[x], 0, 0, 0);
+            }
+        }
+        __syncthreads(); // every wave is done with the tile
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave * 64 + lane) * 4 + v] = (dB[0][v] + dB[1][v]) + (dB[2][v] + dB[3][v]);
+        __syncthreads();
+        {
+            // thread tid sums element (lane l, v) = (tid >> 2, tid & 3) over the waves
+            const int l = tid >> 2, v = tid & 3;
+            const double w = red[(0 * 64 + l) * 4 + v] + red[(1 * 64 + l) * 4 + v] + red[(2 * 64 + l) * 4 + v] +
+                             red[(3 * 64 + l) * 4 + v];
+            const int r = 4 * v + (l >> 4), n = l & 15;
+            if (n < 8 && r < nr) {
+                const int sd = (n >> 2) & 1, sp = (n >> 1) & 1, sl = n & 1;
+                const int i = i0 + r, u = sd ? Ma - i : i;
+                if (!sl || two) PB[(int64_t)(sl ? q1 : q0) * pbq + (sd * 2 + sp) * na + u] = w;
+            }
+        }
+    }
+    // D_A: element v of lane l is column j = 16 jb + 4 v + lk, combination lm
+    double *PA = s.PA[pr];
+    const int64_t paq = (int64_t)G * 4 * nb;
+    if (nval) {
+#pragma unroll
+        for (int q = 0; q < kPerpJPW; ++q) {
+            const int jb = wave + 4 * q;
+            if (jb >= njb) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * jb + 4 * v + lk;
+                if (j >= nb) continue;
+                const int t = nsp ? Mb - j : j;
+                const int64_t o = ((int64_t)(g * 2 + nsp) * 2 + nsd) * nb + t;
+                if (!nsl || two) PA[(nsl ? q1 : q0) * paq + o] = accA[q][v];
+            }
+        }
+    }
+}
+
 hipError_t launch_perp(const SurfArgs &s, hipStream_t st)
 {
     if (!perp_fits(s.M)) return hipErrorInvalidValue;
     for (int pr = 0; pr < 3; ++pr) {
         const int c = pr == 0 ? 2 : (pr == 1 ? 1 : 0);
         if (s.groups[pr] != perp_groups(s.M, pr)) return hipErrorInvalidValue;
-        const size_t lds = perp_lds_bytes(s.M, pr);
-        set_lds((const void *)&k_perp, lds);
-        hipLaunchKernelGGL(k_perp, dim3(s.M[c] + 1, s.groups[pr]), dim3(NT), lds, st, s, pr);
+        if (perp_mfma_fits(s.M)) {
+            const size_t lds = perp_mfma_lds_bytes(s.M, pr);
+            set_lds((const void *)&k_perp_mfma, lds);
+            hipLaunchKernelGGL(k_perp_mfma, dim3(s.M[c] + 1, s.groups[pr]), dim3(NT), lds, st, s, pr);
+        } else {
+            const size_t lds = perp_lds_bytes(s.M, pr);
+            set_lds((const void *)&k_perp, lds);
+            hipLaunchKernelGGL(k_perp, dim3(s.M[c] + 1, s.groups[pr]), dim3(NT), lds, st, s, pr);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

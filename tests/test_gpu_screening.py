@@ -49,12 +49,14 @@ def test_screening_3d(shape, order):
 
 
 @pytest.mark.parametrize("shape", [(41, 37, 45), (65, 65, 65), (9, 30, 12), (129, 129, 129), (150, 20, 41),
-                                   (257, 257, 257)])
+                                   (257, 257, 257), (330, 12, 20), (20, 400, 16)])
 def test_screening_transforms_match_the_direct_sums(shape):
     """The 3D surface sums by transforms (the default) against the direct sums
     of IPS_FLAG_SCREEN_DIRECT, on the same input: one and several row groups
     per wavenumber, one and several table tiles per group, thin boxes, and the
-    bench grid (the direct sums are pinned to the oracle on the smaller grids)."""
+    bench grid (the direct sums are pinned to the oracle on the smaller grids).
+    Face sides up to 320 nodes run the perpendicular sums on the matrix cores,
+    longer ones (the last two shapes) on the vector units."""
     from gpu_util import banner, rel_err, to_dev
 
     banner("screening transforms vs direct %s" % (shape,))
