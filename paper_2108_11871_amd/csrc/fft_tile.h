@@ -360,6 +360,117 @@ __device__ __forceinline__ void fft_ct(T *buf, const cx<T> *tw, int tid)
     }
 }
 
+// Element offset r * rsd + c * csd of a tile in 32-bit arithmetic with
+// 24-bit multiplies: the launchers check that strides stay below 2^23 and a
+// tile spans less than 2^31 elements (true for every supported grid).
+__device__ __forceinline__ int toff(int r, int64_t rsd, int c, int64_t csd)
+{
+    return __mul24(r, (int)rsd) + __mul24(c, (int)csd);
+}
+
+// The compile-time transforms split for tiles that are read from or written
+// to global memory by the transform itself (default (N, pitch) pairs only,
+// where every stage holds one butterfly per thread):
+//   forward:  stage_ct_gin (first stage, inputs from global) + fft_ct_tail
+//   inverse:  fft_ct_head + stage_ct_gout (last stage, outputs to global)
+// The tile never holds the input rows or the output rows in LDS, which saves
+// one LDS write and one read of the tile, and a barrier, per transform.
+template <int N>
+struct CtLast {
+    static constexpr int R = N == 256 ? 4 : N == 512 ? 8 : 2; // radix of the last stage
+};
+
+// Every stage after the first.
+template <typename T, int NT, int N, int RS, int LGS, bool INV>
+__device__ __forceinline__ void fft_ct_tail(T *buf, const cx<T> *tw, int tid)
+{
+    if constexpr (N == 256) {
+        stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 4, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
+    } else if constexpr (N == 512) {
+        stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
+    } else if constexpr (N == 1024) {
+        stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
+        stage_ct<T, 2, NT, N, 512, RS, LGS, INV>(buf, tw, tid);
+    }
+}
+
+// Every stage but the last.
+template <typename T, int NT, int N, int RS, int LGS, bool INV>
+__device__ __forceinline__ void fft_ct_head(T *buf, const cx<T> *tw, int tid)
+{
+    stage_ct<T, 8, NT, N, 1, RS, LGS, INV>(buf, tw, tid);
+    stage_ct<T, 8, NT, N, 8, RS, LGS, INV>(buf, tw, tid);
+    if constexpr (N == 1024) stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
+}
+
+// First stage (radix 8) of the forward transform of zero-padded sequences,
+// read straight from global memory: tile row t = 1..nrows of sequence sq is
+// source row t - 1 of columns 2 sq (real part) and 2 sq + 1 (imaginary part);
+// row 0, rows past nrows (nrows < N/2) and columns >= ncols are zero.
+// Element (r, c) is src[r*rsd + c*csd].  Ends with a barrier.
+template <typename T, typename TI, int NT, int N, int RS, int LGS>
+__device__ __forceinline__ void stage_ct_gin(T *buf, const TI *src, int nrows, int ncols, int64_t rsd,
+                                             int64_t csd, int tid)
+{
+    constexpr int NR = N / 8, SMASK = (1 << LGS) - 1;
+    static_assert((NR << LGS) == NT, "one butterfly per thread");
+    const int sq = tid & SMASK, j = tid >> LGS, c = 2 * sq;
+    cx<T> v[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = j + r * NR;
+        cx<T> z{(T)0, (T)0};
+        if (t >= 1 && t <= nrows) {
+            const TI *p = src + toff(t - 1, rsd, c, csd);
+            if (c < ncols) z.x = (T)p[0];
+            if (c + 1 < ncols) z.y = (T)p[csd];
+        }
+        v[r] = z;
+    }
+    dft8_lower<T, false>(v);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lds_cs(buf, RS, 8 * j + r, sq, v[r]);
+    __syncthreads();
+}
+
+// Last stage (radix CtLast<N>::R) of the inverse transform, written straight
+// to global memory: only output rows t < N/2 are formed (the sine synthesis
+// of an odd-symmetric spectrum needs no more), and rows t = 1..nrows of
+// sequence sq go, scaled, to row t - 1 of columns 2 sq and 2 sq + 1 of dst
+// (columns >= ncols are skipped).  Element (r, c) is dst[r*rsd + c*csd].
+template <typename T, typename TO, int NT, int N, int RS, int LGS>
+__device__ __forceinline__ void stage_ct_gout(const T *buf, const cx<T> *tw, TO *dst, int nrows, int ncols,
+                                              int64_t rsd, int64_t csd, T scale, int tid)
+{
+    constexpr int R = CtLast<N>::R, NR = N / R, NBF = NR << LGS, SMASK = (1 << LGS) - 1;
+    static_assert(NBF % NT == 0, "whole butterflies per thread");
+#pragma unroll
+    for (int i = 0; i < NBF / NT; ++i) {
+        const int b = tid + i * NT;
+        const int sq = b & SMASK, j = b >> LGS, c = 2 * sq;
+        cx<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = lds_c(buf, RS, j + r * NR, sq);
+        if (j != 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twid<T, true>(tw, j * r));
+        }
+        dft_small<T, R, true>(v, tw, N);
+#pragma unroll
+        for (int r = 0; r < R / 2; ++r) {
+            const int t = j + r * NR;
+            if (t >= 1 && t <= nrows) {
+                TO *p = dst + toff(t - 1, rsd, c, csd);
+                if (c < ncols) p[0] = (TO)(scale * v[r].x);
+                if (c + 1 < ncols) p[csd] = (TO)(scale * v[r].y);
+            }
+        }
+    }
+}
+
 // Full length-N complex FFT of 2^lgs sequences held in LDS (in place), in the
 // direction INV (false: exp(-2 pi i t/N), true: the conjugate).
 // P2: N is a power of two (only radix-2/4/8 stages are compiled in).
@@ -517,14 +628,6 @@ __device__ __forceinline__ void pre_even(T *buf, int rs, int lgW, int M, int tid
         buf[(N - j) * rs + c] = buf[j * rs + c];
     }
     __syncthreads();
-}
-
-// Element offset r * rsd + c * csd of a tile in 32-bit arithmetic with
-// 24-bit multiplies: the launchers check that strides stay below 2^23 and a
-// tile spans less than 2^31 elements (true for every supported grid).
-__device__ __forceinline__ int toff(int r, int64_t rsd, int c, int64_t csd)
-{
-    return __mul24(r, (int)rsd) + __mul24(c, (int)csd);
 }
 
 template <typename T, int NT>

@@ -126,8 +126,8 @@ struct FinalArgs {
     const cx<float> *twf;
     int group;      // neighbouring column blocks taken together (their rows share 128-byte lines)
     int pre;        // buf already holds the raw sine spectrum along axis 0 (no forward transform)
-    void *rowtab;   // if set: row table [nbatch][M0 - 1][12] (transform type) in global memory, written by
-                    // launch_final_rows before the pass (required for transforms longer than 2048)
+    void *rowtab;   // row table [nbatch][M0 - 1][12] (transform type) in global memory, written by
+                    // launch_final_rows before the pass; both launchers reject a null table
 };
 
 // Boundary values from the screening charge (screen.hip).
@@ -298,7 +298,7 @@ hipError_t launch_dcorr(const DcorrArgs &a, hipStream_t st);
 // false: dst is extended) or restrict (extract = true: src is extended).
 hipError_t launch_embed(const double *src, double *dst, int d, const int64_t *n, const int64_t *ne,
                         const int64_t *off, bool extract, hipStream_t st);
-// Row table of the final pass (if a.rowtab): once per solve, before launch_final.
+// Row table of the final pass: once per solve, before launch_final.
 hipError_t launch_final_rows(const FinalArgs &a, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);
 // K[dd][ib][ic] (3D) or K[dd][ib] (2D) for faces normal to axis a; (b, c) are

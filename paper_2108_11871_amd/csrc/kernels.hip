@@ -854,6 +854,31 @@ hipError_t launch_gtilde(const GtArgs &a, hipStream_t st)
 //   c(k) = prod(2/M) [ -beta / (pi^2 sum k^2/L^2) + gt_hat / Lambda ]     (order 4)
 // then the inverse sine transform along axis 0, written back in place.
 // ---------------------------------------------------------------------------
+// The 12 staged values of one row or column of the final pass, read as
+// 16-byte vectors (records are 16-byte aligned in both spaces).
+__device__ __forceinline__ void load12(const float *p, float *r)
+{
+    const float4 *v = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float4 t = v[i];
+        r[4 * i] = t.x;
+        r[4 * i + 1] = t.y;
+        r[4 * i + 2] = t.z;
+        r[4 * i + 3] = t.w;
+    }
+}
+__device__ __forceinline__ void load12(const double *p, double *r)
+{
+    const double2 *v = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double2 t = v[i];
+        r[2 * i] = t.x;
+        r[2 * i + 1] = t.y;
+    }
+}
+
 // Staged row kx-1 = i of the final pass (see k_final for the layout).
 template <typename TR>
 __device__ __forceinline__ void final_row(const FinalArgs &a, int i, int kB, double lamB, double qB,
@@ -890,6 +915,10 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     // that fetch the next tile into registers while the current one is
     // processed (for FP32 tiles one tile per block measured faster)
     constexpr bool PF = WC > 0 && !BIG && sizeof(T) == 8;
+    // one-tile blocks with compile-time stages: direct global I/O in the
+    // first forward and the last inverse stage (LGSC: log2 of the sequences)
+    constexpr bool DIO = NC > 0 && !PF;
+    constexpr int LGSC = WC == 4 ? 1 : WC == 8 ? 2 : 3;
     extern __shared__ __align__(16) unsigned char smem[];
     // WC > 0: tile width known at compile time (row offsets become shifts)
     // NC > 0: the transform length, known at compile time (only the
@@ -952,8 +981,14 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     const int c0 = cb * W;
     const int nc = min(W, a.ncols - c0);
     T *g = static_cast<T *>(a.buf) + bt * a.ibs + c0 * a.ics;
+    // Compile-time transforms of one-tile blocks read their input rows in the
+    // first stage of the forward transform and write their output rows in the
+    // last stage of the inverse, straight from and to B (no tile load or store).
+    const bool direct = DIO && !a.pre && a.nrows_in <= M - 1;
+    if (!direct) {
     zero_rows<T, NTT>(buf, rs, lgW, 0, 1, tid);
     zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N, tid);
+    }
     if constexpr (PF) {
         put_pair<T, T, NTT, (PF ? WC : 2), MAXE>(buf, rs, 1, pf, a.nrows_in, rcont, tid);
         const int nx = it + grid;
@@ -965,7 +1000,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
                                                           a.nrows_in, a.irs, a.ics, 0, min(W, a.ncols - c1), 0, 0,
                                                           tid);
         }
-    } else {
+    } else if (!direct) {
         tile_load<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, lgW, tid);
     }
     const Geo &geo = a.geo;
@@ -981,17 +1016,15 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     // so that per element Lambda = r10 + c10 + lambda_z + c2[0][1] lx ly and
     // m_R = r11 + c11 + lx ly (c4[0][1] lx + c4[1][0] ly).
     constexpr int SV = 12;
-    // staging area after the tile, 8-byte aligned, addressed from smem so that
-    // it stays in the LDS address space
-    // (transforms longer than 2048: the row table lives in global memory,
-    // written for the solve by k_final_rows; only the columns are staged)
-    const size_t soff = (twb + (size_t)N * rs * sizeof(T) + 7) & ~(size_t)7;
-    // staged values and the per-element combination are in the transform
-    // type (FP32 in the mixed modes, FP64 otherwise)
-    const bool grows = BIG || a.rowtab != nullptr; // row table in global memory
-    T *rv = grows ? static_cast<T *>(a.rowtab) + (BIG ? 0 : (int64_t)bt * (M - 1) * SV)
-                  : reinterpret_cast<T *>(smem + soff);
-    T *cv = grows ? reinterpret_cast<T *>(smem + soff) : rv + (size_t)(M - 1) * SV;
+    // The row invariants come from the per-solve table in global memory
+    // (written by k_final_rows); the column invariants are staged in LDS after
+    // the tile, 16-byte aligned and addressed from smem, so that every access
+    // to them is an LDS instruction (a pointer that may point to either space
+    // would make every access a flat one). Staged values and the per-element
+    // combination are in the transform type (FP32 in the mixed modes).
+    const size_t soff = (twb + (size_t)N * rs * sizeof(T) + 15) & ~(size_t)15;
+    const T *__restrict__ rv = static_cast<const T *>(a.rowtab) + (int64_t)bt * (M - 1) * SV;
+    T *cv = reinterpret_cast<T *>(smem + soff);
     const int I0 = geo.M[0] - 1, I1 = geo.M[1] - 1, I2 = d == 3 ? geo.M[2] - 1 : 1;
     const int kB = bt + 1;
     const int64_t ss0 = shell_size(geo, 0), ss1 = shell_size(geo, 1);
@@ -1008,8 +1041,6 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     const double c2xz = d == 3 ? geo.c2[0][2] : 0.0, c2yz = d == 3 ? geo.c2[1][2] : 0.0;
     const double c4xz = d == 3 ? geo.c4[0][2] : 0.0, c4zx = d == 3 ? geo.c4[2][0] : 0.0;
     const double c4yz = d == 3 ? geo.c4[1][2] : 0.0, c4zy = d == 3 ? geo.c4[2][1] : 0.0;
-    if (!grows)
-        for (int i = tid; i < I0; i += NTT) final_row<T>(a, i, kB, lamB, qB, rv + i * SV);
     for (int i = tid; i < nc; i += NTT) {
         T *r = cv + i * SV;
         const int j = c0 + i; // k1 - 1
@@ -1027,7 +1058,12 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     }
     __syncthreads();
     // forward transform of the zero-padded rows 1..M0-1 (unless B already holds the spectrum)
-    if (!a.pre) {
+    if (direct) {
+        if constexpr (DIO) {
+            stage_ct_gin<T, T, NTT, NC, WC + 1, LGSC>(buf, g, a.nrows_in, nc, a.irs, a.ics, tid);
+            fft_ct_tail<T, NTT, NC, WC + 1, LGSC, false>(buf, tw, tid);
+        }
+    } else if (!a.pre) {
         if (a.nrows_in <= M - 1)
             fft_tile_zpad<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, tid);
         else
@@ -1054,12 +1090,13 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
             for (int sq = 0; sq < nseq; ++sq) lds_cs(buf, rs, k, sq, cx<T>{(T)0, (T)0});
             continue;
         }
-        const T *r = rv + (k - 1) * SV;
+        T r[SV];
+        load12(rv + (k - 1) * SV, r);
         const T lx = r[0], rq = r[1], rs1 = r[2], rs2 = r[3], r10 = r[10], r11 = r[11];
         // family 1 at (kx, kz) for even / odd ky
         const T Pe0 = r[4], Pe1 = r[5], Pe2 = r[6], Po0 = r[7], Po1 = r[8], Po2 = r[9];
         const int kx = k;
-        const int pco = 4 + ((kx & 1) ? 3 : 0); // family 0 at (ky, kz): parity of kx
+        const bool kodd = (kx & 1) != 0; // family 0 at (ky, kz): parity of kx
         for (int sq = 0; sq < nseq; ++sq) {
             const cx<T> z1 = lds_c(buf, rs, k, sq), z2 = lds_c(buf, rs, N - k, sq);
             T cab[2];
@@ -1071,9 +1108,10 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
                 T cval = (T)0;
                 if (c < nc) {
                     const int ky = 1 + c0 + c; // c0 is even: ky is odd for h2 = 0
-                    const T *q1 = cv + c * SV;
+                    T q1[SV];
+                    load12(cv + c * SV, q1);
                     const T P0 = h2 ? Pe0 : Po0, P1v = h2 ? Pe1 : Po1, P2v = h2 ? Pe2 : Po2;
-                    const T *Pc = q1 + pco;
+                    const T Pc[3] = {kodd ? q1[7] : q1[4], kodd ? q1[8] : q1[5], kodd ? q1[9] : q1[6]};
                     const T ly = q1[0], lxy = lx * ly;
                     const T Lm = r10 + q1[10] + lamBt + c2xy * lxy;
                     T gt = rs1 * Pc[0] + q1[2] * P0;
@@ -1101,8 +1139,15 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
         }
     }
     __syncthreads();
-    fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, true, tid);
-    tile_store<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW, tid);
+    if (direct) {
+        if constexpr (DIO) {
+            fft_ct_head<T, NTT, NC, WC + 1, LGSC, true>(buf, tw, tid);
+            stage_ct_gout<T, T, NTT, NC, WC + 1, LGSC>(buf, tw, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, tid);
+        }
+    } else {
+        fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, true, tid);
+        tile_store<T, T, NTT>(buf, rs, 1, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, lgW, tid);
+    }
     if constexpr (!PF) break; // one tile per block: no loop for the compiler to hoist out of
     __syncthreads();          // the next tile reuses the LDS
     }
@@ -1135,10 +1180,9 @@ static void launch_final_w(const FinalArgs &a, int nblk, size_t lds, hipStream_t
 template <typename T, int MAXE, bool P2>
 static void launch_final_k(const FinalArgs &a, int nblk, hipStream_t st)
 {
-    // tile + staged column (W) invariants and, unless the row table is in
-    // global memory, the row (M0-1) invariants, 12 values of type T each
-    const size_t rows = a.rowtab ? 0 : (size_t)(a.fd.M - 1);
-    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (rows + a.W) * 12 * sizeof(T);
+    // tile + staged column (W) invariants, 12 values of type T each (the row
+    // invariants are in the global row table)
+    const size_t lds = tile_lds<T>(a.fd.N, a.W) + 16 + (size_t)a.W * 12 * sizeof(T);
     // compile-time widths also prefetch the next tile: MAXE registers per
     // thread must cover the tile's rows
     const bool rc = a.irs == 1 && a.ics != 1;
@@ -1158,7 +1202,7 @@ static void launch_final_t(const FinalArgs &a, int nblk, int work, hipStream_t s
     const bool p2 = is_pow2(a.fd.N);
     if (big_fft(a.fd.N)) {
         // tile + staged columns only (the rows come from the global table)
-        const size_t lds = tile_lds<T>(a.fd.N, a.W) + 8 + (size_t)a.W * 12 * sizeof(T);
+        const size_t lds = tile_lds<T>(a.fd.N, a.W) + 16 + (size_t)a.W * 12 * sizeof(T);
         if (work <= 4 * NTB) {
             if (p2)
                 launch_final_w<T, 4, true, 2, NTB>(a, nblk, lds, st);
@@ -1219,7 +1263,7 @@ __global__ void k_final_rows(FinalArgs a)
 
 hipError_t launch_final_rows(const FinalArgs &a, hipStream_t st)
 {
-    if (!a.rowtab) return hipSuccess;
+    if (!a.rowtab) return hipErrorInvalidValue;
     const int64_t tot = (int64_t)(a.geo.M[0] - 1) * a.nbatch;
     const unsigned nb = (unsigned)std::min<int64_t>((tot + NT - 1) / NT, 4096);
     hipLaunchKernelGGL(k_final_rows, dim3(nb), dim3(NT), 0, st, a);
@@ -1231,7 +1275,8 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st)
     const int ncb = (a.ncols + a.W - 1) / a.W;
     const int nblk = ncb * a.nbatch;
     const int work = (a.W / 2) * a.fd.N;
-    if (big_fft(a.fd.N) && (a.geo.d != 2 || !a.rowtab || a.W != 2 || work > 8 * NTB))
+    if (!a.rowtab) return hipErrorInvalidValue; // the row invariants are read from it
+    if (big_fft(a.fd.N) && (a.geo.d != 2 || a.W != 2 || work > 8 * NTB))
         return hipErrorInvalidValue;
     if (!big_fft(a.fd.N) && work > 32 * NT) return hipErrorInvalidValue;
     if (!tile_strides_ok(a.nrows_in, a.irs, a.ncols, a.ics)) return hipErrorInvalidValue;
