@@ -406,44 +406,67 @@ __device__ __forceinline__ void fft_ct_head(T *buf, const cx<T> *tw, int tid)
     if constexpr (N == 1024) stage_ct<T, 8, NT, N, 64, RS, LGS, INV>(buf, tw, tid);
 }
 
-// First stage (radix 8) of the forward transform of zero-padded sequences,
-// read straight from global memory: tile row t = 1..nrows of sequence sq is
-// source row t - 1 of columns 2 sq (real part) and 2 sq + 1 (imaginary part);
-// row 0, rows past nrows (nrows < N/2) and columns >= ncols are zero.
-// Element (r, c) is src[r*rsd + c*csd].  Ends with a barrier.
-template <typename T, typename TI, int NT, int N, int RS, int LGS>
-__device__ __forceinline__ void stage_ct_gin(T *buf, const TI *src, int nrows, int ncols, int64_t rsd,
-                                             int64_t csd, int tid)
+// The inputs of the first forward stage (radix 8) of thread tid, for
+// zero-padded sequences read from global memory: v[2r] and v[2r+1] are
+// tile row t = j + r N/8 (r < 4) of sequence sq (j = tid >> LGS, sq = its low
+// bits), i.e. source row t - 1 of columns 2 sq and 2 sq + 1; row 0, rows past
+// nrows (nrows < N/2) and columns >= ncols are zero.  Element (r, c) is
+// src[r*rsd + c*csd].  A loop over tiles can hold v while it transforms the
+// previous tile.
+template <typename TI, int NT, int N, int LGS>
+__device__ __forceinline__ void fetch_gin(TI (&v)[8], const TI *src, int nrows, int ncols, int64_t rsd, int64_t csd,
+                                          int tid)
 {
     constexpr int NR = N / 8, SMASK = (1 << LGS) - 1;
     static_assert((NR << LGS) == NT, "one butterfly per thread");
     const int sq = tid & SMASK, j = tid >> LGS, c = 2 * sq;
-    cx<T> v[8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int t = j + r * NR;
-        cx<T> z{(T)0, (T)0};
-        if (t >= 1 && t <= nrows) {
-            const TI *p = src + toff(t - 1, rsd, c, csd);
-            if (c < ncols) z.x = (T)p[0];
-            if (c + 1 < ncols) z.y = (T)p[csd];
-        }
-        v[r] = z;
+        const bool ok = t >= 1 && t <= nrows;
+        const TI *p = src + toff(ok ? t - 1 : 0, rsd, c, csd);
+        v[2 * r] = ok && c < ncols ? p[0] : (TI)0;
+        v[2 * r + 1] = ok && c + 1 < ncols ? p[csd] : (TI)0;
     }
-    dft8_lower<T, false>(v);
+}
+
+// First forward stage (radix 8, upper half of the inputs zero) from the
+// registers fetch_gin filled; writes every row of the tile.  Ends with a
+// barrier.
+template <typename T, typename TI, int NT, int N, int RS, int LGS>
+__device__ __forceinline__ void stage_ct_rin(T *buf, const TI (&v)[8], int tid)
+{
+    constexpr int SMASK = (1 << LGS) - 1;
+    const int sq = tid & SMASK, j = tid >> LGS;
+    cx<T> a[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) lds_cs(buf, RS, 8 * j + r, sq, v[r]);
+    for (int r = 0; r < 4; ++r) a[r] = cx<T>{(T)v[2 * r], (T)v[2 * r + 1]};
+    dft8_lower<T, false>(a);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lds_cs(buf, RS, 8 * j + r, sq, a[r]);
     __syncthreads();
+}
+
+// The first forward stage straight from global memory (fetch_gin, then
+// stage_ct_rin).
+template <typename T, typename TI, int NT, int N, int RS, int LGS>
+__device__ __forceinline__ void stage_ct_gin(T *buf, const TI *src, int nrows, int ncols, int64_t rsd,
+                                             int64_t csd, int tid)
+{
+    TI v[8];
+    fetch_gin<TI, NT, N, LGS>(v, src, nrows, ncols, rsd, csd, tid);
+    stage_ct_rin<T, TI, NT, N, RS, LGS>(buf, v, tid);
 }
 
 // Last stage (radix CtLast<N>::R) of the inverse transform, written straight
 // to global memory: only output rows t < N/2 are formed (the sine synthesis
-// of an odd-symmetric spectrum needs no more), and rows t = 1..nrows of
-// sequence sq go, scaled, to row t - 1 of columns 2 sq and 2 sq + 1 of dst
-// (columns >= ncols are skipped).  Element (r, c) is dst[r*rsd + c*csd].
+// of an odd-symmetric spectrum needs no more; the caller checks that the rows
+// it keeps lie below N/2), and rows t = row0..row0+nrows-1 of sequence sq go,
+// scaled, to row t - row0 of columns 2 sq and 2 sq + 1 of dst (columns >=
+// ncols are skipped).  Element (r, c) is dst[r*rsd + c*csd].
 template <typename T, typename TO, int NT, int N, int RS, int LGS>
-__device__ __forceinline__ void stage_ct_gout(const T *buf, const cx<T> *tw, TO *dst, int nrows, int ncols,
-                                              int64_t rsd, int64_t csd, T scale, int tid)
+__device__ __forceinline__ void stage_ct_gout(const T *buf, const cx<T> *tw, TO *dst, int row0, int nrows,
+                                              int ncols, int64_t rsd, int64_t csd, T scale, int tid)
 {
     constexpr int R = CtLast<N>::R, NR = N / R, NBF = NR << LGS, SMASK = (1 << LGS) - 1;
     static_assert(NBF % NT == 0, "whole butterflies per thread");
@@ -461,9 +484,9 @@ __device__ __forceinline__ void stage_ct_gout(const T *buf, const cx<T> *tw, TO 
         dft_small<T, R, true>(v, tw, N);
 #pragma unroll
         for (int r = 0; r < R / 2; ++r) {
-            const int t = j + r * NR;
-            if (t >= 1 && t <= nrows) {
-                TO *p = dst + toff(t - 1, rsd, c, csd);
+            const int t = j + r * NR - row0;
+            if (t >= 0 && t < nrows) {
+                TO *p = dst + toff(t, rsd, c, csd);
                 if (c < ncols) p[0] = (TO)(scale * v[r].x);
                 if (c + 1 < ncols) p[csd] = (TO)(scale * v[r].y);
             }

@@ -911,10 +911,12 @@ template <typename T, int MAXE, bool P2, int WC, int NTT, int NC>
 __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
 {
     constexpr bool BIG = NTT != NT;
-    // FP64 tiles of a compile-time width (short transforms): persistent blocks
-    // that fetch the next tile into registers while the current one is
-    // processed (for FP32 tiles one tile per block measured faster)
-    constexpr bool PF = WC > 0 && !BIG && sizeof(T) == 8;
+    // FP64 tiles of a compile-time width (short transforms) without
+    // compile-time stages: persistent blocks that fetch the next tile into
+    // registers while the current one is processed (for FP32 tiles, and for
+    // the compile-time stages with their direct global I/O, one tile per
+    // block measured faster)
+    constexpr bool PF = WC > 0 && !BIG && sizeof(T) == 8 && NC == 0;
     // one-tile blocks with compile-time stages: direct global I/O in the
     // first forward and the last inverse stage (LGSC: log2 of the sequences)
     constexpr bool DIO = NC > 0 && !PF;
@@ -1142,7 +1144,7 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     if (direct) {
         if constexpr (DIO) {
             fft_ct_head<T, NTT, NC, WC + 1, LGSC, true>(buf, tw, tid);
-            stage_ct_gout<T, T, NTT, NC, WC + 1, LGSC>(buf, tw, g, a.nrows_in, nc, a.irs, a.ics, (T)0.5, tid);
+            stage_ct_gout<T, T, NTT, NC, WC + 1, LGSC>(buf, tw, g, 1, a.nrows_in, nc, a.irs, a.ics, (T)0.5, tid);
         }
     } else {
         fft_tile<T, MAXE, NTT, P2>(buf, rs, lgs, fd, tw, true, tid);
@@ -1159,7 +1161,7 @@ static void launch_final_n(const FinalArgs &a, int nblk, size_t lds, hipStream_t
     const void *fn = (const void *)&k_final<T, MAXE, P2, WC, NTT, NC>;
     set_lds(fn, lds);
     int grid = nblk;
-    if (WC > 0 && NTT == NT && sizeof(T) == 8) {
+    if (WC > 0 && NTT == NT && sizeof(T) == 8 && NC == 0) { // persistent blocks (PF in k_final)
         const int r = resident_blocks(fn, NTT, lds);
         if (r > 0 && r < nblk) grid = r;
     }
