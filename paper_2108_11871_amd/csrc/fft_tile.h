@@ -663,7 +663,7 @@ __device__ __forceinline__ void zero_rows(T *buf, int rs, int lgW, int r0, int r
 }
 
 template <typename T, int NT>
-__device__ void load_twiddles(cx<T> *dst, const cx<double> *src, int N)
+__device__ __forceinline__ void load_twiddles(cx<T> *dst, const cx<double> *src, int N)
 {
     for (int t = threadIdx.x; t < N; t += NT) {
         cx<double> w = src[t];
