@@ -10,6 +10,22 @@
 
 namespace ips {
 
+// Tile lb -> (column block cb, batch entry bt).  Column blocks vary fastest,
+// except where the output's batch stride is 1: there neighbouring batch
+// entries come first, so that the blocks that run side by side (on one XCD)
+// write neighbouring words of the same cache lines (a tile row writes its W
+// values at the output's column stride).
+__device__ __forceinline__ void tile_of(const PassArgs &a, int ncb, int lb, int &cb, int &bt)
+{
+    if (a.obs == 1 && a.nbatch > 1) {
+        bt = lb % a.nbatch;
+        cb = lb / a.nbatch;
+    } else {
+        cb = lb % ncb;
+        bt = lb / ncb;
+    }
+}
+
 // One tile of a pass: tile lb (column block lb % ncb of batch entry lb / ncb),
 // loaded into LDS (rows placed as the input mode needs), transformed along its
 // rows and stored.  WT > 0: the tile width, known at compile time (equal to
@@ -33,7 +49,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int lb)
     const cx<T> *tw = tw_table<T, BIG>(smem, a.tw, a.twf);
     T *buf = reinterpret_cast<T *>(smem + (BIG ? 0 : (size_t)N * sizeof(cx<T>)));
     const int ncb = (a.ncols + W - 1) / W;
-    const int cb = lb % ncb, bt = lb / ncb;
+    int cb, bt;
+    tile_of(a, ncb, lb, cb, bt);
     const int c0 = cb * W;
     const int nc = min(W, a.ncols - c0);
     const TI *in = static_cast<const TI *>(a.in) + bt * a.ibs + c0 * a.ics;
@@ -122,7 +139,8 @@ __global__ __launch_bounds__(NTT) void k_pass(PassArgs a, int ntiles)
     const TI *in0 = static_cast<const TI *>(a.in);
     TO *out0 = static_cast<TO *>(a.out);
     auto tile_at = [&](int it, int &c0, int &nc, int64_t &ioff, int64_t &ooff) {
-        const int cb = it % ncb, bt = it / ncb;
+        int cb, bt;
+        tile_of(a, ncb, it, cb, bt);
         c0 = cb * W;
         nc = min(W, a.ncols - c0);
         ioff = bt * a.ibs + c0 * a.ics;
