@@ -207,19 +207,20 @@ __global__ __launch_bounds__(NTA) void k_adj_sop(AdjArgs a, const double *F, dou
 //   U  += D4_x T_x                                         (k_adj_d4x)
 // with F and T_x taken as zero off the grid (F is zero outside the core: the
 // extrapolation writes every node), which is the tap set of k_adj_sop.  One
-// wave per grid line along the last axis; the lanes walk it contiguously.
+// thread per node; the threads of a block take consecutive nodes of one plane
+// of the first axis (grid.y), so every lane is busy whatever the line length.
 __global__ __launch_bounds__(NTA) void k_adj_d2y(AdjArgs a, int x, const double *F, double *T)
 {
     const Geo &g = a.geo;
     const int n[3] = {(int)a.n[0], (int)a.n[1], (int)a.n[2]};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i0 = blockIdx.y, i1 = blockIdx.x * (NTA / 64) + wave;
-    if (i1 >= n[1]) return;
+    const int pl = blockIdx.x * NTA + threadIdx.x;
+    if (pl >= n[1] * n[2]) return;
+    const int i0 = blockIdx.y, i1 = pl / n[2], i2 = pl - i1 * n[2];
     const int64_t st[3] = {(int64_t)n[1] * n[2], n[2], 1};
     const double hx2 = g.h[x] * g.h[x];
-    for (int i2 = lane; i2 < n[2]; i2 += 64) {
+    {
         const int i[3] = {i0, i1, i2};
-        const int64_t e = i0 * st[0] + i1 * st[1] + i2;
+        const int64_t e = i0 * st[0] + pl;
         double v = 0.0;
 #pragma unroll
         for (int y = 0; y < 3; ++y) {
@@ -235,14 +236,14 @@ __global__ __launch_bounds__(NTA) void k_adj_d2y(AdjArgs a, int x, const double 
 __global__ __launch_bounds__(NTA) void k_adj_d4x(AdjArgs a, int x, const double *T, double *U)
 {
     const int n[3] = {(int)a.n[0], (int)a.n[1], (int)a.n[2]};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i0 = blockIdx.y, i1 = blockIdx.x * (NTA / 64) + wave;
-    if (i1 >= n[1]) return;
+    const int pl = blockIdx.x * NTA + threadIdx.x;
+    if (pl >= n[1] * n[2]) return;
+    const int i0 = blockIdx.y, i1 = pl / n[2], i2 = pl - i1 * n[2];
     const int64_t st[3] = {(int64_t)n[1] * n[2], n[2], 1};
     const double a4[5] = {1.0, -4.0, 6.0, -4.0, 1.0};
-    for (int i2 = lane; i2 < n[2]; i2 += 64) {
+    {
         const int i[3] = {i0, i1, i2};
-        const int64_t e = i0 * st[0] + i1 * st[1] + i2;
+        const int64_t e = i0 * st[0] + pl;
         double v = 0.0;
 #pragma unroll
         for (int dx = -2; dx <= 2; ++dx) {
@@ -258,7 +259,7 @@ hipError_t launch_adj_r6(const AdjArgs &a, const double *A, double *F, double *U
     const int nb = 4096;
     if (a.geo.d == 3) {
         hipLaunchKernelGGL(k_adj_etrans<3>, dim3(nb), dim3(NTA), 0, st, a, A, F);
-        const dim3 grid((unsigned)((a.n[1] + NTA / 64 - 1) / (NTA / 64)), (unsigned)a.n[0]);
+        const dim3 grid((unsigned)((a.n[1] * a.n[2] + NTA - 1) / NTA), (unsigned)a.n[0]);
         for (int x = 0; x < 3; ++x) {
             hipLaunchKernelGGL(k_adj_d2y, grid, dim3(NTA), 0, st, a, x, F, T);
             hipLaunchKernelGGL(k_adj_d4x, grid, dim3(NTA), 0, st, a, x, T, U);
