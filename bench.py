@@ -17,7 +17,8 @@ Prints ONE JSON line.  Besides the contract fields it carries
   roofline      HBM roofline of the dominant kernel (per-launch algorithmic
                 bytes / its average duration from HIP events on the library's
                 stream) and, when counters for the current sources exist
-                under profiles/, the HBM traffic they measured;
+                under profiles/, the HBM traffic they measured; beside the
+                8 TB/s peak, the rate a plain 1 GiB device copy attains;
   cpu_baseline  the FP64 oracle on the host cores: the same 257^3 solve with
                 per-stage times, plus one-thread times of the 2D 65^2 and the
                 3D 129^3 configurations;
@@ -84,6 +85,26 @@ def source_hash() -> str:
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def attainable_hbm(torch, mib: int = 1024, reps: int = 10) -> float:
+    """GB/s of a plain device-to-device copy of `mib` MiB (bytes read plus
+    bytes written over the mean time of `reps` copies, HIP events on the
+    stream the copies run on)."""
+    x = torch.ones(mib * 131072, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2.0 * mib * 1048576 / (ms * 1e-3) / 1e9
 
 
 def stage_bytes(n: int, mode: str, nch: dict) -> dict:
@@ -651,6 +672,9 @@ def main():
             if mode != "fp64" and res[mode]["err"] is None:
                 res[mode]["err"] = float(((res[mode]["phi"] - ref).abs().max() / ref.abs().max()).item())
 
+    attain = attainable_hbm(torch)
+    log("attainable HBM (device copy of 1 GiB): %.0f GB/s" % attain)
+
     if args.copy_calibration > 0:
         x = torch.ones(args.copy_calibration * 131072, dtype=torch.float64, device="cuda:0")
         y = torch.empty_like(x)
@@ -755,6 +779,10 @@ def main():
             "traffic_fetch_write": None if traffic is None else [traffic["fetch"], traffic["write"]],
             "avg_launch_ms": stage_ms[dom],
             "bytes_per_launch": byts[dom],
+            # a plain device copy of 1 GiB (read + write), the rate HBM
+            # delivers in practice
+            "attainable_GBs": attain,
+            "frac_of_attainable": achieved / attain,
         },
         "whole_solve_hbm": {
             # per-node compulsory streams: 16 + 6w B (rho in, phi out, three
