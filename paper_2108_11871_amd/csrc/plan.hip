@@ -1975,7 +1975,7 @@ int execute_adjoint(ips_plan p, const double *w, double *out, hipStream_t st)
             e.obs = (int64_t)N[b] * I[c];
             e.ncols = N[b];
             e.nbatch = I[fam];
-            e.W = tile_width(N[c], p->work, N[b]);
+            e.W = tile_width(N[c], p->work / 2, N[b]);
             e.scale = 1.0 / N[c];
             e.accum = 0;
             e.fd = p->fd[c];
