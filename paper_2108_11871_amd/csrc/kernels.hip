@@ -988,8 +988,8 @@ __global__ __launch_bounds__(NTT) void k_final(FinalArgs a, int ntiles)
     // last stage of the inverse, straight from and to B (no tile load or store).
     const bool direct = DIO && !a.pre && a.nrows_in <= M - 1;
     if (!direct) {
-    zero_rows<T, NTT>(buf, rs, lgW, 0, 1, tid);
-    zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N, tid);
+        zero_rows<T, NTT>(buf, rs, lgW, 0, 1, tid);
+        zero_rows<T, NTT>(buf, rs, lgW, 1 + a.nrows_in, N, tid);
     }
     if constexpr (PF) {
         put_pair<T, T, NTT, (PF ? WC : 2), MAXE>(buf, rs, 1, pf, a.nrows_in, rcont, tid);
