@@ -420,6 +420,24 @@ def ingest_stats(stats_csv, bench_json, title, cmd, out_name, top=20):
         lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f |" % (
             r["Name"].replace("void ", "").replace("ips::", ""), r["Calls"], float(r["AverageNs"]) / 1e3,
             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    # per-stage means of the individual dispatches, when the kernel trace of the
+    # same run sits beside the stats (one name can serve several stages)
+    trace = os.path.join(os.path.dirname(stats_csv), os.path.basename(stats_csv).replace("kernel_stats",
+                                                                                         "kernel_trace"))
+    if trace != stats_csv and os.path.exists(trace):
+        with open(trace) as fh:
+            disp = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+        per = {}
+        for stage, (sub, occ) in STAGE_DISPATCH.items():
+            nper = 1 + max(o for s2, o in STAGE_DISPATCH.values() if s2 == sub)
+            durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in disp if sub in r["Kernel_Name"]]
+            if durs and len(durs) % nper == 0:
+                mine = durs[occ::nper]
+                per[stage] = (sum(mine) / len(mine), len(mine))
+        if per:
+            lines += ["", "Per-stage means of the individual dispatches (kernel trace of the same run; a kernel "
+                      "name that serves several stages is split by its order within each solve):", ""]
+            lines.append(", ".join("%s %.1f us (%d)" % (k, v[0], v[1]) for k, v in per.items()))
     if bench_json:
         with open(bench_json) as fh:
             b = json.loads(fh.read().strip().splitlines()[-1])
